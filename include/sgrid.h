@@ -1,0 +1,177 @@
+/*
+ * sgrid — contiguous narrow-band sparse grids on MI355X (gfx950).
+ *
+ * C ABI of the hot path of "Contiguous Storage of Grid Data for
+ * Heterogeneous Computing": 4x4x4 data packages of the activated coarse
+ * cells held in one contiguous array per field, found through a
+ * cell-to-package index map and a 27-entry neighbour-package table.
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ *  - Domain: the cube [0, 4 M h)^3.  M = n_coarse coarse cells per axis of
+ *    size l_c = 4h; N = 4M data points per axis, data point (i, j, k) at
+ *    ((i, j, k) + 1/2) h.  Coarse cell (a, b, c) has linear index
+ *    a + M b + M^2 c (x fastest).
+ *  - Package ids: 0 is the negative (inside) far field, 1 the positive
+ *    (outside) far field, 2 .. P+1 the P activated cells in ascending
+ *    linear cell order (Sec. 5, Sec. 7.1 step 3).  P^ = P + 2.
+ *  - A field is stored as [P^][64] values; inside a package the data index
+ *    (i, j, k) in 0..3 is stored at i + 4 j + 16 k.  Rows 0 and 1 hold the
+ *    far-field constants -B and +B with B = 16 h (sgrid_fill_far_field).
+ *    Vector fields (the gradient) are three such arrays back to back,
+ *    [3][P^][64].
+ *  - Neighbour slot of the shift (dx, dy, dz) in {-1,0,1}^3 is
+ *    (dx+1) + 3 (dy+1) + 9 (dz+1); slot 13 is the package itself.
+ *    Neighbours outside the domain are package 1; the far-field packages
+ *    neighbour themselves (Sec. 5.2, Sec. 7.1 step 5).
+ *  - Memory: every pointer argument named *_dev, and every field, is device
+ *    memory owned by the caller (16-byte aligned); the grid handle owns its
+ *    index tables.  `stream` is a hipStream_t (NULL = default stream).
+ *    Calls are asynchronous on that stream, except sgrid_build_packages,
+ *    which synchronises once to learn P.
+ *  - Errors: every call returns an sgrid_status and never aborts; the text of
+ *    the last failure on the calling thread is sgrid_last_error().  Argument
+ *    checks run before any device work.  Faults of kernels already queued
+ *    surface at the next call that synchronises.
+ */
+#ifndef SGRID_H
+#define SGRID_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    SGRID_OK = 0,
+    SGRID_E_INVALID = 1,   /* null, misaligned or out-of-range argument */
+    SGRID_E_NOMEM = 2,     /* device allocation failed */
+    SGRID_E_HIP = 3,       /* a HIP runtime call or kernel launch failed */
+    SGRID_E_CAPACITY = 4,  /* a size does not fit the 32-bit index tables */
+    SGRID_E_STATE = 5      /* handle used in a state that does not allow the call */
+} sgrid_status;
+
+typedef enum { SGRID_F32 = 0, SGRID_F64 = 1 } sgrid_dtype;
+
+typedef struct sgrid_grid sgrid_grid;
+typedef struct sgrid_mlp sgrid_mlp;
+typedef struct sgrid_batch sgrid_batch;
+
+typedef struct {
+    int32_t n_coarse;   /* M >= 1, M^3 + 2 < 2^32 */
+    double h;           /* data spacing, > 0; l_c = 4h */
+} sgrid_desc;
+
+typedef struct {
+    int32_t n_coarse;
+    double h;
+    int64_t n_packages;          /* P (activated, excluding the two far-field packages) */
+    int64_t n_core;              /* core packages among them */
+    const uint32_t *cell_pkg;    /* device [M^3]: package id of every coarse cell */
+    const uint32_t *pkg_cell;    /* device [P^]: linear cell of each package, 0xFFFFFFFF for 0 and 1 */
+    const uint8_t *pkg_type;     /* device [P^]: 0 far field, 1 core, 2 inner */
+    const uint32_t *pkg_nbr;     /* device [P^][27]: neighbour package ids */
+    const uint32_t *core_list;   /* device [n_core]: ids of the core packages, ascending */
+} sgrid_info;
+
+/* Text of the last failure on this thread ("" if none). */
+const char *sgrid_last_error(void);
+
+/* Library version, as major * 10000 + minor * 100 + patch. */
+int32_t sgrid_version(void);
+
+/*
+ * Activation, numbering and neighbour table (Sec. 4, Sec. 5, Sec. 7.1 steps
+ * 1-3 and 5).  `coarse_sdf_dev` [M^3] is the signed distance at every coarse
+ * cell centre.  A cell is core when |d| < l_c and inner when it is not core
+ * but one of its 26 neighbours is; both are activated and numbered 2.. in
+ * ascending linear order; every other cell maps to far field 0 (d < 0) or 1.
+ * The result is bit-identical for identical inputs.  On success *out owns the
+ * tables until sgrid_destroy.  Synchronises `stream` once.
+ */
+sgrid_status sgrid_build_packages(const sgrid_desc *desc, const float *coarse_sdf_dev,
+                                  void *stream, sgrid_grid **out);
+
+/* Sizes and device views of the tables (valid until sgrid_destroy). */
+sgrid_status sgrid_get_info(const sgrid_grid *grid, sgrid_info *out);
+
+/* Frees the tables; waits for the device first.  NULL is accepted. */
+sgrid_status sgrid_destroy(sgrid_grid *grid);
+
+/* Writes -B to package 0 and +B to package 1 of `phi_dev` [P^][64] (B = 16h). */
+sgrid_status sgrid_fill_far_field(const sgrid_grid *grid, sgrid_dtype dtype, void *phi_dev,
+                                  void *stream);
+
+/*
+ * Upwind reinitialisation (the paper names level-set operations on the band
+ * without fixing the scheme; this is the Sussman-Smereka-Osher iteration
+ * with Godunov upwinding): n_iter Jacobi sweeps over every point of every
+ * activated package, with
+ *   S = phi / sqrt(phi^2 + h^2), dt = h / 2,
+ *   per axis D- = (phi_p - phi_{p-e}) / h, D+ = (phi_{p+e} - phi_p) / h,
+ *   S > 0: a^2 = max(max(D-,0)^2, min(D+,0)^2); S < 0: max(min(D-,0)^2, max(D+,0)^2),
+ *   phi' = phi - dt S (sqrt(sum a^2) - 1).
+ * Neighbours come through the neighbour table (Sec. 5.2); far-field rows are
+ * read, never written.  `scratch_dev` is a second [P^][64] buffer of the same
+ * dtype; the result is left in `phi_dev` for any n_iter >= 0.
+ */
+sgrid_status sgrid_reinitialize(const sgrid_grid *grid, sgrid_dtype dtype, void *phi_dev,
+                                void *scratch_dev, int32_t n_iter, void *stream);
+
+/*
+ * Central-difference gradient (Sec. 7.3, Listing 5, with the plain average of
+ * the two one-sided differences): g = (phi_{p+e} - phi_{p-e}) / (2h) at every
+ * point of every activated package; rows 0 and 1 of every component are set
+ * to 0.  `grad_dev` is [3][P^][64].
+ */
+sgrid_status sgrid_compute_gradient(const sgrid_grid *grid, sgrid_dtype dtype,
+                                    const void *phi_dev, void *grad_dev, void *stream);
+
+/*
+ * Grid-to-particle probe (Sec. 8): trilinear interpolation of phi and of the
+ * gradient at n particles, then normal = g / |g| (0 where g = 0).  Per axis
+ * u = x / h, s = u - 1/2, i0 = clamp(floor(s), 0, N - 2), t = clamp(s - i0, 0, 1).
+ * The particle's package is the coarse cell clamp(floor(u / 4), 0, M - 1) that
+ * contains it; the eight corners are reached from it through the neighbour
+ * table (index shifts in [-1, 4]), so a particle in a far-field cell reads that
+ * far-field package everywhere.  `pos_dev` [n][3], `phi_out_dev` [n],
+ * `normal_out_dev` [n][3], all in `dtype`.  n may be 0.
+ */
+sgrid_status sgrid_probe_particles(const sgrid_grid *grid, sgrid_dtype dtype, const void *phi_dev,
+                                   const void *grad_dev, const void *pos_dev, int64_t n,
+                                   void *phi_out_dev, void *normal_out_dev, void *stream);
+
+/*
+ * Near-surface kernel integrals (Sec. 8 names the integral with an SPH
+ * smoothing kernel over the sparse grid).  At every data point p of every
+ * core package, with query point q = x_p + (h/2)(1,1,1) and the 32 data points
+ * j within 2h of q:
+ *   out[0] = h^3 sum_j W(|q - x_j|) V_j,
+ *   out[1+a] = h^4 sum_j W'(|q - x_j|) (q - x_j)_a / |q - x_j| V_j,
+ * where W is the Wendland C2 kernel with smoothing length h, g_j the central
+ * difference at j, and V_j the exact fraction of j's cell on the phi > 0 side
+ * of the plane phi_j + g_j.(y - x_j).  FP32.  `out_dev` is [4][n_core * 64],
+ * core packages in core_list order, local index i + 4j + 16k inside each.
+ * With `model` non-NULL the surrogate network is evaluated instead and every
+ * point whose gate fails falls back to the plain integral; the number of
+ * fallback points is written to *n_fallback_dev when that pointer is non-NULL.
+ */
+sgrid_status sgrid_compute_near_surface_integrals(const sgrid_grid *grid, const float *phi_dev,
+                                                  const sgrid_mlp *model, float *out_dev,
+                                                  uint32_t *n_fallback_dev, void *stream);
+
+/*
+ * Tuning knob for sgrid_reinitialize: sweep variant 0 exchanges the interior
+ * neighbours between lanes (DPP row shifts), variant 1 stages each package
+ * and its face halo in an LDS tile; `groups` (1..8) is the number of
+ * four-package sets one wavefront processes.  Process-wide; default (0, 1).
+ * Results are identical for every setting.
+ */
+sgrid_status sgrid_set_sweep_config(int32_t variant, int32_t groups);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SGRID_H */

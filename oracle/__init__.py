@@ -51,7 +51,7 @@ def lib():
             "orc_index_shift": (None, [i32, P, P]),
             "orc_reinit": (None, [i32, f64, f64, P, i64, P, P, i32]),
             "orc_gradient": (None, [i32, f64, f64, P, i64, P, P, P, P]),
-            "orc_probe": (None, [i32, f64, f64, P, P, P, P, P, P, i64, P, P]),
+            "orc_probe": (None, [i32, f64, f64, P, P, P, P, P, P, i64, P, P, P]),
             "orc_plane_cube_fraction": (f64, [f64, f64, f64, f64]),
             "orc_wendland": (f64, [f64]),
             "orc_wendland_dr": (f64, [f64]),
@@ -175,16 +175,17 @@ def gradient(N: int, h: float, B: float, active: np.ndarray, phi: np.ndarray):
 
 
 def probe(N: int, h: float, B: float, cell_pkg: np.ndarray, phi: np.ndarray, g: np.ndarray,
-          pos: np.ndarray):
+          pos: np.ndarray, with_gradient: bool = False):
     pos = np.ascontiguousarray(pos, dtype=np.float64).reshape(-1, 3)
     n = pos.shape[0]
     out = np.empty(n, dtype=np.float64)
     nrm = np.empty((n, 3), dtype=np.float64)
+    gout = np.empty((n, 3), dtype=np.float64) if with_gradient else None
     cp = np.ascontiguousarray(cell_pkg, dtype=np.uint32)
     lib().orc_probe(N, h, B, _p(cp), _p(np.ascontiguousarray(phi)), _p(np.ascontiguousarray(g[0])),
                     _p(np.ascontiguousarray(g[1])), _p(np.ascontiguousarray(g[2])),
-                    _p(pos), n, _p(out), _p(nrm))
-    return out, nrm
+                    _p(pos), n, _p(out), _p(nrm), _p(gout) if with_gradient else None)
+    return (out, nrm, gout) if with_gradient else (out, nrm)
 
 
 def plane_cube_fraction(a: float, g) -> float:

@@ -201,11 +201,12 @@ void orc_gradient(int32_t N, double h, double B, const int64_t *active, int64_t 
 /* t = clamp(s - i0, 0, 1).  The particle's package is the coarse cell        */
 /* clamp(floor(u / 4), 0, M-1) that contains it; when that cell is not        */
 /* activated its package is a far-field one, whose neighbours are itself, so  */
-/* every corner reads the far-field constant and g = 0.                       */
+/* every corner reads the far-field constant and g = 0.  g_out (nullable)     */
+/* receives the interpolated g.                                               */
 /* ------------------------------------------------------------------------ */
 void orc_probe(int32_t N, double h, double B, const uint32_t *cell_pkg,
                const double *phi, const double *gx, const double *gy, const double *gz,
-               const double *pos, int64_t n, double *phi_out, double *nrm_out)
+               const double *pos, int64_t n, double *phi_out, double *nrm_out, double *g_out)
 {
     const int64_t M = N / 4;
 #pragma omp parallel for schedule(static)
@@ -230,6 +231,7 @@ void orc_probe(int32_t N, double h, double B, const uint32_t *cell_pkg,
         if (home < 2) {
             phi_out[q] = (home == FAR_NEG) ? -B : B;
             nrm_out[3 * q] = nrm_out[3 * q + 1] = nrm_out[3 * q + 2] = 0.0;
+            if (g_out) g_out[3 * q] = g_out[3 * q + 1] = g_out[3 * q + 2] = 0.0;
             continue;
         }
         double v = 0, g[3] = {0, 0, 0};
@@ -245,6 +247,7 @@ void orc_probe(int32_t N, double h, double B, const uint32_t *cell_pkg,
         double gn = sqrt(g[0] * g[0] + g[1] * g[1] + g[2] * g[2]);
         phi_out[q] = v;
         for (int a = 0; a < 3; ++a) nrm_out[3 * q + a] = gn > 0 ? g[a] / gn : 0.0;
+        if (g_out) for (int a = 0; a < 3; ++a) g_out[3 * q + a] = g[a];
     }
 }
 

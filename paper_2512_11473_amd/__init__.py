@@ -1,0 +1,241 @@
+"""sgrid: contiguous narrow-band sparse grids on MI355X.
+
+Thin Python binding of the C ABI in ``include/sgrid.h`` (``libsgrid.so``).
+It only marshals arguments: torch tensors supply device memory and the
+current HIP stream, and every step of the hot path runs in the library's HIP
+kernels.  There is no CPU fallback: importing the binding without a built
+library, or calling it without a GPU, raises.
+
+Names follow the C ABI without the ``sgrid_`` prefix.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+import torch
+
+__all__ = [
+    "SgridError", "Grid", "load", "build_packages", "fill_far_field", "reinitialize",
+    "compute_gradient", "probe_particles", "compute_near_surface_integrals", "set_sweep_config",
+    "LIB_PATH", "FAR_FIELD_IN_H",
+]
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libsgrid.so")
+FAR_FIELD_IN_H = 16.0
+_lib = None
+_P = ctypes.c_void_p
+
+
+class SgridError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"sgrid status {status}: {message}")
+        self.status = status
+
+
+class _Desc(ctypes.Structure):
+    _fields_ = [("n_coarse", ctypes.c_int32), ("h", ctypes.c_double)]
+
+
+class _Info(ctypes.Structure):
+    _fields_ = [("n_coarse", ctypes.c_int32), ("h", ctypes.c_double), ("n_packages", ctypes.c_int64),
+                ("n_core", ctypes.c_int64), ("cell_pkg", _P), ("pkg_cell", _P), ("pkg_type", _P),
+                ("pkg_nbr", _P), ("core_list", _P)]
+
+
+_SIGNATURES = {
+    "sgrid_last_error": (ctypes.c_char_p, []),
+    "sgrid_version": (ctypes.c_int32, []),
+    "sgrid_build_packages": (ctypes.c_int, [ctypes.POINTER(_Desc), _P, _P, ctypes.POINTER(_P)]),
+    "sgrid_get_info": (ctypes.c_int, [_P, ctypes.POINTER(_Info)]),
+    "sgrid_destroy": (ctypes.c_int, [_P]),
+    "sgrid_fill_far_field": (ctypes.c_int, [_P, ctypes.c_int, _P, _P]),
+    "sgrid_reinitialize": (ctypes.c_int, [_P, ctypes.c_int, _P, _P, ctypes.c_int32, _P]),
+    "sgrid_compute_gradient": (ctypes.c_int, [_P, ctypes.c_int, _P, _P, _P]),
+    "sgrid_probe_particles": (ctypes.c_int, [_P, ctypes.c_int, _P, _P, _P, ctypes.c_int64, _P, _P, _P]),
+    "sgrid_compute_near_surface_integrals": (ctypes.c_int, [_P, _P, _P, _P, _P, _P]),
+    "sgrid_set_sweep_config": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32]),
+}
+
+
+def load():
+    """Load libsgrid.so (building it first only if it does not exist)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            from . import build as _build
+            _build.build()
+        # the HIP runtime must be the one torch already loaded
+        torch.cuda.is_available()
+        lib = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGNATURES.items():
+            fn = getattr(lib, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = lib
+    return _lib
+
+
+def _check(status: int):
+    if status != 0:
+        msg = load().sgrid_last_error()
+        raise SgridError(status, msg.decode() if msg else "")
+
+
+def _dtype_code(t: torch.Tensor) -> int:
+    if t.dtype == torch.float32:
+        return 0
+    if t.dtype == torch.float64:
+        return 1
+    raise TypeError(f"unsupported dtype {t.dtype}")
+
+
+def _dev(t: torch.Tensor, name: str):
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor")
+    if t.device.type != "cuda":
+        raise ValueError(f"{name} must be a device tensor (got {t.device})")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream=None):
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+class Grid:
+    """An activated narrow band: owns the library's index tables."""
+
+    def __init__(self, handle: ctypes.c_void_p):
+        self._h = handle
+        info = _Info()
+        _check(load().sgrid_get_info(self._h, ctypes.byref(info)))
+        self.n_coarse = int(info.n_coarse)
+        self.h = float(info.h)
+        self.n_packages = int(info.n_packages)
+        self.n_core = int(info.n_core)
+        self._info = info
+
+    @property
+    def handle(self):
+        if self._h is None:
+            raise SgridError(5, "grid already destroyed")
+        return self._h
+
+    @property
+    def n_total(self) -> int:
+        return self.n_packages + 2
+
+    @property
+    def far_field(self) -> float:
+        return FAR_FIELD_IN_H * self.h
+
+    def destroy(self):
+        if getattr(self, "_h", None) is not None:
+            _check(load().sgrid_destroy(self._h))
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+    def tables(self) -> dict:
+        """Copies of the index tables as device tensors (for checks)."""
+        hip = ctypes.CDLL("libamdhip64.so.7")
+        hip.hipMemcpy.argtypes = [_P, _P, ctypes.c_size_t, ctypes.c_int]
+        hip.hipMemcpy.restype = ctypes.c_int
+        info = self._info
+        M, nt = self.n_coarse, self.n_total
+
+        def grab(ptr, n, dtype, esize):
+            t = torch.empty(n, dtype=dtype, device="cuda")
+            if n:
+                torch.cuda.synchronize()
+                rc = hip.hipMemcpy(ctypes.c_void_p(t.data_ptr()), ctypes.c_void_p(ptr), n * esize, 3)
+                if rc != 0:
+                    raise SgridError(3, f"hipMemcpy failed ({rc})")
+            return t
+
+        return {
+            "cell_pkg": grab(info.cell_pkg, M ** 3, torch.int32, 4),
+            "pkg_cell": grab(info.pkg_cell, nt, torch.int32, 4),
+            "pkg_type": grab(info.pkg_type, nt, torch.uint8, 1),
+            "pkg_nbr": grab(info.pkg_nbr, nt * 27, torch.int32, 4).view(nt, 27),
+            "core_list": grab(info.core_list, self.n_core, torch.int32, 4),
+        }
+
+    def empty_field(self, dtype=torch.float32, components: int = 1) -> torch.Tensor:
+        shape = (self.n_total, 64) if components == 1 else (components, self.n_total, 64)
+        return torch.empty(shape, dtype=dtype, device="cuda")
+
+
+def build_packages(coarse_sdf: torch.Tensor, h: float, stream=None) -> Grid:
+    """Activation, numbering and neighbour tables from the coarse distances
+    (float32, M^3 values, x fastest)."""
+    n = coarse_sdf.numel()
+    M = int(round(n ** (1.0 / 3.0)))
+    if M ** 3 != n:
+        raise ValueError(f"coarse_sdf has {n} values, not a cube")
+    if coarse_sdf.dtype != torch.float32:
+        raise TypeError("coarse_sdf must be float32")
+    desc = _Desc(M, float(h))
+    out = ctypes.c_void_p()
+    _check(load().sgrid_build_packages(ctypes.byref(desc), _dev(coarse_sdf, "coarse_sdf"), _stream(stream),
+                                       ctypes.byref(out)))
+    return Grid(out)
+
+
+def fill_far_field(grid: Grid, phi: torch.Tensor, stream=None):
+    _check(load().sgrid_fill_far_field(grid.handle, _dtype_code(phi), _dev(phi, "phi"), _stream(stream)))
+
+
+def reinitialize(grid: Grid, phi: torch.Tensor, scratch: torch.Tensor, n_iter: int, stream=None):
+    if scratch.dtype != phi.dtype or scratch.numel() != phi.numel() or phi.numel() != grid.n_total * 64:
+        raise ValueError("phi and scratch must both be [P+2, 64] of one dtype")
+    _check(load().sgrid_reinitialize(grid.handle, _dtype_code(phi), _dev(phi, "phi"), _dev(scratch, "scratch"),
+                                     int(n_iter), _stream(stream)))
+
+
+def compute_gradient(grid: Grid, phi: torch.Tensor, grad: torch.Tensor, stream=None):
+    if grad.dtype != phi.dtype or grad.numel() != 3 * phi.numel() or phi.numel() != grid.n_total * 64:
+        raise ValueError("grad must be [3, P+2, 64] of phi's dtype")
+    _check(load().sgrid_compute_gradient(grid.handle, _dtype_code(phi), _dev(phi, "phi"), _dev(grad, "grad"),
+                                         _stream(stream)))
+
+
+def probe_particles(grid: Grid, phi: torch.Tensor, grad: torch.Tensor, pos: torch.Tensor,
+                    phi_out: torch.Tensor, normal_out: torch.Tensor, stream=None):
+    n = pos.numel() // 3
+    if pos.numel() != 3 * n or phi_out.numel() != n or normal_out.numel() != 3 * n:
+        raise ValueError("pos [n,3], phi_out [n], normal_out [n,3] expected")
+    for t in (grad, pos, phi_out, normal_out):
+        if t.dtype != phi.dtype:
+            raise TypeError("all probe arrays must share phi's dtype")
+    if phi.numel() != grid.n_total * 64 or grad.numel() != 3 * phi.numel():
+        raise ValueError("phi [P+2, 64] and grad [3, P+2, 64] expected")
+    _check(load().sgrid_probe_particles(grid.handle, _dtype_code(phi), _dev(phi, "phi"), _dev(grad, "grad"),
+                                        _dev(pos, "pos"), n, _dev(phi_out, "phi_out"),
+                                        _dev(normal_out, "normal_out"), _stream(stream)))
+
+
+def compute_near_surface_integrals(grid: Grid, phi: torch.Tensor, out: torch.Tensor, model=None,
+                                   n_fallback: Optional[torch.Tensor] = None, stream=None):
+    if phi.dtype != torch.float32 or out.dtype != torch.float32:
+        raise TypeError("integrals are FP32")
+    if out.numel() != 4 * grid.n_core * 64 or phi.numel() != grid.n_total * 64:
+        raise ValueError("out must be [4, n_core*64]")
+    nf = _dev(n_fallback, "n_fallback") if n_fallback is not None else None
+    mh = model.handle if model is not None else None
+    _check(load().sgrid_compute_near_surface_integrals(grid.handle, _dev(phi, "phi"), mh, _dev(out, "out"), nf,
+                                                       _stream(stream)))
+
+
+def set_sweep_config(variant: int, groups: int):
+    """Select the sweep kernel variant (0 = DPP exchange, 1 = LDS tile) and the
+    number of four-package sets each wavefront processes."""
+    _check(load().sgrid_set_sweep_config(int(variant), int(groups)))

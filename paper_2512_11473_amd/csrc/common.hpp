@@ -1,0 +1,111 @@
+// Internal helpers shared by the sgrid HIP sources: status reporting, the
+// grid handle, launch checks and small device utilities for gfx950.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <stdio.h>
+#include <string>
+
+#include "../../include/sgrid.h"
+
+namespace sgrid {
+
+void set_error(const char *fmt, ...);
+void clear_error();
+
+// Far-field package ids and the far-field constant in units of h.
+constexpr uint32_t kFarNeg = 0u;
+constexpr uint32_t kFarPos = 1u;
+constexpr uint32_t kNoCell = 0xFFFFFFFFu;
+constexpr double kFarFieldInH = 16.0;
+
+// Face slots of the 27-entry neighbour table, in the order the sweeps use:
+// -x, +x, -y, +y, -z, +z.
+constexpr int kFaceSlot[6] = {12, 14, 10, 16, 4, 22};
+
+}  // namespace sgrid
+
+struct sgrid_grid {
+    int32_t M = 0;
+    double h = 0.0;
+    int64_t P = 0;        // activated packages
+    int64_t n_core = 0;
+    int device = 0;
+    uint32_t *cell_pkg = nullptr;   // [M^3]
+    uint32_t *pkg_cell = nullptr;   // [P+2]
+    uint8_t *pkg_type = nullptr;    // [P+2]
+    uint32_t *nbr = nullptr;        // [P+2][27]
+    uint32_t *face = nullptr;       // [P+2][8]: the six face slots of nbr, then two pads
+    uint32_t *core_list = nullptr;  // [n_core]
+    int64_t total() const { return P + 2; }
+};
+
+#define SG_CHECK_HIP(expr)                                                            \
+    do {                                                                              \
+        hipError_t _e = (expr);                                                       \
+        if (_e != hipSuccess) {                                                       \
+            sgrid::set_error("%s failed: %s (%s:%d)", #expr, hipGetErrorString(_e),   \
+                             __FILE__, __LINE__);                                     \
+            return SGRID_E_HIP;                                                       \
+        }                                                                             \
+    } while (0)
+
+#define SG_CHECK_LAUNCH(name)                                                         \
+    do {                                                                              \
+        hipError_t _e = hipGetLastError();                                            \
+        if (_e != hipSuccess) {                                                       \
+            sgrid::set_error("launch of %s failed: %s", name, hipGetErrorString(_e)); \
+            return SGRID_E_HIP;                                                       \
+        }                                                                             \
+    } while (0)
+
+#define SG_REQUIRE(cond, ...)                              \
+    do {                                                   \
+        if (!(cond)) {                                     \
+            sgrid::set_error(__VA_ARGS__);                 \
+            return SGRID_E_INVALID;                        \
+        }                                                  \
+    } while (0)
+
+static inline bool sg_aligned(const void *p, size_t a) { return (reinterpret_cast<uintptr_t>(p) % a) == 0; }
+
+static inline hipStream_t sg_stream(void *s) { return reinterpret_cast<hipStream_t>(s); }
+
+// Grids of more than 2^31 - 1 blocks are not launched; callers loop or stride.
+constexpr int64_t kMaxGrid = 0x7FFFFFFF;
+
+// ---------------------------------------------------------------------------
+// Device utilities
+// ---------------------------------------------------------------------------
+
+// Cross-lane move inside 16-lane rows (DPP).  CTRL is a row_shl / row_shr
+// control: row_shl:n = 0x100 + n (lane l reads lane l + n of its row),
+// row_shr:n = 0x110 + n (lane l reads lane l - n).  Lanes whose source lies
+// outside their 16-lane row must not use the result; callers select a halo
+// value for them.
+constexpr int kRowShl1 = 0x101, kRowShl4 = 0x104, kRowShr1 = 0x111, kRowShr4 = 0x114;
+
+template <int CTRL>
+__device__ __forceinline__ float row_move(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+
+template <int CTRL>
+__device__ __forceinline__ double row_move(double v) {
+    long long b = __double_as_longlong(v);
+    int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xFFFFFFFFll), CTRL, 0xF, 0xF, false);
+    int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// XCD-aware block order: the hardware deals consecutive workgroups round-robin
+// to the 8 XCDs; remapping gives each XCD one contiguous range of block ids,
+// so packages that are neighbours in id order share that XCD's L2.
+__device__ __forceinline__ int64_t xcd_block(int64_t b, int64_t nb) {
+    const int64_t per = (nb + 7) / 8;
+    const int64_t x = b % 8, r = b / 8;
+    const int64_t full = nb % 8 == 0 ? 8 : nb % 8;   // XCDs that receive `per` blocks
+    // XCDs 0..full-1 own ranges of length per, the rest ranges of length per - 1
+    return x < full ? x * per + r : full * per + (x - full) * (per - 1) + r;
+}

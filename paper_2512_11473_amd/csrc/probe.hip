@@ -1,0 +1,92 @@
+// Grid-to-particle probe (Sec. 8): trilinear interpolation of phi and of the
+// gradient at particle positions, reached through the cell-to-package map and
+// the neighbour table (position-based random access, Sec. 5.1 indexing and the
+// index shift of Sec. 5.2).
+//
+// One lane per particle.  The particle's coarse cell gives its home package;
+// the base corner's shift relative to that package lies in [-1, 3] per axis,
+// so the eight corners have shifts in [-1, 4] and the index shift
+// slot = (s + 4) / 4, data = s + 4 - 4 slot stays inside the 27 neighbours.
+#include "common.hpp"
+
+namespace {
+
+// fmax / fmin return the non-NaN operand, so a NaN coordinate clamps to `lo`
+// and every index below stays inside the tables.
+template <typename T>
+__device__ __forceinline__ T clampv(T v, T lo, T hi) { return fmin(fmax(v, lo), hi); }
+
+template <typename T>
+__global__ __launch_bounds__(256) void probe_kernel(const T *__restrict__ phi, const T *__restrict__ grad,
+                                                    const uint32_t *__restrict__ cell_pkg,
+                                                    const uint32_t *__restrict__ nbr, const T *__restrict__ pos,
+                                                    int64_t n, T *__restrict__ phi_out, T *__restrict__ nrm_out,
+                                                    int M, T inv_h, int64_t field_stride) {
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= n) return;
+    const int N = 4 * M;
+    int sh[3], cc[3];
+    T t[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const T u = pos[3 * q + a] * inv_h;
+        const T s = u - T(0.5);
+        const T f = clampv(floor(s), T(0), T(N - 2));
+        t[a] = clampv(s - f, T(0), T(1));
+        cc[a] = (int)clampv(floor(u * T(0.25)), T(0), T(M - 1));
+        sh[a] = (int)f - 4 * cc[a];   // in [-1, 3]
+    }
+    const int64_t home = cell_pkg[cc[0] + (int64_t)M * (cc[1] + (int64_t)M * cc[2])];
+    const uint32_t *row = nbr + home * 27;
+    T v = T(0), gx = T(0), gy = T(0), gz = T(0);
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+        const int bx = b & 1, by = (b >> 1) & 1, bz = (b >> 2) & 1;
+        const int s0 = sh[0] + bx + 4, s1 = sh[1] + by + 4, s2 = sh[2] + bz + 4;   // shift + 4 in [3, 8]
+        const int k0 = s0 >> 2, k1 = s1 >> 2, k2 = s2 >> 2;                        // neighbour slot per axis
+        const int d = (s0 - 4 * k0) + 4 * (s1 - 4 * k1) + 16 * (s2 - 4 * k2);     // data index
+        const int64_t idx = (int64_t)row[k0 + 3 * k1 + 9 * k2] * 64 + d;
+        const T w = (bx ? t[0] : T(1) - t[0]) * (by ? t[1] : T(1) - t[1]) * (bz ? t[2] : T(1) - t[2]);
+        v += w * phi[idx];
+        gx += w * grad[idx];
+        gy += w * grad[field_stride + idx];
+        gz += w * grad[2 * field_stride + idx];
+    }
+    const T gn = sqrt(gx * gx + gy * gy + gz * gz);
+    phi_out[q] = v;
+    const T inv = gn > T(0) ? T(1) / gn : T(0);
+    nrm_out[3 * q] = gx * inv;
+    nrm_out[3 * q + 1] = gy * inv;
+    nrm_out[3 * q + 2] = gz * inv;
+}
+
+}  // namespace
+
+extern "C" sgrid_status sgrid_probe_particles(const sgrid_grid *g, sgrid_dtype dtype, const void *phi,
+                                              const void *grad, const void *pos, int64_t n, void *phi_out,
+                                              void *normal_out, void *stream) {
+    sgrid::clear_error();
+    SG_REQUIRE(g != nullptr, "grid is NULL");
+    SG_REQUIRE(n >= 0, "n must be >= 0");
+    SG_REQUIRE(dtype == SGRID_F32 || dtype == SGRID_F64, "unknown dtype %d", (int)dtype);
+    if (n == 0) return SGRID_OK;
+    SG_REQUIRE(phi && grad && pos && phi_out && normal_out, "NULL field or particle array");
+    const size_t es = dtype == SGRID_F32 ? 4 : 8;
+    SG_REQUIRE(sg_aligned(phi, 16) && sg_aligned(grad, 16), "phi / grad must be 16-byte aligned");
+    SG_REQUIRE(sg_aligned(pos, es) && sg_aligned(phi_out, es) && sg_aligned(normal_out, es),
+               "particle arrays must be aligned to their element size");
+    hipStream_t st = sg_stream(stream);
+    const int64_t nb = (n + 255) / 256;
+    SG_REQUIRE(nb <= kMaxGrid, "too many particles for one launch");
+    const int64_t stride = g->total() * 64;
+    if (dtype == SGRID_F32)
+        hipLaunchKernelGGL(probe_kernel<float>, dim3((unsigned)nb), dim3(256), 0, st, (const float *)phi,
+                           (const float *)grad, g->cell_pkg, g->nbr, (const float *)pos, n, (float *)phi_out,
+                           (float *)normal_out, g->M, (float)(1.0 / g->h), stride);
+    else
+        hipLaunchKernelGGL(probe_kernel<double>, dim3((unsigned)nb), dim3(256), 0, st, (const double *)phi,
+                           (const double *)grad, g->cell_pkg, g->nbr, (const double *)pos, n, (double *)phi_out,
+                           (double *)normal_out, g->M, 1.0 / g->h, stride);
+    SG_CHECK_LAUNCH("probe");
+    return SGRID_OK;
+}

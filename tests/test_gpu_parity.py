@@ -1,0 +1,260 @@
+"""Parity of the HIP path against the FP64 oracle (GPU).
+
+Tables must match bit for bit; fields within the tolerances the method
+states: |dphi| <= 1e-5 h (FP32 against FP64), 1e-12 h for the FP64 kernels;
+gradients and normals (unitless) 1e-5; integrals 1e-5 (K_W) and 1e-5 G0 (h K_grad).
+"""
+import itertools
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+G0 = 0.865663036   # h * K_grad of an axis-aligned half-space through the query point
+
+
+@pytest.fixture(scope="module")
+def sg():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2512_11473_amd as sg
+    sg.load()
+    sg.set_sweep_config(0, 1)
+    return sg
+
+
+def _gpu_tables(sg, d, h):
+    g = sg.build_packages(torch.from_numpy(d).cuda(), h)
+    t = {k: v.cpu().numpy() for k, v in g.tables().items()}
+    return g, t
+
+
+def _assert_tables_equal(t, ref: oracle.Tables):
+    assert np.array_equal(t["cell_pkg"].view(np.uint32), ref.cell_pkg)
+    assert np.array_equal(t["pkg_cell"].view(np.uint32), ref.pkg_cell)
+    assert np.array_equal(t["pkg_type"], ref.pkg_type)
+    assert np.array_equal(t["pkg_nbr"].view(np.uint32), ref.nbr)
+    core = np.nonzero(ref.pkg_type == 1)[0].astype(np.uint32)
+    assert np.array_equal(t["core_list"].view(np.uint32), core)
+
+
+# --------------------------------------------------------------------------
+# Tables (bit-exact)
+# --------------------------------------------------------------------------
+
+def test_tables_all_core_patterns_m2(sg):
+    M = 2
+    rng = np.random.default_rng(0)
+    for pattern in range(256):
+        core = np.array([(pattern >> c) & 1 for c in range(8)], dtype=bool)
+        d = np.where(core, rng.uniform(-0.49, 0.49, 8), rng.choice([-1, 1], 8) * rng.uniform(0.5, 2, 8))
+        d = d.astype(np.float32)
+        g, t = _gpu_tables(sg, d, 1.0 / (4 * M))
+        _assert_tables_equal(t, oracle.build_tables(M, d))
+        g.destroy()
+
+
+@pytest.mark.parametrize("M", [1, 3, 5, 8, 13, 32])
+def test_tables_random_with_ties(sg, M):
+    rng = np.random.default_rng(M)
+    lc = 1.0 / M
+    for _ in range(5):
+        d = (rng.uniform(-3, 3, M ** 3) * lc).astype(np.float32)
+        d[rng.uniform(size=M ** 3) < 0.1] = np.float32(lc)
+        d[rng.uniform(size=M ** 3) < 0.05] = np.float32(-lc)
+        d[rng.uniform(size=M ** 3) < 0.05] = np.float32(-0.0)
+        g, t = _gpu_tables(sg, d, 1.0 / (4 * M))
+        _assert_tables_equal(t, oracle.build_tables(M, d))
+
+
+@pytest.mark.parametrize("cfg", [synth.config_c1(), synth.config_c2()], ids=["sphere64", "prism512"])
+def test_tables_named_workloads(sg, cfg):
+    M = cfg["N"] // 4
+    d = synth.coarse_sdf(cfg["shape"], M)
+    g, t = _gpu_tables(sg, d, 1.0 / cfg["N"])
+    _assert_tables_equal(t, oracle.build_tables(M, d))
+
+
+def test_tables_random_unions(sg):
+    for s in synth.batch_shapes(6, 11, resolutions=(64, 128)):
+        M = s["N"] // 4
+        d = synth.coarse_sdf(s["shape"], M)
+        g, t = _gpu_tables(sg, d, 1.0 / s["N"])
+        _assert_tables_equal(t, oracle.build_tables(M, d))
+
+
+def test_empty_band(sg):
+    M = 6
+    d = np.full(M ** 3, 10.0, dtype=np.float32)
+    g, t = _gpu_tables(sg, d, 1.0 / (4 * M))
+    assert g.n_packages == 0 and g.n_core == 0
+    assert np.all(t["cell_pkg"] == 1)
+    phi = g.empty_field()
+    sg.fill_far_field(g, phi)
+    scratch = torch.empty_like(phi)
+    sg.reinitialize(g, phi, scratch, 3)
+    grad = g.empty_field(components=3)
+    sg.compute_gradient(g, phi, grad)
+    pos = torch.rand(100, 3, device="cuda")
+    po, no = torch.empty(100, device="cuda"), torch.empty(100, 3, device="cuda")
+    sg.probe_particles(g, phi, grad, pos, po, no)
+    out = torch.empty(0, device="cuda")
+    sg.compute_near_surface_integrals(g, phi, out)
+    torch.cuda.synchronize()
+    assert torch.all(po == 16 * g.h) and torch.all(no == 0)
+    assert torch.all(grad == 0)
+
+
+# --------------------------------------------------------------------------
+# Fields
+# --------------------------------------------------------------------------
+
+def _ulp32(x):
+    return np.spacing(np.abs(x).astype(np.float32)).astype(np.float64)
+
+
+def _run_both(sg, cfg, dtype, n_iter, n_particles=None):
+    from paper_2512_11473_amd import workload
+    N = cfg["N"]
+    pos = synth.particles_for(cfg, n_particles) if n_particles else None
+    wl = workload.setup(cfg["shape"], N, cfg["noise_amp"], cfg["noise_seed"], dtype=dtype, particles=pos)
+    run = oracle.setup(cfg["shape"], N, cfg["noise_amp"], cfg["noise_seed"],
+                       phi0_dtype=np.float32 if dtype == torch.float32 else np.float64)
+    return wl, run, pos
+
+
+@pytest.mark.parametrize("dtype,tol_h", [(torch.float32, 1e-5), (torch.float64, 1e-12)], ids=["f32", "f64"])
+def test_sphere64_pipeline(sg, dtype, tol_h):
+    cfg = synth.config_c1()
+    wl, run, pos = _run_both(sg, cfg, dtype, cfg["n_iter"], cfg["n_particles"])
+    h = wl.h
+    pts = wl.points.ravel()
+    # one iteration: a few units in the last place
+    sg.reinitialize(wl.grid, wl.phi, wl.scratch, 1)
+    dense = oracle.dense_state(run.tab, run.active, run.phi0, run.B)
+    one = oracle.reinit(run.N, h, run.B, run.active, dense, 1)
+    got = wl.phi[2:].double().cpu().numpy().ravel()
+    if dtype == torch.float32:
+        assert np.all(np.abs(got - one[pts]) <= 4 * _ulp32(one[pts]) + 2e-7 * h)
+    else:
+        assert np.max(np.abs(got - one[pts])) <= tol_h * h
+    # far-field rows are never written
+    assert torch.all(wl.phi[0] == -16 * h) and torch.all(wl.phi[1] == 16 * h)
+    # the full iteration count
+    wl.reset()
+    sg.reinitialize(wl.grid, wl.phi, wl.scratch, cfg["n_iter"])
+    oracle.run_plain(run, cfg["n_iter"])
+    got = wl.phi[2:].double().cpu().numpy().ravel()
+    err = np.abs(got - run.phi[pts])
+    assert err.max() <= tol_h * h, f"max |dphi| = {err.max() / h:.3e} h"
+    # gradient
+    sg.compute_gradient(wl.grid, wl.phi, wl.grad)
+    gg = wl.grad[:, 2:].double().cpu().numpy().reshape(3, -1)
+    gtol = 1e-5 if dtype == torch.float32 else 1e-11
+    assert np.max(np.abs(gg - run.grad[:, pts])) <= gtol
+    assert torch.all(wl.grad[:, :2] == 0)
+    # probe
+    sg.probe_particles(wl.grid, wl.phi, wl.grad, wl.pos, wl.phi_p, wl.nrm_p)
+    ref_phi, ref_nrm, ref_g = oracle.probe(run.N, h, run.B, run.tab.cell_pkg, run.phi, run.grad,
+                                           pos.astype(np.float64), with_gradient=True)
+    pp = wl.phi_p.double().cpu().numpy()
+    nn = wl.nrm_p.double().cpu().numpy()
+    assert np.max(np.abs(pp - ref_phi)) <= tol_h * h
+    ok = np.linalg.norm(ref_g, axis=1) > 0.25   # normals are ill-conditioned where g vanishes
+    assert ok.mean() > 0.95
+    assert np.max(np.abs(nn[ok] - ref_nrm[ok])) <= (1e-5 if dtype == torch.float32 else 1e-11)
+    far = np.linalg.norm(ref_g, axis=1) == 0
+    assert np.all(nn[far] == 0)
+
+
+def test_sphere64_gradient_on_initial_field(sg):
+    cfg = synth.config_c1()
+    wl, run, _ = _run_both(sg, cfg, torch.float32, 0)
+    sg.compute_gradient(wl.grid, wl.phi, wl.grad)
+    dense = oracle.dense_state(run.tab, run.active, run.phi0, run.B)
+    ref = oracle.gradient(run.N, run.h, run.B, run.active, dense)
+    gg = wl.grad[:, 2:].double().cpu().numpy().reshape(3, -1)
+    assert np.max(np.abs(gg - ref[:, wl.points.ravel()])) <= 1e-6
+
+
+def _core_points(wl):
+    """Fine indices of the core points in output order [n_core * 64]."""
+    t = wl.grid.tables()
+    core = t["core_list"].cpu().numpy().astype(np.int64)
+    return wl.points[core - 2].ravel()
+
+
+@pytest.mark.parametrize("n_iter", [0, 20])
+def test_sphere64_integrals(sg, n_iter):
+    cfg = synth.config_c1()
+    wl, run, _ = _run_both(sg, cfg, torch.float32, n_iter)
+    sg.reinitialize(wl.grid, wl.phi, wl.scratch, n_iter)
+    oracle.run_plain(run, n_iter)
+    out = torch.empty((4, wl.grid.n_core * 64), device="cuda")
+    nf = torch.zeros(1, dtype=torch.int32, device="cuda")
+    sg.compute_near_surface_integrals(wl.grid, wl.phi, out, n_fallback=nf)
+    ref = oracle.integrals(run.N, run.h, run.B, run.phi, _core_points(wl))
+    got = out.double().cpu().numpy().T
+    assert int(nf.item()) == 0
+    assert np.max(np.abs(got[:, 0] - ref[:, 0])) <= 1e-5
+    assert np.max(np.abs(got[:, 1:] - ref[:, 1:])) <= 1e-5 * G0
+    # the band holds both saturated and cut cells
+    assert (ref[:, 0] > 0.01).mean() > 0.2 and (ref[:, 0] < 0.97).mean() > 0.2
+
+
+def test_sweep_variants_identical(sg):
+    cfg = synth.config_c1()
+    from paper_2512_11473_amd import workload
+    wl = workload.setup(cfg["shape"], cfg["N"], cfg["noise_amp"], cfg["noise_seed"])
+    results = []
+    for variant, groups in [(0, 1), (0, 2), (0, 4), (1, 1), (1, 2), (1, 3)]:
+        sg.set_sweep_config(variant, groups)
+        wl.reset()
+        sg.reinitialize(wl.grid, wl.phi, wl.scratch, 7)
+        results.append(wl.phi.clone())
+    sg.set_sweep_config(0, 1)
+    for r in results[1:]:
+        assert torch.equal(r, results[0])
+
+
+def test_determinism(sg):
+    cfg = synth.config_c1()
+    from paper_2512_11473_amd import workload
+    wl = workload.setup(cfg["shape"], cfg["N"], cfg["noise_amp"], cfg["noise_seed"],
+                        particles=synth.particles_for(cfg, 5000))
+    outs = []
+    for _ in range(2):
+        wl.reset()
+        sg.reinitialize(wl.grid, wl.phi, wl.scratch, 5)
+        sg.compute_gradient(wl.grid, wl.phi, wl.grad)
+        sg.probe_particles(wl.grid, wl.phi, wl.grad, wl.pos, wl.phi_p, wl.nrm_p)
+        out = torch.empty((4, wl.grid.n_core * 64), device="cuda")
+        sg.compute_near_surface_integrals(wl.grid, wl.phi, out)
+        outs.append([wl.phi.clone(), wl.grad.clone(), wl.phi_p.clone(), wl.nrm_p.clone(), out])
+    for a, b in zip(*outs):
+        assert torch.equal(a, b)
+
+
+def test_probe_edge_positions(sg):
+    # particles outside the domain, on cell faces, at NaN: clamped, never out of bounds
+    cfg = synth.config_c1()
+    pos = np.array([[-0.3, 0.5, 0.5], [1.7, 0.5, 0.5], [0.5, 0.5, 0.25], [0.0, 0.0, 0.0],
+                    [1.0, 1.0, 1.0], [0.2, 0.5, 0.5], [0.8, 0.8, 0.2]], dtype=np.float32)
+    wl, run, _ = _run_both(sg, cfg, torch.float32, 0)
+    from paper_2512_11473_amd import workload
+    wl = workload.setup(cfg["shape"], cfg["N"], cfg["noise_amp"], cfg["noise_seed"], particles=pos)
+    sg.compute_gradient(wl.grid, wl.phi, wl.grad)
+    sg.probe_particles(wl.grid, wl.phi, wl.grad, wl.pos, wl.phi_p, wl.nrm_p)
+    dense = oracle.dense_state(run.tab, run.active, run.phi0, run.B)
+    g = oracle.gradient(run.N, run.h, run.B, run.active, dense)
+    ref, nrm = oracle.probe(run.N, run.h, run.B, run.tab.cell_pkg, dense, g, pos.astype(np.float64))
+    assert np.max(np.abs(wl.phi_p.double().cpu().numpy() - ref)) <= 1e-5 * run.h
+    nanpos = torch.tensor([[float("nan"), 0.5, 0.5]], device="cuda")
+    po, no = torch.empty(1, device="cuda"), torch.empty(1, 3, device="cuda")
+    sg.probe_particles(wl.grid, wl.phi, wl.grad, nanpos, po, no)
+    torch.cuda.synchronize()
