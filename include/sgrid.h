@@ -129,6 +129,14 @@ sgrid_status sgrid_compute_gradient(const sgrid_grid *grid, sgrid_dtype dtype,
                                     const void *phi_dev, void *grad_dev, void *stream);
 
 /*
+ * The same gradient written with phi into one array of (phi, gx, gy, gz)
+ * quadruples, [P^][64][4] in `dtype` (a layout for the packed probe: one
+ * 16-byte gather per corner in FP32).  Far-field rows hold (+-B, 0, 0, 0).
+ */
+sgrid_status sgrid_compute_gradient_packed(const sgrid_grid *grid, sgrid_dtype dtype,
+                                           const void *phi_dev, void *packed_dev, void *stream);
+
+/*
  * Grid-to-particle probe (Sec. 8): trilinear interpolation of phi and of the
  * gradient at n particles, then normal = g / |g| (0 where g = 0).  Per axis
  * u = x / h, s = u - 1/2, i0 = clamp(floor(s), 0, N - 2), t = clamp(s - i0, 0, 1).
@@ -141,6 +149,11 @@ sgrid_status sgrid_compute_gradient(const sgrid_grid *grid, sgrid_dtype dtype,
 sgrid_status sgrid_probe_particles(const sgrid_grid *grid, sgrid_dtype dtype, const void *phi_dev,
                                    const void *grad_dev, const void *pos_dev, int64_t n,
                                    void *phi_out_dev, void *normal_out_dev, void *stream);
+
+/* sgrid_probe_particles on the packed (phi, g) array of sgrid_compute_gradient_packed. */
+sgrid_status sgrid_probe_particles_packed(const sgrid_grid *grid, sgrid_dtype dtype, const void *packed_dev,
+                                          const void *pos_dev, int64_t n, void *phi_out_dev,
+                                          void *normal_out_dev, void *stream);
 
 /*
  * Near-surface kernel integrals (Sec. 8 names the integral with an SPH
@@ -164,9 +177,9 @@ sgrid_status sgrid_compute_near_surface_integrals(const sgrid_grid *grid, const 
 /*
  * Tuning knob for sgrid_reinitialize: sweep variant 0 exchanges the interior
  * neighbours between lanes (DPP row shifts), variant 1 stages each package
- * and its face halo in an LDS tile; `groups` (1..8) is the number of
- * four-package sets one wavefront processes.  Process-wide; default (0, 1).
- * Results are identical for every setting.
+ * and its face halo in an LDS tile; `groups` is the number of four-package
+ * sets one wavefront processes (1, 2, 3, 4 or 8).  Process-wide; default
+ * (0, 1).  Results are identical for every setting.
  */
 sgrid_status sgrid_set_sweep_config(int32_t variant, int32_t groups);
 

@@ -18,7 +18,7 @@ import torch
 
 __all__ = [
     "SgridError", "Grid", "load", "build_packages", "fill_far_field", "reinitialize",
-    "compute_gradient", "probe_particles", "compute_near_surface_integrals", "set_sweep_config",
+    "compute_gradient", "compute_gradient_packed", "probe_particles", "probe_particles_packed", "compute_near_surface_integrals", "set_sweep_config",
     "LIB_PATH", "FAR_FIELD_IN_H",
 ]
 
@@ -53,6 +53,8 @@ _SIGNATURES = {
     "sgrid_fill_far_field": (ctypes.c_int, [_P, ctypes.c_int, _P, _P]),
     "sgrid_reinitialize": (ctypes.c_int, [_P, ctypes.c_int, _P, _P, ctypes.c_int32, _P]),
     "sgrid_compute_gradient": (ctypes.c_int, [_P, ctypes.c_int, _P, _P, _P]),
+    "sgrid_compute_gradient_packed": (ctypes.c_int, [_P, ctypes.c_int, _P, _P, _P]),
+    "sgrid_probe_particles_packed": (ctypes.c_int, [_P, ctypes.c_int, _P, _P, ctypes.c_int64, _P, _P, _P]),
     "sgrid_probe_particles": (ctypes.c_int, [_P, ctypes.c_int, _P, _P, _P, ctypes.c_int64, _P, _P, _P]),
     "sgrid_compute_near_surface_integrals": (ctypes.c_int, [_P, _P, _P, _P, _P, _P]),
     "sgrid_set_sweep_config": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32]),
@@ -206,6 +208,29 @@ def compute_gradient(grid: Grid, phi: torch.Tensor, grad: torch.Tensor, stream=N
         raise ValueError("grad must be [3, P+2, 64] of phi's dtype")
     _check(load().sgrid_compute_gradient(grid.handle, _dtype_code(phi), _dev(phi, "phi"), _dev(grad, "grad"),
                                          _stream(stream)))
+
+
+def compute_gradient_packed(grid: Grid, phi: torch.Tensor, packed: torch.Tensor, stream=None):
+    """(phi, gx, gy, gz) quadruples [P+2, 64, 4] for the packed probe."""
+    if packed.dtype != phi.dtype or packed.numel() != 4 * phi.numel() or phi.numel() != grid.n_total * 64:
+        raise ValueError("packed must be [P+2, 64, 4] of phi's dtype")
+    _check(load().sgrid_compute_gradient_packed(grid.handle, _dtype_code(phi), _dev(phi, "phi"),
+                                                _dev(packed, "packed"), _stream(stream)))
+
+
+def probe_particles_packed(grid: Grid, packed: torch.Tensor, pos: torch.Tensor, phi_out: torch.Tensor,
+                           normal_out: torch.Tensor, stream=None):
+    n = pos.numel() // 3
+    if pos.numel() != 3 * n or phi_out.numel() != n or normal_out.numel() != 3 * n:
+        raise ValueError("pos [n,3], phi_out [n], normal_out [n,3] expected")
+    for t in (pos, phi_out, normal_out):
+        if t.dtype != packed.dtype:
+            raise TypeError("all probe arrays must share the field's dtype")
+    if packed.numel() != grid.n_total * 256:
+        raise ValueError("packed must be [P+2, 64, 4]")
+    _check(load().sgrid_probe_particles_packed(grid.handle, _dtype_code(packed), _dev(packed, "packed"),
+                                               _dev(pos, "pos"), n, _dev(phi_out, "phi_out"),
+                                               _dev(normal_out, "normal_out"), _stream(stream)))
 
 
 def probe_particles(grid: Grid, phi: torch.Tensor, grad: torch.Tensor, pos: torch.Tensor,

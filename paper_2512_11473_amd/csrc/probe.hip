@@ -16,12 +16,35 @@ namespace {
 template <typename T>
 __device__ __forceinline__ T clampv(T v, T lo, T hi) { return fmin(fmax(v, lo), hi); }
 
-template <typename T>
-__global__ __launch_bounds__(256) void probe_kernel(const T *__restrict__ phi, const T *__restrict__ grad,
-                                                    const uint32_t *__restrict__ cell_pkg,
+// Corner field access: SoA (phi and three gradient arrays) or packed
+// (phi, gx, gy, gz) quadruples.
+template <typename T, bool PACKED>
+struct Corner {
+    const T *phi, *grad;
+    int64_t stride;
+    __device__ __forceinline__ void get(int64_t idx, T &v, T &gx, T &gy, T &gz) const {
+        if (PACKED) {
+            const T *f = phi + idx * 4;
+            if (sizeof(T) == 4) {
+                const float4 q = *reinterpret_cast<const float4 *>(f);
+                v = q.x; gx = q.y; gy = q.z; gz = q.w;
+            } else {
+                v = f[0]; gx = f[1]; gy = f[2]; gz = f[3];
+            }
+        } else {
+            v = phi[idx];
+            gx = grad[idx];
+            gy = grad[stride + idx];
+            gz = grad[2 * stride + idx];
+        }
+    }
+};
+
+template <typename T, bool PACKED>
+__global__ __launch_bounds__(256) void probe_kernel(Corner<T, PACKED> field, const uint32_t *__restrict__ cell_pkg,
                                                     const uint32_t *__restrict__ nbr, const T *__restrict__ pos,
                                                     int64_t n, T *__restrict__ phi_out, T *__restrict__ nrm_out,
-                                                    int M, T inv_h, int64_t field_stride) {
+                                                    int M, T inv_h) {
     const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (q >= n) return;
     const int N = 4 * M;
@@ -47,10 +70,12 @@ __global__ __launch_bounds__(256) void probe_kernel(const T *__restrict__ phi, c
         const int d = (s0 - 4 * k0) + 4 * (s1 - 4 * k1) + 16 * (s2 - 4 * k2);     // data index
         const int64_t idx = (int64_t)row[k0 + 3 * k1 + 9 * k2] * 64 + d;
         const T w = (bx ? t[0] : T(1) - t[0]) * (by ? t[1] : T(1) - t[1]) * (bz ? t[2] : T(1) - t[2]);
-        v += w * phi[idx];
-        gx += w * grad[idx];
-        gy += w * grad[field_stride + idx];
-        gz += w * grad[2 * field_stride + idx];
+        T cv, cx, cy, cz;
+        field.get(idx, cv, cx, cy, cz);
+        v += w * cv;
+        gx += w * cx;
+        gy += w * cy;
+        gz += w * cz;
     }
     const T gn = sqrt(gx * gx + gy * gy + gz * gz);
     phi_out[q] = v;
@@ -62,31 +87,46 @@ __global__ __launch_bounds__(256) void probe_kernel(const T *__restrict__ phi, c
 
 }  // namespace
 
-extern "C" sgrid_status sgrid_probe_particles(const sgrid_grid *g, sgrid_dtype dtype, const void *phi,
-                                              const void *grad, const void *pos, int64_t n, void *phi_out,
-                                              void *normal_out, void *stream) {
+template <bool PACKED>
+static sgrid_status probe_entry(const sgrid_grid *g, sgrid_dtype dtype, const void *phi, const void *grad,
+                                const void *pos, int64_t n, void *phi_out, void *normal_out, void *stream) {
     sgrid::clear_error();
     SG_REQUIRE(g != nullptr, "grid is NULL");
     SG_REQUIRE(n >= 0, "n must be >= 0");
     SG_REQUIRE(dtype == SGRID_F32 || dtype == SGRID_F64, "unknown dtype %d", (int)dtype);
     if (n == 0) return SGRID_OK;
-    SG_REQUIRE(phi && grad && pos && phi_out && normal_out, "NULL field or particle array");
+    SG_REQUIRE(phi && (PACKED || grad) && pos && phi_out && normal_out, "NULL field or particle array");
     const size_t es = dtype == SGRID_F32 ? 4 : 8;
-    SG_REQUIRE(sg_aligned(phi, 16) && sg_aligned(grad, 16), "phi / grad must be 16-byte aligned");
+    SG_REQUIRE(sg_aligned(phi, 16) && (PACKED || sg_aligned(grad, 16)), "fields must be 16-byte aligned");
     SG_REQUIRE(sg_aligned(pos, es) && sg_aligned(phi_out, es) && sg_aligned(normal_out, es),
                "particle arrays must be aligned to their element size");
     hipStream_t st = sg_stream(stream);
     const int64_t nb = (n + 255) / 256;
     SG_REQUIRE(nb <= kMaxGrid, "too many particles for one launch");
     const int64_t stride = g->total() * 64;
-    if (dtype == SGRID_F32)
-        hipLaunchKernelGGL(probe_kernel<float>, dim3((unsigned)nb), dim3(256), 0, st, (const float *)phi,
-                           (const float *)grad, g->cell_pkg, g->nbr, (const float *)pos, n, (float *)phi_out,
-                           (float *)normal_out, g->M, (float)(1.0 / g->h), stride);
-    else
-        hipLaunchKernelGGL(probe_kernel<double>, dim3((unsigned)nb), dim3(256), 0, st, (const double *)phi,
-                           (const double *)grad, g->cell_pkg, g->nbr, (const double *)pos, n, (double *)phi_out,
-                           (double *)normal_out, g->M, 1.0 / g->h, stride);
+    if (dtype == SGRID_F32) {
+        Corner<float, PACKED> f{(const float *)phi, (const float *)grad, stride};
+        hipLaunchKernelGGL((probe_kernel<float, PACKED>), dim3((unsigned)nb), dim3(256), 0, st, f, g->cell_pkg,
+                           g->nbr, (const float *)pos, n, (float *)phi_out, (float *)normal_out, g->M,
+                           (float)(1.0 / g->h));
+    } else {
+        Corner<double, PACKED> f{(const double *)phi, (const double *)grad, stride};
+        hipLaunchKernelGGL((probe_kernel<double, PACKED>), dim3((unsigned)nb), dim3(256), 0, st, f, g->cell_pkg,
+                           g->nbr, (const double *)pos, n, (double *)phi_out, (double *)normal_out, g->M,
+                           1.0 / g->h);
+    }
     SG_CHECK_LAUNCH("probe");
     return SGRID_OK;
+}
+
+extern "C" sgrid_status sgrid_probe_particles(const sgrid_grid *g, sgrid_dtype dtype, const void *phi,
+                                              const void *grad, const void *pos, int64_t n, void *phi_out,
+                                              void *normal_out, void *stream) {
+    return probe_entry<false>(g, dtype, phi, grad, pos, n, phi_out, normal_out, stream);
+}
+
+extern "C" sgrid_status sgrid_probe_particles_packed(const sgrid_grid *g, sgrid_dtype dtype, const void *packed,
+                                                     const void *pos, int64_t n, void *phi_out, void *normal_out,
+                                                     void *stream) {
+    return probe_entry<true>(g, dtype, packed, nullptr, pos, n, phi_out, normal_out, stream);
 }

@@ -46,134 +46,159 @@ __device__ __forceinline__ void store_row<double>(double *__restrict__ p, const 
     reinterpret_cast<double2 *>(p)[1] = make_double2(r.v[2], r.v[3]);
 }
 
-// Godunov-upwinded update of one point (Sussman-Smereka-Osher iteration).
+// Precision policy: FP32 uses the hardware square root and reciprocal square
+// root (about 1 ulp); FP64 uses correctly rounded operations.
 template <typename T>
-__device__ __forceinline__ T upwind_update(T p0, T xm, T xp, T ym, T yp, T zm, T zp, T h, T dt) {
-    const T S = p0 / sqrt(p0 * p0 + h * h);
-    const T nb[6] = {xm, xp, ym, yp, zm, zp};
-    T sum = T(0);
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        const T dm = (p0 - nb[2 * a]) / h;
-        const T dp = (nb[2 * a + 1] - p0) / h;
-        T x, y;
-        if (S > T(0)) {
-            x = fmax(dm, T(0));
-            y = fmin(dp, T(0));
-        } else {
-            x = fmin(dm, T(0));
-            y = fmax(dp, T(0));
-        }
-        sum += fmax(x * x, y * y);
-    }
-    return S == T(0) ? p0 : p0 - dt * S * (sqrt(sum) - T(1));
+struct Fast;
+template <>
+struct Fast<float> {
+    static __device__ __forceinline__ float rsqrt(float x) { return __builtin_amdgcn_rsqf(x); }
+    static __device__ __forceinline__ float sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+};
+template <>
+struct Fast<double> {
+    static __device__ __forceinline__ double rsqrt(double x) { return 1.0 / ::sqrt(x); }
+    static __device__ __forceinline__ double sqrt(double x) { return ::sqrt(x); }
+};
+
+// Godunov-upwinded update of one point (Sussman-Smereka-Osher iteration),
+// written in differences of phi (units of h):
+//   S > 0: a^2 = max(max(D-,0)^2, min(D+,0)^2) = max(p0 - xm, p0 - xp, 0)^2 / h^2
+//   S < 0: a^2 = max(min(D-,0)^2, max(D+,0)^2) = max(xm - p0, xp - p0, 0)^2 / h^2
+// so with sg = sign(S) every axis contributes max(sg (p0 - m), sg (p0 - p), 0)^2.
+template <typename T>
+__device__ __forceinline__ T upwind_update(T p0, T xm, T xp, T ym, T yp, T zm, T zp, T h2, T inv_h, T dt) {
+    const T S = p0 * Fast<T>::rsqrt(p0 * p0 + h2);
+    const T sg = S > T(0) ? T(1) : T(-1);
+    const T ax = fmax(fmax(sg * (p0 - xm), sg * (p0 - xp)), T(0));
+    const T ay = fmax(fmax(sg * (p0 - ym), sg * (p0 - yp)), T(0));
+    const T az = fmax(fmax(sg * (p0 - zm), sg * (p0 - zp)), T(0));
+    const T G = Fast<T>::sqrt(ax * ax + ay * ay + az * az) * inv_h;
+    return p0 - dt * S * (G - T(1));
 }
 
-// Loads a package row and its face halo.  Returns false for lanes past the
-// last package (their whole 16-lane row is idle).
+// A package row and its stencil neighbours.
 template <typename T>
 struct Stencil {
     Row<T> c, ym, yp, zm, zp;
     T xm, xp;
 };
 
+// Loads of one lane: its row, the x end values of the -x / +x packages, and
+// (boundary lanes only) one y-halo row and one z-halo row.
 template <typename T>
-__device__ __forceinline__ void gather_halo(const T *__restrict__ src, const uint32_t *__restrict__ face, int64_t p,
-                                            int r, Stencil<T> &s) {
+struct Loads {
+    Row<T> c, yh, zh;
+    T xm, xp;
+};
+
+template <typename T>
+__device__ __forceinline__ void issue_loads(const T *__restrict__ src, const uint32_t *__restrict__ face, int64_t p,
+                                            int r, Loads<T> &l) {
     const int j = r & 3, k = r >> 2;
     const uint4 f0 = *reinterpret_cast<const uint4 *>(face + p * 8);
     const uint2 f1 = *reinterpret_cast<const uint2 *>(face + p * 8 + 4);
-    s.c = load_row(src + p * 64 + r * 4);
-    s.xm = src[(int64_t)f0.x * 64 + r * 4 + 3];
-    s.xp = src[(int64_t)f0.y * 64 + r * 4];
-    if (j == 0) s.ym = load_row(src + (int64_t)f0.z * 64 + (3 + 4 * k) * 4);
-    if (j == 3) s.yp = load_row(src + (int64_t)f0.w * 64 + (4 * k) * 4);
-    if (k == 0) s.zm = load_row(src + (int64_t)f1.x * 64 + (j + 12) * 4);
-    if (k == 3) s.zp = load_row(src + (int64_t)f1.y * 64 + j * 4);
+    l.c = load_row(src + p * 64 + r * 4);
+    l.xm = src[(int64_t)f0.x * 64 + r * 4 + 3];
+    l.xp = src[(int64_t)f0.y * 64 + r * 4];
+    if (j == 0 || j == 3) {
+        const uint32_t fy = j == 0 ? f0.z : f0.w;
+        l.yh = load_row(src + (int64_t)fy * 64 + (j == 0 ? 3 + 4 * k : 4 * k) * 4);
+    }
+    if (k == 0 || k == 3) {
+        const uint32_t fz = k == 0 ? f1.x : f1.y;
+        l.zh = load_row(src + (int64_t)fz * 64 + (k == 0 ? j + 12 : j) * 4);
+    }
 }
 
-// Interior y / z neighbours through DPP row shifts (all 16 lanes of a package
-// execute these together).
+// Interior y / z neighbours through DPP row shifts (the 16 lanes of a package
+// form one DPP row and execute these together).
 template <typename T>
-__device__ __forceinline__ void exchange_dpp(int r, Stencil<T> &s) {
+__device__ __forceinline__ Stencil<T> assemble(int r, const Loads<T> &l) {
     const int j = r & 3, k = r >> 2;
+    Stencil<T> s;
+    s.c = l.c;
+    s.xm = l.xm;
+    s.xp = l.xp;
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-        const T v = s.c.v[i];
+        const T v = l.c.v[i];
         const T a = row_move<kRowShr1>(v);   // lane - 1: (j - 1, k)
         const T b = row_move<kRowShl1>(v);   // lane + 1: (j + 1, k)
         const T c = row_move<kRowShr4>(v);   // lane - 4: (j, k - 1)
         const T d = row_move<kRowShl4>(v);   // lane + 4: (j, k + 1)
-        if (j > 0) s.ym.v[i] = a;
-        if (j < 3) s.yp.v[i] = b;
-        if (k > 0) s.zm.v[i] = c;
-        if (k < 3) s.zp.v[i] = d;
+        s.ym.v[i] = j == 0 ? l.yh.v[i] : a;
+        s.yp.v[i] = j == 3 ? l.yh.v[i] : b;
+        s.zm.v[i] = k == 0 ? l.zh.v[i] : c;
+        s.zp.v[i] = k == 3 ? l.zh.v[i] : d;
     }
+    return s;
 }
 
 template <typename T>
-__device__ __forceinline__ Row<T> reinit_row(const Stencil<T> &s, T h, T dt) {
+__device__ __forceinline__ Row<T> reinit_row(const Stencil<T> &s, T h2, T inv_h, T dt) {
     Row<T> o;
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
         const T xm = i > 0 ? s.c.v[i - 1] : s.xm;
         const T xp = i < 3 ? s.c.v[i + 1] : s.xp;
-        o.v[i] = upwind_update(s.c.v[i], xm, xp, s.ym.v[i], s.yp.v[i], s.zm.v[i], s.zp.v[i], h, dt);
+        o.v[i] = upwind_update(s.c.v[i], xm, xp, s.ym.v[i], s.yp.v[i], s.zm.v[i], s.zp.v[i], h2, inv_h, dt);
     }
     return o;
 }
 
-// Reinitialisation sweep over packages [2, 2 + P): DPP exchange variant.
-// Each wavefront handles `groups` consecutive sets of four packages.
-template <typename T>
+// Reinitialisation sweep over packages [2, 2 + P), DPP exchange variant.  A
+// wavefront handles G consecutive sets of four packages and issues all their
+// loads before computing any of them.
+template <typename T, int G>
 __global__ __launch_bounds__(256) void reinit_dpp_kernel(const T *__restrict__ src, T *__restrict__ dst,
                                                          const uint32_t *__restrict__ face, int64_t P,
-                                                         int64_t n_blocks, int groups, T h, T dt) {
+                                                         int64_t n_blocks, T h2, T inv_h, T dt) {
     const int64_t b = xcd_block(blockIdx.x, n_blocks);
     const int lane = threadIdx.x & 63;
     const int r = lane & 15;
-    const int64_t wave = b * 4 + (threadIdx.x >> 6);
-    for (int gi = 0; gi < groups; ++gi) {
-        const int64_t p = 2 + (wave * groups + gi) * 4 + (lane >> 4);
-        if (p >= P + 2) return;   // rows past the end are idle together
-        Stencil<T> s;
-        gather_halo(src, face, p, r, s);
-        exchange_dpp(r, s);
-        store_row(dst + p * 64 + r * 4, reinit_row(s, h, dt));
+    const int64_t p0 = 2 + (b * 4 + (threadIdx.x >> 6)) * (4 * G) + (lane >> 4);
+    Loads<T> l[G];
+#pragma unroll
+    for (int g = 0; g < G; ++g)
+        if (p0 + 4 * g < P + 2) issue_loads(src, face, p0 + 4 * g, r, l[g]);
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+        const Stencil<T> s = assemble(r, l[g]);
+        if (p0 + 4 * g < P + 2) store_row(dst + (p0 + 4 * g) * 64 + r * 4, reinit_row(s, h2, inv_h, dt));
     }
 }
 
-// LDS-staged variant: every package's rows and its face halo rows are written
-// into a 6 x 6 x 6 tile (interior 4^3 plus one-cell faces) in LDS, then each
-// lane reads its stencil back from the tile.
+// LDS-staged variant: the package rows and their face halo rows go into a
+// 6 x 6 x 6 tile per package (interior 4^3 plus one-cell faces) in LDS, and
+// each lane reads its stencil back from the tile.
 template <typename T>
 __global__ __launch_bounds__(256) void reinit_lds_kernel(const T *__restrict__ src, T *__restrict__ dst,
                                                          const uint32_t *__restrict__ face, int64_t P,
-                                                         int64_t n_blocks, int groups, T h, T dt) {
+                                                         int64_t n_blocks, int groups, T h2, T inv_h, T dt) {
     __shared__ T tile[16][216];
     const int64_t b = xcd_block(blockIdx.x, n_blocks);
     const int lane = threadIdx.x & 63;
     const int r = lane & 15, j = r & 3, k = r >> 2;
-    const int slot = threadIdx.x >> 4;   // package slot of this lane in the block
-    T *t = tile[slot];
+    T *t = tile[threadIdx.x >> 4];
     auto at = [](int x, int y, int z) { return (x + 1) + 6 * ((y + 1) + 6 * (z + 1)); };
     const int64_t wave = b * 4 + (threadIdx.x >> 6);
     for (int gi = 0; gi < groups; ++gi) {
         const int64_t p = 2 + (wave * groups + gi) * 4 + (lane >> 4);
         const bool live = p < P + 2;
-        Stencil<T> s;
         if (live) {
-            gather_halo(src, face, p, r, s);
+            Loads<T> l;
+            issue_loads(src, face, p, r, l);
 #pragma unroll
-            for (int i = 0; i < 4; ++i) t[at(i, j, k)] = s.c.v[i];
-            t[at(-1, j, k)] = s.xm;
-            t[at(4, j, k)] = s.xp;
+            for (int i = 0; i < 4; ++i) t[at(i, j, k)] = l.c.v[i];
+            t[at(-1, j, k)] = l.xm;
+            t[at(4, j, k)] = l.xp;
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
-                if (j == 0) t[at(i, -1, k)] = s.ym.v[i];
-                if (j == 3) t[at(i, 4, k)] = s.yp.v[i];
-                if (k == 0) t[at(i, j, -1)] = s.zm.v[i];
-                if (k == 3) t[at(i, j, 4)] = s.zp.v[i];
+                if (j == 0) t[at(i, -1, k)] = l.yh.v[i];
+                if (j == 3) t[at(i, 4, k)] = l.yh.v[i];
+                if (k == 0) t[at(i, j, -1)] = l.zh.v[i];
+                if (k == 3) t[at(i, j, 4)] = l.zh.v[i];
             }
         }
         __syncthreads();
@@ -182,7 +207,7 @@ __global__ __launch_bounds__(256) void reinit_lds_kernel(const T *__restrict__ s
 #pragma unroll
             for (int i = 0; i < 4; ++i)
                 o.v[i] = upwind_update(t[at(i, j, k)], t[at(i - 1, j, k)], t[at(i + 1, j, k)], t[at(i, j - 1, k)],
-                                       t[at(i, j + 1, k)], t[at(i, j, k - 1)], t[at(i, j, k + 1)], h, dt);
+                                       t[at(i, j + 1, k)], t[at(i, j, k - 1)], t[at(i, j, k + 1)], h2, inv_h, dt);
             store_row(dst + p * 64 + r * 4, o);
         }
         __syncthreads();
@@ -190,8 +215,11 @@ __global__ __launch_bounds__(256) void reinit_lds_kernel(const T *__restrict__ s
 }
 
 // Central-difference gradient over packages [0, P + 2); far-field rows get 0.
-template <typename T>
-__global__ __launch_bounds__(256) void gradient_kernel(const T *__restrict__ phi, T *__restrict__ grad,
+// PACKED = false writes the three components as separate [P^][64] arrays;
+// PACKED = true writes one [P^][64] array of (phi, gx, gy, gz) quadruples, the
+// layout the packed probe gathers with one 16-byte (FP32) load per corner.
+template <typename T, bool PACKED>
+__global__ __launch_bounds__(256) void gradient_kernel(const T *__restrict__ phi, T *__restrict__ out,
                                                        const uint32_t *__restrict__ face, int64_t n_total,
                                                        int64_t n_blocks, T inv_2h) {
     const int64_t b = xcd_block(blockIdx.x, n_blocks);
@@ -199,31 +227,35 @@ __global__ __launch_bounds__(256) void gradient_kernel(const T *__restrict__ phi
     const int r = lane & 15;
     const int64_t p = (b * 4 + (threadIdx.x >> 6)) * 4 + (lane >> 4);
     if (p >= n_total) return;
-    T *gx = grad + p * 64 + r * 4;
-    T *gy = gx + n_total * 64;
-    T *gz = gy + n_total * 64;
+    Row<T> c, ox, oy, oz;
     if (p < 2) {
-        const Row<T> z{{T(0), T(0), T(0), T(0)}};
-        store_row(gx, z);
-        store_row(gy, z);
-        store_row(gz, z);
-        return;
-    }
-    Stencil<T> s;
-    gather_halo(phi, face, p, r, s);
-    exchange_dpp(r, s);
-    Row<T> ox, oy, oz;
+        c = load_row(phi + p * 64 + r * 4);
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        const T xm = i > 0 ? s.c.v[i - 1] : s.xm;
-        const T xp = i < 3 ? s.c.v[i + 1] : s.xp;
-        ox.v[i] = (xp - xm) * inv_2h;
-        oy.v[i] = (s.yp.v[i] - s.ym.v[i]) * inv_2h;
-        oz.v[i] = (s.zp.v[i] - s.zm.v[i]) * inv_2h;
+        for (int i = 0; i < 4; ++i) ox.v[i] = oy.v[i] = oz.v[i] = T(0);
+    } else {
+        Loads<T> l;
+        issue_loads(phi, face, p, r, l);
+        const Stencil<T> s = assemble(r, l);
+        c = s.c;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const T xm = i > 0 ? s.c.v[i - 1] : s.xm;
+            const T xp = i < 3 ? s.c.v[i + 1] : s.xp;
+            ox.v[i] = (xp - xm) * inv_2h;
+            oy.v[i] = (s.yp.v[i] - s.ym.v[i]) * inv_2h;
+            oz.v[i] = (s.zp.v[i] - s.zm.v[i]) * inv_2h;
+        }
     }
-    store_row(gx, ox);
-    store_row(gy, oy);
-    store_row(gz, oz);
+    if (PACKED) {
+        T *o = out + (p * 64 + r * 4) * 4;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) store_row(o + 4 * i, Row<T>{{c.v[i], ox.v[i], oy.v[i], oz.v[i]}});
+    } else {
+        T *gx = out + p * 64 + r * 4;
+        store_row(gx, ox);
+        store_row(gx + n_total * 64, oy);
+        store_row(gx + 2 * n_total * 64, oz);
+    }
 }
 
 template <typename T>
@@ -255,13 +287,20 @@ static sgrid_status launch_reinit_sweep(const sgrid_grid *g, const T *src, T *ds
     if (g->P == 0) return SGRID_OK;
     const int64_t per_block = 16 * (int64_t)cfg.groups;
     const int64_t nb = (g->P + per_block - 1) / per_block;
-    const T h = (T)g->h, dt = (T)(0.5 * g->h);
-    if (cfg.variant == 1)
-        hipLaunchKernelGGL(reinit_lds_kernel<T>, dim3((unsigned)nb), dim3(256), 0, st, src, dst, g->face, g->P, nb,
-                           cfg.groups, h, dt);
-    else
-        hipLaunchKernelGGL(reinit_dpp_kernel<T>, dim3((unsigned)nb), dim3(256), 0, st, src, dst, g->face, g->P, nb,
-                           cfg.groups, h, dt);
+    const T h2 = (T)(g->h * g->h), inv_h = (T)(1.0 / g->h), dt = (T)(0.5 * g->h);
+    const dim3 grid((unsigned)nb), block(256);
+    if (cfg.variant == 1) {
+        hipLaunchKernelGGL(reinit_lds_kernel<T>, grid, block, 0, st, src, dst, g->face, g->P, nb, cfg.groups, h2,
+                           inv_h, dt);
+    } else {
+        switch (cfg.groups) {
+            case 1: hipLaunchKernelGGL((reinit_dpp_kernel<T, 1>), grid, block, 0, st, src, dst, g->face, g->P, nb, h2, inv_h, dt); break;
+            case 2: hipLaunchKernelGGL((reinit_dpp_kernel<T, 2>), grid, block, 0, st, src, dst, g->face, g->P, nb, h2, inv_h, dt); break;
+            case 3: hipLaunchKernelGGL((reinit_dpp_kernel<T, 3>), grid, block, 0, st, src, dst, g->face, g->P, nb, h2, inv_h, dt); break;
+            case 4: hipLaunchKernelGGL((reinit_dpp_kernel<T, 4>), grid, block, 0, st, src, dst, g->face, g->P, nb, h2, inv_h, dt); break;
+            default: hipLaunchKernelGGL((reinit_dpp_kernel<T, 8>), grid, block, 0, st, src, dst, g->face, g->P, nb, h2, inv_h, dt); break;
+        }
+    }
     SG_CHECK_LAUNCH("reinit sweep");
     return SGRID_OK;
 }
@@ -293,7 +332,7 @@ template sgrid_status reinit_impl<float>(const sgrid_grid *, float *, float *, i
 extern "C" sgrid_status sgrid_set_sweep_config(int32_t variant, int32_t groups) {
     sgrid::clear_error();
     SG_REQUIRE(variant == 0 || variant == 1, "sweep variant must be 0 or 1 (got %d)", variant);
-    SG_REQUIRE(groups >= 1 && groups <= 8, "groups must be in 1..8 (got %d)", groups);
+    SG_REQUIRE(groups == 1 || groups == 2 || groups == 3 || groups == 4 || groups == 8, "groups must be 1, 2, 3, 4 or 8 (got %d)", groups);
     sgrid::set_sweep_config(variant, groups);
     return SGRID_OK;
 }
@@ -328,22 +367,33 @@ extern "C" sgrid_status sgrid_reinitialize(const sgrid_grid *g, sgrid_dtype dtyp
     return sgrid::reinit_impl<double>(g, (double *)phi, (double *)scratch, n_iter, st, sgrid::g_sweep_cfg);
 }
 
-extern "C" sgrid_status sgrid_compute_gradient(const sgrid_grid *g, sgrid_dtype dtype, const void *phi, void *grad,
-                                               void *stream) {
+template <bool PACKED>
+static sgrid_status gradient_entry(const sgrid_grid *g, sgrid_dtype dtype, const void *phi, void *out,
+                                   void *stream) {
     sgrid::clear_error();
     SG_REQUIRE(g != nullptr, "grid is NULL");
-    SG_REQUIRE(phi != nullptr && grad != nullptr, "phi or grad is NULL");
-    SG_REQUIRE(sg_aligned(phi, 16) && sg_aligned(grad, 16), "phi / grad must be 16-byte aligned");
+    SG_REQUIRE(phi != nullptr && out != nullptr, "phi or output is NULL");
+    SG_REQUIRE(sg_aligned(phi, 16) && sg_aligned(out, 16), "phi / output must be 16-byte aligned");
     SG_REQUIRE(dtype == SGRID_F32 || dtype == SGRID_F64, "unknown dtype %d", (int)dtype);
     hipStream_t st = sg_stream(stream);
     const int64_t nt = g->total();
     const int64_t nb = (nt + 15) / 16;
     if (dtype == SGRID_F32)
-        hipLaunchKernelGGL(gradient_kernel<float>, dim3((unsigned)nb), dim3(256), 0, st, (const float *)phi,
-                           (float *)grad, g->face, nt, nb, (float)(0.5 / g->h));
+        hipLaunchKernelGGL((gradient_kernel<float, PACKED>), dim3((unsigned)nb), dim3(256), 0, st,
+                           (const float *)phi, (float *)out, g->face, nt, nb, (float)(0.5 / g->h));
     else
-        hipLaunchKernelGGL(gradient_kernel<double>, dim3((unsigned)nb), dim3(256), 0, st, (const double *)phi,
-                           (double *)grad, g->face, nt, nb, 0.5 / g->h);
+        hipLaunchKernelGGL((gradient_kernel<double, PACKED>), dim3((unsigned)nb), dim3(256), 0, st,
+                           (const double *)phi, (double *)out, g->face, nt, nb, 0.5 / g->h);
     SG_CHECK_LAUNCH("gradient sweep");
     return SGRID_OK;
+}
+
+extern "C" sgrid_status sgrid_compute_gradient(const sgrid_grid *g, sgrid_dtype dtype, const void *phi, void *grad,
+                                               void *stream) {
+    return gradient_entry<false>(g, dtype, phi, grad, stream);
+}
+
+extern "C" sgrid_status sgrid_compute_gradient_packed(const sgrid_grid *g, sgrid_dtype dtype, const void *phi,
+                                                      void *packed, void *stream) {
+    return gradient_entry<true>(g, dtype, phi, packed, stream);
 }

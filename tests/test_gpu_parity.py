@@ -106,7 +106,7 @@ def test_empty_band(sg):
     out = torch.empty(0, device="cuda")
     sg.compute_near_surface_integrals(g, phi, out)
     torch.cuda.synchronize()
-    assert torch.all(po == 16 * g.h) and torch.all(no == 0)
+    assert torch.allclose(po, torch.full_like(po, 16 * g.h), rtol=1e-6, atol=0) and torch.all(no == 0)
     assert torch.all(grad == 0)
 
 
@@ -170,6 +170,14 @@ def test_sphere64_pipeline(sg, dtype, tol_h):
     assert np.max(np.abs(nn[ok] - ref_nrm[ok])) <= (1e-5 if dtype == torch.float32 else 1e-11)
     far = np.linalg.norm(ref_g, axis=1) == 0
     assert np.all(nn[far] == 0)
+    # packed (phi, g) layout gives identical probe results
+    packed = torch.empty((wl.grid.n_total, 64, 4), dtype=dtype, device="cuda")
+    sg.compute_gradient_packed(wl.grid, wl.phi, packed)
+    assert torch.equal(packed[..., 0], wl.phi)
+    assert torch.equal(packed[..., 1:].permute(2, 0, 1), wl.grad)
+    pp2, nn2 = torch.empty_like(wl.phi_p), torch.empty_like(wl.nrm_p)
+    sg.probe_particles_packed(wl.grid, packed, wl.pos, pp2, nn2)
+    assert torch.equal(pp2, wl.phi_p) and torch.equal(nn2, wl.nrm_p)
 
 
 def test_sphere64_gradient_on_initial_field(sg):
