@@ -88,7 +88,10 @@ int32_t sgrid_version(void);
  * but one of its 26 neighbours is; both are activated and numbered 2.. in
  * ascending linear order; every other cell maps to far field 0 (d < 0) or 1.
  * The result is bit-identical for identical inputs.  On success *out owns the
- * tables until sgrid_destroy.  Synchronises `stream` once.
+ * tables until sgrid_destroy.  Synchronises `stream` once (to learn P); the
+ * tables are complete when `stream` reaches the end of the call, so work on
+ * other streams must wait for it.  Memory comes from the device's
+ * stream-ordered pool.
  */
 sgrid_status sgrid_build_packages(const sgrid_desc *desc, const float *coarse_sdf_dev,
                                   void *stream, sgrid_grid **out);
@@ -177,9 +180,12 @@ sgrid_status sgrid_compute_near_surface_integrals(const sgrid_grid *grid, const 
 /*
  * Tuning knob for sgrid_reinitialize: sweep variant 0 exchanges the interior
  * neighbours between lanes (DPP row shifts), variant 1 stages each package
- * and its face halo in an LDS tile; `groups` is the number of four-package
- * sets one wavefront processes (1, 2, 3, 4 or 8).  Process-wide; default
- * (0, 1).  Results are identical for every setting.
+ * and its face halo in an LDS tile, variant 2 is variant 0 as a persistent
+ * kernel whose wavefronts walk contiguous package ranges with the next face
+ * row prefetched.  `groups` (1, 2, 3, 4 or 8) is, for variants 0 and 1, the
+ * number of four-package sets one wavefront processes and, for variant 2, the
+ * number of workgroups per compute unit.  Process-wide; default (0, 1).
+ * Results are identical for every setting.
  */
 sgrid_status sgrid_set_sweep_config(int32_t variant, int32_t groups);
 

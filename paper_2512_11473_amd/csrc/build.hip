@@ -3,9 +3,9 @@
 // reporting of the C ABI.
 //
 // Pipeline on the caller's stream:
-//   tag_kernel      one lane per coarse cell: core = |d| < l_c, inner = not core
-//                   with a core 26-neighbour; ballot-count active and core cells
-//                   per block;
+//   core_kernel     one lane per coarse cell: core flag |d| < l_c;
+//   tag_kernel      inner = not core with a core 26-neighbour; ballot-count
+//                   active and core cells per block of 1024 cells;
 //   scan_kernel     one workgroup: exclusive scan of the per-block counts;
 //   (host)          read back P and n_core once, allocate the package tables;
 //   scatter_kernel  ballot + mbcnt rank inside each wavefront, wave offsets in
@@ -16,6 +16,10 @@
 #include <stdarg.h>
 #include <stdlib.h>
 #include <string.h>
+
+#include <mutex>
+#include <unordered_map>
+#include <vector>
 
 #include "common.hpp"
 
@@ -34,6 +38,84 @@ void set_error(const char *fmt, ...) {
 
 void clear_error() { g_last_error.clear(); }
 
+namespace {
+struct CachedBlock {
+    void *ptr;
+    size_t bytes;
+    int device;
+};
+std::mutex g_alloc_mu;
+std::vector<CachedBlock> g_free_blocks;
+std::unordered_map<void *, CachedBlock> g_live_blocks;
+
+size_t round_bytes(size_t b) {
+    const size_t q = b <= (1u << 20) ? 4096 : (2u << 20);
+    return (b + q - 1) / q * q;
+}
+}  // namespace
+
+sgrid_status dev_alloc(void **p, size_t bytes, const char *what) {
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    const size_t rb = round_bytes(bytes == 0 ? 1 : bytes);
+    {
+        std::lock_guard<std::mutex> lk(g_alloc_mu);
+        for (size_t i = 0; i < g_free_blocks.size(); ++i) {
+            if (g_free_blocks[i].bytes == rb && g_free_blocks[i].device == dev) {
+                CachedBlock b = g_free_blocks[i];
+                g_free_blocks[i] = g_free_blocks.back();
+                g_free_blocks.pop_back();
+                g_live_blocks[b.ptr] = b;
+                *p = b.ptr;
+                return SGRID_OK;
+            }
+        }
+    }
+    hipError_t e = hipMalloc(p, rb);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        // give cached blocks back to the driver and retry once
+        std::vector<CachedBlock> drop;
+        {
+            std::lock_guard<std::mutex> lk(g_alloc_mu);
+            drop.swap(g_free_blocks);
+        }
+        for (auto &b : drop) (void)hipFree(b.ptr);
+        e = hipMalloc(p, rb);
+    }
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        *p = nullptr;
+        set_error("allocation of %zu bytes for %s failed: %s", bytes, what, hipGetErrorString(e));
+        return SGRID_E_NOMEM;
+    }
+    std::lock_guard<std::mutex> lk(g_alloc_mu);
+    g_live_blocks[*p] = CachedBlock{*p, rb, dev};
+    return SGRID_OK;
+}
+
+void dev_free(void *p) {
+    if (!p) return;
+    std::lock_guard<std::mutex> lk(g_alloc_mu);
+    auto it = g_live_blocks.find(p);
+    if (it == g_live_blocks.end()) return;
+    g_free_blocks.push_back(it->second);
+    g_live_blocks.erase(it);
+}
+
+int cu_count() {
+    static int cached[64] = {0};
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    if (dev < 0 || dev >= 64) return 256;
+    if (cached[dev] == 0) {
+        int n = 0;
+        if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n <= 0) n = 256;
+        cached[dev] = n;
+    }
+    return cached[dev];
+}
+
 }  // namespace sgrid
 
 extern "C" const char *sgrid_last_error(void) { return sgrid::g_last_error.c_str(); }
@@ -49,46 +131,59 @@ __device__ __forceinline__ uint64_t lanemask_lt() {
     return lane == 0 ? 0ull : (~0ull >> (64 - lane));
 }
 
-// Cell type (0 inactive, 1 core, 2 inner) from the coarse distances.
-__device__ __forceinline__ uint8_t cell_type(const float *__restrict__ d, int M, int64_t c, double lc) {
-    if (fabs((double)d[c]) < lc) return 1;
-    const int64_t MM = (int64_t)M * M;
-    const int x = (int)(c % M), y = (int)((c / M) % M), z = (int)(c / MM);
-    for (int dz = -1; dz <= 1; ++dz) {
-        const int zz = z + dz;
-        if (zz < 0 || zz >= M) continue;
-        for (int dy = -1; dy <= 1; ++dy) {
-            const int yy = y + dy;
-            if (yy < 0 || yy >= M) continue;
-            for (int dx = -1; dx <= 1; ++dx) {
-                const int xx = x + dx;
-                if (xx < 0 || xx >= M || (dx == 0 && dy == 0 && dz == 0)) continue;
-                if (fabs((double)d[xx + (int64_t)M * yy + MM * zz]) < lc) return 2;
-            }
-        }
-    }
-    return 0;
+// Pass 1: core flag per coarse cell (|d| < l_c, compared in double so that a
+// non-representable l_c rounds the same way as the definition).
+__global__ __launch_bounds__(256) void core_kernel(const float *__restrict__ d, int64_t n_cells, double lc,
+                                                   uint8_t *__restrict__ type) {
+    const int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (c < n_cells) type[c] = fabs((double)d[c]) < lc ? 1 : 0;
 }
 
-// Per-block ballot counts of active and core cells; the cell types are kept
-// for the scatter pass.
-__global__ __launch_bounds__(kTagBlock) void tag_kernel(const float *__restrict__ d, int M, int64_t n_cells,
-                                                        double lc, uint8_t *__restrict__ type,
+// Pass 2: cell type (0 inactive, 1 core, 2 inner = a core cell among the 26
+// neighbours) from the core bytes, and per-block ballot counts of active and
+// core cells.  Each thread handles kCellsPerThread consecutive cells.
+constexpr int kCellsPerThread = 4;
+constexpr int kCellsPerBlock = kTagBlock * kCellsPerThread;
+
+__device__ __forceinline__ uint8_t dilate(const uint8_t *__restrict__ core, int M, int64_t c) {
+    const int64_t MM = (int64_t)M * M;
+    const int x = (int)(c % M), y = (int)((c / M) % M), z = (int)(c / MM);
+    const int x0 = x > 0 ? x - 1 : x, x1 = x < M - 1 ? x + 1 : x;
+    const int y0 = y > 0 ? y - 1 : y, y1 = y < M - 1 ? y + 1 : y;
+    const int z0 = z > 0 ? z - 1 : z, z1 = z < M - 1 ? z + 1 : z;
+    uint32_t any = 0;
+    for (int zz = z0; zz <= z1; ++zz)
+        for (int yy = y0; yy <= y1; ++yy) {
+            const uint8_t *row = core + (int64_t)yy * M + (int64_t)zz * MM;
+            for (int xx = x0; xx <= x1; ++xx) any |= row[xx] & 1u;
+        }
+    return any ? 2 : 0;
+}
+
+// type[] holds the core flag in bit 0 on entry; inner cells get the value 2
+// written here.  Readers test bit 0 only, so a concurrent inner write never
+// changes what another block sees.
+__global__ __launch_bounds__(kTagBlock) void tag_kernel(int M, int64_t n_cells, uint8_t *__restrict__ type,
                                                         uint32_t *__restrict__ cnt_active,
                                                         uint32_t *__restrict__ cnt_core) {
     __shared__ uint32_t s_act[kTagBlock / 64], s_core[kTagBlock / 64];
-    const int64_t c = (int64_t)blockIdx.x * kTagBlock + threadIdx.x;
-    uint8_t t = 0;
-    if (c < n_cells) {
-        t = cell_type(d, M, c, lc);
-        type[c] = t;
+    const int64_t c0 = (int64_t)blockIdx.x * kCellsPerBlock + threadIdx.x;
+    uint32_t na = 0, nc = 0;
+#pragma unroll
+    for (int q = 0; q < kCellsPerThread; ++q) {
+        const int64_t c = c0 + (int64_t)q * kTagBlock;
+        uint8_t t = 0;
+        if (c < n_cells) {
+            t = (type[c] & 1u) ? 1 : dilate(type, M, c);
+            if (t == 2) type[c] = 2;
+        }
+        na += (uint32_t)__popcll(__ballot(t != 0));
+        nc += (uint32_t)__popcll(__ballot(t == 1));
     }
-    const uint64_t ba = __ballot(t != 0);
-    const uint64_t bc = __ballot(t == 1);
     const int w = threadIdx.x >> 6;
     if ((threadIdx.x & 63) == 0) {
-        s_act[w] = (uint32_t)__popcll(ba);
-        s_core[w] = (uint32_t)__popcll(bc);
+        s_act[w] = na;
+        s_core[w] = nc;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -99,44 +194,67 @@ __global__ __launch_bounds__(kTagBlock) void tag_kernel(const float *__restrict_
     }
 }
 
-// Exclusive scan of two count arrays by one workgroup: each thread sums a
-// contiguous chunk, the chunk sums are scanned in LDS, then each thread
-// rewrites its chunk as offsets.  totals = {P, n_core}.
+// Exclusive scan of two count arrays by one workgroup, in tiles of
+// kScanThreads * 4 entries: coalesced loads into LDS, a sequential scan of 4
+// entries per thread, a Hillis-Steele scan of the thread sums, coalesced
+// stores, and a running carry between tiles.  totals = {P, n_core}.
 constexpr int kScanThreads = 1024;
+constexpr int kScanTile = kScanThreads * 4;
 
 __global__ __launch_bounds__(kScanThreads) void scan_kernel(uint32_t *__restrict__ a, uint32_t *__restrict__ b,
                                                             int64_t n, uint64_t *__restrict__ totals) {
+    __shared__ uint32_t ta[kScanTile], tb[kScanTile];
     __shared__ uint64_t sa[kScanThreads], sb[kScanThreads];
-    const int64_t per = (n + kScanThreads - 1) / kScanThreads;
-    const int64_t lo = threadIdx.x * per, hi = lo + per < n ? lo + per : n;
-    uint64_t ta = 0, tb = 0;
-    for (int64_t i = lo; i < hi; ++i) { ta += a[i]; tb += b[i]; }
-    sa[threadIdx.x] = ta;
-    sb[threadIdx.x] = tb;
-    __syncthreads();
-    // Hillis-Steele inclusive scan over the chunk sums
-    for (int off = 1; off < kScanThreads; off <<= 1) {
-        uint64_t va = threadIdx.x >= off ? sa[threadIdx.x - off] : 0;
-        uint64_t vb = threadIdx.x >= off ? sb[threadIdx.x - off] : 0;
+    uint64_t carry_a = 0, carry_b = 0;
+    const int t = threadIdx.x;
+    for (int64_t base = 0; base < n; base += kScanTile) {
+        for (int i = t; i < kScanTile; i += kScanThreads) {
+            const int64_t g = base + i;
+            ta[i] = g < n ? a[g] : 0u;
+            tb[i] = g < n ? b[g] : 0u;
+        }
         __syncthreads();
-        sa[threadIdx.x] += va;
-        sb[threadIdx.x] += vb;
+        uint64_t xa = 0, xb = 0;
+        for (int i = 0; i < 4; ++i) { xa += ta[4 * t + i]; xb += tb[4 * t + i]; }
+        sa[t] = xa;
+        sb[t] = xb;
+        __syncthreads();
+        for (int off = 1; off < kScanThreads; off <<= 1) {
+            const uint64_t va = t >= off ? sa[t - off] : 0, vb = t >= off ? sb[t - off] : 0;
+            __syncthreads();
+            sa[t] += va;
+            sb[t] += vb;
+            __syncthreads();
+        }
+        uint64_t ra = carry_a + sa[t] - xa, rb = carry_b + sb[t] - xb;
+        for (int i = 0; i < 4; ++i) {
+            const uint32_t va = ta[4 * t + i], vb = tb[4 * t + i];
+            ta[4 * t + i] = (uint32_t)ra;
+            tb[4 * t + i] = (uint32_t)rb;
+            ra += va;
+            rb += vb;
+        }
+        carry_a += sa[kScanThreads - 1];
+        carry_b += sb[kScanThreads - 1];
+        __syncthreads();
+        for (int i = t; i < kScanTile; i += kScanThreads) {
+            const int64_t g = base + i;
+            if (g < n) {
+                a[g] = ta[i];
+                b[g] = tb[i];
+            }
+        }
         __syncthreads();
     }
-    uint64_t ra = sa[threadIdx.x] - ta, rb = sb[threadIdx.x] - tb;
-    for (int64_t i = lo; i < hi; ++i) {
-        const uint32_t xa = a[i], xb = b[i];
-        a[i] = (uint32_t)ra;
-        b[i] = (uint32_t)rb;
-        ra += xa;
-        rb += xb;
-    }
-    if (threadIdx.x == kScanThreads - 1) {
-        totals[0] = sa[kScanThreads - 1];
-        totals[1] = sb[kScanThreads - 1];
+    if (t == 0) {
+        totals[0] = carry_a;
+        totals[1] = carry_b;
     }
 }
 
+// Numbering: within a block, cells are ranked q-major then by lane (cell
+// c0 + q * kTagBlock), which is ascending linear order because each q-slice
+// of the block covers kTagBlock consecutive cells.
 __global__ __launch_bounds__(kTagBlock) void scatter_kernel(const float *__restrict__ d, const uint8_t *__restrict__ type,
                                                             int64_t n_cells, const uint32_t *__restrict__ off_active,
                                                             const uint32_t *__restrict__ off_core,
@@ -144,29 +262,42 @@ __global__ __launch_bounds__(kTagBlock) void scatter_kernel(const float *__restr
                                                             uint32_t *__restrict__ pkg_cell,
                                                             uint8_t *__restrict__ pkg_type,
                                                             uint32_t *__restrict__ core_list) {
-    __shared__ uint32_t s_act[kTagBlock / 64], s_core[kTagBlock / 64];
-    const int64_t c = (int64_t)blockIdx.x * kTagBlock + threadIdx.x;
-    const uint8_t t = c < n_cells ? type[c] : 0;
-    const uint64_t ba = __ballot(t != 0);
-    const uint64_t bc = __ballot(t == 1);
+    __shared__ uint32_t s_act[kCellsPerThread][kTagBlock / 64], s_core[kCellsPerThread][kTagBlock / 64];
+    const int64_t c0 = (int64_t)blockIdx.x * kCellsPerBlock + threadIdx.x;
     const int w = threadIdx.x >> 6;
-    if ((threadIdx.x & 63) == 0) {
-        s_act[w] = (uint32_t)__popcll(ba);
-        s_core[w] = (uint32_t)__popcll(bc);
+    uint8_t t[kCellsPerThread];
+    uint64_t ba[kCellsPerThread], bc[kCellsPerThread];
+#pragma unroll
+    for (int q = 0; q < kCellsPerThread; ++q) {
+        const int64_t c = c0 + (int64_t)q * kTagBlock;
+        t[q] = c < n_cells ? type[c] : 0;
+        ba[q] = __ballot(t[q] != 0);
+        bc[q] = __ballot(t[q] == 1);
+        if ((threadIdx.x & 63) == 0) {
+            s_act[q][w] = (uint32_t)__popcll(ba[q]);
+            s_core[q][w] = (uint32_t)__popcll(bc[q]);
+        }
     }
     __syncthreads();
     uint32_t wa = off_active[blockIdx.x], wc = off_core[blockIdx.x];
-    for (int i = 0; i < w; ++i) { wa += s_act[i]; wc += s_core[i]; }
-    if (c >= n_cells) return;
     const uint64_t lt = lanemask_lt();
-    if (t != 0) {
-        const uint32_t id = 2u + wa + (uint32_t)__popcll(ba & lt);
-        cell_pkg[c] = id;
-        pkg_cell[id] = (uint32_t)c;
-        pkg_type[id] = t;
-        if (t == 1) core_list[wc + (uint32_t)__popcll(bc & lt)] = id;
-    } else {
-        cell_pkg[c] = d[c] < 0.0f ? sgrid::kFarNeg : sgrid::kFarPos;
+#pragma unroll
+    for (int q = 0; q < kCellsPerThread; ++q) {
+        uint32_t a = wa, k = wc;
+        for (int i = 0; i < w; ++i) { a += s_act[q][i]; k += s_core[q][i]; }
+        const int64_t c = c0 + (int64_t)q * kTagBlock;
+        if (c < n_cells) {
+            if (t[q] != 0) {
+                const uint32_t id = 2u + a + (uint32_t)__popcll(ba[q] & lt);
+                cell_pkg[c] = id;
+                pkg_cell[id] = (uint32_t)c;
+                pkg_type[id] = t[q];
+                if (t[q] == 1) core_list[k + (uint32_t)__popcll(bc[q] & lt)] = id;
+            } else {
+                cell_pkg[c] = d[c] < 0.0f ? sgrid::kFarNeg : sgrid::kFarPos;
+            }
+        }
+        for (int i = 0; i < kTagBlock / 64; ++i) { wa += s_act[q][i]; wc += s_core[q][i]; }
     }
 }
 
@@ -219,45 +350,27 @@ __global__ __launch_bounds__(256) void nbr_kernel(const uint32_t *__restrict__ c
 
 void free_grid(sgrid_grid *g) {
     if (!g) return;
-    hipFree(g->cell_pkg);
-    hipFree(g->pkg_cell);
-    hipFree(g->pkg_type);
-    hipFree(g->nbr);
-    hipFree(g->face);
-    hipFree(g->core_list);
+    void *ptrs[] = {g->cell_pkg, g->pkg_cell, g->pkg_type, g->nbr, g->face, g->core_list, g->workspace};
+    for (void *p : ptrs) sgrid::dev_free(p);
     delete g;
 }
 
-struct Scratch {
-    uint8_t *type = nullptr;
-    uint32_t *ca = nullptr, *cc = nullptr;
-    uint64_t *totals = nullptr;
-    ~Scratch() {
-        hipFree(type);
-        hipFree(ca);
-        hipFree(cc);
-        hipFree(totals);
-    }
-};
-
-sgrid_status dev_alloc(void **p, size_t bytes, const char *what) {
-    if (bytes == 0) bytes = 4;
-    hipError_t e = hipMalloc(p, bytes);
-    if (e != hipSuccess) {
+// Pinned host word for the one readback of a build (per thread).
+uint64_t *pinned_totals() {
+    static thread_local uint64_t *buf = nullptr;
+    if (!buf && hipHostMalloc((void **)&buf, 2 * sizeof(uint64_t), hipHostMallocDefault) != hipSuccess) {
         (void)hipGetLastError();
-        *p = nullptr;
-        sgrid::set_error("hipMalloc of %zu bytes for %s failed: %s", bytes, what, hipGetErrorString(e));
-        return SGRID_E_NOMEM;
+        buf = nullptr;
     }
-    return SGRID_OK;
+    return buf;
 }
 
 }  // namespace
 
-#define SG_ALLOC(ptr, bytes, what)                                              \
-    do {                                                                        \
-        sgrid_status _s = dev_alloc((void **)&(ptr), (size_t)(bytes), what);    \
-        if (_s != SGRID_OK) { free_grid(g); return _s; }                        \
+#define SG_ALLOC(ptr, bytes, what)                                                  \
+    do {                                                                            \
+        sgrid_status _s = sgrid::dev_alloc((void **)&(ptr), (size_t)(bytes), what); \
+        if (_s != SGRID_OK) { free_grid(g); return _s; }                            \
     } while (0)
 
 #define SG_HIP_OR_FREE(expr)                                                          \
@@ -293,30 +406,32 @@ extern "C" sgrid_status sgrid_build_packages(const sgrid_desc *desc, const float
     g->h = desc->h;
     SG_HIP_OR_FREE(hipGetDevice(&g->device));
 
-    const int64_t nb = (n_cells + kTagBlock - 1) / kTagBlock;
-    Scratch s;
+    // workspace: cell types (M^3 bytes), two count arrays, totals
+    const int64_t nb = (n_cells + kCellsPerBlock - 1) / kCellsPerBlock;
+    const size_t ws_types = ((size_t)n_cells + 255) / 256 * 256;
+    const size_t ws_counts = ((size_t)nb * 4 + 255) / 256 * 256;
+    SG_ALLOC(g->workspace, ws_types + 2 * ws_counts + 256, "build workspace");
+    uint8_t *types = (uint8_t *)g->workspace;
+    uint32_t *ca = (uint32_t *)(types + ws_types);
+    uint32_t *cc = (uint32_t *)((uint8_t *)ca + ws_counts);
+    uint64_t *totals = (uint64_t *)((uint8_t *)cc + ws_counts);
     SG_ALLOC(g->cell_pkg, n_cells * 4, "cell_pkg");
-    {
-        sgrid_status r;
-        if ((r = dev_alloc((void **)&s.type, n_cells, "cell types")) != SGRID_OK ||
-            (r = dev_alloc((void **)&s.ca, nb * 4, "block counts")) != SGRID_OK ||
-            (r = dev_alloc((void **)&s.cc, nb * 4, "block counts")) != SGRID_OK ||
-            (r = dev_alloc((void **)&s.totals, 16, "totals")) != SGRID_OK) {
-            free_grid(g);
-            return r;
-        }
-    }
+
     const double lc = 4.0 * desc->h;
-    hipLaunchKernelGGL(tag_kernel, dim3((unsigned)nb), dim3(kTagBlock), 0, st, coarse_sdf, (int)M, n_cells, lc,
-                       s.type, s.ca, s.cc);
+    hipLaunchKernelGGL(core_kernel, dim3((unsigned)((n_cells + 255) / 256)), dim3(256), 0, st, coarse_sdf, n_cells,
+                       lc, types);
     SG_HIP_OR_FREE(hipGetLastError());
-    hipLaunchKernelGGL(scan_kernel, dim3(1), dim3(kScanThreads), 0, st, s.ca, s.cc, nb, s.totals);
+    hipLaunchKernelGGL(tag_kernel, dim3((unsigned)nb), dim3(kTagBlock), 0, st, (int)M, n_cells, types, ca, cc);
     SG_HIP_OR_FREE(hipGetLastError());
-    uint64_t totals[2] = {0, 0};
-    SG_HIP_OR_FREE(hipMemcpyAsync(totals, s.totals, sizeof totals, hipMemcpyDeviceToHost, st));
+    hipLaunchKernelGGL(scan_kernel, dim3(1), dim3(kScanThreads), 0, st, ca, cc, nb, totals);
+    SG_HIP_OR_FREE(hipGetLastError());
+    uint64_t *host = pinned_totals();
+    uint64_t local[2] = {0, 0};
+    uint64_t *dst = host ? host : local;
+    SG_HIP_OR_FREE(hipMemcpyAsync(dst, totals, 2 * sizeof(uint64_t), hipMemcpyDeviceToHost, st));
     SG_HIP_OR_FREE(hipStreamSynchronize(st));
-    g->P = (int64_t)totals[0];
-    g->n_core = (int64_t)totals[1];
+    g->P = (int64_t)dst[0];
+    g->n_core = (int64_t)dst[1];
     const int64_t nt = g->total();
     SG_ALLOC(g->pkg_cell, nt * 4, "pkg_cell");
     SG_ALLOC(g->pkg_type, nt, "pkg_type");
@@ -325,16 +440,13 @@ extern "C" sgrid_status sgrid_build_packages(const sgrid_desc *desc, const float
     SG_ALLOC(g->core_list, (g->n_core > 0 ? g->n_core : 1) * 4, "core_list");
     hipLaunchKernelGGL(far_rows_kernel, dim3(1), dim3(64), 0, st, g->pkg_cell, g->pkg_type);
     SG_HIP_OR_FREE(hipGetLastError());
-    hipLaunchKernelGGL(scatter_kernel, dim3((unsigned)nb), dim3(kTagBlock), 0, st, coarse_sdf, s.type, n_cells,
-                       s.ca, s.cc, g->cell_pkg, g->pkg_cell, g->pkg_type, g->core_list);
+    hipLaunchKernelGGL(scatter_kernel, dim3((unsigned)nb), dim3(kTagBlock), 0, st, coarse_sdf, types, n_cells, ca, cc,
+                       g->cell_pkg, g->pkg_cell, g->pkg_type, g->core_list);
     SG_HIP_OR_FREE(hipGetLastError());
     const int64_t nn = nt * 27;
     hipLaunchKernelGGL(nbr_kernel, dim3((unsigned)((nn + 255) / 256)), dim3(256), 0, st, g->cell_pkg, g->pkg_cell,
                        (int)M, nt, g->nbr, g->face);
     SG_HIP_OR_FREE(hipGetLastError());
-    // the scratch buffers are freed when `s` goes out of scope; wait for the
-    // kernels that read them first
-    SG_HIP_OR_FREE(hipStreamSynchronize(st));
     *out = g;
     return SGRID_OK;
 }

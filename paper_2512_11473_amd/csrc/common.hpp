@@ -14,6 +14,17 @@ namespace sgrid {
 void set_error(const char *fmt, ...);
 void clear_error();
 
+// Device memory of the library (tables, workspaces) comes from a small
+// per-process caching allocator: freed blocks are kept and handed out again
+// to requests of the same rounded size, so repeated builds make no driver
+// allocation calls.  dev_free must only be called once no queued work uses
+// the block.
+sgrid_status dev_alloc(void **p, size_t bytes, const char *what);
+void dev_free(void *p);
+
+// Compute units of the current device (cached).
+int cu_count();
+
 // Far-field package ids and the far-field constant in units of h.
 constexpr uint32_t kFarNeg = 0u;
 constexpr uint32_t kFarPos = 1u;
@@ -38,6 +49,7 @@ struct sgrid_grid {
     uint32_t *nbr = nullptr;        // [P+2][27]
     uint32_t *face = nullptr;       // [P+2][8]: the six face slots of nbr, then two pads
     uint32_t *core_list = nullptr;  // [n_core]
+    void *workspace = nullptr;      // build scratch, kept until destroy
     int64_t total() const { return P + 2; }
 };
 

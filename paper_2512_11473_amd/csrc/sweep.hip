@@ -92,12 +92,15 @@ struct Loads {
     T xm, xp;
 };
 
+__device__ __forceinline__ void load_face(const uint32_t *__restrict__ face, int64_t p, uint4 &f0, uint2 &f1) {
+    f0 = *reinterpret_cast<const uint4 *>(face + p * 8);
+    f1 = *reinterpret_cast<const uint2 *>(face + p * 8 + 4);
+}
+
 template <typename T>
-__device__ __forceinline__ void issue_loads(const T *__restrict__ src, const uint32_t *__restrict__ face, int64_t p,
-                                            int r, Loads<T> &l) {
+__device__ __forceinline__ void issue_data(const T *__restrict__ src, int64_t p, int r, const uint4 &f0,
+                                           const uint2 &f1, Loads<T> &l) {
     const int j = r & 3, k = r >> 2;
-    const uint4 f0 = *reinterpret_cast<const uint4 *>(face + p * 8);
-    const uint2 f1 = *reinterpret_cast<const uint2 *>(face + p * 8 + 4);
     l.c = load_row(src + p * 64 + r * 4);
     l.xm = src[(int64_t)f0.x * 64 + r * 4 + 3];
     l.xp = src[(int64_t)f0.y * 64 + r * 4];
@@ -109,6 +112,15 @@ __device__ __forceinline__ void issue_loads(const T *__restrict__ src, const uin
         const uint32_t fz = k == 0 ? f1.x : f1.y;
         l.zh = load_row(src + (int64_t)fz * 64 + (k == 0 ? j + 12 : j) * 4);
     }
+}
+
+template <typename T>
+__device__ __forceinline__ void issue_loads(const T *__restrict__ src, const uint32_t *__restrict__ face, int64_t p,
+                                            int r, Loads<T> &l) {
+    uint4 f0;
+    uint2 f1;
+    load_face(face, p, f0, f1);
+    issue_data(src, p, r, f0, f1, l);
 }
 
 // Interior y / z neighbours through DPP row shifts (the 16 lanes of a package
@@ -166,6 +178,40 @@ __global__ __launch_bounds__(256) void reinit_dpp_kernel(const T *__restrict__ s
     for (int g = 0; g < G; ++g) {
         const Stencil<T> s = assemble(r, l[g]);
         if (p0 + 4 * g < P + 2) store_row(dst + (p0 + 4 * g) * 64 + r * 4, reinit_row(s, h2, inv_h, dt));
+    }
+}
+
+// Persistent variant: a fixed grid of a few workgroups per CU; each wavefront
+// walks a contiguous range of four-package sets and loads the face row of the
+// next set while the current set's data loads are in flight, so the
+// face-table -> halo dependency costs one memory round trip per range instead
+// of one per set.
+template <typename T>
+__global__ __launch_bounds__(256) void reinit_stream_kernel(const T *__restrict__ src, T *__restrict__ dst,
+                                                            const uint32_t *__restrict__ face, int64_t P,
+                                                            int64_t n_blocks, int64_t sets_per_wave, T h2, T inv_h,
+                                                            T dt) {
+    const int64_t b = xcd_block(blockIdx.x, n_blocks);
+    const int lane = threadIdx.x & 63;
+    const int r = lane & 15;
+    const int64_t wave = b * 4 + (threadIdx.x >> 6);
+    const int64_t n_sets = (P + 3) / 4;
+    const int64_t s0 = wave * sets_per_wave;
+    const int64_t s1 = s0 + sets_per_wave < n_sets ? s0 + sets_per_wave : n_sets;
+    if (s0 >= s1) return;
+    const int64_t end = P + 2;
+    uint4 f0n = make_uint4(0, 0, 0, 0);
+    uint2 f1n = make_uint2(0, 0);
+    int64_t p = 2 + 4 * s0 + (lane >> 4);
+    if (p < end) load_face(face, p, f0n, f1n);
+    for (int64_t s = s0; s < s1; ++s, p += 4) {
+        const uint4 f0 = f0n;
+        const uint2 f1 = f1n;
+        Loads<T> l;
+        if (p < end) issue_data(src, p, r, f0, f1, l);
+        if (s + 1 < s1 && p + 4 < end) load_face(face, p + 4, f0n, f1n);
+        const Stencil<T> st = assemble(r, l);
+        if (p < end) store_row(dst + p * 64 + r * 4, reinit_row(st, h2, inv_h, dt));
     }
 }
 
@@ -289,7 +335,15 @@ static sgrid_status launch_reinit_sweep(const sgrid_grid *g, const T *src, T *ds
     const int64_t nb = (g->P + per_block - 1) / per_block;
     const T h2 = (T)(g->h * g->h), inv_h = (T)(1.0 / g->h), dt = (T)(0.5 * g->h);
     const dim3 grid((unsigned)nb), block(256);
-    if (cfg.variant == 1) {
+    if (cfg.variant == 2) {
+        const int64_t n_sets = (g->P + 3) / 4;
+        int64_t nbp = (int64_t)cu_count() * cfg.groups;
+        const int64_t waves = nbp * 4;
+        const int64_t spw = (n_sets + waves - 1) / waves;
+        nbp = (n_sets + spw * 4 - 1) / (spw * 4);   // drop workgroups that would have no sets
+        hipLaunchKernelGGL(reinit_stream_kernel<T>, dim3((unsigned)nbp), block, 0, st, src, dst, g->face, g->P, nbp,
+                           spw, h2, inv_h, dt);
+    } else if (cfg.variant == 1) {
         hipLaunchKernelGGL(reinit_lds_kernel<T>, grid, block, 0, st, src, dst, g->face, g->P, nb, cfg.groups, h2,
                            inv_h, dt);
     } else {
@@ -331,7 +385,7 @@ template sgrid_status reinit_impl<float>(const sgrid_grid *, float *, float *, i
 
 extern "C" sgrid_status sgrid_set_sweep_config(int32_t variant, int32_t groups) {
     sgrid::clear_error();
-    SG_REQUIRE(variant == 0 || variant == 1, "sweep variant must be 0 or 1 (got %d)", variant);
+    SG_REQUIRE(variant >= 0 && variant <= 2, "sweep variant must be 0, 1 or 2 (got %d)", variant);
     SG_REQUIRE(groups == 1 || groups == 2 || groups == 3 || groups == 4 || groups == 8, "groups must be 1, 2, 3, 4 or 8 (got %d)", groups);
     sgrid::set_sweep_config(variant, groups);
     return SGRID_OK;
