@@ -177,6 +177,61 @@ sgrid_status sgrid_compute_near_surface_integrals(const sgrid_grid *grid, const 
                                                   const sgrid_mlp *model, float *out_dev,
                                                   uint32_t *n_fallback_dev, void *stream);
 
+/* ------------------------------------------------------------------------
+ * Surrogate network for the near-surface integrals (not in the paper: a
+ * learned replacement of the plain integral above).  216 -> 128 -> 128 -> 4
+ * MLP with tanh-approximated GELU; input the 6x6x6 window of phi / h at
+ * offsets -2..3 around a core data point (x fastest), output
+ * (K_W, h K_grad x, y, z).  Parameters are one packed FP32 vector of 44,804
+ * values: W1[128][216], b1[128], W2[128][128], b2[128], W3[4][128], b3[4]
+ * (row-major, y = W x + b).  Kernels use BF16 MFMA with FP32 accumulation;
+ * the first layer splits its input into BF16 hi + lo parts.
+ * ------------------------------------------------------------------------ */
+
+/* Creates a model on the current device from host parameters (copied). */
+sgrid_status sgrid_mlp_create(const float *params_host, sgrid_mlp **out);
+sgrid_status sgrid_mlp_destroy(sgrid_mlp *model);
+
+/* Copies the FP32 parameters, Adam moments and step count to host buffers
+ * (each nullable); synchronises the device. */
+sgrid_status sgrid_mlp_get_params(const sgrid_mlp *model, float *params_host, float *adam_m_host,
+                                  float *adam_v_host, int64_t *step);
+
+/* Restores Adam moments and the step count (for resuming training). */
+sgrid_status sgrid_mlp_set_state(sgrid_mlp *model, const float *adam_m_host, const float *adam_v_host,
+                                 int64_t step);
+
+/* Gate of the learned integrals: a non-saturated point takes the network's
+ * output when the mean squared residual of its window after the best affine
+ * fit (units of h^2) is <= tau and the predicted K_W lies in [kw_lo, kw_hi];
+ * otherwise it falls back to the plain integral.  Default: tau = FLT_MAX,
+ * [-0.05, 1.05]. */
+sgrid_status sgrid_mlp_set_gate(sgrid_mlp *model, float tau, float kw_lo, float kw_hi);
+
+/* y_dev [B][4] = network(x_dev [B][216]).  16-byte aligned device arrays. */
+sgrid_status sgrid_mlp_forward(const sgrid_mlp *model, const float *x_dev, int64_t B, float *y_dev,
+                               void *stream);
+
+/* grad_dev [44804] = d(sum_b dy[b] . y[b]) / d(params) for x_dev [B][216],
+ * dy_dev [B][4]; the sum over the batch is reduced in a fixed order, so
+ * repeated calls give identical bits. */
+sgrid_status sgrid_mlp_backward(sgrid_mlp *model, const float *x_dev, const float *dy_dev, int64_t B,
+                                float *grad_dev, void *stream);
+
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected) on the
+ * loss sum_b sum_o w_o (y_bo - t_bo)^2 / B with w = loss_weights_host[4];
+ * the loss before the step goes to *loss_dev (nullable, the sum over the
+ * batch before dividing by B). */
+sgrid_status sgrid_mlp_train_step(sgrid_mlp *model, const float *x_dev, const float *t_dev, int64_t B,
+                                  const float *loss_weights_host, float lr, float *loss_dev, void *stream);
+
+/* Network inputs of every core point in the integrals' output order:
+ * x_dev [n_core * 64][216] (nullable) = window of phi / h; unsat_dev
+ * [n_core * 64] (nullable) = 1 when some tap's cut fraction is strictly
+ * between 0 and 1, else 0. */
+sgrid_status sgrid_gather_windows(const sgrid_grid *grid, const float *phi_dev, float *x_dev,
+                                  uint8_t *unsat_dev, void *stream);
+
 /*
  * Tuning knob for sgrid_reinitialize: sweep variant 0 exchanges the interior
  * neighbours between lanes (DPP row shifts), variant 1 stages each package

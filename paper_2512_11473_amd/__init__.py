@@ -19,6 +19,7 @@ import torch
 __all__ = [
     "SgridError", "Grid", "load", "build_packages", "fill_far_field", "reinitialize",
     "compute_gradient", "compute_gradient_packed", "probe_particles", "probe_particles_packed", "compute_near_surface_integrals", "set_sweep_config",
+    "Mlp", "gather_windows", "MLP_N_PARAMS",
     "LIB_PATH", "FAR_FIELD_IN_H",
 ]
 
@@ -58,6 +59,15 @@ _SIGNATURES = {
     "sgrid_probe_particles": (ctypes.c_int, [_P, ctypes.c_int, _P, _P, _P, ctypes.c_int64, _P, _P, _P]),
     "sgrid_compute_near_surface_integrals": (ctypes.c_int, [_P, _P, _P, _P, _P, _P]),
     "sgrid_set_sweep_config": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32]),
+    "sgrid_mlp_create": (ctypes.c_int, [_P, ctypes.POINTER(_P)]),
+    "sgrid_mlp_destroy": (ctypes.c_int, [_P]),
+    "sgrid_mlp_get_params": (ctypes.c_int, [_P, _P, _P, _P, ctypes.POINTER(ctypes.c_int64)]),
+    "sgrid_mlp_set_state": (ctypes.c_int, [_P, _P, _P, ctypes.c_int64]),
+    "sgrid_mlp_set_gate": (ctypes.c_int, [_P, ctypes.c_float, ctypes.c_float, ctypes.c_float]),
+    "sgrid_mlp_forward": (ctypes.c_int, [_P, _P, ctypes.c_int64, _P, _P]),
+    "sgrid_mlp_backward": (ctypes.c_int, [_P, _P, _P, ctypes.c_int64, _P, _P]),
+    "sgrid_mlp_train_step": (ctypes.c_int, [_P, _P, _P, ctypes.c_int64, _P, ctypes.c_float, _P, _P]),
+    "sgrid_gather_windows": (ctypes.c_int, [_P, _P, _P, _P, _P]),
 }
 
 
@@ -258,6 +268,93 @@ def compute_near_surface_integrals(grid: Grid, phi: torch.Tensor, out: torch.Ten
     mh = model.handle if model is not None else None
     _check(load().sgrid_compute_near_surface_integrals(grid.handle, _dev(phi, "phi"), mh, _dev(out, "out"), nf,
                                                        _stream(stream)))
+
+
+MLP_N_PARAMS = 44804
+
+
+class Mlp:
+    """Surrogate network handle (FP32 master parameters on the device)."""
+
+    def __init__(self, params):
+        import numpy as np
+        p = np.ascontiguousarray(params, dtype=np.float32)
+        if p.shape != (MLP_N_PARAMS,):
+            raise ValueError(f"expected {MLP_N_PARAMS} parameters")
+        out = ctypes.c_void_p()
+        _check(load().sgrid_mlp_create(p.ctypes.data_as(_P), ctypes.byref(out)))
+        self._h = out
+
+    @property
+    def handle(self):
+        if self._h is None:
+            raise SgridError(5, "model already destroyed")
+        return self._h
+
+    def destroy(self):
+        if getattr(self, "_h", None) is not None:
+            _check(load().sgrid_mlp_destroy(self._h))
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+    def state(self):
+        """(params, adam_m, adam_v, step) as host arrays."""
+        import numpy as np
+        w, m, v = (np.empty(MLP_N_PARAMS, dtype=np.float32) for _ in range(3))
+        step = ctypes.c_int64()
+        _check(load().sgrid_mlp_get_params(self.handle, w.ctypes.data_as(_P), m.ctypes.data_as(_P),
+                                           v.ctypes.data_as(_P), ctypes.byref(step)))
+        return w, m, v, int(step.value)
+
+    def set_state(self, adam_m, adam_v, step: int):
+        import numpy as np
+        m = np.ascontiguousarray(adam_m, dtype=np.float32)
+        v = np.ascontiguousarray(adam_v, dtype=np.float32)
+        _check(load().sgrid_mlp_set_state(self.handle, m.ctypes.data_as(_P), v.ctypes.data_as(_P), int(step)))
+
+    def set_gate(self, tau: float, kw_lo: float = -0.05, kw_hi: float = 1.05):
+        _check(load().sgrid_mlp_set_gate(self.handle, float(tau), float(kw_lo), float(kw_hi)))
+
+    def forward(self, x: torch.Tensor, y: torch.Tensor, stream=None):
+        B = x.shape[0]
+        if x.dtype != torch.float32 or x.shape != (B, 216) or y.shape != (B, 4):
+            raise ValueError("x [B,216] and y [B,4] float32 expected")
+        _check(load().sgrid_mlp_forward(self.handle, _dev(x, "x"), B, _dev(y, "y"), _stream(stream)))
+
+    def backward(self, x: torch.Tensor, dy: torch.Tensor, grad: torch.Tensor, stream=None):
+        B = x.shape[0]
+        if x.shape != (B, 216) or dy.shape != (B, 4) or grad.numel() != MLP_N_PARAMS:
+            raise ValueError("x [B,216], dy [B,4], grad [44804] expected")
+        _check(load().sgrid_mlp_backward(self.handle, _dev(x, "x"), _dev(dy, "dy"), B, _dev(grad, "grad"),
+                                         _stream(stream)))
+
+    def train_step(self, x: torch.Tensor, t: torch.Tensor, loss_weights, lr: float,
+                   loss: Optional[torch.Tensor] = None, stream=None):
+        import numpy as np
+        B = x.shape[0]
+        if x.shape != (B, 216) or t.shape != (B, 4):
+            raise ValueError("x [B,216] and t [B,4] expected")
+        lw = np.ascontiguousarray(loss_weights, dtype=np.float32)
+        lp = _dev(loss, "loss") if loss is not None else None
+        _check(load().sgrid_mlp_train_step(self.handle, _dev(x, "x"), _dev(t, "t"), B, lw.ctypes.data_as(_P),
+                                           float(lr), lp, _stream(stream)))
+
+
+def gather_windows(grid: Grid, phi: torch.Tensor, x: Optional[torch.Tensor] = None,
+                   unsat: Optional[torch.Tensor] = None, stream=None):
+    """Windows of phi/h [n_core*64, 216] and unsaturated flags [n_core*64] of the core points."""
+    n = grid.n_core * 64
+    if x is not None and (x.shape != (n, 216) or x.dtype != torch.float32):
+        raise ValueError("x must be [n_core*64, 216] float32")
+    if unsat is not None and (unsat.numel() != n or unsat.dtype != torch.uint8):
+        raise ValueError("unsat must be [n_core*64] uint8")
+    _check(load().sgrid_gather_windows(grid.handle, _dev(phi, "phi"), _dev(x, "x") if x is not None else None,
+                                       _dev(unsat, "unsat") if unsat is not None else None, _stream(stream)))
 
 
 def set_sweep_config(variant: int, groups: int):

@@ -1,13 +1,845 @@
-// Surrogate network for the near-surface integrals (filled in by the MLP
-// kernels); until a model is created every call uses the plain integral.
-#include "common.hpp"
+// Surrogate network for the near-surface integrals: a 216 -> 128 -> 128 -> 4
+// MLP with tanh-approximated GELU, input the 6 x 6 x 6 window of phi / h
+// around a core data point (offsets -2..3, x fastest), output
+// (K_W, h K_grad).  Training (forward, backward, Adam) and inference run on
+// BF16 MFMA (v_mfma_f32_16x16x32_bf16) with FP32 accumulation; the first
+// layer splits its input into BF16 hi and lo parts (x = hi + lo, two MFMAs)
+// so the input keeps about 16 significant bits.
+//
+// MFMA lane layout used throughout (16 x 16 x 32, wave64, lane l, r = l % 16,
+// q = l / 16):  A[m][k] with m = r, k = 8q + j (j = 0..7);
+//               B[k][n] with k = 8q + j, n = r;
+//               C[m][n] with m = 4q + i (i = 0..3), n = r.
+// A wavefront owns a tile of 16 samples; activations move from the C layout
+// to the A layout of the next layer through a row-major BF16 tile in LDS.
+//
+// Parameters are FP32 masters in one packed vector (W1[128][216], b1[128],
+// W2[128][128], b2[128], W3[4][128], b3[4]), with BF16 copies laid out for
+// the B operands: W1 [128][224] (zero padded), W2 [128][128], its transpose
+// for the backward pass, W3 [16][128] (rows 4..15 zero).
+#include <float.h>
+#include <string.h>
+
+#include <vector>
+
+#include "fraction.hpp"
+
+typedef __bf16 bf16;
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+namespace {
+
+constexpr int kIn = 216, kInPad = 224, kH = 128, kOut = 4;
+constexpr int kNParam = 44804;
+constexpr int oW1 = 0, oB1 = oW1 + kH * kIn, oW2 = oB1 + kH, oB2 = oW2 + kH * kH, oW3 = oB2 + kH,
+              oB3 = oW3 + kOut * kH;
+static_assert(oB3 + kOut == kNParam, "parameter layout");
+
+struct MlpDev {
+    const float *w;      // FP32 masters
+    const bf16 *w1b;     // [128][224]
+    const bf16 *w2b;     // [128][128]
+    const bf16 *w2tb;    // [128][128], transposed
+    const bf16 *w3b;     // [16][128]
+};
+
+__device__ __forceinline__ floatx4 mfma(const bf16x8 &a, const bf16x8 &b, const floatx4 &c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+
+__device__ __forceinline__ bf16x8 ld8(const bf16 *p) { return *reinterpret_cast<const bf16x8 *>(p); }
+
+__device__ __forceinline__ float gelu(float z) {
+    const float u = 0.7978845608028654f * (z + 0.044715f * z * z * z);
+    return 0.5f * z * (1.0f + tanhf(u));
+}
+
+__device__ __forceinline__ float gelu_grad(float z) {
+    const float u = 0.7978845608028654f * (z + 0.044715f * z * z * z);
+    const float th = tanhf(u);
+    return 0.5f * (1.0f + th) + 0.5f * z * (1.0f - th * th) * 0.7978845608028654f * (1.0f + 3.0f * 0.044715f * z * z);
+}
+
+struct Tile {
+    floatx4 z1[8], z2[8];
+    floatx4 y;
+};
+
+// Forward pass of one 16-sample tile.  `xs(m, k0, v)` returns the 8 inputs
+// k0..k0+7 of sample m (zero past 215).  `a1`, `a2` are the wave's row-major
+// [16][128] BF16 activation tiles in LDS; `xh` (nullable) receives the BF16 hi
+// part of the inputs [16][224] for the weight gradient.  Ends with the wave's
+// LDS writes complete; callers synchronise the workgroup between phases.
+template <class XSrc>
+__device__ __forceinline__ void forward_tile(const XSrc &xs, const MlpDev &W, bf16 *a1, bf16 *a2, bf16 *xh, Tile &T,
+                                             int lane) {
+    const int r = lane & 15, q = lane >> 4;
+#pragma unroll
+    for (int t = 0; t < 8; ++t) T.z1[t] = floatx4{0.f, 0.f, 0.f, 0.f};
+    for (int s = 0; s < kInPad / 32; ++s) {
+        float v[8];
+        xs(r, 32 * s + 8 * q, v);
+        bf16x8 ah, al;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const bf16 hi = (bf16)v[j];
+            ah[j] = hi;
+            al[j] = (bf16)(v[j] - (float)hi);
+        }
+        if (xh) *reinterpret_cast<bf16x8 *>(xh + r * kInPad + 32 * s + 8 * q) = ah;
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+            const bf16x8 b = ld8(W.w1b + (16 * t + r) * kInPad + 32 * s + 8 * q);
+            T.z1[t] = mfma(ah, b, T.z1[t]);
+            T.z1[t] = mfma(al, b, T.z1[t]);
+        }
+    }
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+        const float bb = W.w[oB1 + 16 * t + r];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            T.z1[t][i] += bb;
+            a1[(4 * q + i) * kH + 16 * t + r] = (bf16)gelu(T.z1[t][i]);
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int t = 0; t < 8; ++t) T.z2[t] = floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int s = 0; s < kH / 32; ++s) {
+        const bf16x8 a = ld8(a1 + r * kH + 32 * s + 8 * q);
+#pragma unroll
+        for (int t = 0; t < 8; ++t) T.z2[t] = mfma(a, ld8(W.w2b + (16 * t + r) * kH + 32 * s + 8 * q), T.z2[t]);
+    }
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+        const float bb = W.w[oB2 + 16 * t + r];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            T.z2[t][i] += bb;
+            a2[(4 * q + i) * kH + 16 * t + r] = (bf16)gelu(T.z2[t][i]);
+        }
+    }
+    __syncthreads();
+    T.y = floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int s = 0; s < kH / 32; ++s)
+        T.y = mfma(ld8(a2 + r * kH + 32 * s + 8 * q), ld8(W.w3b + r * kH + 32 * s + 8 * q), T.y);
+    if (r < kOut) {
+        const float bb = W.w[oB3 + r];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) T.y[i] += bb;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Training: forward + backward of 64 samples per workgroup (4 wavefronts x 16)
+// and this workgroup's partial weight gradient, written to part[blockIdx.x].
+// dY is either given (`dy_in`, [B][4]) or the gradient of the weighted
+// squared error sum_o w_o (y_o - t_o)^2 / B (`t_in`, [B][4], `lw` = w_o).
+// ---------------------------------------------------------------------------
+struct GlobalX {
+    const float *x;
+    int64_t base, B;
+    __device__ __forceinline__ void operator()(int m, int k0, float *v) const {
+        const int64_t s = base + m;
+        if (s < B && k0 + 8 <= kIn) {
+            const float4 a = *reinterpret_cast<const float4 *>(x + s * kIn + k0);
+            const float4 b = *reinterpret_cast<const float4 *>(x + s * kIn + k0 + 4);
+            v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
+            v[4] = b.x; v[5] = b.y; v[6] = b.z; v[7] = b.w;
+        } else {
+#pragma unroll
+            for (int j = 0; j < 8; ++j) v[j] = 0.f;
+        }
+    }
+};
+
+constexpr int kTrainRows = 64;
+
+__global__ __launch_bounds__(256) void train_kernel(MlpDev W, const float *__restrict__ x, int64_t B,
+                                                    const float *__restrict__ t_in, const float *__restrict__ dy_in,
+                                                    float4 lw, float *__restrict__ part, float *__restrict__ loss_part) {
+    __shared__ __attribute__((aligned(16))) bf16 s_xh[kTrainRows * kInPad];
+    __shared__ __attribute__((aligned(16))) bf16 s_a1[kTrainRows * kH];
+    __shared__ __attribute__((aligned(16))) bf16 s_a2[kTrainRows * kH];
+    __shared__ __attribute__((aligned(16))) bf16 s_d1[kTrainRows * kH];
+    __shared__ __attribute__((aligned(16))) bf16 s_d2[kTrainRows * kH];
+    __shared__ float s_dy[kTrainRows][kOut];
+    __shared__ float s_loss[4];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, r = lane & 15, q = lane >> 4;
+    const int64_t base = (int64_t)blockIdx.x * kTrainRows + 16 * w;
+    Tile T;
+    GlobalX xs{x, base, B};
+    forward_tile(xs, W, s_a1 + 16 * w * kH, s_a2 + 16 * w * kH, s_xh + 16 * w * kInPad, T, lane);
+
+    // dY (rows past B contribute nothing)
+    float lsum = 0.f;
+    if (r < kOut) {
+        const float wo = r == 0 ? lw.x : (r == 1 ? lw.y : (r == 2 ? lw.z : lw.w));
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int64_t s = base + 4 * q + i;
+            float d = 0.f;
+            if (s < B) {
+                if (dy_in) {
+                    d = dy_in[s * kOut + r];
+                } else {
+                    const float e = T.y[i] - t_in[s * kOut + r];
+                    lsum += wo * e * e;
+                    d = 2.0f * wo * e / (float)B;
+                }
+            }
+            s_dy[16 * w + 4 * q + i][r] = d;
+        }
+    }
+    // wave-level loss sum
+    for (int off = 32; off > 0; off >>= 1) lsum += __shfl_down(lsum, off);
+    if (lane == 0) s_loss[w] = lsum;
+    __syncthreads();
+
+    // dA2 = dY W3 (K = 4, FP32 masters), dZ2 = dA2 * gelu'(z2)
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+        const int n = 16 * t + r;
+        const float w0 = W.w[oW3 + n], w1 = W.w[oW3 + kH + n], w2 = W.w[oW3 + 2 * kH + n], w3 = W.w[oW3 + 3 * kH + n];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const float *d = s_dy[16 * w + 4 * q + i];
+            const float da = d[0] * w0 + d[1] * w1 + d[2] * w2 + d[3] * w3;
+            s_d2[(16 * w + 4 * q + i) * kH + n] = (bf16)(da * gelu_grad(T.z2[t][i]));
+        }
+    }
+    __syncthreads();
+    // dA1 = dZ2 W2 (B operand from the transposed copy), dZ1 = dA1 * gelu'(z1)
+    {
+        floatx4 acc[8];
+#pragma unroll
+        for (int t = 0; t < 8; ++t) acc[t] = floatx4{0.f, 0.f, 0.f, 0.f};
+        const bf16 *d2 = s_d2 + 16 * w * kH;
+#pragma unroll
+        for (int s = 0; s < kH / 32; ++s) {
+            const bf16x8 a = ld8(d2 + r * kH + 32 * s + 8 * q);
+#pragma unroll
+            for (int t = 0; t < 8; ++t) acc[t] = mfma(a, ld8(W.w2tb + (16 * t + r) * kH + 32 * s + 8 * q), acc[t]);
+        }
+#pragma unroll
+        for (int t = 0; t < 8; ++t)
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+                s_d1[(16 * w + 4 * q + i) * kH + 16 * t + r] = (bf16)(acc[t][i] * gelu_grad(T.z1[t][i]));
+    }
+    __syncthreads();
+
+    // Weight gradients over the 64 rows: C[o][i] = sum_m D[m][o] S[m][i], with
+    // A[o][m] gathered from column o of D and B[m][i] from column i of S.
+    float *P = part + (int64_t)blockIdx.x * kNParam;
+    const int n_w1 = 8 * (kInPad / 16), n_w2 = 64, n_w3 = 8;
+    for (int tile = w; tile < n_w1 + n_w2 + n_w3; tile += 4) {
+        const bf16 *D, *S;
+        int sl, ot, it, obase, ostride, omax, imax;
+        if (tile < n_w1) {
+            D = s_d1; S = s_xh; sl = kInPad; ot = tile / (kInPad / 16); it = tile % (kInPad / 16);
+            obase = oW1; ostride = kIn; omax = kH; imax = kIn;
+        } else if (tile < n_w1 + n_w2) {
+            const int u = tile - n_w1;
+            D = s_d2; S = s_a1; sl = kH; ot = u / 8; it = u % 8;
+            obase = oW2; ostride = kH; omax = kH; imax = kH;
+        } else {
+            D = nullptr; S = s_a2; sl = kH; ot = 0; it = tile - n_w1 - n_w2;
+            obase = oW3; ostride = kH; omax = kOut; imax = kH;
+        }
+        floatx4 acc = floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int ks = 0; ks < kTrainRows / 32; ++ks) {
+            bf16x8 a, b;
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                const int m = 32 * ks + 8 * q + j;
+                const int o = 16 * ot + r;
+                a[j] = D ? D[m * kH + o] : (o < kOut ? (bf16)s_dy[m][o] : (bf16)0.f);
+                b[j] = S[m * sl + 16 * it + r];
+            }
+            acc = mfma(a, b, acc);
+        }
+        const int i = 16 * it + r;
+#pragma unroll
+        for (int jj = 0; jj < 4; ++jj) {
+            const int o = 16 * ot + 4 * q + jj;
+            if (o < omax && i < imax) P[obase + o * ostride + i] = acc[jj];
+        }
+    }
+    // bias gradients: column sums of dZ1, dZ2 (BF16 tiles) and dY (FP32)
+    if (threadIdx.x < kH) {
+        const int o = threadIdx.x;
+        float s1 = 0.f, s2 = 0.f;
+        for (int m = 0; m < kTrainRows; ++m) {
+            s1 += (float)s_d1[m * kH + o];
+            s2 += (float)s_d2[m * kH + o];
+        }
+        P[oB1 + o] = s1;
+        P[oB2 + o] = s2;
+    } else if (threadIdx.x < kH + kOut) {
+        const int o = threadIdx.x - kH;
+        float s3 = 0.f;
+        for (int m = 0; m < kTrainRows; ++m) s3 += s_dy[m][o];
+        P[oB3 + o] = s3;
+    }
+    if (threadIdx.x == 0) loss_part[blockIdx.x] = s_loss[0] + s_loss[1] + s_loss[2] + s_loss[3];
+}
+
+// grad[p] = sum over workgroups of part[wg][p], in workgroup order (deterministic).
+__global__ __launch_bounds__(256) void reduce_kernel(const float *__restrict__ part, int n_part,
+                                                     float *__restrict__ grad, const float *__restrict__ loss_part,
+                                                     float *__restrict__ loss_out) {
+    const int p = blockIdx.x * 256 + threadIdx.x;
+    if (p < kNParam) {
+        float s = 0.f;
+        for (int g = 0; g < n_part; ++g) s += part[(int64_t)g * kNParam + p];
+        grad[p] = s;
+    }
+    if (p == 0 && loss_out) {
+        float s = 0.f;
+        for (int g = 0; g < n_part; ++g) s += loss_part[g];
+        *loss_out = s;
+    }
+}
+
+// Refresh the BF16 operand copies of parameter p from the FP32 master.
+__device__ __forceinline__ void write_bf16_copy(int p, float v, bf16 *w1b, bf16 *w2b, bf16 *w2tb, bf16 *w3b) {
+    if (p < oB1) {
+        const int o = p / kIn, i = p % kIn;
+        w1b[o * kInPad + i] = (bf16)v;
+    } else if (p >= oW2 && p < oB2) {
+        const int o = (p - oW2) / kH, i = (p - oW2) % kH;
+        w2b[o * kH + i] = (bf16)v;
+        w2tb[i * kH + o] = (bf16)v;
+    } else if (p >= oW3 && p < oB3) {
+        const int o = (p - oW3) / kH, i = (p - oW3) % kH;
+        w3b[o * kH + i] = (bf16)v;
+    }
+}
+
+__global__ __launch_bounds__(256) void sync_copies_kernel(const float *__restrict__ w, bf16 *w1b, bf16 *w2b,
+                                                          bf16 *w2tb, bf16 *w3b) {
+    const int p = blockIdx.x * 256 + threadIdx.x;
+    if (p < kNParam) write_bf16_copy(p, w[p], w1b, w2b, w2tb, w3b);
+}
+
+// Adam (Kingma & Ba 2015) with bias correction, then the BF16 copies.
+__global__ __launch_bounds__(256) void adam_kernel(float *__restrict__ w, float *__restrict__ m, float *__restrict__ v,
+                                                   const float *__restrict__ g, float lr, float b1, float b2, float eps,
+                                                   float c1, float c2, bf16 *w1b, bf16 *w2b, bf16 *w2tb, bf16 *w3b) {
+    const int p = blockIdx.x * 256 + threadIdx.x;
+    if (p >= kNParam) return;
+    const float gp = g[p];
+    const float mp = b1 * m[p] + (1.0f - b1) * gp;
+    const float vp = b2 * v[p] + (1.0f - b2) * gp * gp;
+    m[p] = mp;
+    v[p] = vp;
+    const float wp = w[p] - lr * (mp / c1) / (sqrtf(vp / c2) + eps);
+    w[p] = wp;
+    write_bf16_copy(p, wp, w1b, w2b, w2tb, w3b);
+}
+
+// Forward only, for [B][216] inputs.
+__global__ __launch_bounds__(256) void forward_kernel(MlpDev W, const float *__restrict__ x, int64_t B,
+                                                      float *__restrict__ y) {
+    __shared__ __attribute__((aligned(16))) bf16 s_a1[64 * kH];
+    __shared__ __attribute__((aligned(16))) bf16 s_a2[64 * kH];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, r = lane & 15, q = lane >> 4;
+    const int64_t base = (int64_t)blockIdx.x * 64 + 16 * w;
+    Tile T;
+    forward_tile(GlobalX{x, base, B}, W, s_a1 + 16 * w * kH, s_a2 + 16 * w * kH, nullptr, T, lane);
+    if (r < kOut)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int64_t s = base + 4 * q + i;
+            if (s < B) y[s * kOut + r] = T.y[i];
+        }
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Handle
+// ---------------------------------------------------------------------------
+struct sgrid_mlp {
+    int device = 0;
+    float *w = nullptr, *m = nullptr, *v = nullptr, *grad = nullptr, *loss = nullptr;
+    bf16 *w1b = nullptr, *w2b = nullptr, *w2tb = nullptr, *w3b = nullptr;
+    float *part = nullptr;        // training partial gradients
+    float *loss_part = nullptr;
+    int64_t part_rows = 0;        // workgroups the partial buffers hold
+    int64_t step = 0;
+    float gate_tau = FLT_MAX;     // non-planarity threshold (mean squared residual, units of h^2)
+    float kw_lo = -0.05f, kw_hi = 1.05f;
+    uint32_t *fallback = nullptr;  // fallback cell list of the learned integrals
+    int64_t fallback_cap = 0;
+    MlpDev dev() const { return MlpDev{w, w1b, w2b, w2tb, w3b}; }
+};
 
 namespace sgrid {
 
-sgrid_status integrals_learned(const sgrid_grid *, const float *, const sgrid_mlp *, float *, uint32_t *,
-                               hipStream_t) {
-    set_error("no surrogate model support in this build");
-    return SGRID_E_STATE;
+static void free_mlp(sgrid_mlp *m) {
+    if (!m) return;
+    void *ptrs[] = {m->w, m->m, m->v, m->grad, m->loss, m->w1b, m->w2b, m->w2tb, m->w3b, m->part, m->loss_part,
+                    m->fallback};
+    for (void *p : ptrs) dev_free(p);
+    delete m;
+}
+
+static sgrid_status ensure_part(sgrid_mlp *m, int64_t rows) {
+    if (rows <= m->part_rows) return SGRID_OK;
+    dev_free(m->part);
+    dev_free(m->loss_part);
+    m->part = nullptr;
+    m->loss_part = nullptr;
+    m->part_rows = 0;
+    sgrid_status s = dev_alloc((void **)&m->part, (size_t)rows * kNParam * 4, "MLP partial gradients");
+    if (s != SGRID_OK) return s;
+    s = dev_alloc((void **)&m->loss_part, (size_t)rows * 4, "MLP partial losses");
+    if (s != SGRID_OK) return s;
+    m->part_rows = rows;
+    return SGRID_OK;
+}
+
+sgrid_status mlp_ensure_fallback(sgrid_mlp *m, int64_t cells) {
+    if (cells <= m->fallback_cap) return SGRID_OK;
+    dev_free(m->fallback);
+    m->fallback = nullptr;
+    m->fallback_cap = 0;
+    sgrid_status s = dev_alloc((void **)&m->fallback, (size_t)(cells + 1) * 4, "fallback list");
+    if (s != SGRID_OK) return s;
+    m->fallback_cap = cells;
+    return SGRID_OK;
+}
+
+static sgrid_status run_backward(sgrid_mlp *m, const float *x, int64_t B, const float *t, const float *dy,
+                                 const float lw[4], hipStream_t st) {
+    const int64_t nwg = (B + kTrainRows - 1) / kTrainRows;
+    sgrid_status s = ensure_part(m, nwg);
+    if (s != SGRID_OK) return s;
+    hipLaunchKernelGGL(train_kernel, dim3((unsigned)nwg), dim3(256), 0, st, m->dev(), x, B, t, dy,
+                       make_float4(lw[0], lw[1], lw[2], lw[3]), m->part, m->loss_part);
+    SG_CHECK_LAUNCH("MLP train kernel");
+    hipLaunchKernelGGL(reduce_kernel, dim3((kNParam + 255) / 256), dim3(256), 0, st, m->part, (int)nwg, m->grad,
+                       m->loss_part, m->loss);
+    SG_CHECK_LAUNCH("MLP gradient reduction");
+    return SGRID_OK;
 }
 
 }  // namespace sgrid
+
+extern "C" sgrid_status sgrid_mlp_create(const float *params_host, sgrid_mlp **out) {
+    sgrid::clear_error();
+    SG_REQUIRE(out != nullptr, "out is NULL");
+    *out = nullptr;
+    SG_REQUIRE(params_host != nullptr, "params is NULL");
+    sgrid_mlp *m = new sgrid_mlp();
+    SG_CHECK_HIP(hipGetDevice(&m->device));
+    struct A { void **p; size_t bytes; };
+    A allocs[] = {{(void **)&m->w, kNParam * 4}, {(void **)&m->m, kNParam * 4}, {(void **)&m->v, kNParam * 4},
+                  {(void **)&m->grad, kNParam * 4}, {(void **)&m->loss, 4},
+                  {(void **)&m->w1b, kH * kInPad * 2}, {(void **)&m->w2b, kH * kH * 2},
+                  {(void **)&m->w2tb, kH * kH * 2}, {(void **)&m->w3b, 16 * kH * 2}};
+    for (auto &a : allocs) {
+        sgrid_status s = sgrid::dev_alloc(a.p, a.bytes, "MLP parameters");
+        if (s != SGRID_OK) { sgrid::free_mlp(m); return s; }
+    }
+    hipError_t e = hipSuccess;
+    if (e == hipSuccess) e = hipMemcpy(m->w, params_host, kNParam * 4, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemset(m->m, 0, kNParam * 4);
+    if (e == hipSuccess) e = hipMemset(m->v, 0, kNParam * 4);
+    if (e == hipSuccess) e = hipMemset(m->w1b, 0, kH * kInPad * 2);
+    if (e == hipSuccess) e = hipMemset(m->w3b, 0, 16 * kH * 2);
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(sync_copies_kernel, dim3((kNParam + 255) / 256), dim3(256), 0, nullptr, m->w, m->w1b,
+                           m->w2b, m->w2tb, m->w3b);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    if (e != hipSuccess) {
+        sgrid::set_error("MLP setup failed: %s", hipGetErrorString(e));
+        sgrid::free_mlp(m);
+        return SGRID_E_HIP;
+    }
+    *out = m;
+    return SGRID_OK;
+}
+
+extern "C" sgrid_status sgrid_mlp_destroy(sgrid_mlp *m) {
+    sgrid::clear_error();
+    if (!m) return SGRID_OK;
+    hipError_t e = hipDeviceSynchronize();
+    sgrid::free_mlp(m);
+    if (e != hipSuccess) {
+        sgrid::set_error("hipDeviceSynchronize before destroy failed: %s", hipGetErrorString(e));
+        return SGRID_E_HIP;
+    }
+    return SGRID_OK;
+}
+
+extern "C" sgrid_status sgrid_mlp_get_params(const sgrid_mlp *m, float *params_host, float *adam_m_host,
+                                             float *adam_v_host, int64_t *step) {
+    sgrid::clear_error();
+    SG_REQUIRE(m != nullptr, "model is NULL");
+    SG_CHECK_HIP(hipDeviceSynchronize());
+    if (params_host) SG_CHECK_HIP(hipMemcpy(params_host, m->w, kNParam * 4, hipMemcpyDeviceToHost));
+    if (adam_m_host) SG_CHECK_HIP(hipMemcpy(adam_m_host, m->m, kNParam * 4, hipMemcpyDeviceToHost));
+    if (adam_v_host) SG_CHECK_HIP(hipMemcpy(adam_v_host, m->v, kNParam * 4, hipMemcpyDeviceToHost));
+    if (step) *step = m->step;
+    return SGRID_OK;
+}
+
+extern "C" sgrid_status sgrid_mlp_set_state(sgrid_mlp *m, const float *adam_m_host, const float *adam_v_host,
+                                            int64_t step) {
+    sgrid::clear_error();
+    SG_REQUIRE(m != nullptr && adam_m_host != nullptr && adam_v_host != nullptr, "NULL argument");
+    SG_REQUIRE(step >= 0, "step must be >= 0");
+    SG_CHECK_HIP(hipDeviceSynchronize());
+    SG_CHECK_HIP(hipMemcpy(m->m, adam_m_host, kNParam * 4, hipMemcpyHostToDevice));
+    SG_CHECK_HIP(hipMemcpy(m->v, adam_v_host, kNParam * 4, hipMemcpyHostToDevice));
+    m->step = step;
+    return SGRID_OK;
+}
+
+extern "C" sgrid_status sgrid_mlp_set_gate(sgrid_mlp *m, float tau, float kw_lo, float kw_hi) {
+    sgrid::clear_error();
+    SG_REQUIRE(m != nullptr, "model is NULL");
+    SG_REQUIRE(tau >= 0.f && kw_lo <= kw_hi, "gate needs tau >= 0 and kw_lo <= kw_hi");
+    m->gate_tau = tau;
+    m->kw_lo = kw_lo;
+    m->kw_hi = kw_hi;
+    return SGRID_OK;
+}
+
+extern "C" sgrid_status sgrid_mlp_forward(const sgrid_mlp *m, const float *x, int64_t B, float *y, void *stream) {
+    sgrid::clear_error();
+    SG_REQUIRE(m != nullptr, "model is NULL");
+    SG_REQUIRE(B >= 0, "B must be >= 0");
+    if (B == 0) return SGRID_OK;
+    SG_REQUIRE(x && y && sg_aligned(x, 16) && sg_aligned(y, 16), "x / y NULL or not 16-byte aligned");
+    const int64_t nwg = (B + 63) / 64;
+    SG_REQUIRE(nwg <= kMaxGrid, "batch too large");
+    hipLaunchKernelGGL(forward_kernel, dim3((unsigned)nwg), dim3(256), 0, sg_stream(stream), m->dev(), x, B, y);
+    SG_CHECK_LAUNCH("MLP forward");
+    return SGRID_OK;
+}
+
+extern "C" sgrid_status sgrid_mlp_backward(sgrid_mlp *m, const float *x, const float *dy, int64_t B, float *grad,
+                                           void *stream) {
+    sgrid::clear_error();
+    SG_REQUIRE(m != nullptr, "model is NULL");
+    SG_REQUIRE(B >= 1, "B must be >= 1");
+    SG_REQUIRE(x && dy && grad && sg_aligned(x, 16) && sg_aligned(dy, 16) && sg_aligned(grad, 4),
+               "x / dy / grad NULL or misaligned");
+    hipStream_t st = sg_stream(stream);
+    const float lw[4] = {0, 0, 0, 0};
+    sgrid_status s = sgrid::run_backward(m, x, B, nullptr, dy, lw, st);
+    if (s != SGRID_OK) return s;
+    SG_CHECK_HIP(hipMemcpyAsync(grad, m->grad, kNParam * 4, hipMemcpyDeviceToDevice, st));
+    return SGRID_OK;
+}
+
+extern "C" sgrid_status sgrid_mlp_train_step(sgrid_mlp *m, const float *x, const float *t, int64_t B,
+                                             const float *loss_weights, float lr, float *loss_dev, void *stream) {
+    sgrid::clear_error();
+    SG_REQUIRE(m != nullptr, "model is NULL");
+    SG_REQUIRE(B >= 1, "B must be >= 1");
+    SG_REQUIRE(x && t && loss_weights && sg_aligned(x, 16) && sg_aligned(t, 16), "x / t / weights NULL or misaligned");
+    SG_REQUIRE(lr >= 0.f, "lr must be >= 0");
+    hipStream_t st = sg_stream(stream);
+    sgrid_status s = sgrid::run_backward(m, x, B, t, nullptr, loss_weights, st);
+    if (s != SGRID_OK) return s;
+    m->step += 1;
+    const double b1 = 0.9, b2 = 0.999;
+    const float c1 = (float)(1.0 - pow(b1, (double)m->step)), c2 = (float)(1.0 - pow(b2, (double)m->step));
+    hipLaunchKernelGGL(adam_kernel, dim3((kNParam + 255) / 256), dim3(256), 0, st, m->w, m->m, m->v, m->grad, lr,
+                       (float)b1, (float)b2, 1e-8f, c1, c2, m->w1b, m->w2b, m->w2tb, m->w3b);
+    SG_CHECK_LAUNCH("Adam");
+    if (loss_dev) SG_CHECK_HIP(hipMemcpyAsync(loss_dev, m->loss, 4, hipMemcpyDeviceToDevice, st));
+    return SGRID_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Learned near-surface integrals with gate and plain fallback
+// ---------------------------------------------------------------------------
+namespace {
+
+constexpr int kWin = 9, kWinN = 729;   // phi window of a package, local -2..6
+constexpr int kVol = 7, kVolN = 343;   // points -1..5 whose cut fraction a tap may use
+
+// Stages the 9^3 phi window of core package p into LDS (all threads of the block).
+__device__ __forceinline__ void stage_window(const float *__restrict__ phi, const uint32_t *__restrict__ nbr,
+                                             int64_t p, float *s_phi, uint32_t *s_ids) {
+    if (threadIdx.x < 27) s_ids[threadIdx.x] = nbr[p * 27 + threadIdx.x];
+    __syncthreads();
+    for (int v = threadIdx.x; v < kWinN; v += blockDim.x) {
+        const int x = v % kWin - 2, y = (v / kWin) % kWin - 2, z = v / (kWin * kWin) - 2;
+        const int kx = (x + 4) >> 2, ky = (y + 4) >> 2, kz = (z + 4) >> 2;
+        const int d = (x + 4 - 4 * kx) + 4 * (y + 4 - 4 * ky) + 16 * (z + 4 - 4 * kz);
+        s_phi[v] = phi[(int64_t)s_ids[kx + 3 * ky + 9 * kz] * 64 + d];
+    }
+    __syncthreads();
+}
+
+// Network input of cell c (local index i + 4j + 16k) from the staged window.
+struct WindowX {
+    const float *f;
+    int cell0;
+    float inv_h;
+    __device__ __forceinline__ void operator()(int m, int k0, float *v) const {
+        const int c = cell0 + m;
+        const int i = c & 3, j = (c >> 2) & 3, k = c >> 4;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const int kk = k0 + e;
+            if (kk < kIn) {
+                const int ox = kk % 6, oy = (kk / 6) % 6, oz = kk / 36;   // offset + 2
+                v[e] = f[(i + ox) + kWin * ((j + oy) + kWin * (k + oz))] * inv_h;
+            } else {
+                v[e] = 0.f;
+            }
+        }
+    }
+};
+
+// Saturation of the cut fraction at the 7^3 tap points: bit 0 = V in {0, 1}
+// (|phi/h| >= |g|_1 / 2 with phi != 0), bit 1 = phi > 0.
+__device__ __forceinline__ void saturation_flags(const float *f, float inv_h, float inv_2h, uint8_t *s_sat) {
+    for (int v = threadIdx.x; v < kVolN; v += blockDim.x) {
+        const int x = v % kVol + 1, y = (v / kVol) % kVol + 1, z = v / (kVol * kVol) + 1;
+        const int c = x + kWin * (y + kWin * z);
+        const float gx = (f[c + 1] - f[c - 1]) * inv_2h;
+        const float gy = (f[c + kWin] - f[c - kWin]) * inv_2h;
+        const float gz = (f[c + kWin * kWin] - f[c - kWin * kWin]) * inv_2h;
+        const float a = f[c] * inv_h;
+        const bool sat = a != 0.f && fabsf(a) >= 0.5f * (fabsf(gx) + fabsf(gy) + fabsf(gz));
+        s_sat[v] = (uint8_t)((sat ? 1 : 0) | (a > 0.f ? 2 : 0));
+    }
+}
+
+struct Taps {
+    float Wn, Wf, Dn, Df;
+};
+
+__device__ __forceinline__ Taps make_taps() {
+    return Taps{(float)sgrid::wendland_u(sqrt(0.75)), (float)sgrid::wendland_u(sqrt(2.75)),
+                (float)sgrid::wendland_dr_over_r_u(sqrt(0.75)), (float)sgrid::wendland_dr_over_r_u(sqrt(2.75))};
+}
+
+__global__ __launch_bounds__(256) void zero_u32_kernel(uint32_t *p) { *p = 0u; }
+
+__global__ __launch_bounds__(256) void learned_kernel(MlpDev W, const float *__restrict__ phi,
+                                                      const uint32_t *__restrict__ nbr,
+                                                      const uint32_t *__restrict__ core_list, int64_t n_core,
+                                                      float inv_h, float inv_2h, float tau, float kw_lo, float kw_hi,
+                                                      float *__restrict__ out, uint32_t *__restrict__ fb_list,
+                                                      uint32_t *__restrict__ fb_count) {
+    __shared__ float s_phi[kWinN];
+    __shared__ uint32_t s_ids[27];
+    __shared__ uint8_t s_sat[kVolN];
+    __shared__ __attribute__((aligned(16))) bf16 s_a1[64 * kH];
+    __shared__ __attribute__((aligned(16))) bf16 s_a2[64 * kH];
+    __shared__ float s_y[64][kOut];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, r = lane & 15, q = lane >> 4;
+    const int64_t ci = blockIdx.x;
+    const int64_t p = core_list[ci];
+    stage_window(phi, nbr, p, s_phi, s_ids);
+    saturation_flags(s_phi, inv_h, inv_2h, s_sat);
+    Tile T;
+    forward_tile(WindowX{s_phi, 16 * w, inv_h}, W, s_a1 + 16 * w * kH, s_a2 + 16 * w * kH, nullptr, T, lane);
+    if (r < kOut)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) s_y[16 * w + 4 * q + i][r] = T.y[i];
+    __syncthreads();
+    if (threadIdx.x >= 64) return;
+    const int c = threadIdx.x;
+    const int i = c & 3, j = (c >> 2) & 3, k = c >> 4;
+    const int64_t o = ci * 64 + c, stride = n_core * 64;
+    // saturated cells: every tap fraction is 0 or 1, the sum is exact
+    bool sat = true;
+    float kw = 0.f, kx = 0.f, ky = 0.f, kz = 0.f;
+    const Taps tp = make_taps();
+    for (int oz = -1; oz <= 2; ++oz)
+        for (int oy = -1; oy <= 2; ++oy)
+            for (int ox = -1; ox <= 2; ++ox) {
+                const float dx = 0.5f - ox, dy = 0.5f - oy, dz = 0.5f - oz;
+                const float r2 = dx * dx + dy * dy + dz * dz;
+                if (r2 >= 4.0f) continue;
+                const uint8_t f = s_sat[(i + ox + 1) + kVol * ((j + oy + 1) + kVol * (k + oz + 1))];
+                sat = sat && (f & 1);
+                const float vv = (f & 2) ? 1.f : 0.f;
+                const bool nearp = r2 < 1.0f;
+                const float Wt = nearp ? tp.Wn : tp.Wf, Dt = nearp ? tp.Dn : tp.Df;
+                kw += Wt * vv;
+                kx += Dt * dx * vv;
+                ky += Dt * dy * vv;
+                kz += Dt * dz * vv;
+            }
+    if (!sat) {
+        // non-planarity: mean squared residual of the window after its
+        // least-squares affine fit (the affine basis is orthogonal on the window)
+        const float *f = s_phi;
+        float s0 = 0.f, sx = 0.f, sy = 0.f, sz = 0.f;
+        for (int e = 0; e < kIn; ++e) {
+            const int ex = e % 6, ey = (e / 6) % 6, ez = e / 36;
+            const float v = f[(i + ex) + kWin * ((j + ey) + kWin * (k + ez))] * inv_h;
+            s0 += v;
+            sx += (ex - 2.5f) * v;
+            sy += (ey - 2.5f) * v;
+            sz += (ez - 2.5f) * v;
+        }
+        const float c0 = s0 / 216.f, cx = sx / 630.f, cy = sy / 630.f, cz = sz / 630.f;
+        float res = 0.f;
+        for (int e = 0; e < kIn; ++e) {
+            const int ex = e % 6, ey = (e / 6) % 6, ez = e / 36;
+            const float v = f[(i + ex) + kWin * ((j + ey) + kWin * (k + ez))] * inv_h;
+            const float d = v - c0 - cx * (ex - 2.5f) - cy * (ey - 2.5f) - cz * (ez - 2.5f);
+            res += d * d;
+        }
+        res *= 1.0f / 216.f;
+        const float y0 = s_y[c][0];
+        if (res <= tau && y0 >= kw_lo && y0 <= kw_hi) {
+            kw = y0;
+            kx = s_y[c][1];
+            ky = s_y[c][2];
+            kz = s_y[c][3];
+        } else {
+            fb_list[atomicAdd(fb_count, 1u)] = (uint32_t)o;
+            return;
+        }
+    }
+    out[o] = kw;
+    out[stride + o] = kx;
+    out[2 * stride + o] = ky;
+    out[3 * stride + o] = kz;
+}
+
+// Plain integral of single cells (the fallback): the 32 taps of the cell's
+// dual-cell query, each with its own cut fraction from central differences,
+// in the same arithmetic and summation order as the plain package kernel.
+__global__ __launch_bounds__(256) void fallback_kernel(const float *__restrict__ phi, const uint32_t *__restrict__ nbr,
+                                                       const uint32_t *__restrict__ core_list, int64_t n_core,
+                                                       float inv_h, float inv_2h, const uint32_t *__restrict__ fb_list,
+                                                       const uint32_t *__restrict__ fb_count, float *__restrict__ out) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (int64_t)*fb_count) return;
+    const int64_t o = fb_list[t];
+    const int64_t ci = o / 64;
+    const int c = (int)(o % 64);
+    const int i = c & 3, j = (c >> 2) & 3, k = c >> 4;
+    const uint32_t *row = nbr + (int64_t)core_list[ci] * 27;
+    auto at = [&](int x, int y, int z) -> float {   // local shift in [-2, 6] per axis
+        const int kx = (x + 4) >> 2, ky = (y + 4) >> 2, kz = (z + 4) >> 2;
+        const int d = (x + 4 - 4 * kx) + 4 * (y + 4 - 4 * ky) + 16 * (z + 4 - 4 * kz);
+        return phi[(int64_t)row[kx + 3 * ky + 9 * kz] * 64 + d];
+    };
+    const Taps tp = make_taps();
+    float kw = 0.f, kx = 0.f, ky = 0.f, kz = 0.f;
+    for (int oz = -1; oz <= 2; ++oz)
+        for (int oy = -1; oy <= 2; ++oy)
+            for (int ox = -1; ox <= 2; ++ox) {
+                const float dx = 0.5f - ox, dy = 0.5f - oy, dz = 0.5f - oz;
+                const float r2 = dx * dx + dy * dy + dz * dz;
+                if (r2 >= 4.0f) continue;
+                const int x = i + ox, y = j + oy, z = k + oz;
+                const float gx = (at(x + 1, y, z) - at(x - 1, y, z)) * inv_2h;
+                const float gy = (at(x, y + 1, z) - at(x, y - 1, z)) * inv_2h;
+                const float gz = (at(x, y, z + 1) - at(x, y, z - 1)) * inv_2h;
+                const float vv = sgrid::plane_cube_fraction(at(x, y, z) * inv_h, gx, gy, gz);
+                const bool nearp = r2 < 1.0f;
+                const float Wt = nearp ? tp.Wn : tp.Wf, Dt = nearp ? tp.Dn : tp.Df;
+                kw += Wt * vv;
+                kx += Dt * dx * vv;
+                ky += Dt * dy * vv;
+                kz += Dt * dz * vv;
+            }
+    const int64_t stride = n_core * 64;
+    out[o] = kw;
+    out[stride + o] = kx;
+    out[2 * stride + o] = ky;
+    out[3 * stride + o] = kz;
+}
+
+// Network inputs (windows of phi / h) and saturation of every core point, in
+// the output order of the integrals.  unsat[o] = 1 when some tap fraction lies
+// strictly between 0 and 1.
+__global__ __launch_bounds__(256) void gather_windows_kernel(const float *__restrict__ phi,
+                                                             const uint32_t *__restrict__ nbr,
+                                                             const uint32_t *__restrict__ core_list, float inv_h,
+                                                             float inv_2h, float *__restrict__ x,
+                                                             uint8_t *__restrict__ unsat) {
+    __shared__ float s_phi[kWinN];
+    __shared__ uint32_t s_ids[27];
+    __shared__ uint8_t s_sat[kVolN];
+    const int64_t ci = blockIdx.x;
+    stage_window(phi, nbr, core_list[ci], s_phi, s_ids);
+    saturation_flags(s_phi, inv_h, inv_2h, s_sat);
+    __syncthreads();
+    if (x) {
+        for (int e = threadIdx.x; e < 64 * kIn; e += blockDim.x) {
+            const int c = e / kIn, kk = e % kIn;
+            const int i = c & 3, j = (c >> 2) & 3, k = c >> 4;
+            const int ox = kk % 6, oy = (kk / 6) % 6, oz = kk / 36;
+            x[(ci * 64 + c) * kIn + kk] = s_phi[(i + ox) + kWin * ((j + oy) + kWin * (k + oz))] * inv_h;
+        }
+    }
+    if (unsat && threadIdx.x < 64) {
+        const int c = threadIdx.x;
+        const int i = c & 3, j = (c >> 2) & 3, k = c >> 4;
+        bool all = true;
+        for (int oz = -1; oz <= 2; ++oz)
+            for (int oy = -1; oy <= 2; ++oy)
+                for (int ox = -1; ox <= 2; ++ox) {
+                    const float dx = 0.5f - ox, dy = 0.5f - oy, dz = 0.5f - oz;
+                    if (dx * dx + dy * dy + dz * dz >= 4.0f) continue;
+                    all = all && (s_sat[(i + ox + 1) + kVol * ((j + oy + 1) + kVol * (k + oz + 1))] & 1);
+                }
+        unsat[ci * 64 + c] = all ? 0 : 1;
+    }
+}
+
+}  // namespace
+
+namespace sgrid {
+
+sgrid_status integrals_learned(const sgrid_grid *g, const float *phi, const sgrid_mlp *model_c, float *out,
+                               uint32_t *n_fallback, hipStream_t st) {
+    sgrid_mlp *m = const_cast<sgrid_mlp *>(model_c);
+    const int64_t cells = g->n_core * 64;
+    sgrid_status s = mlp_ensure_fallback(m, cells);
+    if (s != SGRID_OK) return s;
+    uint32_t *count = n_fallback ? n_fallback : m->fallback + m->fallback_cap;
+    hipLaunchKernelGGL(zero_u32_kernel, dim3(1), dim3(1), 0, st, count);
+    SG_CHECK_LAUNCH("fallback counter reset");
+    if (g->n_core == 0) return SGRID_OK;
+    SG_REQUIRE(g->n_core <= kMaxGrid, "too many core packages");
+    const float inv_h = (float)(1.0 / g->h), inv_2h = (float)(0.5 / g->h);
+    hipLaunchKernelGGL(learned_kernel, dim3((unsigned)g->n_core), dim3(256), 0, st, m->dev(), phi, g->nbr,
+                       g->core_list, g->n_core, inv_h, inv_2h, m->gate_tau, m->kw_lo, m->kw_hi, out, m->fallback,
+                       count);
+    SG_CHECK_LAUNCH("learned integrals");
+    hipLaunchKernelGGL(fallback_kernel, dim3((unsigned)((cells + 255) / 256)), dim3(256), 0, st, phi, g->nbr,
+                       g->core_list, g->n_core, inv_h, inv_2h, m->fallback, count, out);
+    SG_CHECK_LAUNCH("fallback integrals");
+    return SGRID_OK;
+}
+
+}  // namespace sgrid
+
+extern "C" sgrid_status sgrid_gather_windows(const sgrid_grid *g, const float *phi, float *x_dev, uint8_t *unsat_dev,
+                                             void *stream) {
+    sgrid::clear_error();
+    SG_REQUIRE(g != nullptr && phi != nullptr, "grid or phi is NULL");
+    SG_REQUIRE(sg_aligned(phi, 16) && sg_aligned(x_dev, 4), "phi / x misaligned");
+    if (g->n_core == 0) return SGRID_OK;
+    SG_REQUIRE(g->n_core <= kMaxGrid, "too many core packages");
+    hipLaunchKernelGGL(gather_windows_kernel, dim3((unsigned)g->n_core), dim3(256), 0, sg_stream(stream), phi, g->nbr,
+                       g->core_list, (float)(1.0 / g->h), (float)(0.5 / g->h), x_dev, unsat_dev);
+    SG_CHECK_LAUNCH("gather windows");
+    return SGRID_OK;
+}
