@@ -232,6 +232,45 @@ sgrid_status sgrid_mlp_train_step(sgrid_mlp *model, const float *x_dev, const fl
 sgrid_status sgrid_gather_windows(const sgrid_grid *grid, const float *phi_dev, float *x_dev,
                                   uint8_t *unsat_dev, void *stream);
 
+/* ------------------------------------------------------------------------
+ * Batched reinitialisation of many grids (shapes of uneven size) in one
+ * persistent launch per iteration over a global package worklist, with the
+ * iteration loop replayable as a HIP graph (not in the paper).
+ *
+ * The fields of the batch are the grids' [P_s + 2][64] FP32 arrays
+ * concatenated in the order given: grid s starts at package row base_s
+ * (sgrid_batch_info), its far-field rows first.  Each grid's result is
+ * bit-identical to sgrid_reinitialize on that grid alone.
+ * ------------------------------------------------------------------------ */
+
+/* Builds the rebased face tables and the worklist of `n` grids (the grids
+ * must stay alive while the batch is used).  Synchronises `stream`. */
+sgrid_status sgrid_batch_create(const sgrid_grid *const *grids, int32_t n, void *stream, sgrid_batch **out);
+sgrid_status sgrid_batch_destroy(sgrid_batch *batch);
+
+/* Total package rows of the concatenated fields, worklist length, and the
+ * first row of every grid (bases_host [n], nullable). */
+sgrid_status sgrid_batch_info(const sgrid_batch *batch, int64_t *n_total, int64_t *n_work,
+                              int64_t *bases_host);
+
+/* Kernel choice: variant 0 = DPP lane exchange, 1 = LDS tile; workgroups per
+ * compute unit of the persistent launch (1..16). */
+sgrid_status sgrid_batch_set_config(sgrid_batch *batch, int32_t variant, int32_t blocks_per_cu);
+
+/* Times every (variant, workgroups per CU in {1, 2, 4, 8, 16}) candidate with
+ * `reps` sweeps that read phi_dev and write scratch_dev (phi is not
+ * modified), keeps the fastest as the batch's configuration and returns it;
+ * us_table [2][5] (nullable) receives the microseconds per sweep. */
+sgrid_status sgrid_batch_autotune(sgrid_batch *batch, const float *phi_dev, float *scratch_dev, int32_t reps,
+                                  void *stream, int32_t *variant_out, int32_t *blocks_per_cu_out,
+                                  float *us_table);
+
+/* n_iter sweeps of the upwind reinitialisation over every grid of the batch;
+ * with use_graph the iteration loop is captured once per (buffers, n_iter,
+ * configuration) and replayed as a HIP graph.  The result is left in phi. */
+sgrid_status sgrid_batch_reinitialize(sgrid_batch *batch, float *phi_dev, float *scratch_dev, int32_t n_iter,
+                                      int32_t use_graph, void *stream);
+
 /*
  * Tuning knob for sgrid_reinitialize: sweep variant 0 exchanges the interior
  * neighbours between lanes (DPP row shifts), variant 1 stages each package

@@ -19,7 +19,7 @@ import torch
 __all__ = [
     "SgridError", "Grid", "load", "build_packages", "fill_far_field", "reinitialize",
     "compute_gradient", "compute_gradient_packed", "probe_particles", "probe_particles_packed", "compute_near_surface_integrals", "set_sweep_config",
-    "Mlp", "gather_windows", "MLP_N_PARAMS",
+    "Mlp", "gather_windows", "MLP_N_PARAMS", "Batch",
     "LIB_PATH", "FAR_FIELD_IN_H",
 ]
 
@@ -68,6 +68,13 @@ _SIGNATURES = {
     "sgrid_mlp_backward": (ctypes.c_int, [_P, _P, _P, ctypes.c_int64, _P, _P]),
     "sgrid_mlp_train_step": (ctypes.c_int, [_P, _P, _P, ctypes.c_int64, _P, ctypes.c_float, _P, _P]),
     "sgrid_gather_windows": (ctypes.c_int, [_P, _P, _P, _P, _P]),
+    "sgrid_batch_create": (ctypes.c_int, [_P, ctypes.c_int32, _P, ctypes.POINTER(_P)]),
+    "sgrid_batch_destroy": (ctypes.c_int, [_P]),
+    "sgrid_batch_info": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64), _P]),
+    "sgrid_batch_set_config": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int32]),
+    "sgrid_batch_autotune": (ctypes.c_int, [_P, _P, _P, ctypes.c_int32, _P, ctypes.POINTER(ctypes.c_int32),
+                                            ctypes.POINTER(ctypes.c_int32), _P]),
+    "sgrid_batch_reinitialize": (ctypes.c_int, [_P, _P, _P, ctypes.c_int32, ctypes.c_int32, _P]),
 }
 
 
@@ -355,6 +362,59 @@ def gather_windows(grid: Grid, phi: torch.Tensor, x: Optional[torch.Tensor] = No
         raise ValueError("unsat must be [n_core*64] uint8")
     _check(load().sgrid_gather_windows(grid.handle, _dev(phi, "phi"), _dev(x, "x") if x is not None else None,
                                        _dev(unsat, "unsat") if unsat is not None else None, _stream(stream)))
+
+
+class Batch:
+    """Many grids swept together; fields are the grids' fields concatenated."""
+
+    def __init__(self, grids, stream=None):
+        import numpy as np
+        self.grids = list(grids)
+        arr = (_P * len(self.grids))(*[g.handle for g in self.grids])
+        out = ctypes.c_void_p()
+        _check(load().sgrid_batch_create(arr, len(self.grids), _stream(stream), ctypes.byref(out)))
+        self._h = out
+        nt, nw = ctypes.c_int64(), ctypes.c_int64()
+        bases = np.zeros(len(self.grids), dtype=np.int64)
+        _check(load().sgrid_batch_info(self._h, ctypes.byref(nt), ctypes.byref(nw), bases.ctypes.data_as(_P)))
+        self.n_total, self.n_work, self.bases = int(nt.value), int(nw.value), bases
+
+    @property
+    def handle(self):
+        if self._h is None:
+            raise SgridError(5, "batch already destroyed")
+        return self._h
+
+    def destroy(self):
+        if getattr(self, "_h", None) is not None:
+            _check(load().sgrid_batch_destroy(self._h))
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+    def set_config(self, variant: int, blocks_per_cu: int):
+        _check(load().sgrid_batch_set_config(self.handle, int(variant), int(blocks_per_cu)))
+
+    def autotune(self, phi: torch.Tensor, scratch: torch.Tensor, reps: int = 10, stream=None):
+        """Returns (variant, blocks_per_cu, table[2][5] of us per sweep)."""
+        import numpy as np
+        v, b = ctypes.c_int32(), ctypes.c_int32()
+        table = np.zeros(10, dtype=np.float32)
+        _check(load().sgrid_batch_autotune(self.handle, _dev(phi, "phi"), _dev(scratch, "scratch"), int(reps),
+                                           _stream(stream), ctypes.byref(v), ctypes.byref(b),
+                                           table.ctypes.data_as(_P)))
+        return int(v.value), int(b.value), table.reshape(2, 5)
+
+    def reinitialize(self, phi: torch.Tensor, scratch: torch.Tensor, n_iter: int, use_graph: bool = True,
+                     stream=None):
+        if phi.numel() != self.n_total * 64 or scratch.numel() != phi.numel() or phi.dtype != torch.float32:
+            raise ValueError("phi and scratch must be [n_total, 64] float32")
+        _check(load().sgrid_batch_reinitialize(self.handle, _dev(phi, "phi"), _dev(scratch, "scratch"),
+                                               int(n_iter), int(bool(use_graph)), _stream(stream)))
 
 
 def set_sweep_config(variant: int, groups: int):

@@ -1,0 +1,481 @@
+// Batched reinitialisation: many grids (shapes of uneven size) swept by one
+// persistent launch per iteration over a global package worklist, the
+// iteration loop replayed as a HIP graph, and an autotuner that times the
+// candidate kernels on the caller's data.
+//
+// Layout: the fields of all grids are concatenated, grid s occupying package
+// ids [base_s, base_s + P_s + 2) (its two far-field rows first).  The batch
+// keeps a face table rebased to these global ids, whose row for package g is
+// (-x, +x, -y, +y, -z, +z, g, s): the last pad holds the grid index, which
+// selects that grid's (h^2, 1/h, h/2) in a small parameter table.  The
+// worklist lists the activated packages of every grid; each wavefront of the
+// persistent kernel walks a contiguous range of it, four packages at a time.
+//
+// The per-point update is the same function as the single-grid sweep with the
+// same per-grid constants, so every grid's result is bit-identical to its own
+// sgrid_reinitialize.
+#include <string.h>
+
+#include <vector>
+
+#include "common.hpp"
+
+namespace sgrid {
+template <typename T>
+struct SweepParams {
+    T h2, inv_h, dt;
+};
+}  // namespace sgrid
+
+namespace {
+
+template <typename T>
+struct Row4 { T v[4]; };
+
+__device__ __forceinline__ Row4<float> ld_row(const float *__restrict__ p) {
+    const float4 a = *reinterpret_cast<const float4 *>(p);
+    return Row4<float>{{a.x, a.y, a.z, a.w}};
+}
+__device__ __forceinline__ void st_row(float *__restrict__ p, const Row4<float> &r) {
+    *reinterpret_cast<float4 *>(p) = make_float4(r.v[0], r.v[1], r.v[2], r.v[3]);
+}
+
+// Same arithmetic as the single-grid sweep (FP32).
+__device__ __forceinline__ float upwind(float p0, float xm, float xp, float ym, float yp, float zm, float zp, float h2,
+                                        float inv_h, float dt) {
+    const float S = p0 * __builtin_amdgcn_rsqf(p0 * p0 + h2);
+    const float sg = S > 0.f ? 1.f : -1.f;
+    const float ax = fmaxf(fmaxf(sg * (p0 - xm), sg * (p0 - xp)), 0.f);
+    const float ay = fmaxf(fmaxf(sg * (p0 - ym), sg * (p0 - yp)), 0.f);
+    const float az = fmaxf(fmaxf(sg * (p0 - zm), sg * (p0 - zp)), 0.f);
+    const float G = __builtin_amdgcn_sqrtf(ax * ax + ay * ay + az * az) * inv_h;
+    return p0 - dt * S * (G - 1.f);
+}
+
+struct Halo {
+    Row4<float> c, yh, zh;
+    float xm, xp;
+};
+
+__device__ __forceinline__ void batch_loads(const float *__restrict__ src, const uint32_t *__restrict__ face,
+                                            int64_t g, int r, Halo &l, uint32_t &shape) {
+    const int j = r & 3, k = r >> 2;
+    const uint4 f0 = *reinterpret_cast<const uint4 *>(face + g * 8);
+    const uint4 f1 = *reinterpret_cast<const uint4 *>(face + g * 8 + 4);
+    shape = f1.w;
+    l.c = ld_row(src + g * 64 + r * 4);
+    l.xm = src[(int64_t)f0.x * 64 + r * 4 + 3];
+    l.xp = src[(int64_t)f0.y * 64 + r * 4];
+    if (j == 0 || j == 3) {
+        const uint32_t fy = j == 0 ? f0.z : f0.w;
+        l.yh = ld_row(src + (int64_t)fy * 64 + (j == 0 ? 3 + 4 * k : 4 * k) * 4);
+    }
+    if (k == 0 || k == 3) {
+        const uint32_t fz = k == 0 ? f1.x : f1.y;
+        l.zh = ld_row(src + (int64_t)fz * 64 + (k == 0 ? j + 12 : j) * 4);
+    }
+}
+
+__device__ __forceinline__ float row_shr1(float v) { return row_move<kRowShr1>(v); }
+__device__ __forceinline__ float row_shl1(float v) { return row_move<kRowShl1>(v); }
+__device__ __forceinline__ float row_shr4(float v) { return row_move<kRowShr4>(v); }
+__device__ __forceinline__ float row_shl4(float v) { return row_move<kRowShl4>(v); }
+
+__device__ __forceinline__ Row4<float> update_row_dpp(int r, const Halo &l, const sgrid::SweepParams<float> &sp) {
+    const int j = r & 3, k = r >> 2;
+    Row4<float> o;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const float v = l.c.v[i];
+        const float a = row_shr1(v), b = row_shl1(v), c = row_shr4(v), d = row_shl4(v);
+        const float ym = j == 0 ? l.yh.v[i] : a;
+        const float yp = j == 3 ? l.yh.v[i] : b;
+        const float zm = k == 0 ? l.zh.v[i] : c;
+        const float zp = k == 3 ? l.zh.v[i] : d;
+        const float xm = i > 0 ? l.c.v[i - 1] : l.xm;
+        const float xp = i < 3 ? l.c.v[i + 1] : l.xp;
+        o.v[i] = upwind(v, xm, xp, ym, yp, zm, zp, sp.h2, sp.inv_h, sp.dt);
+    }
+    return o;
+}
+
+// Persistent worklist sweep, DPP exchange.  Wavefront w processes the sets
+// [w * spw, (w + 1) * spw) of four worklist entries.
+__global__ __launch_bounds__(256) void batch_dpp_kernel(const float *__restrict__ src, float *__restrict__ dst,
+                                                        const uint32_t *__restrict__ face,
+                                                        const uint32_t *__restrict__ work, int64_t n_work,
+                                                        const sgrid::SweepParams<float> *__restrict__ params,
+                                                        int64_t n_blocks, int64_t spw) {
+    const int64_t b = xcd_block(blockIdx.x, n_blocks);
+    const int lane = threadIdx.x & 63, r = lane & 15;
+    const int64_t wave = b * 4 + (threadIdx.x >> 6);
+    const int64_t n_sets = (n_work + 3) / 4;
+    const int64_t s0 = wave * spw, s1 = s0 + spw < n_sets ? s0 + spw : n_sets;
+    for (int64_t s = s0; s < s1; ++s) {
+        const int64_t e = 4 * s + (lane >> 4);
+        const bool live = e < n_work;
+        Halo l;
+        uint32_t shape = 0;
+        const int64_t g = live ? work[e] : 0;
+        if (live) batch_loads(src, face, g, r, l, shape);
+        const sgrid::SweepParams<float> sp = params[shape];
+        const Row4<float> o = update_row_dpp(r, l, sp);
+        if (live) st_row(dst + g * 64 + r * 4, o);
+    }
+}
+
+// Persistent worklist sweep, LDS tile (package + one-cell face halo).
+__global__ __launch_bounds__(256) void batch_lds_kernel(const float *__restrict__ src, float *__restrict__ dst,
+                                                        const uint32_t *__restrict__ face,
+                                                        const uint32_t *__restrict__ work, int64_t n_work,
+                                                        const sgrid::SweepParams<float> *__restrict__ params,
+                                                        int64_t n_blocks, int64_t spw) {
+    __shared__ float tile[16][216];
+    const int64_t b = xcd_block(blockIdx.x, n_blocks);
+    const int lane = threadIdx.x & 63, r = lane & 15, j = r & 3, k = r >> 2;
+    float *t = tile[threadIdx.x >> 4];
+    auto at = [](int x, int y, int z) { return (x + 1) + 6 * ((y + 1) + 6 * (z + 1)); };
+    const int64_t wave = b * 4 + (threadIdx.x >> 6);
+    const int64_t n_sets = (n_work + 3) / 4;
+    const int64_t s0 = wave * spw, s1 = s0 + spw < n_sets ? s0 + spw : n_sets;
+    // every wavefront of the block runs the same number of iterations (barriers)
+    const int64_t wave0 = b * 4;
+    const int64_t iters = spw;
+    for (int64_t it = 0; it < iters; ++it) {
+        const int64_t s = s0 + it;
+        const int64_t e = 4 * s + (lane >> 4);
+        const bool live = s < s1 && e < n_work;
+        Halo l;
+        uint32_t shape = 0;
+        const int64_t g = live ? work[e] : 0;
+        if (live) {
+            batch_loads(src, face, g, r, l, shape);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) t[at(i, j, k)] = l.c.v[i];
+            t[at(-1, j, k)] = l.xm;
+            t[at(4, j, k)] = l.xp;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                if (j == 0) t[at(i, -1, k)] = l.yh.v[i];
+                if (j == 3) t[at(i, 4, k)] = l.yh.v[i];
+                if (k == 0) t[at(i, j, -1)] = l.zh.v[i];
+                if (k == 3) t[at(i, j, 4)] = l.zh.v[i];
+            }
+        }
+        __syncthreads();
+        if (live) {
+            const sgrid::SweepParams<float> sp = params[shape];
+            Row4<float> o;
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+                o.v[i] = upwind(t[at(i, j, k)], t[at(i - 1, j, k)], t[at(i + 1, j, k)], t[at(i, j - 1, k)],
+                                t[at(i, j + 1, k)], t[at(i, j, k - 1)], t[at(i, j, k + 1)], sp.h2, sp.inv_h, sp.dt);
+            st_row(dst + g * 64 + r * 4, o);
+        }
+        __syncthreads();
+    }
+    (void)wave0;
+}
+
+// Batch tables: rebased face rows of grid s, worklist entries, far-field rows.
+__global__ __launch_bounds__(256) void rebase_kernel(const uint32_t *__restrict__ face_s, int64_t n_total_s,
+                                                     uint32_t base, uint32_t shape, uint32_t *__restrict__ face_all,
+                                                     uint32_t *__restrict__ work, int64_t work_base) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n_total_s) return;
+    uint32_t *o = face_all + ((int64_t)base + t) * 8;
+    const uint32_t *in = face_s + t * 8;
+#pragma unroll
+    for (int f = 0; f < 6; ++f) o[f] = base + in[f];
+    o[6] = base + (uint32_t)t;
+    o[7] = shape;
+    if (t >= 2) work[work_base + t - 2] = base + (uint32_t)t;
+}
+
+// Copies the far-field rows of every grid from one buffer to the other.
+__global__ __launch_bounds__(128) void far_rows_copy_kernel(const float *__restrict__ src, float *__restrict__ dst,
+                                                            const uint32_t *__restrict__ bases) {
+    const int64_t base = bases[blockIdx.x];
+    const int t = threadIdx.x;   // 128 values: rows base and base + 1
+    dst[base * 64 + t] = src[base * 64 + t];
+}
+
+}  // namespace
+
+struct sgrid_batch {
+    int device = 0;
+    int32_t n = 0;
+    int64_t n_total = 0;      // concatenated package rows
+    int64_t n_work = 0;
+    uint32_t *face = nullptr;
+    uint32_t *work = nullptr;
+    uint32_t *bases = nullptr;        // device copy of grid bases
+    sgrid::SweepParams<float> *params = nullptr;
+    std::vector<int64_t> base_host, total_host;
+    int32_t variant = 0, blocks_per_cu = 4;   // tuned configuration
+    bool tuned = false;
+    // captured iteration loop
+    hipGraphExec_t exec = nullptr;
+    hipGraph_t graph = nullptr;
+    hipStream_t cap_stream = nullptr;
+    const void *g_phi = nullptr, *g_scratch = nullptr;
+    int32_t g_iter = -1, g_variant = -1, g_bpc = -1;
+};
+
+namespace {
+
+sgrid_status launch_batch_sweep(const sgrid_batch *b, const float *src, float *dst, int variant, int bpc,
+                                hipStream_t st) {
+    if (b->n_work == 0) return SGRID_OK;
+    const int64_t n_sets = (b->n_work + 3) / 4;
+    int64_t nb = (int64_t)sgrid::cu_count() * bpc;
+    const int64_t spw = (n_sets + nb * 4 - 1) / (nb * 4);
+    nb = (n_sets + spw * 4 - 1) / (spw * 4);
+    if (variant == 1)
+        hipLaunchKernelGGL(batch_lds_kernel, dim3((unsigned)nb), dim3(256), 0, st, src, dst, b->face, b->work,
+                           b->n_work, b->params, nb, spw);
+    else
+        hipLaunchKernelGGL(batch_dpp_kernel, dim3((unsigned)nb), dim3(256), 0, st, src, dst, b->face, b->work,
+                           b->n_work, b->params, nb, spw);
+    SG_CHECK_LAUNCH("batch sweep");
+    return SGRID_OK;
+}
+
+// The iteration loop on `st`: far-field rows into the scratch buffer, then
+// n_iter ping-pong sweeps; an odd count leaves the result in scratch.
+sgrid_status enqueue_loop(const sgrid_batch *b, float *phi, float *scratch, int32_t n_iter, int variant, int bpc,
+                          hipStream_t st) {
+    hipLaunchKernelGGL(far_rows_copy_kernel, dim3((unsigned)b->n), dim3(128), 0, st, phi, scratch, b->bases);
+    SG_CHECK_LAUNCH("far-field rows");
+    float *a = phi, *c = scratch;
+    for (int32_t it = 0; it < n_iter; ++it) {
+        sgrid_status s = launch_batch_sweep(b, a, c, variant, bpc, st);
+        if (s != SGRID_OK) return s;
+        float *t = a;
+        a = c;
+        c = t;
+    }
+    return SGRID_OK;
+}
+
+void drop_graph(sgrid_batch *b) {
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    b->exec = nullptr;
+    b->graph = nullptr;
+    b->g_iter = -1;
+}
+
+}  // namespace
+
+extern "C" sgrid_status sgrid_batch_create(const sgrid_grid *const *grids, int32_t n, void *stream,
+                                           sgrid_batch **out) {
+    sgrid::clear_error();
+    SG_REQUIRE(out != nullptr, "out is NULL");
+    *out = nullptr;
+    SG_REQUIRE(grids != nullptr && n >= 1, "need at least one grid");
+    int64_t total = 0, work = 0;
+    for (int32_t s = 0; s < n; ++s) {
+        SG_REQUIRE(grids[s] != nullptr, "grid %d is NULL", s);
+        total += grids[s]->total();
+        work += grids[s]->P;
+    }
+    if (total >= (int64_t)0xFFFFFFFFll) {
+        sgrid::set_error("batch of %lld package rows exceeds 32-bit ids", (long long)total);
+        return SGRID_E_CAPACITY;
+    }
+    hipStream_t st = sg_stream(stream);
+    sgrid_batch *b = new sgrid_batch();
+    (void)hipGetDevice(&b->device);
+    b->n = n;
+    b->n_total = total;
+    b->n_work = work;
+    auto fail = [&](sgrid_status s) {
+        sgrid::dev_free(b->face);
+        sgrid::dev_free(b->work);
+        sgrid::dev_free(b->bases);
+        sgrid::dev_free(b->params);
+        delete b;
+        return s;
+    };
+    sgrid_status s;
+    if ((s = sgrid::dev_alloc((void **)&b->face, (size_t)total * 32, "batch face table")) != SGRID_OK) return fail(s);
+    if ((s = sgrid::dev_alloc((void **)&b->work, (size_t)(work > 0 ? work : 1) * 4, "worklist")) != SGRID_OK)
+        return fail(s);
+    if ((s = sgrid::dev_alloc((void **)&b->bases, (size_t)n * 4, "grid bases")) != SGRID_OK) return fail(s);
+    if ((s = sgrid::dev_alloc((void **)&b->params, (size_t)n * sizeof(sgrid::SweepParams<float>), "grid params")) !=
+        SGRID_OK)
+        return fail(s);
+    std::vector<uint32_t> bases(n);
+    std::vector<sgrid::SweepParams<float>> params(n);
+    int64_t base = 0, wbase = 0;
+    for (int32_t k = 0; k < n; ++k) {
+        const sgrid_grid *g = grids[k];
+        bases[k] = (uint32_t)base;
+        b->base_host.push_back(base);
+        b->total_host.push_back(g->total());
+        // the same constants as the single-grid sweep
+        params[k] = sgrid::SweepParams<float>{(float)(g->h * g->h), (float)(1.0 / g->h), (float)(0.5 * g->h)};
+        const int64_t nt = g->total();
+        hipLaunchKernelGGL(rebase_kernel, dim3((unsigned)((nt + 255) / 256)), dim3(256), 0, st, g->face, nt,
+                           (uint32_t)base, (uint32_t)k, b->face, b->work, wbase);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) {
+            sgrid::set_error("batch table launch failed: %s", hipGetErrorString(e));
+            return fail(SGRID_E_HIP);
+        }
+        base += nt;
+        wbase += g->P;
+    }
+    hipError_t e = hipMemcpyAsync(b->bases, bases.data(), (size_t)n * 4, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(b->params, params.data(), (size_t)n * sizeof(params[0]), hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) {
+        sgrid::set_error("batch table upload failed: %s", hipGetErrorString(e));
+        return fail(SGRID_E_HIP);
+    }
+    *out = b;
+    return SGRID_OK;
+}
+
+extern "C" sgrid_status sgrid_batch_destroy(sgrid_batch *b) {
+    sgrid::clear_error();
+    if (!b) return SGRID_OK;
+    hipError_t e = hipDeviceSynchronize();
+    drop_graph(b);
+    if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
+    sgrid::dev_free(b->face);
+    sgrid::dev_free(b->work);
+    sgrid::dev_free(b->bases);
+    sgrid::dev_free(b->params);
+    delete b;
+    if (e != hipSuccess) {
+        sgrid::set_error("hipDeviceSynchronize before destroy failed: %s", hipGetErrorString(e));
+        return SGRID_E_HIP;
+    }
+    return SGRID_OK;
+}
+
+extern "C" sgrid_status sgrid_batch_info(const sgrid_batch *b, int64_t *n_total, int64_t *n_work,
+                                         int64_t *bases_host) {
+    sgrid::clear_error();
+    SG_REQUIRE(b != nullptr, "batch is NULL");
+    if (n_total) *n_total = b->n_total;
+    if (n_work) *n_work = b->n_work;
+    if (bases_host)
+        for (int32_t k = 0; k < b->n; ++k) bases_host[k] = b->base_host[k];
+    return SGRID_OK;
+}
+
+extern "C" sgrid_status sgrid_batch_set_config(sgrid_batch *b, int32_t variant, int32_t blocks_per_cu) {
+    sgrid::clear_error();
+    SG_REQUIRE(b != nullptr, "batch is NULL");
+    SG_REQUIRE(variant == 0 || variant == 1, "batch variant must be 0 or 1");
+    SG_REQUIRE(blocks_per_cu >= 1 && blocks_per_cu <= 16, "blocks_per_cu must be in 1..16");
+    b->variant = variant;
+    b->blocks_per_cu = blocks_per_cu;
+    b->tuned = true;
+    return SGRID_OK;
+}
+
+extern "C" sgrid_status sgrid_batch_autotune(sgrid_batch *b, const float *phi, float *scratch, int32_t reps,
+                                             void *stream, int32_t *variant_out, int32_t *bpc_out,
+                                             float *us_table /* [2][5] */) {
+    sgrid::clear_error();
+    SG_REQUIRE(b != nullptr && phi != nullptr && scratch != nullptr, "NULL argument");
+    SG_REQUIRE(reps >= 1 && reps <= 1000, "reps must be in 1..1000");
+    hipStream_t st = sg_stream(stream);
+    static const int kBpc[5] = {1, 2, 4, 8, 16};
+    hipEvent_t e0, e1;
+    SG_CHECK_HIP(hipEventCreate(&e0));
+    SG_CHECK_HIP(hipEventCreate(&e1));
+    float best = 1e30f;
+    int bv = 0, bb = 4;
+    for (int v = 0; v < 2; ++v)
+        for (int i = 0; i < 5; ++i) {
+            // phi is only read: every timed sweep writes scratch
+            sgrid_status s = launch_batch_sweep(b, phi, scratch, v, kBpc[i], st);
+            if (s != SGRID_OK) return s;
+            SG_CHECK_HIP(hipEventRecord(e0, st));
+            for (int k = 0; k < reps; ++k) {
+                s = launch_batch_sweep(b, phi, scratch, v, kBpc[i], st);
+                if (s != SGRID_OK) return s;
+            }
+            SG_CHECK_HIP(hipEventRecord(e1, st));
+            SG_CHECK_HIP(hipEventSynchronize(e1));
+            float ms = 0.f;
+            SG_CHECK_HIP(hipEventElapsedTime(&ms, e0, e1));
+            const float us = 1e3f * ms / reps;
+            if (us_table) us_table[v * 5 + i] = us;
+            if (us < best) {
+                best = us;
+                bv = v;
+                bb = kBpc[i];
+            }
+        }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    b->variant = bv;
+    b->blocks_per_cu = bb;
+    b->tuned = true;
+    if (variant_out) *variant_out = bv;
+    if (bpc_out) *bpc_out = bb;
+    return SGRID_OK;
+}
+
+extern "C" sgrid_status sgrid_batch_reinitialize(sgrid_batch *b, float *phi, float *scratch, int32_t n_iter,
+                                                 int32_t use_graph, void *stream) {
+    sgrid::clear_error();
+    SG_REQUIRE(b != nullptr && phi != nullptr && scratch != nullptr, "NULL argument");
+    SG_REQUIRE(phi != scratch, "phi and scratch must be distinct");
+    SG_REQUIRE(sg_aligned(phi, 16) && sg_aligned(scratch, 16), "phi / scratch must be 16-byte aligned");
+    SG_REQUIRE(n_iter >= 0, "n_iter must be >= 0");
+    if (n_iter == 0) return SGRID_OK;
+    hipStream_t st = sg_stream(stream);
+    if (!use_graph) {
+        sgrid_status s = enqueue_loop(b, phi, scratch, n_iter, b->variant, b->blocks_per_cu, st);
+        if (s != SGRID_OK) return s;
+    } else {
+        if (b->g_phi != phi || b->g_scratch != scratch || b->g_iter != n_iter || b->g_variant != b->variant ||
+            b->g_bpc != b->blocks_per_cu || !b->exec) {
+            drop_graph(b);
+            if (!b->cap_stream) SG_CHECK_HIP(hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking));
+            SG_CHECK_HIP(hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal));
+            sgrid_status s = enqueue_loop(b, phi, scratch, n_iter, b->variant, b->blocks_per_cu, b->cap_stream);
+            hipGraph_t g = nullptr;
+            hipError_t e = hipStreamEndCapture(b->cap_stream, &g);
+            if (s != SGRID_OK) {
+                if (g) (void)hipGraphDestroy(g);
+                return s;
+            }
+            if (e != hipSuccess) {
+                sgrid::set_error("graph capture failed: %s", hipGetErrorString(e));
+                return SGRID_E_HIP;
+            }
+            b->graph = g;
+            e = hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0);
+            if (e != hipSuccess) {
+                drop_graph(b);
+                sgrid::set_error("graph instantiation failed: %s", hipGetErrorString(e));
+                return SGRID_E_HIP;
+            }
+            b->g_phi = phi;
+            b->g_scratch = scratch;
+            b->g_iter = n_iter;
+            b->g_variant = b->variant;
+            b->g_bpc = b->blocks_per_cu;
+        }
+        SG_CHECK_HIP(hipGraphLaunch(b->exec, st));
+    }
+    if (n_iter & 1) {
+        // the result sits in scratch: copy the activated rows of every grid back
+        for (int32_t k = 0; k < b->n; ++k) {
+            const int64_t r0 = b->base_host[k] + 2, nr = b->total_host[k] - 2;
+            if (nr > 0)
+                SG_CHECK_HIP(hipMemcpyAsync(phi + r0 * 64, scratch + r0 * 64, (size_t)nr * 64 * 4,
+                                            hipMemcpyDeviceToDevice, st));
+        }
+    }
+    return SGRID_OK;
+}

@@ -79,3 +79,33 @@ def setup(shape: Dict, N: int, noise_amp: float, noise_seed: int, dtype=torch.fl
         wl.nrm_p = torch.empty((p.shape[0], 3), dtype=dtype, device="cuda")
     torch.cuda.synchronize()
     return wl
+
+
+@dataclass
+class BatchWorkload:
+    parts: list                   # per-shape Workload (their own phi0 kept for checks)
+    batch: object                 # paper_2512_11473_amd.Batch
+    phi0: torch.Tensor            # [n_total, 64] concatenated initial fields
+    phi: torch.Tensor
+    scratch: torch.Tensor
+
+    @property
+    def n_updates_per_iter(self) -> int:
+        return 64 * self.batch.n_work
+
+    def reset(self):
+        self.phi.copy_(self.phi0)
+
+    def slice(self, k: int, t: torch.Tensor) -> torch.Tensor:
+        b = int(self.batch.bases[k])
+        return t[b:b + self.parts[k].grid.n_total]
+
+
+def setup_batch(specs, noise_amp: float) -> BatchWorkload:
+    """Grids of several shapes (dicts with shape, N, noise_seed) in one batch."""
+    from . import Batch
+    parts = [setup(s["shape"], s["N"], noise_amp, s["noise_seed"]) for s in specs]
+    batch = Batch([p.grid for p in parts])
+    phi0 = torch.cat([p.phi0 for p in parts], dim=0).contiguous()
+    assert phi0.shape[0] == batch.n_total
+    return BatchWorkload(parts, batch, phi0, phi0.clone(), torch.empty_like(phi0))
