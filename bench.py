@@ -1,24 +1,31 @@
 """Benchmark of the narrow-band sparse-grid hot path on one MI355X.
 
-Workload (extruded triangular prism, edges 0.6, extrusion 0.8, 512^3 data
-points, 4^3 packages within about two package widths of the surface, phi0 =
-SDF * (1 + 0.05 u), 100 reinitialisation iterations, central-difference
-gradient, 1e7 particles jittered N(0, 0.5h) about the surface, plain
-near-surface integrals on every core point).
+Default workload (prism512): extruded triangular prism (edges 0.6, extrusion
+0.8) at 512^3 data points, 4^3 packages within about two package widths of
+the surface, phi0 = SDF * (1 + 0.05 u); 100 reinitialisation iterations, the
+central-difference gradient, 1e7 particles jittered N(0, 0.5h) about the
+surface, plain near-surface integrals on every core point.
 
-One step = one pass of the whole hot path over the resident inputs:
-package build from the coarse distances, phi reset from phi0 (device copy),
-n_iter reinitialisation sweeps, gradient, probe, integrals.  Inputs are
-generated once, uploaded, and resident in HBM before timing starts.
+One step = one pass of the whole hot path over resident inputs: package
+build from the coarse distances, phi reset from phi0 (device copy), 100
+reinitialisation sweeps, packed gradient, packed probe, plain integrals.
+Inputs are generated once and resident in HBM before timing starts.
 
-Prints one JSON line.  `value` = package-cell updates (64 P n_iter per step)
-per second of whole-step time.
+`value` = package-cell updates (64 P n_iter per step) per second of
+whole-step time.  The learned-versus-plain comparison (surrogate trained by
+the library's kernels on points of seeded random shapes) and the oracle's CPU
+baseline are added to the same JSON line.
+
+Other workloads: --workload batch64 (64 random unions, one persistent launch
+per iteration, graph replay, autotuned configuration).
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -27,8 +34,9 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 REINIT_BYTES_PER_UPDATE = 8.375      # read + write one FP32 value, plus 6 face ids / 64 points
-GRAD_BYTES_PER_POINT = 16.375        # read phi, write 3 components, face ids
 PROBE_BYTES_PER_PARTICLE = 28.0      # 12 B position in, 16 B value + normal out
+COUNTERS = os.path.join(ROOT, "profiles", "reinit_sweep_prism512_counters.txt")
+SWEEP_SRC = os.path.join(ROOT, "paper_2512_11473_amd", "csrc", "sweep.hip")
 
 
 def parse():
@@ -36,18 +44,39 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--n-iter", type=int, default=100)
+    ap.add_argument("--workload", default="prism512", choices=["prism512", "batch64"])
+    ap.add_argument("--n-iter", type=int, default=None)
     ap.add_argument("--particles", type=int, default=10_000_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=8)
+    ap.add_argument("--train-cells", type=int, default=2_000_000)
+    ap.add_argument("--epochs", type=int, default=50)
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="run one 256 MiB device copy first (counter calibration under rocprofv3)")
     return ap.parse_args()
+
+
+def sweep_source_hash() -> str:
+    return hashlib.sha256(open(SWEEP_SRC, "rb").read()).hexdigest()[:16]
+
+
+def measured_traffic(per_launch_algorithmic: float):
+    """HBM bytes per sweep launch from the committed counter summary, when it
+    was taken on the current sweep source; else None."""
+    if not os.path.exists(COUNTERS):
+        return None
+    text = open(COUNTERS).read()
+    m = re.search(r"sweep_source_sha256_16:\s*(\w+)", text)
+    t = re.search(r"calibrated_bytes_per_launch:\s*([0-9.eE+]+)", text)
+    if not m or not t or m.group(1) != sweep_source_hash():
+        return None
+    return float(t.group(1))
 
 
 def cpu_baseline(cfg, n_iter_sample):
     """The oracle (FP64, dense grid, OpenMP) timed on the host on a bounded
-    sample of the workload: `n_iter_sample` reinitialisation sweeps over the
-    full band, then updates/s."""
-    import numpy as np
+    sample: `n_iter_sample` reinitialisation sweeps over the full band."""
     import oracle
     t0 = time.perf_counter()
     run = oracle.setup(cfg["shape"], cfg["N"], cfg["noise_amp"], cfg["noise_seed"])
@@ -60,33 +89,73 @@ def cpu_baseline(cfg, n_iter_sample):
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     return {"value": len(run.active) * n_iter_sample / dt, "unit": "package-cell updates/s",
             "cores": threads, "kind": "oracle",
-            "sample": f"{n_iter_sample} FP64 reinitialisation sweeps over the full prism512 band "
-                      f"({len(run.active)} points, {dt:.1f} s; setup {setup_s:.1f} s)"}
+            "sample": f"{n_iter_sample} FP64 reinitialisation sweeps of the oracle over the full prism512 band "
+                      f"({len(run.active)} points, {dt:.1f} s; dense-grid setup {setup_s:.1f} s)"}
 
 
-def main():
-    args = parse()
-    if args.gpus != 1:
-        print(json.dumps({"error": "this benchmark runs on exactly one GPU; the path has no multi-GPU mode",
-                          "n_gpus": args.gpus}))
-        sys.exit(2)
+def learned_vs_plain(sg, wl, args, log):
+    """Train the surrogate on method-generated points, score it on held-out
+    points, and time learned (gated, with fallback) against plain integrals on
+    the benchmark grid's core points."""
+    import torch
+    from paper_2512_11473_amd import surrogate
+    tr = surrogate.generate(256, 101, args.train_cells)
+    ho = surrogate.generate(128, 202, args.train_cells // 2)
+    log(f"surrogate data: train {tuple(tr.x.shape)} in {tr.seconds:.1f}s, held-out {tuple(ho.x.shape)}")
+    res = surrogate.train(tr, epochs=args.epochs, log=log)
+    ev = surrogate.evaluate(res.model, ho, res.tau)
+    n = wl.grid.n_core * 64
+    out_p = torch.empty((4, n), device="cuda")
+    out_l = torch.empty((4, n), device="cuda")
+    nf = torch.zeros(1, dtype=torch.int32, device="cuda")
+
+    def t(fn, reps=10):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    ms_plain = t(lambda: sg.compute_near_surface_integrals(wl.grid, wl.phi, out_p))
+    ms_learn = t(lambda: sg.compute_near_surface_integrals(wl.grid, wl.phi, out_l, model=res.model, n_fallback=nf))
+    e = surrogate.relative_error(out_l.t(), out_p.t())
+    return {
+        "plain_cells_per_s": n / (ms_plain * 1e-3),
+        "learned_cells_per_s": n / (ms_learn * 1e-3),
+        "learned_over_plain": ms_plain / ms_learn,
+        "target_rel_error": 1e-3,
+        "heldout": ev,
+        "bench_grid_error": surrogate.error_stats(e),
+        "bench_grid_fallback_fraction": int(nf.item()) / n,
+        "train": {"points": int(tr.x.shape[0]), "shapes": tr.shapes, "epochs": args.epochs,
+                  "steps": res.steps, "seconds": res.seconds, "final_loss": res.losses[-1],
+                  "gate_tau": res.tau},
+    }
+
+
+def bench_prism(args, log):
     import numpy as np
     import torch
     import paper_2512_11473_amd as sg
     import synth
     from paper_2512_11473_amd import workload
 
-    assert torch.cuda.is_available(), "bench.py needs a GPU"
-    torch.cuda.set_device(0)
     cfg = synth.config_c2()
-    cfg["n_iter"] = args.n_iter
+    if args.n_iter is not None:
+        cfg["n_iter"] = args.n_iter
     t0 = time.perf_counter()
     pos = synth.particles_for(cfg, args.particles)
     wl = workload.setup(cfg["shape"], cfg["N"], cfg["noise_amp"], cfg["noise_seed"], particles=pos)
     setup_s = time.perf_counter() - t0
+    log(f"prism512 set up in {setup_s:.1f}s")
     P = wl.grid.n_packages
     n_core = wl.grid.n_core
     integ = torch.empty((4, n_core * 64), device="cuda")
+    packed = torch.empty((wl.grid.n_total, 64, 4), device="cuda")
     stream = torch.cuda.current_stream()
 
     ev = {k: [torch.cuda.Event(enable_timing=True) for _ in range(2)] for k in
@@ -105,10 +174,10 @@ def main():
         sg.reinitialize(g, wl.phi, wl.scratch, cfg["n_iter"])
         mark("reinit", 1)
         mark("grad", 0)
-        sg.compute_gradient(g, wl.phi, wl.grad)
+        sg.compute_gradient_packed(g, wl.phi, packed)
         mark("grad", 1)
         mark("probe", 0)
-        sg.probe_particles(g, wl.phi, wl.grad, wl.pos, wl.phi_p, wl.nrm_p)
+        sg.probe_particles_packed(g, packed, wl.pos, wl.phi_p, wl.nrm_p)
         mark("probe", 1)
         mark("integ", 0)
         sg.compute_near_surface_integrals(g, wl.phi, integ)
@@ -116,27 +185,25 @@ def main():
         return g
 
     for _ in range(args.warmup):
-        step(False)
+        step(False).destroy()
     torch.cuda.synchronize()
-    grids = []
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        grids.append(step(True))
-        torch.cuda.synchronize()
+        g = step(True)
+        torch.cuda.synchronize()   # the build already synchronises once per step
         for k in ev:
             acc[k] += ev[k][0].elapsed_time(ev[k][1])
+        g.destroy()
     torch.cuda.synchronize()
     total_s = time.perf_counter() - t0
-    for g in grids:
-        g.destroy()
 
     K = args.steps
     ms_step = 1e3 * total_s / K
     upd_step = 64 * P * cfg["n_iter"]
     reinit_ms = acc["reinit"] / K
     sweep_ms = reinit_ms / cfg["n_iter"]
-    achieved = REINIT_BYTES_PER_UPDATE * 64 * P / (sweep_ms * 1e-3) / 1e9
-    n_pts = 64 * (P + 2)
+    bytes_launch = REINIT_BYTES_PER_UPDATE * 64 * P
+    achieved = bytes_launch / (sweep_ms * 1e-3) / 1e9
     rec = {
         "metric": "package-cell updates/s (reinit), probes/s; learned vs plain integral @1e-3",
         "value": upd_step / (ms_step * 1e-3),
@@ -144,23 +211,104 @@ def main():
         "n_gpus": 1, "steps": K, "warmup": args.warmup, "ms_per_step": ms_step,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32", "data": "synthetic",
-        "config": {"workload": "prism512: extruded triangular prism, 512^3, 100 reinit iterations, "
-                               "gradient, 1e7 jittered particles, plain integrals",
+        "config": {"workload": "prism512: extruded triangular prism (edges 0.6, extrusion 0.8) at 512^3, "
+                               "5% noise, 100 reinitialisation iterations, gradient, 1e7 jittered particles, "
+                               "plain integrals on all core points",
                    "N": cfg["N"], "n_packages": P, "n_core": n_core, "n_iter": cfg["n_iter"],
                    "particles": int(wl.pos.shape[0])},
         "breakdown_ms": {k: acc[k] / K for k in acc},
         "reinit_updates_per_s": upd_step / (reinit_ms * 1e-3),
         "probes_per_s": wl.pos.shape[0] / (acc["probe"] / K * 1e-3),
-        "gradient_points_per_s": n_pts / (acc["grad"] / K * 1e-3),
+        "probe_particle_order": "as generated (random over the surface)",
         "integral_cells_per_s": n_core * 64 / (acc["integ"] / K * 1e-3),
         "roofline": {"bound": "hbm", "kernel": "reinit sweep", "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "avg_launch_us": sweep_ms * 1e3,
-                     "bytes_per_launch": REINIT_BYTES_PER_UPDATE * 64 * P},
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(bytes_launch),
+                     "avg_launch_us": sweep_ms * 1e3, "algorithmic_bytes_per_launch": bytes_launch,
+                     "note": "phi ping-pong of 64 MB is resident in the 256 MB Infinity Cache"},
         "setup_s": setup_s,
     }
+    log(f"timed {K} steps: {ms_step:.2f} ms per step")
+    if not args.no_learned:
+        rec["learned"] = learned_vs_plain(sg, wl, args, log)
+        log("learned vs plain done")
     if not args.no_cpu_baseline:
         rec["cpu_baseline"] = cpu_baseline(cfg, args.cpu_iters)
+        log("cpu baseline done")
+    return rec
+
+
+def bench_batch(args, log):
+    import numpy as np
+    import torch
+    import synth
+    from paper_2512_11473_amd import workload
+
+    cfg = synth.config_c3()
+    n_iter = args.n_iter or cfg["n_iter"]
+    t0 = time.perf_counter()
+    bw = workload.setup_batch(cfg["shapes"], cfg["noise_amp"])
+    setup_s = time.perf_counter() - t0
+    v, b, table = bw.batch.autotune(bw.phi0, bw.scratch, reps=5)
+    counts = [p.grid.n_packages for p in bw.parts]
+    for _ in range(args.warmup):
+        bw.reset()
+        bw.batch.reinitialize(bw.phi, bw.scratch, n_iter, use_graph=True)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ms = 0.0
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        bw.phi.copy_(bw.phi0)
+        e0.record()
+        bw.batch.reinitialize(bw.phi, bw.scratch, n_iter, use_graph=True)
+        e1.record()
+        torch.cuda.synchronize()
+        ms += e0.elapsed_time(e1)
+    total_s = time.perf_counter() - t0
+    K = args.steps
+    upd = 64 * bw.batch.n_work * n_iter
+    sweep_ms = ms / K / n_iter
+    achieved = REINIT_BYTES_PER_UPDATE * 64 * bw.batch.n_work / (sweep_ms * 1e-3) / 1e9
+    return {
+        "metric": "package-cell updates/s (reinit), probes/s; learned vs plain integral @1e-3",
+        "value": upd / (ms / K * 1e-3), "unit": "package-cell updates/s",
+        "n_gpus": 1, "steps": K, "warmup": args.warmup, "ms_per_step": 1e3 * total_s / K,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "batch64: 64 seeded random unions at 64^3..512^3, one persistent launch per "
+                               "iteration over a global worklist, 50 iterations replayed as a HIP graph",
+                   "n_shapes": len(counts), "n_packages": int(bw.batch.n_work), "n_iter": n_iter,
+                   "packages_min": int(min(counts)), "packages_max": int(max(counts))},
+        "autotuned": {"variant": ["dpp", "lds"][v], "blocks_per_cu": b,
+                      "us_per_sweep": {f"{['dpp', 'lds'][i]}_bpc{bb}": float(table[i, j])
+                                       for i in range(2) for j, bb in enumerate((1, 2, 4, 8, 16))}},
+        "roofline": {"bound": "hbm", "kernel": "batched sweep", "achieved": achieved, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "avg_launch_us": sweep_ms * 1e3},
+        "setup_s": setup_s,
+    }
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this benchmark runs on exactly one GPU; the path has no multi-GPU mode",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+    import torch
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+
+    def log(msg):
+        print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+    if args.calibrate_copy:
+        a = torch.ones(64 * 1024 * 1024, device="cuda")
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+    rec = bench_batch(args, log) if args.workload == "batch64" else bench_prism(args, log)
     print(json.dumps(rec), flush=True)
 
 
