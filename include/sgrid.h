@@ -133,8 +133,11 @@ sgrid_status sgrid_compute_gradient(const sgrid_grid *grid, sgrid_dtype dtype,
 
 /*
  * The same gradient written with phi into one array of (phi, gx, gy, gz)
- * quadruples, [P^][64][4] in `dtype` (a layout for the packed probe: one
- * 16-byte gather per corner in FP32).  Far-field rows hold (+-B, 0, 0, 0).
+ * quadruples, [P^][64][4] in `dtype`, a layout for the packed probe: one
+ * 16-byte gather per corner in FP32.  Inside a package the points are in
+ * 2x2x2 blocks: point (i, j, k) is at 8 ((i>>1) + 2 (j>>1) + 4 (k>>1)) +
+ * ((i&1) + 2 (j&1) + 4 (k&1)), so a cell inside one block is one 128-byte
+ * line.  Far-field rows hold (+-B, 0, 0, 0).
  */
 sgrid_status sgrid_compute_gradient_packed(const sgrid_grid *grid, sgrid_dtype dtype,
                                            const void *phi_dev, void *packed_dev, void *stream);
@@ -155,6 +158,18 @@ sgrid_status sgrid_probe_particles(const sgrid_grid *grid, sgrid_dtype dtype, co
 
 /* sgrid_probe_particles on the packed (phi, g) array of sgrid_compute_gradient_packed. */
 sgrid_status sgrid_probe_particles_packed(const sgrid_grid *grid, sgrid_dtype dtype, const void *packed_dev,
+                                          const void *pos_dev, int64_t n, void *phi_out_dev,
+                                          void *normal_out_dev, void *stream);
+
+/*
+ * sgrid_probe_particles_packed for particles in any order, through a counting
+ * sort by home package: the particles of one package are probed together, so
+ * its cache lines are fetched once, and results are written back in input
+ * order.  Results are identical to sgrid_probe_particles_packed.  Uses a
+ * workspace cached on the grid (12 bytes per particle plus 4 per package);
+ * calls on one grid from different streams must not overlap.
+ */
+sgrid_status sgrid_probe_particles_binned(const sgrid_grid *grid, sgrid_dtype dtype, const void *packed_dev,
                                           const void *pos_dev, int64_t n, void *phi_out_dev,
                                           void *normal_out_dev, void *stream);
 

@@ -56,6 +56,7 @@ _SIGNATURES = {
     "sgrid_compute_gradient": (ctypes.c_int, [_P, ctypes.c_int, _P, _P, _P]),
     "sgrid_compute_gradient_packed": (ctypes.c_int, [_P, ctypes.c_int, _P, _P, _P]),
     "sgrid_probe_particles_packed": (ctypes.c_int, [_P, ctypes.c_int, _P, _P, ctypes.c_int64, _P, _P, _P]),
+    "sgrid_probe_particles_binned": (ctypes.c_int, [_P, ctypes.c_int, _P, _P, ctypes.c_int64, _P, _P, _P]),
     "sgrid_probe_particles": (ctypes.c_int, [_P, ctypes.c_int, _P, _P, _P, ctypes.c_int64, _P, _P, _P]),
     "sgrid_compute_near_surface_integrals": (ctypes.c_int, [_P, _P, _P, _P, _P, _P]),
     "sgrid_set_sweep_config": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32]),
@@ -236,7 +237,7 @@ def compute_gradient_packed(grid: Grid, phi: torch.Tensor, packed: torch.Tensor,
 
 
 def probe_particles_packed(grid: Grid, packed: torch.Tensor, pos: torch.Tensor, phi_out: torch.Tensor,
-                           normal_out: torch.Tensor, stream=None):
+                           normal_out: torch.Tensor, stream=None, binned: bool = False):
     n = pos.numel() // 3
     if pos.numel() != 3 * n or phi_out.numel() != n or normal_out.numel() != 3 * n:
         raise ValueError("pos [n,3], phi_out [n], normal_out [n,3] expected")
@@ -245,9 +246,9 @@ def probe_particles_packed(grid: Grid, packed: torch.Tensor, pos: torch.Tensor, 
             raise TypeError("all probe arrays must share the field's dtype")
     if packed.numel() != grid.n_total * 256:
         raise ValueError("packed must be [P+2, 64, 4]")
-    _check(load().sgrid_probe_particles_packed(grid.handle, _dtype_code(packed), _dev(packed, "packed"),
-                                               _dev(pos, "pos"), n, _dev(phi_out, "phi_out"),
-                                               _dev(normal_out, "normal_out"), _stream(stream)))
+    fn = load().sgrid_probe_particles_binned if binned else load().sgrid_probe_particles_packed
+    _check(fn(grid.handle, _dtype_code(packed), _dev(packed, "packed"), _dev(pos, "pos"), n,
+              _dev(phi_out, "phi_out"), _dev(normal_out, "normal_out"), _stream(stream)))
 
 
 def probe_particles(grid: Grid, phi: torch.Tensor, grad: torch.Tensor, pos: torch.Tensor,

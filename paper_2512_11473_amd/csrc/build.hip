@@ -350,7 +350,7 @@ __global__ __launch_bounds__(256) void nbr_kernel(const uint32_t *__restrict__ c
 
 void free_grid(sgrid_grid *g) {
     if (!g) return;
-    void *ptrs[] = {g->cell_pkg, g->pkg_cell, g->pkg_type, g->nbr, g->face, g->core_list, g->workspace};
+    void *ptrs[] = {g->cell_pkg, g->pkg_cell, g->pkg_type, g->nbr, g->face, g->core_list, g->workspace, g->probe_ws};
     for (void *p : ptrs) sgrid::dev_free(p);
     delete g;
 }

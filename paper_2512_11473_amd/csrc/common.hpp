@@ -50,6 +50,8 @@ struct sgrid_grid {
     uint32_t *face = nullptr;       // [P+2][8]: the six face slots of nbr, then two pads
     uint32_t *core_list = nullptr;  // [n_core]
     void *workspace = nullptr;      // build scratch, kept until destroy
+    void *probe_ws = nullptr;       // binned-probe scratch (grows on demand)
+    size_t probe_ws_bytes = 0;
     int64_t total() const { return P + 2; }
 };
 
@@ -109,6 +111,13 @@ __device__ __forceinline__ double row_move(double v) {
     int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xFFFFFFFFll), CTRL, 0xF, 0xF, false);
     int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
     return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// Point order of the packed (phi, g) probe field: the 64 points of a package
+// in 2 x 2 x 2 blocks, so the eight corners of a trilinear cell that lies
+// inside one block share one 128-byte line (FP32).
+__host__ __device__ __forceinline__ int blocked_index(int i, int j, int k) {
+    return 8 * ((i >> 1) + 2 * (j >> 1) + 4 * (k >> 1)) + ((i & 1) + 2 * (j & 1) + 4 * (k & 1));
 }
 
 // XCD-aware block order: the hardware deals consecutive workgroups round-robin

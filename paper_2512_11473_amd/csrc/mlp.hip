@@ -633,90 +633,133 @@ __device__ __forceinline__ Taps make_taps() {
 
 __global__ __launch_bounds__(256) void zero_u32_kernel(uint32_t *p) { *p = 0u; }
 
-__global__ __launch_bounds__(256) void learned_kernel(MlpDev W, const float *__restrict__ phi,
+// Persistent learned-integral kernel: one workgroup per compute unit keeps
+// the BF16 weights (94 KB) in LDS and walks the core packages; per package
+// the 9^3 window is staged, saturation flags are set, four wavefronts run the
+// network on 16 points each, and four lanes per point evaluate the exact
+// saturated sum or the gate.
+constexpr int kW1N = kH * kInPad, kW2N = kH * kH, kW3N = 16 * kH;
+
+__global__ __launch_bounds__(256) void learned_kernel(MlpDev Wg, const float *__restrict__ phi,
                                                       const uint32_t *__restrict__ nbr,
                                                       const uint32_t *__restrict__ core_list, int64_t n_core,
                                                       float inv_h, float inv_2h, float tau, float kw_lo, float kw_hi,
                                                       float *__restrict__ out, uint32_t *__restrict__ fb_list,
                                                       uint32_t *__restrict__ fb_count) {
+    __shared__ __attribute__((aligned(16))) bf16 s_w1[kW1N];
+    __shared__ __attribute__((aligned(16))) bf16 s_w2[kW2N];
+    __shared__ __attribute__((aligned(16))) bf16 s_w3[kW3N];
     __shared__ float s_phi[kWinN];
     __shared__ uint32_t s_ids[27];
     __shared__ uint8_t s_sat[kVolN];
     __shared__ __attribute__((aligned(16))) bf16 s_a1[64 * kH];
     __shared__ __attribute__((aligned(16))) bf16 s_a2[64 * kH];
     __shared__ float s_y[64][kOut];
+    // weights into LDS once
+    for (int e = threadIdx.x; e < kW1N / 8; e += blockDim.x)
+        reinterpret_cast<bf16x8 *>(s_w1)[e] = reinterpret_cast<const bf16x8 *>(Wg.w1b)[e];
+    for (int e = threadIdx.x; e < kW2N / 8; e += blockDim.x)
+        reinterpret_cast<bf16x8 *>(s_w2)[e] = reinterpret_cast<const bf16x8 *>(Wg.w2b)[e];
+    for (int e = threadIdx.x; e < kW3N / 8; e += blockDim.x)
+        reinterpret_cast<bf16x8 *>(s_w3)[e] = reinterpret_cast<const bf16x8 *>(Wg.w3b)[e];
+    const MlpDev W{Wg.w, s_w1, s_w2, Wg.w2tb, s_w3};
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, r = lane & 15, q = lane >> 4;
-    const int64_t ci = blockIdx.x;
-    const int64_t p = core_list[ci];
-    stage_window(phi, nbr, p, s_phi, s_ids);
-    saturation_flags(s_phi, inv_h, inv_2h, s_sat);
-    Tile T;
-    forward_tile(WindowX{s_phi, 16 * w, inv_h}, W, s_a1 + 16 * w * kH, s_a2 + 16 * w * kH, nullptr, T, lane);
-    if (r < kOut)
-#pragma unroll
-        for (int i = 0; i < 4; ++i) s_y[16 * w + 4 * q + i][r] = T.y[i];
-    __syncthreads();
-    if (threadIdx.x >= 64) return;
-    const int c = threadIdx.x;
-    const int i = c & 3, j = (c >> 2) & 3, k = c >> 4;
-    const int64_t o = ci * 64 + c, stride = n_core * 64;
-    // saturated cells: every tap fraction is 0 or 1, the sum is exact
-    bool sat = true;
-    float kw = 0.f, kx = 0.f, ky = 0.f, kz = 0.f;
     const Taps tp = make_taps();
-    for (int oz = -1; oz <= 2; ++oz)
-        for (int oy = -1; oy <= 2; ++oy)
-            for (int ox = -1; ox <= 2; ++ox) {
-                const float dx = 0.5f - ox, dy = 0.5f - oy, dz = 0.5f - oz;
-                const float r2 = dx * dx + dy * dy + dz * dz;
-                if (r2 >= 4.0f) continue;
-                const uint8_t f = s_sat[(i + ox + 1) + kVol * ((j + oy + 1) + kVol * (k + oz + 1))];
-                sat = sat && (f & 1);
-                const float vv = (f & 2) ? 1.f : 0.f;
-                const bool nearp = r2 < 1.0f;
-                const float Wt = nearp ? tp.Wn : tp.Wf, Dt = nearp ? tp.Dn : tp.Df;
-                kw += Wt * vv;
-                kx += Dt * dx * vv;
-                ky += Dt * dy * vv;
-                kz += Dt * dz * vv;
+    // point handled in the epilogue: c = threadIdx.x / 4, part = threadIdx.x % 4
+    const int c = threadIdx.x >> 2, part = threadIdx.x & 3;
+    const int ci_ = c & 3, cj = (c >> 2) & 3, ck = c >> 4;
+    for (int64_t ci = blockIdx.x; ci < n_core; ci += gridDim.x) {
+        __syncthreads();   // previous package's LDS reads are done
+        stage_window(phi, nbr, core_list[ci], s_phi, s_ids);
+        saturation_flags(s_phi, inv_h, inv_2h, s_sat);
+        Tile T;
+        forward_tile(WindowX{s_phi, 16 * w, inv_h}, W, s_a1 + 16 * w * kH, s_a2 + 16 * w * kH, nullptr, T, lane);
+        if (r < kOut)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) s_y[16 * w + 4 * q + i][r] = T.y[i];
+        __syncthreads();
+        // saturated taps: 32 taps split over the point's 4 lanes (taps t = part, part + 4, ...)
+        bool sat = true;
+        float kw = 0.f, kx = 0.f, ky = 0.f, kz = 0.f;
+        int tap = 0;
+        for (int oz = -1; oz <= 2; ++oz)
+            for (int oy = -1; oy <= 2; ++oy)
+                for (int ox = -1; ox <= 2; ++ox) {
+                    const float dx = 0.5f - ox, dy = 0.5f - oy, dz = 0.5f - oz;
+                    const float r2 = dx * dx + dy * dy + dz * dz;
+                    if (r2 >= 4.0f) continue;
+                    if ((tap++ & 3) != part) continue;
+                    const uint8_t f = s_sat[(ci_ + ox + 1) + kVol * ((cj + oy + 1) + kVol * (ck + oz + 1))];
+                    sat = sat && (f & 1);
+                    const float vv = (f & 2) ? 1.f : 0.f;
+                    const bool nearp = r2 < 1.0f;
+                    const float Wt = nearp ? tp.Wn : tp.Wf, Dt = nearp ? tp.Dn : tp.Df;
+                    kw += Wt * vv;
+                    kx += Dt * dx * vv;
+                    ky += Dt * dy * vv;
+                    kz += Dt * dz * vv;
+                }
+        // combine the 4 lanes of the point (adjacent lanes)
+#pragma unroll
+        for (int m = 1; m < 4; m <<= 1) {
+            kw += __shfl_xor(kw, m);
+            kx += __shfl_xor(kx, m);
+            ky += __shfl_xor(ky, m);
+            kz += __shfl_xor(kz, m);
+            const int other = __shfl_xor(sat ? 1 : 0, m);   // every lane takes part in the shuffle
+            sat = sat && other != 0;
+        }
+        // non-planarity: mean squared residual after the window's least-squares
+        // affine fit.  The basis 1, ox, oy, oz (offsets centred at 2.5) is
+        // orthogonal on the window, so the residual is sum x^2 minus the
+        // squared projections: 216 c0^2 + 630 (cx^2 + cy^2 + cz^2).
+        float s0 = 0.f, s2 = 0.f, sx = 0.f, sy = 0.f, sz = 0.f;
+        for (int ez = 0; ez < 6; ++ez)
+            for (int ey = 0; ey < 6; ++ey) {
+                if (((ez * 6 + ey) & 3) != part) continue;
+                const float *row = s_phi + ci_ + kWin * ((cj + ey) + kWin * (ck + ez));
+#pragma unroll
+                for (int ex = 0; ex < 6; ++ex) {
+                    const float v = row[ex] * inv_h;
+                    s0 += v;
+                    s2 += v * v;
+                    sx += (ex - 2.5f) * v;
+                    sy += (ey - 2.5f) * v;
+                    sz += (ez - 2.5f) * v;
+                }
             }
-    if (!sat) {
-        // non-planarity: mean squared residual of the window after its
-        // least-squares affine fit (the affine basis is orthogonal on the window)
-        const float *f = s_phi;
-        float s0 = 0.f, sx = 0.f, sy = 0.f, sz = 0.f;
-        for (int e = 0; e < kIn; ++e) {
-            const int ex = e % 6, ey = (e / 6) % 6, ez = e / 36;
-            const float v = f[(i + ex) + kWin * ((j + ey) + kWin * (k + ez))] * inv_h;
-            s0 += v;
-            sx += (ex - 2.5f) * v;
-            sy += (ey - 2.5f) * v;
-            sz += (ez - 2.5f) * v;
+#pragma unroll
+        for (int m = 1; m < 4; m <<= 1) {
+            s0 += __shfl_xor(s0, m);
+            s2 += __shfl_xor(s2, m);
+            sx += __shfl_xor(sx, m);
+            sy += __shfl_xor(sy, m);
+            sz += __shfl_xor(sz, m);
         }
-        const float c0 = s0 / 216.f, cx = sx / 630.f, cy = sy / 630.f, cz = sz / 630.f;
-        float res = 0.f;
-        for (int e = 0; e < kIn; ++e) {
-            const int ex = e % 6, ey = (e / 6) % 6, ez = e / 36;
-            const float v = f[(i + ex) + kWin * ((j + ey) + kWin * (k + ez))] * inv_h;
-            const float d = v - c0 - cx * (ex - 2.5f) - cy * (ey - 2.5f) - cz * (ez - 2.5f);
-            res += d * d;
-        }
-        res *= 1.0f / 216.f;
-        const float y0 = s_y[c][0];
-        if (res <= tau && y0 >= kw_lo && y0 <= kw_hi) {
-            kw = y0;
-            kx = s_y[c][1];
-            ky = s_y[c][2];
-            kz = s_y[c][3];
-        } else {
-            fb_list[atomicAdd(fb_count, 1u)] = (uint32_t)o;
-            return;
+        const float res = (s2 - s0 * s0 / 216.f - (sx * sx + sy * sy + sz * sz) / 630.f) * (1.0f / 216.f);
+        if (part == 0) {
+            const int64_t o = ci * 64 + c, stride = n_core * 64;
+            bool write = true;
+            if (!sat) {
+                const float y0 = s_y[c][0];
+                if (res <= tau && y0 >= kw_lo && y0 <= kw_hi) {
+                    kw = y0;
+                    kx = s_y[c][1];
+                    ky = s_y[c][2];
+                    kz = s_y[c][3];
+                } else {
+                    fb_list[atomicAdd(fb_count, 1u)] = (uint32_t)o;
+                    write = false;
+                }
+            }
+            if (write) {
+                out[o] = kw;
+                out[stride + o] = kx;
+                out[2 * stride + o] = ky;
+                out[3 * stride + o] = kz;
+            }
         }
     }
-    out[o] = kw;
-    out[stride + o] = kx;
-    out[2 * stride + o] = ky;
-    out[3 * stride + o] = kz;
 }
 
 // Plain integral of single cells (the fallback): the 32 taps of the cell's
@@ -819,7 +862,8 @@ sgrid_status integrals_learned(const sgrid_grid *g, const float *phi, const sgri
     if (g->n_core == 0) return SGRID_OK;
     SG_REQUIRE(g->n_core <= kMaxGrid, "too many core packages");
     const float inv_h = (float)(1.0 / g->h), inv_2h = (float)(0.5 / g->h);
-    hipLaunchKernelGGL(learned_kernel, dim3((unsigned)g->n_core), dim3(256), 0, st, m->dev(), phi, g->nbr,
+    const int64_t nwg = g->n_core < (int64_t)cu_count() ? g->n_core : (int64_t)cu_count();
+    hipLaunchKernelGGL(learned_kernel, dim3((unsigned)nwg), dim3(256), 0, st, m->dev(), phi, g->nbr,
                        g->core_list, g->n_core, inv_h, inv_2h, m->gate_tau, m->kw_lo, m->kw_hi, out, m->fallback,
                        count);
     SG_CHECK_LAUNCH("learned integrals");

@@ -262,8 +262,9 @@ __global__ __launch_bounds__(256) void reinit_lds_kernel(const T *__restrict__ s
 
 // Central-difference gradient over packages [0, P + 2); far-field rows get 0.
 // PACKED = false writes the three components as separate [P^][64] arrays;
-// PACKED = true writes one [P^][64] array of (phi, gx, gy, gz) quadruples, the
-// layout the packed probe gathers with one 16-byte (FP32) load per corner.
+// PACKED = true writes one [P^][64] array of (phi, gx, gy, gz) quadruples in
+// the blocked point order (blocked_index), the layout the packed probe gathers
+// with one 16-byte (FP32) load per corner.
 template <typename T, bool PACKED>
 __global__ __launch_bounds__(256) void gradient_kernel(const T *__restrict__ phi, T *__restrict__ out,
                                                        const uint32_t *__restrict__ face, int64_t n_total,
@@ -293,9 +294,11 @@ __global__ __launch_bounds__(256) void gradient_kernel(const T *__restrict__ phi
         }
     }
     if (PACKED) {
-        T *o = out + (p * 64 + r * 4) * 4;
+        const int j = r & 3, k = r >> 2;
+        T *o = out + p * 64 * 4;
 #pragma unroll
-        for (int i = 0; i < 4; ++i) store_row(o + 4 * i, Row<T>{{c.v[i], ox.v[i], oy.v[i], oz.v[i]}});
+        for (int i = 0; i < 4; ++i)
+            store_row(o + 4 * blocked_index(i, j, k), Row<T>{{c.v[i], ox.v[i], oy.v[i], oz.v[i]}});
     } else {
         T *gx = out + p * 64 + r * 4;
         store_row(gx, ox);

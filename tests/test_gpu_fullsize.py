@@ -1,0 +1,96 @@
+"""Full-size parity (GPU): the prism512 workload exactly as bench.py runs it
+(default sweep configuration, packed gradient and probe, plain integrals),
+compared with the oracle on every point, every particle and every core
+point; and the 64-shape batch in its autotuned, graph-replayed form against
+each member's own sweep."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+G0 = 0.865663036
+
+
+@pytest.fixture(scope="module")
+def sg():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2512_11473_amd as sg
+    sg.load()
+    sg.set_sweep_config(0, 1)
+    return sg
+
+
+def _blocked():
+    loc = np.arange(64)
+    i, j, k = loc % 4, (loc // 4) % 4, loc // 16
+    return 8 * ((i >> 1) + 2 * (j >> 1) + 4 * (k >> 1)) + ((i & 1) + 2 * (j & 1) + 4 * (k & 1))
+
+
+def test_prism512_full_pipeline(sg):
+    from paper_2512_11473_amd import workload
+    cfg = synth.config_c2()
+    pos = synth.particles_for(cfg)
+    wl = workload.setup(cfg["shape"], cfg["N"], cfg["noise_amp"], cfg["noise_seed"], particles=pos)
+    g = sg.build_packages(wl.coarse, wl.h)          # the build as the benchmark step runs it
+    assert g.n_packages == 124308 and g.n_core == 56880
+    sg.reinitialize(g, wl.phi, wl.scratch, cfg["n_iter"])
+    packed = torch.empty((g.n_total, 64, 4), device="cuda")
+    sg.compute_gradient_packed(g, wl.phi, packed)
+    sg.probe_particles_packed(g, packed, wl.pos, wl.phi_p, wl.nrm_p, binned=True)
+    integ = torch.empty((4, g.n_core * 64), device="cuda")
+    sg.compute_near_surface_integrals(g, wl.phi, integ)
+    torch.cuda.synchronize()
+
+    run = oracle.setup(cfg["shape"], cfg["N"], cfg["noise_amp"], cfg["noise_seed"])
+    t = {k: v.cpu().numpy() for k, v in g.tables().items()}
+    assert np.array_equal(t["cell_pkg"].view(np.uint32), run.tab.cell_pkg)
+    assert np.array_equal(t["pkg_nbr"].view(np.uint32), run.tab.nbr)
+    oracle.run_plain(run, cfg["n_iter"])
+    h = run.h
+    pts = wl.points.ravel()
+    err = np.abs(wl.phi[2:].double().cpu().numpy().ravel() - run.phi[pts])
+    assert err.max() <= 1e-5 * h, f"max |dphi| = {err.max() / h:.3e} h"
+    unpacked = packed[:, torch.from_numpy(_blocked()).cuda(), :]
+    gg = unpacked[2:, :, 1:].double().cpu().numpy().reshape(-1, 3).T
+    assert np.max(np.abs(gg - run.grad[:, pts])) <= 1e-5
+    ref_phi, ref_nrm, ref_g = oracle.probe(run.N, h, run.B, run.tab.cell_pkg, run.phi, run.grad,
+                                           pos.astype(np.float64), with_gradient=True)
+    assert np.max(np.abs(wl.phi_p.double().cpu().numpy() - ref_phi)) <= 1e-5 * h
+    ok = np.linalg.norm(ref_g, axis=1) > 0.25
+    assert ok.mean() > 0.95
+    assert np.max(np.abs(wl.nrm_p.double().cpu().numpy()[ok] - ref_nrm[ok])) <= 1e-5
+    core = t["core_list"].astype(np.int64)
+    ref = oracle.integrals(run.N, h, run.B, run.phi, wl.points[core - 2].ravel())
+    got = integ.double().cpu().numpy().T
+    assert np.max(np.abs(got[:, 0] - ref[:, 0])) <= 1e-5
+    assert np.max(np.abs(got[:, 1:] - ref[:, 1:])) <= 1e-5 * G0
+
+
+def test_batch64_full_size(sg):
+    from paper_2512_11473_amd import workload
+    cfg = synth.config_c3()
+    bw = workload.setup_batch(cfg["shapes"], cfg["noise_amp"])
+    assert len(bw.parts) == 64
+    bw.batch.autotune(bw.phi0, bw.scratch, reps=2)
+    bw.reset()
+    bw.batch.reinitialize(bw.phi, bw.scratch, cfg["n_iter"], use_graph=True)
+    torch.cuda.synchronize()
+    counts = np.array([p.grid.n_packages for p in bw.parts])
+    pick = sorted({int(np.argmin(counts)), int(np.argmax(counts)), 7, 31, 63})
+    for k in pick:
+        p = bw.parts[k]
+        p.reset()
+        sg.reinitialize(p.grid, p.phi, p.scratch, cfg["n_iter"])
+        assert torch.equal(bw.slice(k, bw.phi), p.phi), k
+    # the smallest member against the oracle
+    k = int(np.argmin(counts))
+    spec = cfg["shapes"][k]
+    run = oracle.setup(spec["shape"], spec["N"], cfg["noise_amp"], spec["noise_seed"])
+    oracle.run_plain(run, cfg["n_iter"])
+    got = bw.slice(k, bw.phi)[2:].double().cpu().numpy().ravel()
+    assert np.max(np.abs(got - run.phi[bw.parts[k].points.ravel()])) <= 1e-5 * run.h

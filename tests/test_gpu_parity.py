@@ -173,11 +173,19 @@ def test_sphere64_pipeline(sg, dtype, tol_h):
     # packed (phi, g) layout gives identical probe results
     packed = torch.empty((wl.grid.n_total, 64, 4), dtype=dtype, device="cuda")
     sg.compute_gradient_packed(wl.grid, wl.phi, packed)
-    assert torch.equal(packed[..., 0], wl.phi)
-    assert torch.equal(packed[..., 1:].permute(2, 0, 1), wl.grad)
+    loc = np.arange(64)
+    i, j, k = loc % 4, (loc // 4) % 4, loc // 16
+    blk = torch.from_numpy(8 * ((i >> 1) + 2 * (j >> 1) + 4 * (k >> 1)) + ((i & 1) + 2 * (j & 1) + 4 * (k & 1))).cuda()
+    unpacked = packed[:, blk, :]             # back to the i + 4j + 16k order
+    assert torch.equal(unpacked[..., 0], wl.phi)
+    assert torch.equal(unpacked[..., 1:].permute(2, 0, 1), wl.grad)
     pp2, nn2 = torch.empty_like(wl.phi_p), torch.empty_like(wl.nrm_p)
     sg.probe_particles_packed(wl.grid, packed, wl.pos, pp2, nn2)
     assert torch.equal(pp2, wl.phi_p) and torch.equal(nn2, wl.nrm_p)
+    # binned (counting-sorted) probe: same values in input order
+    pp3, nn3 = torch.full_like(wl.phi_p, float("nan")), torch.full_like(wl.nrm_p, float("nan"))
+    sg.probe_particles_packed(wl.grid, packed, wl.pos, pp3, nn3, binned=True)
+    assert torch.equal(pp3, wl.phi_p) and torch.equal(nn3, wl.nrm_p)
 
 
 def test_sphere64_gradient_on_initial_field(sg):
