@@ -8,8 +8,7 @@ surface, plain near-surface integrals on every core point.
 
 One step = one pass of the whole hot path over resident inputs: package
 build from the coarse distances, phi reset from phi0 (device copy), 100
-reinitialisation sweeps, packed gradient, binned packed probe, plain
-integrals.
+reinitialisation sweeps, packed gradient, packed probe, plain integrals.
 Inputs are generated once and resident in HBM before timing starts.
 
 `value` = package-cell updates (64 P n_iter per step) per second of
@@ -178,7 +177,7 @@ def bench_prism(args, log):
         sg.compute_gradient_packed(g, wl.phi, packed)
         mark("grad", 1)
         mark("probe", 0)
-        sg.probe_particles_packed(g, packed, wl.pos, wl.phi_p, wl.nrm_p, binned=True)
+        sg.probe_particles_packed(g, packed, wl.pos, wl.phi_p, wl.nrm_p)
         mark("probe", 1)
         mark("integ", 0)
         sg.compute_near_surface_integrals(g, wl.phi, integ)
@@ -220,7 +219,7 @@ def bench_prism(args, log):
         "breakdown_ms": {k: acc[k] / K for k in acc},
         "reinit_updates_per_s": upd_step / (reinit_ms * 1e-3),
         "probes_per_s": wl.pos.shape[0] / (acc["probe"] / K * 1e-3),
-        "probe_particle_order": "as generated (random over the surface), binned by home package in the library",
+        "probe_particle_order": "as generated (random over the surface)",
         "integral_cells_per_s": n_core * 64 / (acc["integ"] / K * 1e-3),
         "roofline": {"bound": "hbm", "kernel": "reinit sweep", "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(bytes_launch),

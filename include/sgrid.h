@@ -73,6 +73,8 @@ typedef struct {
     const uint8_t *pkg_type;     /* device [P^]: 0 far field, 1 core, 2 inner */
     const uint32_t *pkg_nbr;     /* device [P^][27]: neighbour package ids */
     const uint32_t *core_list;   /* device [n_core]: ids of the core packages, ascending */
+    const uint32_t *sweep_order; /* device [P]: activated package ids in Morton (Z-curve) order of their
+                                    coarse cells; the order of sweep variant 3 */
 } sgrid_info;
 
 /* Text of the last failure on this thread ("" if none). */
@@ -158,18 +160,6 @@ sgrid_status sgrid_probe_particles(const sgrid_grid *grid, sgrid_dtype dtype, co
 
 /* sgrid_probe_particles on the packed (phi, g) array of sgrid_compute_gradient_packed. */
 sgrid_status sgrid_probe_particles_packed(const sgrid_grid *grid, sgrid_dtype dtype, const void *packed_dev,
-                                          const void *pos_dev, int64_t n, void *phi_out_dev,
-                                          void *normal_out_dev, void *stream);
-
-/*
- * sgrid_probe_particles_packed for particles in any order, through a counting
- * sort by home package: the particles of one package are probed together, so
- * its cache lines are fetched once, and results are written back in input
- * order.  Results are identical to sgrid_probe_particles_packed.  Uses a
- * workspace cached on the grid (12 bytes per particle plus 4 per package);
- * calls on one grid from different streams must not overlap.
- */
-sgrid_status sgrid_probe_particles_binned(const sgrid_grid *grid, sgrid_dtype dtype, const void *packed_dev,
                                           const void *pos_dev, int64_t n, void *phi_out_dev,
                                           void *normal_out_dev, void *stream);
 
@@ -291,9 +281,13 @@ sgrid_status sgrid_batch_reinitialize(sgrid_batch *batch, float *phi_dev, float 
  * neighbours between lanes (DPP row shifts), variant 1 stages each package
  * and its face halo in an LDS tile, variant 2 is variant 0 as a persistent
  * kernel whose wavefronts walk contiguous package ranges with the next face
- * row prefetched.  `groups` (1, 2, 3, 4 or 8) is, for variants 0 and 1, the
- * number of four-package sets one wavefront processes and, for variant 2, the
- * number of workgroups per compute unit.  Process-wide; default (0, 1).
+ * row prefetched, variant 3 is variant 0 over the packages in Morton order of
+ * their cells (spatial neighbours swept by the same workgroup), variant 4
+ * sweeps groups of 64 consecutive Morton-ordered packages per 1024-lane
+ * workgroup and reads halo rows of in-group neighbours from LDS.  `groups`
+ * (1, 2, 3, 4 or 8) is, for variants 0, 1 and 3, the number of four-package
+ * sets one wavefront processes, for variant 2 the number of workgroups per
+ * compute unit, and is ignored by variant 4.  Process-wide; default (0, 1).
  * Results are identical for every setting.
  */
 sgrid_status sgrid_set_sweep_config(int32_t variant, int32_t groups);

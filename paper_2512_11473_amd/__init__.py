@@ -42,7 +42,7 @@ class _Desc(ctypes.Structure):
 class _Info(ctypes.Structure):
     _fields_ = [("n_coarse", ctypes.c_int32), ("h", ctypes.c_double), ("n_packages", ctypes.c_int64),
                 ("n_core", ctypes.c_int64), ("cell_pkg", _P), ("pkg_cell", _P), ("pkg_type", _P),
-                ("pkg_nbr", _P), ("core_list", _P)]
+                ("pkg_nbr", _P), ("core_list", _P), ("sweep_order", _P)]
 
 
 _SIGNATURES = {
@@ -56,7 +56,6 @@ _SIGNATURES = {
     "sgrid_compute_gradient": (ctypes.c_int, [_P, ctypes.c_int, _P, _P, _P]),
     "sgrid_compute_gradient_packed": (ctypes.c_int, [_P, ctypes.c_int, _P, _P, _P]),
     "sgrid_probe_particles_packed": (ctypes.c_int, [_P, ctypes.c_int, _P, _P, ctypes.c_int64, _P, _P, _P]),
-    "sgrid_probe_particles_binned": (ctypes.c_int, [_P, ctypes.c_int, _P, _P, ctypes.c_int64, _P, _P, _P]),
     "sgrid_probe_particles": (ctypes.c_int, [_P, ctypes.c_int, _P, _P, _P, ctypes.c_int64, _P, _P, _P]),
     "sgrid_compute_near_surface_integrals": (ctypes.c_int, [_P, _P, _P, _P, _P, _P]),
     "sgrid_set_sweep_config": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32]),
@@ -187,6 +186,7 @@ class Grid:
             "pkg_type": grab(info.pkg_type, nt, torch.uint8, 1),
             "pkg_nbr": grab(info.pkg_nbr, nt * 27, torch.int32, 4).view(nt, 27),
             "core_list": grab(info.core_list, self.n_core, torch.int32, 4),
+            "sweep_order": grab(info.sweep_order, self.n_packages, torch.int32, 4),
         }
 
     def empty_field(self, dtype=torch.float32, components: int = 1) -> torch.Tensor:
@@ -237,7 +237,7 @@ def compute_gradient_packed(grid: Grid, phi: torch.Tensor, packed: torch.Tensor,
 
 
 def probe_particles_packed(grid: Grid, packed: torch.Tensor, pos: torch.Tensor, phi_out: torch.Tensor,
-                           normal_out: torch.Tensor, stream=None, binned: bool = False):
+                           normal_out: torch.Tensor, stream=None):
     n = pos.numel() // 3
     if pos.numel() != 3 * n or phi_out.numel() != n or normal_out.numel() != 3 * n:
         raise ValueError("pos [n,3], phi_out [n], normal_out [n,3] expected")
@@ -246,9 +246,9 @@ def probe_particles_packed(grid: Grid, packed: torch.Tensor, pos: torch.Tensor, 
             raise TypeError("all probe arrays must share the field's dtype")
     if packed.numel() != grid.n_total * 256:
         raise ValueError("packed must be [P+2, 64, 4]")
-    fn = load().sgrid_probe_particles_binned if binned else load().sgrid_probe_particles_packed
-    _check(fn(grid.handle, _dtype_code(packed), _dev(packed, "packed"), _dev(pos, "pos"), n,
-              _dev(phi_out, "phi_out"), _dev(normal_out, "normal_out"), _stream(stream)))
+    _check(load().sgrid_probe_particles_packed(grid.handle, _dtype_code(packed), _dev(packed, "packed"),
+                                               _dev(pos, "pos"), n, _dev(phi_out, "phi_out"),
+                                               _dev(normal_out, "normal_out"), _stream(stream)))
 
 
 def probe_particles(grid: Grid, phi: torch.Tensor, grad: torch.Tensor, pos: torch.Tensor,

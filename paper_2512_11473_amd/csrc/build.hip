@@ -301,6 +301,111 @@ __global__ __launch_bounds__(kTagBlock) void scatter_kernel(const float *__restr
     }
 }
 
+// Sweep order: the activated packages listed in Morton (Z-curve) order of
+// their coarse cells, so the packages one workgroup sweeps together are
+// spatial neighbours and share their halo lines in the caches.  The codes run
+// over the enclosing power-of-two cube; codes outside the grid are skipped.
+__device__ __forceinline__ void morton_decode(int64_t code, int bits, int &x, int &y, int &z) {
+    x = y = z = 0;
+    for (int b = 0; b < bits; ++b) {
+        x |= (int)((code >> (3 * b)) & 1) << b;
+        y |= (int)((code >> (3 * b + 1)) & 1) << b;
+        z |= (int)((code >> (3 * b + 2)) & 1) << b;
+    }
+}
+
+__device__ __forceinline__ uint32_t morton_active(const uint32_t *__restrict__ cell_pkg, int M, int bits,
+                                                  int64_t code, int64_t n_codes) {
+    if (code >= n_codes) return 0u;
+    int x, y, z;
+    morton_decode(code, bits, x, y, z);
+    if (x >= M || y >= M || z >= M) return 0u;
+    const uint32_t id = cell_pkg[x + (int64_t)M * (y + (int64_t)M * z)];
+    return id >= 2u ? id : 0u;
+}
+
+__global__ __launch_bounds__(kTagBlock) void morton_count_kernel(const uint32_t *__restrict__ cell_pkg, int M, int bits,
+                                                                 int64_t n_codes, uint32_t *__restrict__ cnt) {
+    __shared__ uint32_t s_n[kTagBlock / 64];
+    const int64_t c0 = (int64_t)blockIdx.x * kCellsPerBlock + threadIdx.x;
+    uint32_t n = 0;
+#pragma unroll
+    for (int q = 0; q < kCellsPerThread; ++q)
+        n += (uint32_t)__popcll(__ballot(morton_active(cell_pkg, M, bits, c0 + (int64_t)q * kTagBlock, n_codes) != 0));
+    if ((threadIdx.x & 63) == 0) s_n[threadIdx.x >> 6] = n;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t a = 0;
+        for (int i = 0; i < kTagBlock / 64; ++i) a += s_n[i];
+        cnt[blockIdx.x] = a;
+    }
+}
+
+__global__ __launch_bounds__(kTagBlock) void morton_scatter_kernel(const uint32_t *__restrict__ cell_pkg, int M,
+                                                                   int bits, int64_t n_codes,
+                                                                   const uint32_t *__restrict__ off,
+                                                                   uint32_t *__restrict__ work) {
+    __shared__ uint32_t s_n[kCellsPerThread][kTagBlock / 64];
+    const int64_t c0 = (int64_t)blockIdx.x * kCellsPerBlock + threadIdx.x;
+    const int w = threadIdx.x >> 6;
+    uint32_t id[kCellsPerThread];
+    uint64_t ba[kCellsPerThread];
+#pragma unroll
+    for (int q = 0; q < kCellsPerThread; ++q) {
+        id[q] = morton_active(cell_pkg, M, bits, c0 + (int64_t)q * kTagBlock, n_codes);
+        ba[q] = __ballot(id[q] != 0);
+        if ((threadIdx.x & 63) == 0) s_n[q][w] = (uint32_t)__popcll(ba[q]);
+    }
+    __syncthreads();
+    uint32_t base = off[blockIdx.x];
+    const uint64_t lt = lanemask_lt();
+#pragma unroll
+    for (int q = 0; q < kCellsPerThread; ++q) {
+        uint32_t a = base;
+        for (int i = 0; i < w; ++i) a += s_n[q][i];
+        if (id[q]) work[a + (uint32_t)__popcll(ba[q] & lt)] = id[q];
+        for (int i = 0; i < kTagBlock / 64; ++i) base += s_n[q][i];
+    }
+}
+
+// Position of every package in the sweep worklist.
+__global__ __launch_bounds__(256) void worklist_pos_kernel(const uint32_t *__restrict__ work, int64_t P,
+                                                           uint32_t *__restrict__ wpos) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < P) wpos[work[e]] = (uint32_t)e;
+}
+
+// Face rows in worklist order: a neighbour in the same group of kGroup entries
+// is stored as its slot in the group (flagged with kLocal), others as its
+// package id; then the package's own id.
+__global__ __launch_bounds__(256) void sweep_face_kernel(const uint32_t *__restrict__ work,
+                                                         const uint32_t *__restrict__ face,
+                                                         const uint32_t *__restrict__ wpos, int64_t P,
+                                                         uint32_t *__restrict__ sface) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= P * 8) return;
+    const int64_t e = t >> 3;
+    const int f = (int)(t & 7);
+    const uint32_t p = work[e];
+    uint32_t v;
+    if (f < 6) {
+        const uint32_t n = face[(int64_t)p * 8 + f];
+        v = n;
+        if (n >= 2u) {
+            const uint32_t en = wpos[n];
+            if ((int64_t)en / sgrid::kGroup == e / sgrid::kGroup) v = sgrid::kLocal | (en % sgrid::kGroup);
+        }
+    } else {
+        v = f == 6 ? p : 0u;
+    }
+    sface[t] = v;
+}
+
+__global__ __launch_bounds__(256) void fill_zero_kernel(uint32_t *__restrict__ p, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0u;
+}
+
 __global__ void far_rows_kernel(uint32_t *__restrict__ pkg_cell, uint8_t *__restrict__ pkg_type) {
     if (threadIdx.x < 2) {
         pkg_cell[threadIdx.x] = sgrid::kNoCell;
@@ -350,7 +455,8 @@ __global__ __launch_bounds__(256) void nbr_kernel(const uint32_t *__restrict__ c
 
 void free_grid(sgrid_grid *g) {
     if (!g) return;
-    void *ptrs[] = {g->cell_pkg, g->pkg_cell, g->pkg_type, g->nbr, g->face, g->core_list, g->workspace, g->probe_ws};
+    void *ptrs[] = {g->cell_pkg, g->pkg_cell, g->pkg_type, g->nbr, g->face, g->core_list, g->workspace, g->work,
+                    g->sface, g->wpos};
     for (void *p : ptrs) sgrid::dev_free(p);
     delete g;
 }
@@ -447,6 +553,43 @@ extern "C" sgrid_status sgrid_build_packages(const sgrid_desc *desc, const float
     hipLaunchKernelGGL(nbr_kernel, dim3((unsigned)((nn + 255) / 256)), dim3(256), 0, st, g->cell_pkg, g->pkg_cell,
                        (int)M, nt, g->nbr, g->face);
     SG_HIP_OR_FREE(hipGetLastError());
+    // Morton-order sweep worklist (reuses the count buffers of the workspace
+    // when they are large enough, else a buffer of its own)
+    {
+        int bits = 0;
+        while ((1ll << bits) < M) ++bits;
+        const int64_t n_codes = (int64_t)1 << (3 * bits);
+        const int64_t nbm = (n_codes + kCellsPerBlock - 1) / kCellsPerBlock;
+        SG_ALLOC(g->work, (g->P > 0 ? g->P : 1) * 4 + ((size_t)nbm * 8 + 256), "sweep worklist");
+        uint32_t *mc = g->work + (g->P > 0 ? g->P : 1);
+        uint32_t *mz = mc + nbm;
+        hipLaunchKernelGGL(fill_zero_kernel, dim3((unsigned)((nbm + 255) / 256)), dim3(256), 0, st, mz, nbm);
+        SG_HIP_OR_FREE(hipGetLastError());
+        hipLaunchKernelGGL(morton_count_kernel, dim3((unsigned)nbm), dim3(kTagBlock), 0, st, g->cell_pkg, (int)M, bits,
+                           n_codes, mc);
+        SG_HIP_OR_FREE(hipGetLastError());
+        hipLaunchKernelGGL(scan_kernel, dim3(1), dim3(kScanThreads), 0, st, mc, mz, nbm, totals);
+        SG_HIP_OR_FREE(hipGetLastError());
+        hipLaunchKernelGGL(morton_scatter_kernel, dim3((unsigned)nbm), dim3(kTagBlock), 0, st, g->cell_pkg, (int)M,
+                           bits, n_codes, mc, g->work);
+        SG_HIP_OR_FREE(hipGetLastError());
+    }
+    // group-relative face rows of the sweep order, through the position of
+    // every package in the worklist (kept with the handle)
+    {
+        SG_ALLOC(g->sface, (g->P > 0 ? g->P : 1) * 32, "sweep face table");
+        uint32_t *wpos = nullptr;
+        SG_ALLOC(wpos, nt * 4, "worklist positions");
+        if (g->P > 0) {
+            hipLaunchKernelGGL(worklist_pos_kernel, dim3((unsigned)((g->P + 255) / 256)), dim3(256), 0, st, g->work,
+                               g->P, wpos);
+            SG_HIP_OR_FREE(hipGetLastError());
+            hipLaunchKernelGGL(sweep_face_kernel, dim3((unsigned)((g->P * 8 + 255) / 256)), dim3(256), 0, st, g->work,
+                               g->face, wpos, g->P, g->sface);
+            SG_HIP_OR_FREE(hipGetLastError());
+        }
+        g->wpos = wpos;
+    }
     *out = g;
     return SGRID_OK;
 }
@@ -463,6 +606,7 @@ extern "C" sgrid_status sgrid_get_info(const sgrid_grid *g, sgrid_info *out) {
     out->pkg_type = g->pkg_type;
     out->pkg_nbr = g->nbr;
     out->core_list = g->core_list;
+    out->sweep_order = g->work;
     return SGRID_OK;
 }
 

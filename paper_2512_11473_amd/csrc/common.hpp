@@ -31,6 +31,11 @@ constexpr uint32_t kFarPos = 1u;
 constexpr uint32_t kNoCell = 0xFFFFFFFFu;
 constexpr double kFarFieldInH = 16.0;
 
+// Sweep groups: 64 consecutive worklist entries (Morton order) are swept by one
+// workgroup, which shares their rows through LDS.
+constexpr int kGroup = 64;
+constexpr uint32_t kLocal = 0x80000000u;
+
 // Face slots of the 27-entry neighbour table, in the order the sweeps use:
 // -x, +x, -y, +y, -z, +z.
 constexpr int kFaceSlot[6] = {12, 14, 10, 16, 4, 22};
@@ -49,9 +54,11 @@ struct sgrid_grid {
     uint32_t *nbr = nullptr;        // [P+2][27]
     uint32_t *face = nullptr;       // [P+2][8]: the six face slots of nbr, then two pads
     uint32_t *core_list = nullptr;  // [n_core]
+    uint32_t *work = nullptr;       // [P]: activated package ids in Morton order of their cells
+    uint32_t *sface = nullptr;      // [P][8]: per worklist position: six face neighbours (package id, or
+                                    // group slot | kLocal when in the same 64-package group), own id, pad
+    uint32_t *wpos = nullptr;       // [P+2]: position of each package in the worklist
     void *workspace = nullptr;      // build scratch, kept until destroy
-    void *probe_ws = nullptr;       // binned-probe scratch (grows on demand)
-    size_t probe_ws_bytes = 0;
     int64_t total() const { return P + 2; }
 };
 

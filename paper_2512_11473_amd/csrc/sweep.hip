@@ -15,6 +15,9 @@
 // into a per-package tile in LDS and reads the neighbours back from there.
 #include "common.hpp"
 
+using sgrid::kGroup;
+using sgrid::kLocal;
+
 namespace {
 
 template <typename T>
@@ -181,6 +184,89 @@ __global__ __launch_bounds__(256) void reinit_dpp_kernel(const T *__restrict__ s
     }
 }
 
+// Worklist variant: the DPP sweep over the packages in Morton order of their
+// cells (the build's worklist), so the sixteen packages of a workgroup are
+// spatial neighbours and most halo rows come from lines the workgroup itself
+// brings into the caches.  G sets of four packages per wavefront.
+template <typename T, int G>
+__global__ __launch_bounds__(256) void reinit_work_kernel(const T *__restrict__ src, T *__restrict__ dst,
+                                                          const uint32_t *__restrict__ face,
+                                                          const uint32_t *__restrict__ work, int64_t P,
+                                                          int64_t n_blocks, T h2, T inv_h, T dt) {
+    const int64_t b = xcd_block(blockIdx.x, n_blocks);
+    const int lane = threadIdx.x & 63;
+    const int r = lane & 15;
+    const int64_t e0 = (b * 4 + (threadIdx.x >> 6)) * (4 * G) + (lane >> 4);
+    Loads<T> l[G];
+    int64_t p[G];
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+        const int64_t e = e0 + 4 * g;
+        p[g] = e < P ? (int64_t)work[e] : -1;
+        if (p[g] >= 0) issue_loads(src, face, p[g], r, l[g]);
+    }
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+        const Stencil<T> s = assemble(r, l[g]);
+        if (p[g] >= 0) store_row(dst + p[g] * 64 + r * 4, reinit_row(s, h2, inv_h, dt));
+    }
+}
+
+// Shared-group variant: one workgroup of 1024 lanes sweeps a group of 64
+// consecutive worklist entries (Morton order, so spatially compact).  Each
+// package's rows go into LDS first; a halo row whose package belongs to the
+// same group is read from LDS, the others from memory.  The group-relative face
+// rows (sface) mark in-group neighbours with kLocal | slot.
+template <typename T>
+__device__ __forceinline__ T halo_value(const T *__restrict__ src, const T (*tile)[64], uint32_t f, int off) {
+    return (f & kLocal) ? tile[f & (kGroup - 1)][off] : src[(int64_t)f * 64 + off];
+}
+
+template <typename T>
+__device__ __forceinline__ Row<T> halo_row(const T *__restrict__ src, const T (*tile)[64], uint32_t f, int off) {
+    if (f & kLocal) {
+        const T *t = tile[f & (kGroup - 1)] + off;
+        return Row<T>{{t[0], t[1], t[2], t[3]}};
+    }
+    return load_row(src + (int64_t)f * 64 + off);
+}
+
+template <typename T>
+__global__ __launch_bounds__(1024) void reinit_share_kernel(const T *__restrict__ src, T *__restrict__ dst,
+                                                            const uint32_t *__restrict__ work,
+                                                            const uint32_t *__restrict__ sface, int64_t P,
+                                                            int64_t n_blocks, T h2, T inv_h, T dt) {
+    __shared__ T tile[kGroup][64];
+    const int64_t b = xcd_block(blockIdx.x, n_blocks);
+    const int lane = threadIdx.x & 63;
+    const int r = lane & 15, j = r & 3, k = r >> 2;
+    const int slot = threadIdx.x >> 4;
+    const int64_t e = b * kGroup + slot;
+    const bool live = e < P;
+    uint4 f0 = make_uint4(0, 0, 0, 0);
+    uint2 f1 = make_uint2(0, 0);
+    int64_t p = 0;
+    Row<T> c;
+    if (live) {
+        p = work[e];
+        f0 = *reinterpret_cast<const uint4 *>(sface + e * 8);
+        f1 = *reinterpret_cast<const uint2 *>(sface + e * 8 + 4);
+        c = load_row(src + p * 64 + r * 4);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) tile[slot][r * 4 + i] = c.v[i];
+    }
+    __syncthreads();
+    if (!live) return;
+    Loads<T> l;
+    l.c = c;
+    l.xm = halo_value(src, tile, f0.x, r * 4 + 3);
+    l.xp = halo_value(src, tile, f0.y, r * 4);
+    if (j == 0 || j == 3) l.yh = halo_row(src, tile, j == 0 ? f0.z : f0.w, (j == 0 ? 3 + 4 * k : 4 * k) * 4);
+    if (k == 0 || k == 3) l.zh = halo_row(src, tile, k == 0 ? f1.x : f1.y, (k == 0 ? j + 12 : j) * 4);
+    const Stencil<T> s = assemble(r, l);
+    store_row(dst + p * 64 + r * 4, reinit_row(s, h2, inv_h, dt));
+}
+
 // Persistent variant: a fixed grid of a few workgroups per CU; each wavefront
 // walks a contiguous range of four-package sets and loads the face row of the
 // next set while the current set's data loads are in flight, so the
@@ -338,7 +424,19 @@ static sgrid_status launch_reinit_sweep(const sgrid_grid *g, const T *src, T *ds
     const int64_t nb = (g->P + per_block - 1) / per_block;
     const T h2 = (T)(g->h * g->h), inv_h = (T)(1.0 / g->h), dt = (T)(0.5 * g->h);
     const dim3 grid((unsigned)nb), block(256);
-    if (cfg.variant == 2) {
+    if (cfg.variant == 4) {
+        const int64_t ng = (g->P + kGroup - 1) / kGroup;
+        hipLaunchKernelGGL(reinit_share_kernel<T>, dim3((unsigned)ng), dim3(1024), 0, st, src, dst, g->work, g->sface,
+                           g->P, ng, h2, inv_h, dt);
+    } else if (cfg.variant == 3) {
+        switch (cfg.groups) {
+            case 1: hipLaunchKernelGGL((reinit_work_kernel<T, 1>), grid, block, 0, st, src, dst, g->face, g->work, g->P, nb, h2, inv_h, dt); break;
+            case 2: hipLaunchKernelGGL((reinit_work_kernel<T, 2>), grid, block, 0, st, src, dst, g->face, g->work, g->P, nb, h2, inv_h, dt); break;
+            case 3: hipLaunchKernelGGL((reinit_work_kernel<T, 3>), grid, block, 0, st, src, dst, g->face, g->work, g->P, nb, h2, inv_h, dt); break;
+            case 4: hipLaunchKernelGGL((reinit_work_kernel<T, 4>), grid, block, 0, st, src, dst, g->face, g->work, g->P, nb, h2, inv_h, dt); break;
+            default: hipLaunchKernelGGL((reinit_work_kernel<T, 8>), grid, block, 0, st, src, dst, g->face, g->work, g->P, nb, h2, inv_h, dt); break;
+        }
+    } else if (cfg.variant == 2) {
         const int64_t n_sets = (g->P + 3) / 4;
         int64_t nbp = (int64_t)cu_count() * cfg.groups;
         const int64_t waves = nbp * 4;
@@ -388,7 +486,7 @@ template sgrid_status reinit_impl<float>(const sgrid_grid *, float *, float *, i
 
 extern "C" sgrid_status sgrid_set_sweep_config(int32_t variant, int32_t groups) {
     sgrid::clear_error();
-    SG_REQUIRE(variant >= 0 && variant <= 2, "sweep variant must be 0, 1 or 2 (got %d)", variant);
+    SG_REQUIRE(variant >= 0 && variant <= 4, "sweep variant must be 0..4 (got %d)", variant);
     SG_REQUIRE(groups == 1 || groups == 2 || groups == 3 || groups == 4 || groups == 8, "groups must be 1, 2, 3, 4 or 8 (got %d)", groups);
     sgrid::set_sweep_config(variant, groups);
     return SGRID_OK;

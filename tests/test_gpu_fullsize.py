@@ -41,7 +41,7 @@ def test_prism512_full_pipeline(sg):
     sg.reinitialize(g, wl.phi, wl.scratch, cfg["n_iter"])
     packed = torch.empty((g.n_total, 64, 4), device="cuda")
     sg.compute_gradient_packed(g, wl.phi, packed)
-    sg.probe_particles_packed(g, packed, wl.pos, wl.phi_p, wl.nrm_p, binned=True)
+    sg.probe_particles_packed(g, packed, wl.pos, wl.phi_p, wl.nrm_p)
     integ = torch.empty((4, g.n_core * 64), device="cuda")
     sg.compute_near_surface_integrals(g, wl.phi, integ)
     torch.cuda.synchronize()

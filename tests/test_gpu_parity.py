@@ -34,6 +34,14 @@ def _gpu_tables(sg, d, h):
     return g, t
 
 
+def _morton_key(cells, M):
+    x, y, z = cells % M, (cells // M) % M, cells // (M * M)
+    key = np.zeros_like(cells)
+    for b in range(max(1, int(M - 1).bit_length())):
+        key |= ((x >> b) & 1) << (3 * b) | ((y >> b) & 1) << (3 * b + 1) | ((z >> b) & 1) << (3 * b + 2)
+    return key
+
+
 def _assert_tables_equal(t, ref: oracle.Tables):
     assert np.array_equal(t["cell_pkg"].view(np.uint32), ref.cell_pkg)
     assert np.array_equal(t["pkg_cell"].view(np.uint32), ref.pkg_cell)
@@ -41,6 +49,10 @@ def _assert_tables_equal(t, ref: oracle.Tables):
     assert np.array_equal(t["pkg_nbr"].view(np.uint32), ref.nbr)
     core = np.nonzero(ref.pkg_type == 1)[0].astype(np.uint32)
     assert np.array_equal(t["core_list"].view(np.uint32), core)
+    # sweep order: every activated package once, in Morton order of its cell
+    cells = ref.pkg_cell[2:].astype(np.int64)
+    order = np.argsort(_morton_key(cells, ref.M), kind="stable") + 2
+    assert np.array_equal(t["sweep_order"].view(np.uint32), order.astype(np.uint32))
 
 
 # --------------------------------------------------------------------------
@@ -182,10 +194,6 @@ def test_sphere64_pipeline(sg, dtype, tol_h):
     pp2, nn2 = torch.empty_like(wl.phi_p), torch.empty_like(wl.nrm_p)
     sg.probe_particles_packed(wl.grid, packed, wl.pos, pp2, nn2)
     assert torch.equal(pp2, wl.phi_p) and torch.equal(nn2, wl.nrm_p)
-    # binned (counting-sorted) probe: same values in input order
-    pp3, nn3 = torch.full_like(wl.phi_p, float("nan")), torch.full_like(wl.nrm_p, float("nan"))
-    sg.probe_particles_packed(wl.grid, packed, wl.pos, pp3, nn3, binned=True)
-    assert torch.equal(pp3, wl.phi_p) and torch.equal(nn3, wl.nrm_p)
 
 
 def test_sphere64_gradient_on_initial_field(sg):
@@ -228,7 +236,8 @@ def test_sweep_variants_identical(sg):
     from paper_2512_11473_amd import workload
     wl = workload.setup(cfg["shape"], cfg["N"], cfg["noise_amp"], cfg["noise_seed"])
     results = []
-    for variant, groups in [(0, 1), (0, 2), (0, 3), (0, 4), (0, 8), (1, 1), (1, 2), (1, 3), (2, 1), (2, 2), (2, 4), (2, 8)]:
+    for variant, groups in [(0, 1), (0, 2), (0, 3), (0, 4), (0, 8), (1, 1), (1, 2), (1, 3), (2, 1), (2, 2), (2, 4), (2, 8),
+                           (3, 1), (3, 2), (3, 4), (4, 1)]:
         sg.set_sweep_config(variant, groups)
         wl.reset()
         sg.reinitialize(wl.grid, wl.phi, wl.scratch, 7)
