@@ -633,43 +633,29 @@ __device__ __forceinline__ Taps make_taps() {
 
 __global__ __launch_bounds__(256) void zero_u32_kernel(uint32_t *p) { *p = 0u; }
 
-// Persistent learned-integral kernel: one workgroup per compute unit keeps
-// the BF16 weights (94 KB) in LDS and walks the core packages; per package
-// the 9^3 window is staged, saturation flags are set, four wavefronts run the
-// network on 16 points each, and four lanes per point evaluate the exact
-// saturated sum or the gate.
-constexpr int kW1N = kH * kInPad, kW2N = kH * kH, kW3N = 16 * kH;
-
-__global__ __launch_bounds__(256) void learned_kernel(MlpDev Wg, const float *__restrict__ phi,
+// Learned-integral kernel: one workgroup per core package.  The 9^3 window is
+// staged, saturation flags are set, four wavefronts run the network on 16
+// points each (BF16 weights from L2), and four lanes per point evaluate the
+// exact saturated sum or the gate.
+__global__ __launch_bounds__(256) void learned_kernel(MlpDev W, const float *__restrict__ phi,
                                                       const uint32_t *__restrict__ nbr,
                                                       const uint32_t *__restrict__ core_list, int64_t n_core,
                                                       float inv_h, float inv_2h, float tau, float kw_lo, float kw_hi,
                                                       float *__restrict__ out, uint32_t *__restrict__ fb_list,
                                                       uint32_t *__restrict__ fb_count) {
-    __shared__ __attribute__((aligned(16))) bf16 s_w1[kW1N];
-    __shared__ __attribute__((aligned(16))) bf16 s_w2[kW2N];
-    __shared__ __attribute__((aligned(16))) bf16 s_w3[kW3N];
     __shared__ float s_phi[kWinN];
     __shared__ uint32_t s_ids[27];
     __shared__ uint8_t s_sat[kVolN];
     __shared__ __attribute__((aligned(16))) bf16 s_a1[64 * kH];
     __shared__ __attribute__((aligned(16))) bf16 s_a2[64 * kH];
     __shared__ float s_y[64][kOut];
-    // weights into LDS once
-    for (int e = threadIdx.x; e < kW1N / 8; e += blockDim.x)
-        reinterpret_cast<bf16x8 *>(s_w1)[e] = reinterpret_cast<const bf16x8 *>(Wg.w1b)[e];
-    for (int e = threadIdx.x; e < kW2N / 8; e += blockDim.x)
-        reinterpret_cast<bf16x8 *>(s_w2)[e] = reinterpret_cast<const bf16x8 *>(Wg.w2b)[e];
-    for (int e = threadIdx.x; e < kW3N / 8; e += blockDim.x)
-        reinterpret_cast<bf16x8 *>(s_w3)[e] = reinterpret_cast<const bf16x8 *>(Wg.w3b)[e];
-    const MlpDev W{Wg.w, s_w1, s_w2, Wg.w2tb, s_w3};
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, r = lane & 15, q = lane >> 4;
     const Taps tp = make_taps();
     // point handled in the epilogue: c = threadIdx.x / 4, part = threadIdx.x % 4
     const int c = threadIdx.x >> 2, part = threadIdx.x & 3;
     const int ci_ = c & 3, cj = (c >> 2) & 3, ck = c >> 4;
-    for (int64_t ci = blockIdx.x; ci < n_core; ci += gridDim.x) {
-        __syncthreads();   // previous package's LDS reads are done
+    {
+        const int64_t ci = blockIdx.x;
         stage_window(phi, nbr, core_list[ci], s_phi, s_ids);
         saturation_flags(s_phi, inv_h, inv_2h, s_sat);
         Tile T;
@@ -862,8 +848,7 @@ sgrid_status integrals_learned(const sgrid_grid *g, const float *phi, const sgri
     if (g->n_core == 0) return SGRID_OK;
     SG_REQUIRE(g->n_core <= kMaxGrid, "too many core packages");
     const float inv_h = (float)(1.0 / g->h), inv_2h = (float)(0.5 / g->h);
-    const int64_t nwg = g->n_core < (int64_t)cu_count() ? g->n_core : (int64_t)cu_count();
-    hipLaunchKernelGGL(learned_kernel, dim3((unsigned)nwg), dim3(256), 0, st, m->dev(), phi, g->nbr,
+    hipLaunchKernelGGL(learned_kernel, dim3((unsigned)g->n_core), dim3(256), 0, st, m->dev(), phi, g->nbr,
                        g->core_list, g->n_core, inv_h, inv_2h, m->gate_tau, m->kw_lo, m->kw_hi, out, m->fallback,
                        count);
     SG_CHECK_LAUNCH("learned integrals");
