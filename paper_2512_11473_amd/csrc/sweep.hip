@@ -212,6 +212,49 @@ __global__ __launch_bounds__(256) void reinit_work_kernel(const T *__restrict__ 
     }
 }
 
+// Row-exchange variant: the y / z neighbour rows move through LDS instead of
+// DPP, which takes the exchange off the VALU.  Every wavefront writes its own
+// four packages' rows (and their y / z halo rows) into a 6 x 6 grid of rows
+// per package and reads the four neighbour rows back; a wavefront only ever
+// reads rows it wrote itself, and LDS operations of one wavefront complete in
+// order, so no workgroup barrier is needed.
+template <typename T, int G>
+__global__ __launch_bounds__(256) void reinit_rows_kernel(const T *__restrict__ src, T *__restrict__ dst,
+                                                          const uint32_t *__restrict__ face, int64_t P,
+                                                          int64_t n_blocks, T h2, T inv_h, T dt) {
+    __shared__ Row<T> rows[16][36];   // [package slot in block][(z+1) * 6 + (y+1)]
+    const int64_t b = xcd_block(blockIdx.x, n_blocks);
+    const int lane = threadIdx.x & 63;
+    const int r = lane & 15, j = r & 3, k = r >> 2;
+    const int slot = threadIdx.x >> 4;
+    Row<T> *R = rows[slot];
+    const int64_t p0 = 2 + (b * 4 + (threadIdx.x >> 6)) * (4 * G) + (lane >> 4);
+    Loads<T> l[G];
+#pragma unroll
+    for (int g = 0; g < G; ++g)
+        if (p0 + 4 * g < P + 2) issue_loads(src, face, p0 + 4 * g, r, l[g]);
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+        const int64_t p = p0 + 4 * g;
+        R[(k + 1) * 6 + (j + 1)] = l[g].c;
+        if (j == 0) R[(k + 1) * 6] = l[g].yh;
+        if (j == 3) R[(k + 1) * 6 + 5] = l[g].yh;
+        if (k == 0) R[j + 1] = l[g].zh;
+        if (k == 3) R[30 + j + 1] = l[g].zh;
+        __builtin_amdgcn_wave_barrier();
+        Stencil<T> s;
+        s.c = l[g].c;
+        s.xm = l[g].xm;
+        s.xp = l[g].xp;
+        s.ym = R[(k + 1) * 6 + j];
+        s.yp = R[(k + 1) * 6 + j + 2];
+        s.zm = R[k * 6 + (j + 1)];
+        s.zp = R[(k + 2) * 6 + (j + 1)];
+        __builtin_amdgcn_wave_barrier();
+        if (p < P + 2) store_row(dst + p * 64 + r * 4, reinit_row(s, h2, inv_h, dt));
+    }
+}
+
 // Shared-group variant: one workgroup of 1024 lanes sweeps a group of 64
 // consecutive worklist entries (Morton order, so spatially compact).  Each
 // package's rows go into LDS first; a halo row whose package belongs to the
@@ -424,7 +467,15 @@ static sgrid_status launch_reinit_sweep(const sgrid_grid *g, const T *src, T *ds
     const int64_t nb = (g->P + per_block - 1) / per_block;
     const T h2 = (T)(g->h * g->h), inv_h = (T)(1.0 / g->h), dt = (T)(0.5 * g->h);
     const dim3 grid((unsigned)nb), block(256);
-    if (cfg.variant == 4) {
+    if (cfg.variant == 5) {
+        switch (cfg.groups) {
+            case 1: hipLaunchKernelGGL((reinit_rows_kernel<T, 1>), grid, block, 0, st, src, dst, g->face, g->P, nb, h2, inv_h, dt); break;
+            case 2: hipLaunchKernelGGL((reinit_rows_kernel<T, 2>), grid, block, 0, st, src, dst, g->face, g->P, nb, h2, inv_h, dt); break;
+            case 3: hipLaunchKernelGGL((reinit_rows_kernel<T, 3>), grid, block, 0, st, src, dst, g->face, g->P, nb, h2, inv_h, dt); break;
+            case 4: hipLaunchKernelGGL((reinit_rows_kernel<T, 4>), grid, block, 0, st, src, dst, g->face, g->P, nb, h2, inv_h, dt); break;
+            default: hipLaunchKernelGGL((reinit_rows_kernel<T, 8>), grid, block, 0, st, src, dst, g->face, g->P, nb, h2, inv_h, dt); break;
+        }
+    } else if (cfg.variant == 4) {
         const int64_t ng = (g->P + kGroup - 1) / kGroup;
         hipLaunchKernelGGL(reinit_share_kernel<T>, dim3((unsigned)ng), dim3(1024), 0, st, src, dst, g->work, g->sface,
                            g->P, ng, h2, inv_h, dt);
@@ -486,7 +537,7 @@ template sgrid_status reinit_impl<float>(const sgrid_grid *, float *, float *, i
 
 extern "C" sgrid_status sgrid_set_sweep_config(int32_t variant, int32_t groups) {
     sgrid::clear_error();
-    SG_REQUIRE(variant >= 0 && variant <= 4, "sweep variant must be 0..4 (got %d)", variant);
+    SG_REQUIRE(variant >= 0 && variant <= 5, "sweep variant must be 0..5 (got %d)", variant);
     SG_REQUIRE(groups == 1 || groups == 2 || groups == 3 || groups == 4 || groups == 8, "groups must be 1, 2, 3, 4 or 8 (got %d)", groups);
     sgrid::set_sweep_config(variant, groups);
     return SGRID_OK;

@@ -22,9 +22,12 @@ run x fastest.
 from __future__ import annotations
 
 import math
+import os
+from concurrent.futures import ThreadPoolExecutor
 from typing import Dict, List, Sequence
 
 import numpy as np
+
 
 __all__ = [
     "splitmix64", "unit_noise", "sdf", "coarse_sdf", "fine_points",
@@ -32,6 +35,27 @@ __all__ = [
     "random_union", "batch_shapes", "shell_particles", "surface_particles",
     "config_c1", "config_c2", "config_c3", "config_c5",
 ]
+
+def _threads() -> int:
+    """Worker threads for chunked evaluation (numpy releases the GIL in its
+    array kernels, so chunks run in parallel)."""
+    try:
+        n = int(os.environ.get("OMP_NUM_THREADS", "0"))
+    except ValueError:
+        n = 0
+    return max(1, min(16, n or (os.cpu_count() or 1)))
+
+
+def _chunked(n: int, chunk: int, fn):
+    """Calls fn(start, stop) over [0, n) in chunks on a thread pool."""
+    starts = list(range(0, n, chunk))
+    if len(starts) <= 1:
+        for a in starts:
+            fn(a, min(a + chunk, n))
+        return
+    with ThreadPoolExecutor(max_workers=_threads()) as ex:
+        list(ex.map(lambda a: fn(a, min(a + chunk, n)), starts))
+
 
 # ---------------------------------------------------------------------------
 # Counter-based noise: SplitMix64 (Steele, Lea & Flood, "Fast splittable
@@ -181,18 +205,21 @@ def sdf(s: Dict, x: np.ndarray) -> np.ndarray:
 # Grid sampling
 # ---------------------------------------------------------------------------
 
-def coarse_sdf(s: Dict, n_coarse: int, chunk: int = 1 << 22) -> np.ndarray:
+def coarse_sdf(s: Dict, n_coarse: int, chunk: int = 1 << 20) -> np.ndarray:
     """float32 signed distance at every coarse-cell centre, x fastest, shape (M^3,).
 
     Evaluated in float64 and rounded once to float32."""
     M = int(n_coarse)
     lc = 1.0 / M
     out = np.empty(M ** 3, dtype=np.float32)
-    for start in range(0, M ** 3, chunk):
-        lin = np.arange(start, min(start + chunk, M ** 3), dtype=np.int64)
-        a, b, c = lin % M, (lin // M) % M, lin // (M * M)
-        x = (np.stack([a, b, c], axis=1).astype(np.float64) + 0.5) * lc
-        out[start:start + len(lin)] = sdf(s, x).astype(np.float32)
+
+    def work(a, b):
+        lin = np.arange(a, b, dtype=np.int64)
+        i, j, k = lin % M, (lin // M) % M, lin // (M * M)
+        x = (np.stack([i, j, k], axis=1).astype(np.float64) + 0.5) * lc
+        out[a:b] = sdf(s, x).astype(np.float32)
+
+    _chunked(M ** 3, chunk, work)
     return out
 
 
@@ -204,18 +231,21 @@ def fine_points(lin: np.ndarray, N: int) -> np.ndarray:
 
 
 def phi0_at(s: Dict, N: int, lin: np.ndarray, noise_amp: float, noise_seed: int,
-            chunk: int = 1 << 22) -> np.ndarray:
+            chunk: int = 1 << 20) -> np.ndarray:
     """Initial level-set values (float64) at fine linear indices `lin`:
     sdf(x) * (1 + noise_amp * u(seed, lin)).  The multiplicative form keeps the
     sign and the zero set of the signed distance."""
     lin = np.asarray(lin, dtype=np.int64).ravel()
     out = np.empty(lin.shape[0], dtype=np.float64)
-    for start in range(0, lin.shape[0], chunk):
-        l = lin[start:start + chunk]
+
+    def work(a, b):
+        l = lin[a:b]
         v = sdf(s, fine_points(l, N))
         if noise_amp != 0.0:
             v = v * (1.0 + noise_amp * unit_noise(noise_seed, l))
-        out[start:start + len(l)] = v
+        out[a:b] = v
+
+    _chunked(lin.shape[0], chunk, work)
     return out
 
 
@@ -315,21 +345,29 @@ def _torus_surface(s: Dict, n: int, rng) -> np.ndarray:
     return np.concatenate(pts)[:n]
 
 
-def surface_particles(s: Dict, n: int, seed: int, sigma: float) -> np.ndarray:
+def surface_particles(s: Dict, n: int, seed: int, sigma: float, chunk: int = 1 << 20) -> np.ndarray:
     """n points area-uniform on the surface of `s` plus isotropic N(0, sigma^2 I)
-    jitter, float32.  Supports prisms and (displaced) tori."""
-    rng = np.random.default_rng(seed)
-    if s["kind"] == "prism":
-        p = _prism_surface(s, n, rng)
-    elif s["kind"] in ("torus", "displaced_torus"):
-        p = _torus_surface(s, n, rng)
-    elif s["kind"] == "sphere":
-        d = rng.standard_normal((n, 3))
-        p = np.asarray(s["center"]) + s["radius"] * d / np.linalg.norm(d, axis=1, keepdims=True)
-    else:
-        raise ValueError(f"surface sampling not provided for {s['kind']!r}")
-    p = p + sigma * rng.standard_normal((n, 3))
-    return p.astype(np.float32)
+    jitter, float32.  Supports prisms, spheres and (displaced) tori.  Chunk c
+    of `chunk` points draws from the generator seeded with (seed, c), so the
+    set does not depend on how many threads produce it."""
+    out = np.empty((n, 3), dtype=np.float32)
+
+    def work(a, b):
+        rng = np.random.default_rng([seed, a // chunk])
+        m = b - a
+        if s["kind"] == "prism":
+            p = _prism_surface(s, m, rng)
+        elif s["kind"] in ("torus", "displaced_torus"):
+            p = _torus_surface(s, m, rng)
+        elif s["kind"] == "sphere":
+            d = rng.standard_normal((m, 3))
+            p = np.asarray(s["center"]) + s["radius"] * d / np.linalg.norm(d, axis=1, keepdims=True)
+        else:
+            raise ValueError(f"surface sampling not provided for {s['kind']!r}")
+        out[a:b] = (p + sigma * rng.standard_normal((m, 3))).astype(np.float32)
+
+    _chunked(n, chunk, work)
+    return out
 
 
 # ---------------------------------------------------------------------------

@@ -61,7 +61,7 @@ def test_invalid_arguments_rejected_without_device(lib):
     lib.sgrid_compute_near_surface_integrals.argtypes = [P, P, P, P, P, P]
     assert lib.sgrid_compute_near_surface_integrals(None, None, None, None, None, None) == E_INVALID
     lib.sgrid_set_sweep_config.argtypes = [ctypes.c_int32, ctypes.c_int32]
-    assert lib.sgrid_set_sweep_config(5, 1) == E_INVALID
+    assert lib.sgrid_set_sweep_config(6, 1) == E_INVALID
     assert lib.sgrid_set_sweep_config(0, 9) == E_INVALID
     lib.sgrid_destroy.argtypes = [P]
     assert lib.sgrid_destroy(None) == 0

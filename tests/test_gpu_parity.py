@@ -237,7 +237,7 @@ def test_sweep_variants_identical(sg):
     wl = workload.setup(cfg["shape"], cfg["N"], cfg["noise_amp"], cfg["noise_seed"])
     results = []
     for variant, groups in [(0, 1), (0, 2), (0, 3), (0, 4), (0, 8), (1, 1), (1, 2), (1, 3), (2, 1), (2, 2), (2, 4), (2, 8),
-                           (3, 1), (3, 2), (3, 4), (4, 1)]:
+                           (3, 1), (3, 2), (3, 4), (4, 1), (5, 1), (5, 2), (5, 4)]:
         sg.set_sweep_config(variant, groups)
         wl.reset()
         sg.reinitialize(wl.grid, wl.phi, wl.scratch, 7)
