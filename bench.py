@@ -16,8 +16,12 @@ whole-step time.  The learned-versus-plain comparison (surrogate trained by
 the library's kernels on points of seeded random shapes) and the oracle's CPU
 baseline are added to the same JSON line.
 
-Other workloads: --workload batch64 (64 random unions, one persistent launch
-per iteration, graph replay, autotuned configuration).
+Other workloads: --workload torus2048 (displaced torus R=0.35, r=0.1 at
+2048^3 data points, narrow band only: 100 iterations, gradient, 5e7 surface
+particles, plain and gated learned integrals on its 46 M core points; the
+CPU baseline is the oracle on a 100^3-coarse-cell crop of the band) and
+--workload batch64 (64 random unions, one persistent launch per iteration,
+graph replay, autotuned configuration).
 """
 from __future__ import annotations
 
@@ -44,12 +48,13 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="prism512", choices=["prism512", "batch64"])
+    ap.add_argument("--workload", default="prism512", choices=["prism512", "torus2048", "batch64"])
     ap.add_argument("--n-iter", type=int, default=None)
-    ap.add_argument("--particles", type=int, default=10_000_000)
+    ap.add_argument("--particles", type=int, default=None, help="default: the workload's count")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-learned", action="store_true")
-    ap.add_argument("--cpu-iters", type=int, default=8)
+    ap.add_argument("--cpu-iters", type=int, default=None,
+                    help="oracle sweeps timed for the CPU baseline (default: the workload's iteration count)")
     ap.add_argument("--train-cells", type=int, default=2_000_000)
     ap.add_argument("--epochs", type=int, default=50)
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -74,12 +79,24 @@ def measured_traffic(per_launch_algorithmic: float):
     return float(t.group(1))
 
 
+# 100^3 coarse cells around the top of the torus tube, (0.85, 0.5, 0.6): the
+# oracle's sample of the 2048^3 band
+TORUS_CROP = ((385, 206, 257), 100)
+
+
 def cpu_baseline(cfg, n_iter_sample):
     """The oracle (FP64, dense grid, OpenMP) timed on the host on a bounded
-    sample: `n_iter_sample` reinitialisation sweeps over the full band."""
+    sample: `n_iter_sample` reinitialisation sweeps over the full band, or over
+    a crop of it where the dense grid would not fit (2048^3)."""
     import oracle
     t0 = time.perf_counter()
-    run = oracle.setup(cfg["shape"], cfg["N"], cfg["noise_amp"], cfg["noise_seed"])
+    if cfg["N"] > 1024:
+        origin, extent = TORUS_CROP
+        run = oracle.setup_crop(cfg["shape"], cfg["N"], origin, extent, cfg["noise_amp"], cfg["noise_seed"])
+        where = f"a {extent}^3-coarse-cell crop of the {cfg['name']} band"
+    else:
+        run = oracle.setup(cfg["shape"], cfg["N"], cfg["noise_amp"], cfg["noise_seed"])
+        where = f"the full {cfg['name']} band"
     dense = oracle.dense_state(run.tab, run.active, run.phi0, run.B)
     setup_s = time.perf_counter() - t0
     oracle.reinit(run.N, run.h, run.B, run.active, dense, 1)       # warm-up
@@ -89,7 +106,7 @@ def cpu_baseline(cfg, n_iter_sample):
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     return {"value": len(run.active) * n_iter_sample / dt, "unit": "package-cell updates/s",
             "cores": threads, "kind": "oracle",
-            "sample": f"{n_iter_sample} FP64 reinitialisation sweeps of the oracle over the full prism512 band "
+            "sample": f"{n_iter_sample} FP64 reinitialisation sweeps of the oracle over {where} "
                       f"({len(run.active)} points, {dt:.1f} s; dense-grid setup {setup_s:.1f} s)"}
 
 
@@ -137,21 +154,43 @@ def learned_vs_plain(sg, wl, args, log):
     }
 
 
-def bench_prism(args, log):
+WORKLOAD_TEXT = {
+    "prism512": "prism512: extruded triangular prism (edges 0.6, extrusion 0.8) at 512^3, 5% noise, "
+                "100 reinitialisation iterations, gradient, 1e7 jittered particles, plain integrals on all "
+                "core points",
+    "torus2048": "torus2048: torus R=0.35, r=0.1 displaced by 0.02 x 8 seeded modes at 2048^3 (narrow band "
+                 "only), 100 reinitialisation iterations, gradient, 5e7 jittered particles, plain integrals "
+                 "on all core points; learned integrals with gate and fallback timed beside the step",
+}
+
+
+def cell_sorted(pos, N):
+    """The particles reordered by the linear index of their home coarse cell
+    (for the sorted-order probe figure)."""
+    import numpy as np
+    M = N // 4
+    c = np.clip(np.floor(pos.astype(np.float64) * M).astype(np.int64), 0, M - 1)
+    key = c[:, 0] + M * (c[:, 1] + M * c[:, 2])
+    return np.ascontiguousarray(pos[np.argsort(key, kind="stable")])
+
+
+def bench_single(args, log):
     import numpy as np
     import torch
     import paper_2512_11473_amd as sg
     import synth
     from paper_2512_11473_amd import workload
 
-    cfg = synth.config_c2()
+    cfg = synth.config_c5() if args.workload == "torus2048" else synth.config_c2()
     if args.n_iter is not None:
         cfg["n_iter"] = args.n_iter
     t0 = time.perf_counter()
     pos = synth.particles_for(cfg, args.particles)
     wl = workload.setup(cfg["shape"], cfg["N"], cfg["noise_amp"], cfg["noise_seed"], particles=pos)
+    pos_sorted = torch.from_numpy(cell_sorted(pos, cfg["N"])).cuda()
+    del pos
     setup_s = time.perf_counter() - t0
-    log(f"prism512 set up in {setup_s:.1f}s")
+    log(f"{cfg['name']} set up in {setup_s:.1f}s: {wl.grid.n_packages} packages, {wl.grid.n_core} core")
     P = wl.grid.n_packages
     n_core = wl.grid.n_core
     integ = torch.empty((4, n_core * 64), device="cuda")
@@ -197,9 +236,27 @@ def bench_prism(args, log):
     torch.cuda.synchronize()
     total_s = time.perf_counter() - t0
 
+    # the same probe over cell-sorted particles (not part of the step)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    g = sg.build_packages(wl.coarse, wl.h)
+    sg.reinitialize(g, wl.phi, wl.scratch, cfg["n_iter"])
+    sg.compute_gradient_packed(g, wl.phi, packed)
+    sg.probe_particles_packed(g, packed, pos_sorted, wl.phi_p, wl.nrm_p)
+    e0.record(stream)
+    for _ in range(5):
+        sg.probe_particles_packed(g, packed, pos_sorted, wl.phi_p, wl.nrm_p)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    probe_sorted_ms = e0.elapsed_time(e1) / 5
+    g.destroy()
+    del pos_sorted
+
     K = args.steps
     ms_step = 1e3 * total_s / K
     upd_step = 64 * P * cfg["n_iter"]
+    n_part = int(wl.pos.shape[0])
+    probe_ms = acc["probe"] / K
+    probe_bytes = PROBE_BYTES_PER_PARTICLE * n_part + 16.0 * 64 * P
     reinit_ms = acc["reinit"] / K
     sweep_ms = reinit_ms / cfg["n_iter"]
     bytes_launch = REINIT_BYTES_PER_UPDATE * 64 * P
@@ -211,20 +268,27 @@ def bench_prism(args, log):
         "n_gpus": 1, "steps": K, "warmup": args.warmup, "ms_per_step": ms_step,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32", "data": "synthetic",
-        "config": {"workload": "prism512: extruded triangular prism (edges 0.6, extrusion 0.8) at 512^3, "
-                               "5% noise, 100 reinitialisation iterations, gradient, 1e7 jittered particles, "
-                               "plain integrals on all core points",
+        "config": {"workload": WORKLOAD_TEXT[cfg["name"]],
                    "N": cfg["N"], "n_packages": P, "n_core": n_core, "n_iter": cfg["n_iter"],
-                   "particles": int(wl.pos.shape[0])},
+                   "particles": n_part},
         "breakdown_ms": {k: acc[k] / K for k in acc},
         "reinit_updates_per_s": upd_step / (reinit_ms * 1e-3),
-        "probes_per_s": wl.pos.shape[0] / (acc["probe"] / K * 1e-3),
+        "probes_per_s": n_part / (probe_ms * 1e-3),
         "probe_particle_order": "as generated (random over the surface)",
+        "probes_per_s_cell_sorted": n_part / (probe_sorted_ms * 1e-3),
+        "probe_hbm": {"algorithmic_bytes_per_launch": probe_bytes,
+                      "note": "28 B per particle (position in, value and normal out) plus the packed field once",
+                      "random_order_GBps": probe_bytes / (probe_ms * 1e-3) / 1e9,
+                      "cell_sorted_GBps": probe_bytes / (probe_sorted_ms * 1e-3) / 1e9,
+                      "cell_sorted_frac": probe_bytes / (probe_sorted_ms * 1e-3) / 1e9 / HBM_PEAK_GBS},
         "integral_cells_per_s": n_core * 64 / (acc["integ"] / K * 1e-3),
         "roofline": {"bound": "hbm", "kernel": "reinit sweep", "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(bytes_launch),
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": measured_traffic(bytes_launch) if cfg["name"] == "prism512" else None,
                      "avg_launch_us": sweep_ms * 1e3, "algorithmic_bytes_per_launch": bytes_launch,
-                     "note": "phi ping-pong of 64 MB is resident in the 256 MB Infinity Cache"},
+                     "note": ("phi ping-pong of 64 MB is resident in the 256 MB Infinity Cache"
+                              if cfg["name"] == "prism512" else
+                              "phi ping-pong of 0.9 GB streams from HBM")},
         "setup_s": setup_s,
     }
     log(f"timed {K} steps: {ms_step:.2f} ms per step")
@@ -232,7 +296,7 @@ def bench_prism(args, log):
         rec["learned"] = learned_vs_plain(sg, wl, args, log)
         log("learned vs plain done")
     if not args.no_cpu_baseline:
-        rec["cpu_baseline"] = cpu_baseline(cfg, args.cpu_iters)
+        rec["cpu_baseline"] = cpu_baseline(cfg, args.cpu_iters or cfg["n_iter"])
         log("cpu baseline done")
     return rec
 
@@ -308,7 +372,7 @@ def main():
         b.copy_(a)
         torch.cuda.synchronize()
         del a, b
-    rec = bench_batch(args, log) if args.workload == "batch64" else bench_prism(args, log)
+    rec = bench_batch(args, log) if args.workload == "batch64" else bench_single(args, log)
     print(json.dumps(rec), flush=True)
 
 

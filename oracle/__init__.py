@@ -103,11 +103,12 @@ class Tables:
         return int(self.pkg_cell.shape[0]) - 2
 
 
-def build_tables(M: int, d: np.ndarray) -> Tables:
+def build_tables(M: int, d: np.ndarray, lc: Optional[float] = None) -> Tables:
     """Activation, numbering and neighbour table for coarse distances d[M^3]
-    with coarse cell size 1/M (the unit cube)."""
+    with coarse cell size `lc` (default 1/M, the unit cube; a crop of a larger
+    grid passes that grid's cell size)."""
     d = np.ascontiguousarray(d, dtype=np.float32)
-    lc = 1.0 / M
+    lc = 1.0 / M if lc is None else float(lc)
     t = classify(M, lc, d)
     n = M ** 3
     cell_pkg = np.zeros(n, dtype=np.uint32)
@@ -284,6 +285,38 @@ def setup(shape, N: int, noise_amp: float, noise_seed: int, phi0_dtype=np.float3
     act = active_points(tab)
     phi0 = synth.phi0_at(shape, N, act, noise_amp, noise_seed).astype(phi0_dtype).astype(np.float64)
     return DenseRun(N, h, 16.0 * h, tab, act, phi0)
+
+
+@dataclass
+class CropRun(DenseRun):
+    origin: tuple = (0, 0, 0)     # first coarse cell of the crop in the full grid
+    n_full: int = 0               # data points per axis of the full grid
+
+
+def setup_crop(shape, N: int, origin, extent: int, noise_amp: float, noise_seed: int,
+               phi0_dtype=np.float32) -> CropRun:
+    """The dense oracle state of a sub-box of a grid too large to hold whole:
+    extent^3 coarse cells starting at coarse cell `origin` of the N^3 grid, with
+    the full grid's spacing, far-field constant and initial values.  Inside the
+    crop everything is local: N of the returned run is 4 extent.
+
+    Every update reads face neighbours only, so after n iterations (and one
+    gradient) a crop point whose distance to every crop face exceeds n plus the
+    reach of activation (one coarse cell) holds exactly the value the full grid
+    computes there; points nearer the faces see the crop's edge as far field."""
+    import synth
+    M = N // 4
+    o = tuple(int(v) for v in origin)
+    assert all(0 <= v and v + extent <= M for v in o)
+    h = 1.0 / N
+    d = synth.coarse_sdf(shape, M, origin=o, extent=extent)
+    tab = build_tables(extent, d, lc=1.0 / M)
+    act = active_points(tab)
+    n = 4 * extent
+    i, j, k = act % n + 4 * o[0], (act // n) % n + 4 * o[1], act // (n * n) + 4 * o[2]
+    glob = i + N * (j + N * k)
+    phi0 = synth.phi0_at(shape, N, glob, noise_amp, noise_seed).astype(phi0_dtype).astype(np.float64)
+    return CropRun(n, h, 16.0 * h, tab, act, phi0, origin=o, n_full=N)
 
 
 def run_plain(run: DenseRun, n_iter: int) -> DenseRun:

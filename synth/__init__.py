@@ -205,21 +205,27 @@ def sdf(s: Dict, x: np.ndarray) -> np.ndarray:
 # Grid sampling
 # ---------------------------------------------------------------------------
 
-def coarse_sdf(s: Dict, n_coarse: int, chunk: int = 1 << 20) -> np.ndarray:
-    """float32 signed distance at every coarse-cell centre, x fastest, shape (M^3,).
+def coarse_sdf(s: Dict, n_coarse: int, chunk: int = 1 << 20, origin=(0, 0, 0),
+               extent: int | None = None) -> np.ndarray:
+    """float32 signed distance at coarse-cell centres, x fastest, evaluated in
+    float64 and rounded once to float32.
 
-    Evaluated in float64 and rounded once to float32."""
+    With the defaults it covers the whole M^3 background grid (shape (M^3,)).
+    `origin` and `extent` select the sub-box of extent^3 coarse cells starting
+    at coarse cell `origin` (cell size still 1/M), for crops of large grids."""
     M = int(n_coarse)
+    E = M if extent is None else int(extent)
+    o = np.asarray(origin, dtype=np.int64)
     lc = 1.0 / M
-    out = np.empty(M ** 3, dtype=np.float32)
+    out = np.empty(E ** 3, dtype=np.float32)
 
     def work(a, b):
         lin = np.arange(a, b, dtype=np.int64)
-        i, j, k = lin % M, (lin // M) % M, lin // (M * M)
+        i, j, k = lin % E + o[0], (lin // E) % E + o[1], lin // (E * E) + o[2]
         x = (np.stack([i, j, k], axis=1).astype(np.float64) + 0.5) * lc
         out[a:b] = sdf(s, x).astype(np.float32)
 
-    _chunked(M ** 3, chunk, work)
+    _chunked(E ** 3, chunk, work)
     return out
 
 

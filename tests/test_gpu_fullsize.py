@@ -1,13 +1,16 @@
 """Full-size parity (GPU): the prism512 workload exactly as bench.py runs it
 (default sweep configuration, packed gradient and probe, plain integrals),
 compared with the oracle on every point, every particle and every core
-point; and the 64-shape batch in its autotuned, graph-replayed form against
-each member's own sweep."""
+point; the 64-shape batch in its autotuned, graph-replayed form against each
+member's own sweep; and the 2048^3 displaced torus, whose tables are checked
+whole and whose fields are checked on an oracle crop (a dense FP64 oracle of
+the whole 2048^3 grid would need 69 GB per array)."""
 import numpy as np
 import pytest
 
 import oracle
 import synth
+from tables_check import assert_tables_equal
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -94,3 +97,93 @@ def test_batch64_full_size(sg):
     oracle.run_plain(run, cfg["n_iter"])
     got = bw.slice(k, bw.phi)[2:].double().cpu().numpy().ravel()
     assert np.max(np.abs(got - run.phi[bw.parts[k].points.ravel()])) <= 1e-5 * run.h
+
+
+# 100^3 coarse cells around the top of the tube, (0.85, 0.5, 0.6)
+CROP_ORIGIN = (385, 206, 257)
+CROP_EXTENT = 100
+
+
+def _global_rows(t, local, n, origin, M):
+    """Package id and local point index, on the full grid, of crop-local fine
+    indices."""
+    N = 4 * M
+    i = local % n + 4 * origin[0]
+    j = (local // n) % n + 4 * origin[1]
+    k = local // (n * n) + 4 * origin[2]
+    cell = (i >> 2) + M * ((j >> 2) + M * (k >> 2))
+    pkg = t["cell_pkg"].view(np.uint32)[cell].astype(np.int64)
+    loc = (i & 3) + 4 * (j & 3) + 16 * (k & 3)
+    return pkg, loc
+
+
+def _interior(local, n, m):
+    i, j, k = local % n, (local // n) % n, local // (n * n)
+    return (i >= m) & (i < n - m) & (j >= m) & (j < n - m) & (k >= m) & (k < n - m)
+
+
+@pytest.mark.timeout(900)
+def test_torus2048_full_size(sg):
+    from paper_2512_11473_amd import workload
+    cfg = synth.config_c5()
+    N, n_iter = cfg["N"], cfg["n_iter"]
+    M = N // 4
+    pos = synth.particles_for(cfg)
+    wl = workload.setup(cfg["shape"], N, cfg["noise_amp"], cfg["noise_seed"], particles=pos)
+    g = wl.grid
+    sg.reinitialize(g, wl.phi, wl.scratch, n_iter)
+    packed = torch.empty((g.n_total, 64, 4), device="cuda")
+    sg.compute_gradient_packed(g, wl.phi, packed)
+    sg.probe_particles_packed(g, packed, wl.pos, wl.phi_p, wl.nrm_p)
+    integ = torch.empty((4, g.n_core * 64), device="cuda")
+    sg.compute_near_surface_integrals(g, wl.phi, integ)
+    torch.cuda.synchronize()
+
+    # tables: the whole 512^3 background grid, bit for bit
+    t = {k: v.cpu().numpy() for k, v in g.tables().items()}
+    ref = oracle.build_tables(M, wl.coarse.cpu().numpy())
+    assert_tables_equal(t, ref)
+    del ref
+
+    # fields: a crop, at points beyond the reach of its faces
+    crop = oracle.setup_crop(cfg["shape"], N, CROP_ORIGIN, CROP_EXTENT, cfg["noise_amp"], cfg["noise_seed"])
+    oracle.run_plain(crop, n_iter)
+    n, h = 4 * CROP_EXTENT, crop.h
+    m = n_iter + 6
+    act = crop.active[_interior(crop.active, n, m)]
+    assert act.size > 500_000
+    pkg, loc = _global_rows(t, act, n, CROP_ORIGIN, M)
+    assert np.all(pkg >= 2)                            # activated on both sides
+    rows = torch.from_numpy(pkg).cuda()
+    cols = torch.from_numpy(loc).cuda()
+    got = wl.phi[rows, cols].double().cpu().numpy()
+    assert np.max(np.abs(got - crop.phi[act])) <= 1e-5 * h
+    bl = torch.from_numpy(_blocked()[loc]).cuda()
+    gg = packed[rows, bl, 1:].double().cpu().numpy().T
+    assert np.max(np.abs(gg - crop.grad[:, act])) <= 1e-5
+
+    # particles whose interpolation stencil lies inside the checked region
+    p64 = pos.astype(np.float64) - 4 * h * np.asarray(CROP_ORIGIN, dtype=np.float64)
+    base = np.floor(p64 / h - 0.5)
+    sel = np.nonzero(np.all((base >= m) & (base <= n - m - 2), axis=1))[0]
+    assert sel.size > 100_000
+    ref_phi, ref_nrm, ref_g = oracle.probe(n, h, crop.B, crop.tab.cell_pkg, crop.phi, crop.grad,
+                                           p64[sel], with_gradient=True)
+    sel_d = torch.from_numpy(sel).cuda()
+    assert np.max(np.abs(wl.phi_p[sel_d].double().cpu().numpy() - ref_phi)) <= 1e-5 * h
+    ok = np.linalg.norm(ref_g, axis=1) > 0.25
+    assert ok.mean() > 0.95
+    assert np.max(np.abs(wl.nrm_p[sel_d].double().cpu().numpy()[ok] - ref_nrm[ok])) <= 1e-5
+
+    # integrals of the core points whose 9^3 window lies inside the checked region
+    core_pts = oracle.active_points(crop.tab, (1,))
+    core_pts = core_pts[_interior(core_pts, n, m + 4)]
+    assert core_pts.size > 100_000
+    pkg, loc = _global_rows(t, core_pts, n, CROP_ORIGIN, M)
+    rank = np.searchsorted(t["core_list"].view(np.uint32).astype(np.int64), pkg)
+    assert np.array_equal(t["core_list"][rank].astype(np.int64), pkg)
+    col = torch.from_numpy(rank * 64 + loc).cuda()
+    got = integ[:, col].double().cpu().numpy().T
+    ref = oracle.integrals(n, h, crop.B, crop.phi, core_pts)
+    assert np.max(np.abs(got[:, 0] - ref[:, 0])) <= 1e-5
+    assert np.max(np.abs(got[:, 1:] - ref[:, 1:])) <= 1e-5 * G0
