@@ -54,7 +54,9 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=None,
-                    help="oracle sweeps timed for the CPU baseline (default: the workload's iteration count)")
+                    help="oracle sweeps per CPU-baseline pass (default: the workload's iteration count)")
+    ap.add_argument("--cpu-seconds", type=float, default=10.0,
+                    help="minimum oracle sweeping time of the CPU baseline")
     ap.add_argument("--train-cells", type=int, default=2_000_000)
     ap.add_argument("--epochs", type=int, default=50)
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -79,35 +81,42 @@ def measured_traffic(per_launch_algorithmic: float):
     return float(t.group(1))
 
 
-# 100^3 coarse cells around the top of the torus tube, (0.85, 0.5, 0.6): the
-# oracle's sample of the 2048^3 band
-TORUS_CROP = ((385, 206, 257), 100)
+# 100^3-coarse-cell crops around the top of the torus tube at four angles:
+# the oracle's samples of the 2048^3 band
+TORUS_CROPS = [(385, 206, 257), (206, 385, 257), (26, 206, 257), (206, 26, 257)]
+TORUS_CROP_EXTENT = 100
 
 
-def cpu_baseline(cfg, n_iter_sample):
+def cpu_baseline(cfg, n_iter, min_seconds=10.0):
     """The oracle (FP64, dense grid, OpenMP) timed on the host on a bounded
-    sample: `n_iter_sample` reinitialisation sweeps over the full band, or over
-    a crop of it where the dense grid would not fit (2048^3)."""
+    sample of the workload: passes of `n_iter` reinitialisation sweeps from
+    phi0 over the full band (or, at 2048^3 where the dense grid would not fit,
+    over crops of it in turn), repeated until `min_seconds` of sweeping."""
     import oracle
     t0 = time.perf_counter()
     if cfg["N"] > 1024:
-        origin, extent = TORUS_CROP
-        run = oracle.setup_crop(cfg["shape"], cfg["N"], origin, extent, cfg["noise_amp"], cfg["noise_seed"])
-        where = f"a {extent}^3-coarse-cell crop of the {cfg['name']} band"
+        runs = [oracle.setup_crop(cfg["shape"], cfg["N"], o, TORUS_CROP_EXTENT, cfg["noise_amp"], cfg["noise_seed"])
+                for o in TORUS_CROPS]
+        where = f"{len(runs)} crops of {TORUS_CROP_EXTENT}^3 coarse cells of the {cfg['name']} band in turn"
     else:
-        run = oracle.setup(cfg["shape"], cfg["N"], cfg["noise_amp"], cfg["noise_seed"])
+        runs = [oracle.setup(cfg["shape"], cfg["N"], cfg["noise_amp"], cfg["noise_seed"])]
         where = f"the full {cfg['name']} band"
-    dense = oracle.dense_state(run.tab, run.active, run.phi0, run.B)
+    dense = [oracle.dense_state(r.tab, r.active, r.phi0, r.B) for r in runs]
     setup_s = time.perf_counter() - t0
-    oracle.reinit(run.N, run.h, run.B, run.active, dense, 1)       # warm-up
-    t0 = time.perf_counter()
-    oracle.reinit(run.N, run.h, run.B, run.active, dense, n_iter_sample)
-    dt = time.perf_counter() - t0
+    oracle.reinit(runs[0].N, runs[0].h, runs[0].B, runs[0].active, dense[0], 1)       # warm-up
+    updates, secs, passes = 0, 0.0, 0
+    while secs < min_seconds:
+        r, d = runs[passes % len(runs)], dense[passes % len(runs)]
+        t0 = time.perf_counter()
+        oracle.reinit(r.N, r.h, r.B, r.active, d, n_iter)
+        secs += time.perf_counter() - t0
+        updates += len(r.active) * n_iter
+        passes += 1
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    return {"value": len(run.active) * n_iter_sample / dt, "unit": "package-cell updates/s",
-            "cores": threads, "kind": "oracle",
-            "sample": f"{n_iter_sample} FP64 reinitialisation sweeps of the oracle over {where} "
-                      f"({len(run.active)} points, {dt:.1f} s; dense-grid setup {setup_s:.1f} s)"}
+    pts = sum(len(r.active) for r in runs) // len(runs)
+    return {"value": updates / secs, "unit": "package-cell updates/s", "cores": threads, "kind": "oracle",
+            "sample": f"{passes} pass{'es' if passes != 1 else ''} of {n_iter} FP64 reinitialisation sweeps of the oracle over {where} "
+                      f"({pts} points per pass, {secs:.1f} s of sweeping; dense-grid setup {setup_s:.1f} s)"}
 
 
 def learned_vs_plain(sg, wl, args, log):
@@ -296,7 +305,7 @@ def bench_single(args, log):
         rec["learned"] = learned_vs_plain(sg, wl, args, log)
         log("learned vs plain done")
     if not args.no_cpu_baseline:
-        rec["cpu_baseline"] = cpu_baseline(cfg, args.cpu_iters or cfg["n_iter"])
+        rec["cpu_baseline"] = cpu_baseline(cfg, args.cpu_iters or cfg["n_iter"], args.cpu_seconds)
         log("cpu baseline done")
     return rec
 

@@ -286,11 +286,11 @@ sgrid_status sgrid_batch_reinitialize(sgrid_batch *batch, float *phi_dev, float 
  * sweeps groups of 64 consecutive Morton-ordered packages per 1024-lane
  * workgroup and reads halo rows of in-group neighbours from LDS, variant 5
  * is variant 0 with the y / z neighbour rows exchanged through LDS instead of
- * DPP (no workgroup barrier).  `groups`
- * (1, 2, 3, 4 or 8) is, for variants 0, 1, 3 and 5, the number of four-package
- * sets one wavefront processes, for variant 2 the number of workgroups per
- * compute unit, and is ignored by variant 4.  Process-wide; default (0, 1).
- * Results are identical for every setting.
+ * DPP (no workgroup barrier).  `groups` (1, 2, 3, 4 or 8) is, for variants 0,
+ * 1, 3 and 5, the number of four-package sets one wavefront processes, for
+ * variant 2 the number of workgroups per compute unit, and is ignored by
+ * variant 4.  Process-wide; default (0, 1).  Results are identical for every
+ * setting.
  */
 sgrid_status sgrid_set_sweep_config(int32_t variant, int32_t groups);
 

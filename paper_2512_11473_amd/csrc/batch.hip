@@ -19,6 +19,7 @@
 #include <vector>
 
 #include "common.hpp"
+#include "upwind.hpp"
 
 namespace sgrid {
 template <typename T>
@@ -40,18 +41,6 @@ __device__ __forceinline__ void st_row(float *__restrict__ p, const Row4<float> 
     *reinterpret_cast<float4 *>(p) = make_float4(r.v[0], r.v[1], r.v[2], r.v[3]);
 }
 
-// Same arithmetic as the single-grid sweep (FP32).
-__device__ __forceinline__ float upwind(float p0, float xm, float xp, float ym, float yp, float zm, float zp, float h2,
-                                        float inv_h, float dt) {
-    const float S = p0 * __builtin_amdgcn_rsqf(p0 * p0 + h2);
-    const float sg = S > 0.f ? 1.f : -1.f;
-    const float ax = fmaxf(fmaxf(sg * (p0 - xm), sg * (p0 - xp)), 0.f);
-    const float ay = fmaxf(fmaxf(sg * (p0 - ym), sg * (p0 - yp)), 0.f);
-    const float az = fmaxf(fmaxf(sg * (p0 - zm), sg * (p0 - zp)), 0.f);
-    const float G = __builtin_amdgcn_sqrtf(ax * ax + ay * ay + az * az) * inv_h;
-    return p0 - dt * S * (G - 1.f);
-}
-
 struct Halo {
     Row4<float> c, yh, zh;
     float xm, xp;
@@ -66,35 +55,31 @@ __device__ __forceinline__ void batch_loads(const float *__restrict__ src, const
     l.c = ld_row(src + g * 64 + r * 4);
     l.xm = src[(int64_t)f0.x * 64 + r * 4 + 3];
     l.xp = src[(int64_t)f0.y * 64 + r * 4];
-    if (j == 0 || j == 3) {
-        const uint32_t fy = j == 0 ? f0.z : f0.w;
-        l.yh = ld_row(src + (int64_t)fy * 64 + (j == 0 ? 3 + 4 * k : 4 * k) * 4);
-    }
-    if (k == 0 || k == 3) {
-        const uint32_t fz = k == 0 ? f1.x : f1.y;
-        l.zh = ld_row(src + (int64_t)fz * 64 + (k == 0 ? j + 12 : j) * 4);
-    }
+    // unconditional (a lane without a y / z halo re-reads its own row), so the
+    // halo loads issue together instead of behind a branch that waits
+    const int64_t fy = j == 0 ? (int64_t)f0.z : j == 3 ? (int64_t)f0.w : g;
+    const int ry = j == 0 ? 3 + 4 * k : j == 3 ? 4 * k : r;
+    l.yh = ld_row(src + fy * 64 + ry * 4);
+    const int64_t fz = k == 0 ? (int64_t)f1.x : k == 3 ? (int64_t)f1.y : g;
+    const int rz = k == 0 ? j + 12 : k == 3 ? j : r;
+    l.zh = ld_row(src + fz * 64 + rz * 4);
 }
 
-__device__ __forceinline__ float row_shr1(float v) { return row_move<kRowShr1>(v); }
-__device__ __forceinline__ float row_shl1(float v) { return row_move<kRowShl1>(v); }
-__device__ __forceinline__ float row_shr4(float v) { return row_move<kRowShr4>(v); }
-__device__ __forceinline__ float row_shl4(float v) { return row_move<kRowShl4>(v); }
 
 __device__ __forceinline__ Row4<float> update_row_dpp(int r, const Halo &l, const sgrid::SweepParams<float> &sp) {
-    const int j = r & 3, k = r >> 2;
+    const int j = r & 3;
     Row4<float> o;
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
         const float v = l.c.v[i];
-        const float a = row_shr1(v), b = row_shl1(v), c = row_shr4(v), d = row_shl4(v);
+        const float a = row_move<kRowShr1>(v), b = row_move<kRowShl1>(v);   // every lane, before the selects
         const float ym = j == 0 ? l.yh.v[i] : a;
         const float yp = j == 3 ? l.yh.v[i] : b;
-        const float zm = k == 0 ? l.zh.v[i] : c;
-        const float zp = k == 3 ? l.zh.v[i] : d;
+        const float zm = row_move_keep<kRowShr4, 0xE>(v, l.zh.v[i]);   // k = 0 lanes (bank 0) keep the halo
+        const float zp = row_move_keep<kRowShl4, 0x7>(v, l.zh.v[i]);   // k = 3 lanes (bank 3) keep the halo
         const float xm = i > 0 ? l.c.v[i - 1] : l.xm;
         const float xp = i < 3 ? l.c.v[i + 1] : l.xp;
-        o.v[i] = upwind(v, xm, xp, ym, yp, zm, zp, sp.h2, sp.inv_h, sp.dt);
+        o.v[i] = sgrid::upwind_update(v, xm, xp, ym, yp, zm, zp, sp.h2, sp.inv_h, sp.dt);
     }
     return o;
 }
@@ -168,7 +153,7 @@ __global__ __launch_bounds__(256) void batch_lds_kernel(const float *__restrict_
             Row4<float> o;
 #pragma unroll
             for (int i = 0; i < 4; ++i)
-                o.v[i] = upwind(t[at(i, j, k)], t[at(i - 1, j, k)], t[at(i + 1, j, k)], t[at(i, j - 1, k)],
+                o.v[i] = sgrid::upwind_update(t[at(i, j, k)], t[at(i - 1, j, k)], t[at(i + 1, j, k)], t[at(i, j - 1, k)],
                                 t[at(i, j + 1, k)], t[at(i, j, k - 1)], t[at(i, j, k + 1)], sp.h2, sp.inv_h, sp.dt);
             st_row(dst + g * 64 + r * 4, o);
         }

@@ -102,21 +102,40 @@ constexpr int64_t kMaxGrid = 0x7FFFFFFF;
 
 // Cross-lane move inside 16-lane rows (DPP).  CTRL is a row_shl / row_shr
 // control: row_shl:n = 0x100 + n (lane l reads lane l + n of its row),
-// row_shr:n = 0x110 + n (lane l reads lane l - n).  Lanes whose source lies
-// outside their 16-lane row must not use the result; callers select a halo
-// value for them.
+// row_shr:n = 0x110 + n (lane l reads lane l - n).  row_move: lanes whose
+// source lies outside their 16-lane row read 0 and must not use the result
+// (callers select a halo value for them).  row_move_keep: lanes of the banks
+// (groups of four lanes of a row) left out of BANKS keep `keep` instead, which
+// takes a halo value in without a select.  Both must run in every lane of the
+// row: a lane outside the active mask supplies 0 to its neighbours, so a move
+// written inside a lane-dependent branch (an arm of ?: included) reads wrong
+// values.
 constexpr int kRowShl1 = 0x101, kRowShl4 = 0x104, kRowShr1 = 0x111, kRowShr4 = 0x114;
 
 template <int CTRL>
 __device__ __forceinline__ float row_move(float v) {
-    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, 0xF, 0xF, true));
 }
 
 template <int CTRL>
 __device__ __forceinline__ double row_move(double v) {
-    long long b = __double_as_longlong(v);
-    int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xFFFFFFFFll), CTRL, 0xF, 0xF, false);
-    int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_mov_dpp((int)(b & 0xFFFFFFFFll), CTRL, 0xF, 0xF, true);
+    const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), CTRL, 0xF, 0xF, true);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+template <int CTRL, int BANKS>
+__device__ __forceinline__ float row_move_keep(float v, float keep) {
+    return __int_as_float(
+        __builtin_amdgcn_update_dpp(__float_as_int(keep), __float_as_int(v), CTRL, 0xF, BANKS, false));
+}
+
+template <int CTRL, int BANKS>
+__device__ __forceinline__ double row_move_keep(double v, double keep) {
+    const long long b = __double_as_longlong(v), o = __double_as_longlong(keep);
+    const int lo = __builtin_amdgcn_update_dpp((int)(o & 0xFFFFFFFFll), (int)(b & 0xFFFFFFFFll), CTRL, 0xF, BANKS, false);
+    const int hi = __builtin_amdgcn_update_dpp((int)(o >> 32), (int)(b >> 32), CTRL, 0xF, BANKS, false);
     return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 

@@ -60,20 +60,31 @@ __device__ __forceinline__ int64_t locate(const T *x, int M, T inv_h, int sh[3],
 }
 
 // Trilinear blend of phi and g over the eight corners reached from the home
-// package's neighbour row, then the normal.
+// package's neighbour row, then the normal.  The eight row reads are
+// unconditional so that they issue together (a read skipped per lane, e.g.
+// for the self slot, turns into a branch with a wait inside and serialises
+// the gathers).
 template <typename T, bool PACKED>
 __device__ __forceinline__ void blend(const Corner<T, PACKED> &field, const uint32_t *__restrict__ row, const int sh[3],
                                       const T t[3], T &v, T n[3]) {
-    v = T(0);
-    T gx = T(0), gy = T(0), gz = T(0);
+    // the eight package ids first, so the row reads issue back to back
+    uint32_t pk[8];
+    int d[8];
 #pragma unroll
     for (int b = 0; b < 8; ++b) {
         const int bx = b & 1, by = (b >> 1) & 1, bz = (b >> 2) & 1;
         const int s0 = sh[0] + bx + 4, s1 = sh[1] + by + 4, s2 = sh[2] + bz + 4;   // shift + 4 in [3, 8]
         const int k0 = s0 >> 2, k1 = s1 >> 2, k2 = s2 >> 2;                        // neighbour slot per axis
         const int di = s0 - 4 * k0, dj = s1 - 4 * k1, dk = s2 - 4 * k2;            // data index
-        const int d = PACKED ? blocked_index(di, dj, dk) : di + 4 * dj + 16 * dk;
-        const int64_t idx = (int64_t)row[k0 + 3 * k1 + 9 * k2] * 64 + d;
+        d[b] = PACKED ? blocked_index(di, dj, dk) : di + 4 * dj + 16 * dk;
+        pk[b] = row[k0 + 3 * k1 + 9 * k2];
+    }
+    v = T(0);
+    T gx = T(0), gy = T(0), gz = T(0);
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+        const int bx = b & 1, by = (b >> 1) & 1, bz = (b >> 2) & 1;
+        const int64_t idx = (int64_t)pk[b] * 64 + d[b];
         const T w = (bx ? t[0] : T(1) - t[0]) * (by ? t[1] : T(1) - t[1]) * (bz ? t[2] : T(1) - t[2]);
         T cv, cx, cy, cz;
         field.get(idx, cv, cx, cy, cz);
@@ -98,8 +109,8 @@ __global__ __launch_bounds__(256) void probe_kernel(Corner<T, PACKED> field, con
     if (q >= n) return;
     int sh[3];
     T t[3], v, nr[3];
-    const int64_t home = cell_pkg[locate(pos + 3 * q, M, inv_h, sh, t)];
-    blend(field, nbr + home * 27, sh, t, v, nr);
+    const uint32_t home = cell_pkg[locate(pos + 3 * q, M, inv_h, sh, t)];
+    blend(field, nbr + (int64_t)home * 27, sh, t, v, nr);
     phi_out[q] = v;
     nrm_out[3 * q] = nr[0];
     nrm_out[3 * q + 1] = nr[1];

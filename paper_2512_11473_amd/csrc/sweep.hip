@@ -14,9 +14,11 @@
 // 16-lane DPP row).  The LDS-staged variant writes the same rows and halos
 // into a per-package tile in LDS and reads the neighbours back from there.
 #include "common.hpp"
+#include "upwind.hpp"
 
 using sgrid::kGroup;
 using sgrid::kLocal;
+using sgrid::upwind_update;
 
 namespace {
 
@@ -49,37 +51,6 @@ __device__ __forceinline__ void store_row<double>(double *__restrict__ p, const 
     reinterpret_cast<double2 *>(p)[1] = make_double2(r.v[2], r.v[3]);
 }
 
-// Precision policy: FP32 uses the hardware square root and reciprocal square
-// root (about 1 ulp); FP64 uses correctly rounded operations.
-template <typename T>
-struct Fast;
-template <>
-struct Fast<float> {
-    static __device__ __forceinline__ float rsqrt(float x) { return __builtin_amdgcn_rsqf(x); }
-    static __device__ __forceinline__ float sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
-};
-template <>
-struct Fast<double> {
-    static __device__ __forceinline__ double rsqrt(double x) { return 1.0 / ::sqrt(x); }
-    static __device__ __forceinline__ double sqrt(double x) { return ::sqrt(x); }
-};
-
-// Godunov-upwinded update of one point (Sussman-Smereka-Osher iteration),
-// written in differences of phi (units of h):
-//   S > 0: a^2 = max(max(D-,0)^2, min(D+,0)^2) = max(p0 - xm, p0 - xp, 0)^2 / h^2
-//   S < 0: a^2 = max(min(D-,0)^2, max(D+,0)^2) = max(xm - p0, xp - p0, 0)^2 / h^2
-// so with sg = sign(S) every axis contributes max(sg (p0 - m), sg (p0 - p), 0)^2.
-template <typename T>
-__device__ __forceinline__ T upwind_update(T p0, T xm, T xp, T ym, T yp, T zm, T zp, T h2, T inv_h, T dt) {
-    const T S = p0 * Fast<T>::rsqrt(p0 * p0 + h2);
-    const T sg = S > T(0) ? T(1) : T(-1);
-    const T ax = fmax(fmax(sg * (p0 - xm), sg * (p0 - xp)), T(0));
-    const T ay = fmax(fmax(sg * (p0 - ym), sg * (p0 - yp)), T(0));
-    const T az = fmax(fmax(sg * (p0 - zm), sg * (p0 - zp)), T(0));
-    const T G = Fast<T>::sqrt(ax * ax + ay * ay + az * az) * inv_h;
-    return p0 - dt * S * (G - T(1));
-}
-
 // A package row and its stencil neighbours.
 template <typename T>
 struct Stencil {
@@ -100,6 +71,10 @@ __device__ __forceinline__ void load_face(const uint32_t *__restrict__ face, int
     f1 = *reinterpret_cast<const uint2 *>(face + p * 8 + 4);
 }
 
+// Every lane issues all five loads: a lane with no y (z) halo row re-reads its
+// own row, which the caches already hold.  Loads under a per-lane condition
+// would become branches, and the compiler then waits for every earlier load
+// before the branch's own, adding a memory round trip.
 template <typename T>
 __device__ __forceinline__ void issue_data(const T *__restrict__ src, int64_t p, int r, const uint4 &f0,
                                            const uint2 &f1, Loads<T> &l) {
@@ -107,14 +82,12 @@ __device__ __forceinline__ void issue_data(const T *__restrict__ src, int64_t p,
     l.c = load_row(src + p * 64 + r * 4);
     l.xm = src[(int64_t)f0.x * 64 + r * 4 + 3];
     l.xp = src[(int64_t)f0.y * 64 + r * 4];
-    if (j == 0 || j == 3) {
-        const uint32_t fy = j == 0 ? f0.z : f0.w;
-        l.yh = load_row(src + (int64_t)fy * 64 + (j == 0 ? 3 + 4 * k : 4 * k) * 4);
-    }
-    if (k == 0 || k == 3) {
-        const uint32_t fz = k == 0 ? f1.x : f1.y;
-        l.zh = load_row(src + (int64_t)fz * 64 + (k == 0 ? j + 12 : j) * 4);
-    }
+    const int64_t fy = j == 0 ? (int64_t)f0.z : j == 3 ? (int64_t)f0.w : p;
+    const int ry = j == 0 ? 3 + 4 * k : j == 3 ? 4 * k : r;
+    l.yh = load_row(src + fy * 64 + ry * 4);
+    const int64_t fz = k == 0 ? (int64_t)f1.x : k == 3 ? (int64_t)f1.y : p;
+    const int rz = k == 0 ? j + 12 : k == 3 ? j : r;
+    l.zh = load_row(src + fz * 64 + rz * 4);
 }
 
 template <typename T>
@@ -140,12 +113,12 @@ __device__ __forceinline__ Stencil<T> assemble(int r, const Loads<T> &l) {
         const T v = l.c.v[i];
         const T a = row_move<kRowShr1>(v);   // lane - 1: (j - 1, k)
         const T b = row_move<kRowShl1>(v);   // lane + 1: (j + 1, k)
-        const T c = row_move<kRowShr4>(v);   // lane - 4: (j, k - 1)
-        const T d = row_move<kRowShl4>(v);   // lane + 4: (j, k + 1)
         s.ym.v[i] = j == 0 ? l.yh.v[i] : a;
         s.yp.v[i] = j == 3 ? l.yh.v[i] : b;
-        s.zm.v[i] = k == 0 ? l.zh.v[i] : c;
-        s.zp.v[i] = k == 3 ? l.zh.v[i] : d;
+        // lane -+ 4: (j, k -+ 1); the k = 0 (k = 3) lanes are bank 0 (bank 3)
+        // of the row and keep their z halo value
+        s.zm.v[i] = row_move_keep<kRowShr4, 0xE>(v, l.zh.v[i]);
+        s.zp.v[i] = row_move_keep<kRowShl4, 0x7>(v, l.zh.v[i]);
     }
     return s;
 }
@@ -446,7 +419,8 @@ __global__ void far_field_kernel(T *__restrict__ phi, T B) {
 
 namespace sgrid {
 
-// Sweep variants selectable by the tuner: 0 = DPP exchange, 1 = LDS tile.
+// Sweep variants: 0 DPP exchange, 1 LDS tile, 2 persistent, 3 Morton
+// worklist, 4 group-shared LDS, 5 LDS row exchange.
 struct SweepConfig {
     int variant = 0;
     int groups = 1;   // sets of four packages per wavefront

@@ -227,6 +227,46 @@ def test_sweep_variants_identical(sg):
         assert torch.equal(r, results[0])
 
 
+@pytest.mark.parametrize("dtype", [torch.float32, torch.float64], ids=["f32", "f64"])
+def test_sweep_domain_edge(sg, dtype):
+    """A band cut by two domain faces (out-of-domain neighbours are the
+    positive far field) with far field on both sides, every sweep variant,
+    even and odd iteration counts.  The shapes' interiors stay clear of the
+    faces: where an interior touches a face, its points see the +B far field
+    across it, the update there jumps by several h per iteration, and FP32
+    rounding is amplified beyond 1e-5 h within a few iterations (a property of
+    the iteration, shown by a correctly rounded FP32 emulation of it, not of
+    the kernels)."""
+    from paper_2512_11473_amd import workload
+    s = synth.union([synth.sphere((0.14, 0.5, 0.5), 0.12), synth.box((0.6, 0.8, 0.5), (0.25, 0.16, 0.25))])
+    N = 64
+    wl = workload.setup(s, N, 0.1, 21, dtype=dtype)
+    run = oracle.setup(s, N, 0.1, 21, phi0_dtype=np.float32 if dtype == torch.float32 else np.float64)
+    tab = {k: v.cpu().numpy() for k, v in wl.grid.tables().items()}
+    nbr = tab["pkg_nbr"].view(np.uint32)
+    cells = tab["pkg_cell"].view(np.uint32)[2:].astype(np.int64)
+    M = N // 4
+    x, y = cells % M, (cells // M) % M
+    assert np.any(x == 0) and np.any(y == M - 1)           # the band reaches both faces
+    assert np.any(nbr[2:] == 0) and np.any(nbr[2:] == 1)    # far field on both sides
+    tol = 1e-5 if dtype == torch.float32 else 1e-12
+    configs = [(0, 1), (0, 4), (1, 1), (2, 1), (3, 1), (4, 1), (5, 1)]
+    for n_iter in (1, 2, 5, 12):
+        outs = []
+        for variant, groups in configs:
+            sg.set_sweep_config(variant, groups)
+            wl.reset()
+            sg.reinitialize(wl.grid, wl.phi, wl.scratch, n_iter)
+            outs.append(wl.phi.clone())
+        sg.set_sweep_config(0, 1)
+        for o in outs[1:]:
+            assert torch.equal(outs[0], o), n_iter
+        phi = oracle.reinit(run.N, run.h, run.B, run.active,
+                            oracle.dense_state(run.tab, run.active, run.phi0, run.B), n_iter)
+        got = outs[0][2:].double().cpu().numpy().ravel()
+        assert np.max(np.abs(got - phi[wl.points.ravel()])) <= tol * run.h, n_iter
+
+
 def test_determinism(sg):
     cfg = synth.config_c1()
     from paper_2512_11473_amd import workload
