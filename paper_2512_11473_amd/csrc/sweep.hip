@@ -135,25 +135,25 @@ __device__ __forceinline__ Row<T> reinit_row(const Stencil<T> &s, T h2, T inv_h,
     return o;
 }
 
-// Reinitialisation sweep over packages [2, 2 + P), DPP exchange variant.  A
-// wavefront handles G consecutive sets of four packages and issues all their
-// loads before computing any of them.
+// Reinitialisation sweep over the packages [first, end) (all of them: [2,
+// 2 + P)), DPP exchange variant.  A wavefront handles G consecutive sets of
+// four packages and issues all their loads before computing any of them.
 template <typename T, int G>
 __global__ __launch_bounds__(256) void reinit_dpp_kernel(const T *__restrict__ src, T *__restrict__ dst,
-                                                         const uint32_t *__restrict__ face, int64_t P,
-                                                         int64_t n_blocks, T h2, T inv_h, T dt) {
+                                                         const uint32_t *__restrict__ face, int64_t first,
+                                                         int64_t end, int64_t n_blocks, T h2, T inv_h, T dt) {
     const int64_t b = xcd_block(blockIdx.x, n_blocks);
     const int lane = threadIdx.x & 63;
     const int r = lane & 15;
-    const int64_t p0 = 2 + (b * 4 + (threadIdx.x >> 6)) * (4 * G) + (lane >> 4);
+    const int64_t p0 = first + (b * 4 + (threadIdx.x >> 6)) * (4 * G) + (lane >> 4);
     Loads<T> l[G];
 #pragma unroll
     for (int g = 0; g < G; ++g)
-        if (p0 + 4 * g < P + 2) issue_loads(src, face, p0 + 4 * g, r, l[g]);
+        if (p0 + 4 * g < end) issue_loads(src, face, p0 + 4 * g, r, l[g]);
 #pragma unroll
     for (int g = 0; g < G; ++g) {
         const Stencil<T> s = assemble(r, l[g]);
-        if (p0 + 4 * g < P + 2) store_row(dst + (p0 + 4 * g) * 64 + r * 4, reinit_row(s, h2, inv_h, dt));
+        if (p0 + 4 * g < end) store_row(dst + (p0 + 4 * g) * 64 + r * 4, reinit_row(s, h2, inv_h, dt));
     }
 }
 
@@ -434,6 +434,22 @@ void set_sweep_config(int variant, int groups) {
 }
 
 template <typename T>
+static void launch_dpp_range(const sgrid_grid *g, const T *src, T *dst, int64_t first, int64_t end, int groups,
+                             hipStream_t st) {
+    const int64_t per_block = 16 * (int64_t)groups;
+    const int64_t nb = (end - first + per_block - 1) / per_block;
+    const T h2 = (T)(g->h * g->h), inv_h = (T)(1.0 / g->h), dt = (T)(0.5 * g->h);
+    const dim3 grid((unsigned)nb), block(256);
+    switch (groups) {
+        case 1: hipLaunchKernelGGL((reinit_dpp_kernel<T, 1>), grid, block, 0, st, src, dst, g->face, first, end, nb, h2, inv_h, dt); break;
+        case 2: hipLaunchKernelGGL((reinit_dpp_kernel<T, 2>), grid, block, 0, st, src, dst, g->face, first, end, nb, h2, inv_h, dt); break;
+        case 3: hipLaunchKernelGGL((reinit_dpp_kernel<T, 3>), grid, block, 0, st, src, dst, g->face, first, end, nb, h2, inv_h, dt); break;
+        case 4: hipLaunchKernelGGL((reinit_dpp_kernel<T, 4>), grid, block, 0, st, src, dst, g->face, first, end, nb, h2, inv_h, dt); break;
+        default: hipLaunchKernelGGL((reinit_dpp_kernel<T, 8>), grid, block, 0, st, src, dst, g->face, first, end, nb, h2, inv_h, dt); break;
+    }
+}
+
+template <typename T>
 static sgrid_status launch_reinit_sweep(const sgrid_grid *g, const T *src, T *dst, hipStream_t st,
                                         const SweepConfig &cfg) {
     if (g->P == 0) return SGRID_OK;
@@ -473,13 +489,7 @@ static sgrid_status launch_reinit_sweep(const sgrid_grid *g, const T *src, T *ds
         hipLaunchKernelGGL(reinit_lds_kernel<T>, grid, block, 0, st, src, dst, g->face, g->P, nb, cfg.groups, h2,
                            inv_h, dt);
     } else {
-        switch (cfg.groups) {
-            case 1: hipLaunchKernelGGL((reinit_dpp_kernel<T, 1>), grid, block, 0, st, src, dst, g->face, g->P, nb, h2, inv_h, dt); break;
-            case 2: hipLaunchKernelGGL((reinit_dpp_kernel<T, 2>), grid, block, 0, st, src, dst, g->face, g->P, nb, h2, inv_h, dt); break;
-            case 3: hipLaunchKernelGGL((reinit_dpp_kernel<T, 3>), grid, block, 0, st, src, dst, g->face, g->P, nb, h2, inv_h, dt); break;
-            case 4: hipLaunchKernelGGL((reinit_dpp_kernel<T, 4>), grid, block, 0, st, src, dst, g->face, g->P, nb, h2, inv_h, dt); break;
-            default: hipLaunchKernelGGL((reinit_dpp_kernel<T, 8>), grid, block, 0, st, src, dst, g->face, g->P, nb, h2, inv_h, dt); break;
-        }
+        launch_dpp_range<T>(g, src, dst, 2, 2 + g->P, cfg.groups, st);
     }
     SG_CHECK_LAUNCH("reinit sweep");
     return SGRID_OK;
