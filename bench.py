@@ -39,7 +39,6 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 REINIT_BYTES_PER_UPDATE = 8.375      # read + write one FP32 value, plus 6 face ids / 64 points
 PROBE_BYTES_PER_PARTICLE = 28.0      # 12 B position in, 16 B value + normal out
-COUNTERS = os.path.join(ROOT, "profiles", "reinit_sweep_prism512_counters.txt")
 SWEEP_SRC = os.path.join(ROOT, "paper_2512_11473_amd", "csrc", "sweep.hip")
 
 
@@ -50,6 +49,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="prism512", choices=["prism512", "torus2048", "batch64"])
     ap.add_argument("--n-iter", type=int, default=None)
+    ap.add_argument("--sweep", default="auto",
+                    help="sweep configuration 'variant,groups', or 'auto' to autotune it on the grid (default)")
     ap.add_argument("--particles", type=int, default=None, help="default: the workload's count")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-learned", action="store_true")
@@ -68,15 +69,20 @@ def sweep_source_hash() -> str:
     return hashlib.sha256(open(SWEEP_SRC, "rb").read()).hexdigest()[:16]
 
 
-def measured_traffic(per_launch_algorithmic: float):
-    """HBM bytes per sweep launch from the committed counter summary, when it
-    was taken on the current sweep source; else None."""
-    if not os.path.exists(COUNTERS):
+def measured_traffic(workload: str, sweep: tuple):
+    """HBM bytes per sweep launch from the committed counter summary of this
+    workload, when it was taken on the current sweep source and with the same
+    sweep configuration; else None."""
+    path = os.path.join(ROOT, "profiles", f"reinit_sweep_{workload}_counters.txt")
+    if not os.path.exists(path):
         return None
-    text = open(COUNTERS).read()
+    text = open(path).read()
     m = re.search(r"sweep_source_sha256_16:\s*(\w+)", text)
+    c = re.search(r"sweep_config:\s*(\d+),(\d+)", text)
     t = re.search(r"calibrated_bytes_per_launch:\s*([0-9.eE+]+)", text)
-    if not m or not t or m.group(1) != sweep_source_hash():
+    if not m or not t or not c or m.group(1) != sweep_source_hash():
+        return None
+    if (int(c.group(1)), int(c.group(2))) != tuple(sweep):
         return None
     return float(t.group(1))
 
@@ -200,6 +206,16 @@ def bench_single(args, log):
     del pos
     setup_s = time.perf_counter() - t0
     log(f"{cfg['name']} set up in {setup_s:.1f}s: {wl.grid.n_packages} packages, {wl.grid.n_core} core")
+    # sweep configuration: tuned once on this grid (phi0 is only read), or fixed
+    if args.sweep == "auto":
+        tv, tg, ttab = sg.autotune_sweep(wl.grid, wl.phi0, wl.scratch, reps=10)
+        tuned = {"variant": tv, "groups": tg, "source": "autotuned",
+                 "us_per_sweep": {f"v{v}g{g}": float(x) for (v, g), x in zip(sg.SWEEP_TUNE_CANDIDATES, ttab)}}
+    else:
+        tv, tg = (int(x) for x in args.sweep.split(","))
+        sg.set_sweep_config(tv, tg)
+        tuned = {"variant": tv, "groups": tg, "source": "--sweep"}
+    log(f"sweep configuration: variant {tv}, groups {tg}")
     P = wl.grid.n_packages
     n_core = wl.grid.n_core
     integ = torch.empty((4, n_core * 64), device="cuda")
@@ -282,6 +298,7 @@ def bench_single(args, log):
                    "particles": n_part},
         "breakdown_ms": {k: acc[k] / K for k in acc},
         "reinit_updates_per_s": upd_step / (reinit_ms * 1e-3),
+        "sweep_config": tuned,
         "probes_per_s": n_part / (probe_ms * 1e-3),
         "probe_particle_order": "as generated (random over the surface)",
         "probes_per_s_cell_sorted": n_part / (probe_sorted_ms * 1e-3),
@@ -291,9 +308,9 @@ def bench_single(args, log):
                       "cell_sorted_GBps": probe_bytes / (probe_sorted_ms * 1e-3) / 1e9,
                       "cell_sorted_frac": probe_bytes / (probe_sorted_ms * 1e-3) / 1e9 / HBM_PEAK_GBS},
         "integral_cells_per_s": n_core * 64 / (acc["integ"] / K * 1e-3),
-        "roofline": {"bound": "hbm", "kernel": "reinit sweep", "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": measured_traffic(bytes_launch) if cfg["name"] == "prism512" else None,
+        "roofline": {"bound": "hbm", "kernel": f"reinit sweep (variant {tv}, groups {tg})", "achieved": achieved,
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": measured_traffic(cfg["name"], (tv, tg)),
                      "avg_launch_us": sweep_ms * 1e3, "algorithmic_bytes_per_launch": bytes_launch,
                      "note": ("phi ping-pong of 64 MB is resident in the 256 MB Infinity Cache"
                               if cfg["name"] == "prism512" else
@@ -351,9 +368,9 @@ def bench_batch(args, log):
                                "iteration over a global worklist, 50 iterations replayed as a HIP graph",
                    "n_shapes": len(counts), "n_packages": int(bw.batch.n_work), "n_iter": n_iter,
                    "packages_min": int(min(counts)), "packages_max": int(max(counts))},
-        "autotuned": {"variant": ["dpp", "lds"][v], "blocks_per_cu": b,
-                      "us_per_sweep": {f"{['dpp', 'lds'][i]}_bpc{bb}": float(table[i, j])
-                                       for i in range(2) for j, bb in enumerate((1, 2, 4, 8, 16))}},
+        "autotuned": {"variant": ["dpp", "lds"][v], "blocks_per_cu": b if b else "one wavefront per 4 packages",
+                      "us_per_sweep": {f"{['dpp', 'lds'][i]}_{'bpc%d' % bb if bb else 'flat'}": float(table[i, j])
+                                       for i in range(2) for j, bb in enumerate((1, 2, 4, 8, 16, 0))}},
         "roofline": {"bound": "hbm", "kernel": "batched sweep", "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
                      "avg_launch_us": sweep_ms * 1e3},

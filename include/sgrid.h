@@ -259,13 +259,15 @@ sgrid_status sgrid_batch_info(const sgrid_batch *batch, int64_t *n_total, int64_
                               int64_t *bases_host);
 
 /* Kernel choice: variant 0 = DPP lane exchange, 1 = LDS tile; workgroups per
- * compute unit of the persistent launch (1..16). */
+ * compute unit of the persistent launch (1..16), or 0 for one wavefront per
+ * four worklist entries (no persistence). */
 sgrid_status sgrid_batch_set_config(sgrid_batch *batch, int32_t variant, int32_t blocks_per_cu);
 
-/* Times every (variant, workgroups per CU in {1, 2, 4, 8, 16}) candidate with
- * `reps` sweeps that read phi_dev and write scratch_dev (phi is not
+/* Times every (variant, workgroups per CU in {1, 2, 4, 8, 16, 0}) candidate
+ * with `reps` sweeps that read phi_dev and write scratch_dev (phi is not
  * modified), keeps the fastest as the batch's configuration and returns it;
- * us_table [2][5] (nullable) receives the microseconds per sweep. */
+ * us_table [2][6] (nullable) receives the microseconds per sweep in that
+ * order. */
 sgrid_status sgrid_batch_autotune(sgrid_batch *batch, const float *phi_dev, float *scratch_dev, int32_t reps,
                                   void *stream, int32_t *variant_out, int32_t *blocks_per_cu_out,
                                   float *us_table);
@@ -293,6 +295,20 @@ sgrid_status sgrid_batch_reinitialize(sgrid_batch *batch, float *phi_dev, float 
  * setting.
  */
 sgrid_status sgrid_set_sweep_config(int32_t variant, int32_t groups);
+
+/*
+ * Autotuner of sgrid_reinitialize on the caller's grid: times the candidates
+ * (variant, groups) = (0, 1), (0, 2), (0, 4), (3, 1), (3, 2), (5, 1) with
+ * `reps` sweeps each (1..1000) that read phi and write scratch (phi is not
+ * modified; scratch rows 2.. are overwritten), makes the fastest the
+ * process-wide configuration (as sgrid_set_sweep_config) and returns it.
+ * us_table [6] (nullable) receives the microseconds per sweep in that order.
+ * Synchronises the stream.  Results are identical for every candidate, so
+ * tuning changes only speed.
+ */
+sgrid_status sgrid_autotune_sweep(const sgrid_grid *grid, sgrid_dtype dtype, const void *phi_dev,
+                                  void *scratch_dev, int32_t reps, void *stream, int32_t *variant_out,
+                                  int32_t *groups_out, float *us_table);
 
 #ifdef __cplusplus
 }

@@ -19,6 +19,7 @@ import torch
 __all__ = [
     "SgridError", "Grid", "load", "build_packages", "fill_far_field", "reinitialize",
     "compute_gradient", "compute_gradient_packed", "probe_particles", "probe_particles_packed", "compute_near_surface_integrals", "set_sweep_config",
+    "autotune_sweep", "SWEEP_TUNE_CANDIDATES",
     "Mlp", "gather_windows", "MLP_N_PARAMS", "Batch",
     "LIB_PATH", "FAR_FIELD_IN_H",
 ]
@@ -59,6 +60,8 @@ _SIGNATURES = {
     "sgrid_probe_particles": (ctypes.c_int, [_P, ctypes.c_int, _P, _P, _P, ctypes.c_int64, _P, _P, _P]),
     "sgrid_compute_near_surface_integrals": (ctypes.c_int, [_P, _P, _P, _P, _P, _P]),
     "sgrid_set_sweep_config": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32]),
+    "sgrid_autotune_sweep": (ctypes.c_int, [_P, ctypes.c_int, _P, _P, ctypes.c_int32, _P,
+                                            ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32), _P]),
     "sgrid_mlp_create": (ctypes.c_int, [_P, ctypes.POINTER(_P)]),
     "sgrid_mlp_destroy": (ctypes.c_int, [_P]),
     "sgrid_mlp_get_params": (ctypes.c_int, [_P, _P, _P, _P, ctypes.POINTER(ctypes.c_int64)]),
@@ -401,14 +404,15 @@ class Batch:
         _check(load().sgrid_batch_set_config(self.handle, int(variant), int(blocks_per_cu)))
 
     def autotune(self, phi: torch.Tensor, scratch: torch.Tensor, reps: int = 10, stream=None):
-        """Returns (variant, blocks_per_cu, table[2][5] of us per sweep)."""
+        """Returns (variant, blocks_per_cu, table[2][6] of us per sweep for
+        blocks_per_cu in (1, 2, 4, 8, 16, 0))."""
         import numpy as np
         v, b = ctypes.c_int32(), ctypes.c_int32()
-        table = np.zeros(10, dtype=np.float32)
+        table = np.zeros(12, dtype=np.float32)
         _check(load().sgrid_batch_autotune(self.handle, _dev(phi, "phi"), _dev(scratch, "scratch"), int(reps),
                                            _stream(stream), ctypes.byref(v), ctypes.byref(b),
                                            table.ctypes.data_as(_P)))
-        return int(v.value), int(b.value), table.reshape(2, 5)
+        return int(v.value), int(b.value), table.reshape(2, 6)
 
     def reinitialize(self, phi: torch.Tensor, scratch: torch.Tensor, n_iter: int, use_graph: bool = True,
                      stream=None):
@@ -416,6 +420,24 @@ class Batch:
             raise ValueError("phi and scratch must be [n_total, 64] float32")
         _check(load().sgrid_batch_reinitialize(self.handle, _dev(phi, "phi"), _dev(scratch, "scratch"),
                                                int(n_iter), int(bool(use_graph)), _stream(stream)))
+
+
+SWEEP_TUNE_CANDIDATES = ((0, 1), (0, 2), (0, 4), (3, 1), (3, 2), (5, 1))
+
+
+def autotune_sweep(grid: "Grid", phi: torch.Tensor, scratch: torch.Tensor, reps: int = 10, stream=None):
+    """Times the sweep candidates on this grid (phi is read, scratch written),
+    makes the fastest the configuration and returns (variant, groups, us per
+    sweep for each of SWEEP_TUNE_CANDIDATES)."""
+    import numpy as np
+    if scratch.dtype != phi.dtype or scratch.numel() != phi.numel() or phi.numel() != grid.n_total * 64:
+        raise ValueError("phi and scratch must both be [P+2, 64] of one dtype")
+    v, g = ctypes.c_int32(), ctypes.c_int32()
+    table = np.zeros(len(SWEEP_TUNE_CANDIDATES), dtype=np.float32)
+    _check(load().sgrid_autotune_sweep(grid.handle, _dtype_code(phi), _dev(phi, "phi"), _dev(scratch, "scratch"),
+                                       int(reps), _stream(stream), ctypes.byref(v), ctypes.byref(g),
+                                       table.ctypes.data_as(_P)))
+    return int(v.value), int(g.value), table
 
 
 def set_sweep_config(variant: int, groups: int):

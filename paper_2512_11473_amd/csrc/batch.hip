@@ -4,12 +4,13 @@
 // candidate kernels on the caller's data.
 //
 // Layout: the fields of all grids are concatenated, grid s occupying package
-// ids [base_s, base_s + P_s + 2) (its two far-field rows first).  The batch
-// keeps a face table rebased to these global ids, whose row for package g is
-// (-x, +x, -y, +y, -z, +z, g, s): the last pad holds the grid index, which
-// selects that grid's (h^2, 1/h, h/2) in a small parameter table.  The
-// worklist lists the activated packages of every grid; each wavefront of the
-// persistent kernel walks a contiguous range of it, four packages at a time.
+// ids [base_s, base_s + P_s + 2) (its two far-field rows first).  The
+// worklist lists the activated packages of every grid, each grid's in the
+// Morton order of its cells (the grids' own sweep order), and holds one row
+// per entry: (-x, +x, -y, +y, -z, +z, g, s) with the neighbours and the
+// package g rebased to global ids and the grid index s, which selects that
+// grid's (h^2, 1/h, h/2) in a small parameter table.  Each wavefront walks a
+// contiguous range of the worklist, four packages at a time.
 //
 // The per-point update is the same function as the single-grid sweep with the
 // same per-grid constants, so every grid's result is bit-identical to its own
@@ -46,11 +47,14 @@ struct Halo {
     float xm, xp;
 };
 
-__device__ __forceinline__ void batch_loads(const float *__restrict__ src, const uint32_t *__restrict__ face,
-                                            int64_t g, int r, Halo &l, uint32_t &shape) {
+// Loads of worklist entry e: its row of the worklist table (face neighbours,
+// package id g, grid index), then the package row and its halos.
+__device__ __forceinline__ void batch_loads(const float *__restrict__ src, const uint32_t *__restrict__ wrow,
+                                            int64_t e, int r, Halo &l, int64_t &g, uint32_t &shape) {
     const int j = r & 3, k = r >> 2;
-    const uint4 f0 = *reinterpret_cast<const uint4 *>(face + g * 8);
-    const uint4 f1 = *reinterpret_cast<const uint4 *>(face + g * 8 + 4);
+    const uint4 f0 = *reinterpret_cast<const uint4 *>(wrow + e * 8);
+    const uint4 f1 = *reinterpret_cast<const uint4 *>(wrow + e * 8 + 4);
+    g = (int64_t)f1.z;
     shape = f1.w;
     l.c = ld_row(src + g * 64 + r * 4);
     l.xm = src[(int64_t)f0.x * 64 + r * 4 + 3];
@@ -64,7 +68,6 @@ __device__ __forceinline__ void batch_loads(const float *__restrict__ src, const
     const int rz = k == 0 ? j + 12 : k == 3 ? j : r;
     l.zh = ld_row(src + fz * 64 + rz * 4);
 }
-
 
 __device__ __forceinline__ Row4<float> update_row_dpp(int r, const Halo &l, const sgrid::SweepParams<float> &sp) {
     const int j = r & 3;
@@ -87,8 +90,7 @@ __device__ __forceinline__ Row4<float> update_row_dpp(int r, const Halo &l, cons
 // Persistent worklist sweep, DPP exchange.  Wavefront w processes the sets
 // [w * spw, (w + 1) * spw) of four worklist entries.
 __global__ __launch_bounds__(256) void batch_dpp_kernel(const float *__restrict__ src, float *__restrict__ dst,
-                                                        const uint32_t *__restrict__ face,
-                                                        const uint32_t *__restrict__ work, int64_t n_work,
+                                                        const uint32_t *__restrict__ wrow, int64_t n_work,
                                                         const sgrid::SweepParams<float> *__restrict__ params,
                                                         int64_t n_blocks, int64_t spw) {
     const int64_t b = xcd_block(blockIdx.x, n_blocks);
@@ -101,8 +103,8 @@ __global__ __launch_bounds__(256) void batch_dpp_kernel(const float *__restrict_
         const bool live = e < n_work;
         Halo l;
         uint32_t shape = 0;
-        const int64_t g = live ? work[e] : 0;
-        if (live) batch_loads(src, face, g, r, l, shape);
+        int64_t g = 0;
+        if (live) batch_loads(src, wrow, e, r, l, g, shape);
         const sgrid::SweepParams<float> sp = params[shape];
         const Row4<float> o = update_row_dpp(r, l, sp);
         if (live) st_row(dst + g * 64 + r * 4, o);
@@ -111,8 +113,7 @@ __global__ __launch_bounds__(256) void batch_dpp_kernel(const float *__restrict_
 
 // Persistent worklist sweep, LDS tile (package + one-cell face halo).
 __global__ __launch_bounds__(256) void batch_lds_kernel(const float *__restrict__ src, float *__restrict__ dst,
-                                                        const uint32_t *__restrict__ face,
-                                                        const uint32_t *__restrict__ work, int64_t n_work,
+                                                        const uint32_t *__restrict__ wrow, int64_t n_work,
                                                         const sgrid::SweepParams<float> *__restrict__ params,
                                                         int64_t n_blocks, int64_t spw) {
     __shared__ float tile[16][216];
@@ -132,9 +133,9 @@ __global__ __launch_bounds__(256) void batch_lds_kernel(const float *__restrict_
         const bool live = s < s1 && e < n_work;
         Halo l;
         uint32_t shape = 0;
-        const int64_t g = live ? work[e] : 0;
+        int64_t g = 0;
         if (live) {
-            batch_loads(src, face, g, r, l, shape);
+            batch_loads(src, wrow, e, r, l, g, shape);
 #pragma unroll
             for (int i = 0; i < 4; ++i) t[at(i, j, k)] = l.c.v[i];
             t[at(-1, j, k)] = l.xm;
@@ -162,19 +163,17 @@ __global__ __launch_bounds__(256) void batch_lds_kernel(const float *__restrict_
     (void)wave0;
 }
 
-// Batch tables: rebased face rows of grid s, worklist entries, far-field rows.
-__global__ __launch_bounds__(256) void rebase_kernel(const uint32_t *__restrict__ face_s, int64_t n_total_s,
-                                                     uint32_t base, uint32_t shape, uint32_t *__restrict__ face_all,
-                                                     uint32_t *__restrict__ work, int64_t work_base) {
+// Worklist rows of grid s: its sweep-order face rows (wface) rebased to global
+// ids, with the grid index in the last slot.
+__global__ __launch_bounds__(256) void rebase_kernel(const uint32_t *__restrict__ wface_s, int64_t P_s, uint32_t base,
+                                                     uint32_t shape, uint32_t *__restrict__ wrow, int64_t work_base) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= n_total_s) return;
-    uint32_t *o = face_all + ((int64_t)base + t) * 8;
-    const uint32_t *in = face_s + t * 8;
+    if (t >= P_s) return;
+    uint32_t *o = wrow + (work_base + t) * 8;
+    const uint32_t *in = wface_s + t * 8;
 #pragma unroll
-    for (int f = 0; f < 6; ++f) o[f] = base + in[f];
-    o[6] = base + (uint32_t)t;
+    for (int f = 0; f < 7; ++f) o[f] = base + in[f];
     o[7] = shape;
-    if (t >= 2) work[work_base + t - 2] = base + (uint32_t)t;
 }
 
 // Copies the far-field rows of every grid from one buffer to the other.
@@ -192,8 +191,7 @@ struct sgrid_batch {
     int32_t n = 0;
     int64_t n_total = 0;      // concatenated package rows
     int64_t n_work = 0;
-    uint32_t *face = nullptr;
-    uint32_t *work = nullptr;
+    uint32_t *wrow = nullptr;         // [n_work][8] worklist rows
     uint32_t *bases = nullptr;        // device copy of grid bases
     sgrid::SweepParams<float> *params = nullptr;
     std::vector<int64_t> base_host, total_host;
@@ -212,16 +210,18 @@ namespace {
 sgrid_status launch_batch_sweep(const sgrid_batch *b, const float *src, float *dst, int variant, int bpc,
                                 hipStream_t st) {
     if (b->n_work == 0) return SGRID_OK;
+    // bpc workgroups per CU walk the worklist persistently; bpc = 0 launches
+    // one wavefront per set of four packages instead
     const int64_t n_sets = (b->n_work + 3) / 4;
-    int64_t nb = (int64_t)sgrid::cu_count() * bpc;
+    int64_t nb = bpc > 0 ? (int64_t)sgrid::cu_count() * bpc : (n_sets + 3) / 4;
     const int64_t spw = (n_sets + nb * 4 - 1) / (nb * 4);
     nb = (n_sets + spw * 4 - 1) / (spw * 4);
     if (variant == 1)
-        hipLaunchKernelGGL(batch_lds_kernel, dim3((unsigned)nb), dim3(256), 0, st, src, dst, b->face, b->work,
-                           b->n_work, b->params, nb, spw);
+        hipLaunchKernelGGL(batch_lds_kernel, dim3((unsigned)nb), dim3(256), 0, st, src, dst, b->wrow, b->n_work,
+                           b->params, nb, spw);
     else
-        hipLaunchKernelGGL(batch_dpp_kernel, dim3((unsigned)nb), dim3(256), 0, st, src, dst, b->face, b->work,
-                           b->n_work, b->params, nb, spw);
+        hipLaunchKernelGGL(batch_dpp_kernel, dim3((unsigned)nb), dim3(256), 0, st, src, dst, b->wrow, b->n_work,
+                           b->params, nb, spw);
     SG_CHECK_LAUNCH("batch sweep");
     return SGRID_OK;
 }
@@ -276,16 +276,14 @@ extern "C" sgrid_status sgrid_batch_create(const sgrid_grid *const *grids, int32
     b->n_total = total;
     b->n_work = work;
     auto fail = [&](sgrid_status s) {
-        sgrid::dev_free(b->face);
-        sgrid::dev_free(b->work);
+        sgrid::dev_free(b->wrow);
         sgrid::dev_free(b->bases);
         sgrid::dev_free(b->params);
         delete b;
         return s;
     };
     sgrid_status s;
-    if ((s = sgrid::dev_alloc((void **)&b->face, (size_t)total * 32, "batch face table")) != SGRID_OK) return fail(s);
-    if ((s = sgrid::dev_alloc((void **)&b->work, (size_t)(work > 0 ? work : 1) * 4, "worklist")) != SGRID_OK)
+    if ((s = sgrid::dev_alloc((void **)&b->wrow, (size_t)(work > 0 ? work : 1) * 32, "worklist rows")) != SGRID_OK)
         return fail(s);
     if ((s = sgrid::dev_alloc((void **)&b->bases, (size_t)n * 4, "grid bases")) != SGRID_OK) return fail(s);
     if ((s = sgrid::dev_alloc((void **)&b->params, (size_t)n * sizeof(sgrid::SweepParams<float>), "grid params")) !=
@@ -302,8 +300,9 @@ extern "C" sgrid_status sgrid_batch_create(const sgrid_grid *const *grids, int32
         // the same constants as the single-grid sweep
         params[k] = sgrid::SweepParams<float>{(float)(g->h * g->h), (float)(1.0 / g->h), (float)(0.5 * g->h)};
         const int64_t nt = g->total();
-        hipLaunchKernelGGL(rebase_kernel, dim3((unsigned)((nt + 255) / 256)), dim3(256), 0, st, g->face, nt,
-                           (uint32_t)base, (uint32_t)k, b->face, b->work, wbase);
+        if (g->P > 0)
+            hipLaunchKernelGGL(rebase_kernel, dim3((unsigned)((g->P + 255) / 256)), dim3(256), 0, st, g->wface, g->P,
+                               (uint32_t)base, (uint32_t)k, b->wrow, wbase);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) {
             sgrid::set_error("batch table launch failed: %s", hipGetErrorString(e));
@@ -330,8 +329,7 @@ extern "C" sgrid_status sgrid_batch_destroy(sgrid_batch *b) {
     hipError_t e = hipDeviceSynchronize();
     drop_graph(b);
     if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
-    sgrid::dev_free(b->face);
-    sgrid::dev_free(b->work);
+    sgrid::dev_free(b->wrow);
     sgrid::dev_free(b->bases);
     sgrid::dev_free(b->params);
     delete b;
@@ -357,7 +355,7 @@ extern "C" sgrid_status sgrid_batch_set_config(sgrid_batch *b, int32_t variant, 
     sgrid::clear_error();
     SG_REQUIRE(b != nullptr, "batch is NULL");
     SG_REQUIRE(variant == 0 || variant == 1, "batch variant must be 0 or 1");
-    SG_REQUIRE(blocks_per_cu >= 1 && blocks_per_cu <= 16, "blocks_per_cu must be in 1..16");
+    SG_REQUIRE(blocks_per_cu >= 0 && blocks_per_cu <= 16, "blocks_per_cu must be in 0..16");
     b->variant = variant;
     b->blocks_per_cu = blocks_per_cu;
     b->tuned = true;
@@ -366,19 +364,19 @@ extern "C" sgrid_status sgrid_batch_set_config(sgrid_batch *b, int32_t variant, 
 
 extern "C" sgrid_status sgrid_batch_autotune(sgrid_batch *b, const float *phi, float *scratch, int32_t reps,
                                              void *stream, int32_t *variant_out, int32_t *bpc_out,
-                                             float *us_table /* [2][5] */) {
+                                             float *us_table /* [2][6] */) {
     sgrid::clear_error();
     SG_REQUIRE(b != nullptr && phi != nullptr && scratch != nullptr, "NULL argument");
     SG_REQUIRE(reps >= 1 && reps <= 1000, "reps must be in 1..1000");
     hipStream_t st = sg_stream(stream);
-    static const int kBpc[5] = {1, 2, 4, 8, 16};
+    static const int kBpc[6] = {1, 2, 4, 8, 16, 0};
     hipEvent_t e0, e1;
     SG_CHECK_HIP(hipEventCreate(&e0));
     SG_CHECK_HIP(hipEventCreate(&e1));
     float best = 1e30f;
     int bv = 0, bb = 4;
     for (int v = 0; v < 2; ++v)
-        for (int i = 0; i < 5; ++i) {
+        for (int i = 0; i < 6; ++i) {
             // phi is only read: every timed sweep writes scratch
             sgrid_status s = launch_batch_sweep(b, phi, scratch, v, kBpc[i], st);
             if (s != SGRID_OK) return s;
@@ -392,7 +390,7 @@ extern "C" sgrid_status sgrid_batch_autotune(sgrid_batch *b, const float *phi, f
             float ms = 0.f;
             SG_CHECK_HIP(hipEventElapsedTime(&ms, e0, e1));
             const float us = 1e3f * ms / reps;
-            if (us_table) us_table[v * 5 + i] = us;
+            if (us_table) us_table[v * 6 + i] = us;
             if (us < best) {
                 best = us;
                 bv = v;

@@ -375,29 +375,30 @@ __global__ __launch_bounds__(256) void worklist_pos_kernel(const uint32_t *__res
     if (e < P) wpos[work[e]] = (uint32_t)e;
 }
 
-// Face rows in worklist order: a neighbour in the same group of kGroup entries
-// is stored as its slot in the group (flagged with kLocal), others as its
-// package id; then the package's own id.
+// Face rows in worklist order, twice: wface holds the six face neighbours'
+// package ids and the package's own id; sface marks a neighbour in the same
+// group of kGroup entries by its slot in the group (flagged with kLocal).
 __global__ __launch_bounds__(256) void sweep_face_kernel(const uint32_t *__restrict__ work,
                                                          const uint32_t *__restrict__ face,
                                                          const uint32_t *__restrict__ wpos, int64_t P,
-                                                         uint32_t *__restrict__ sface) {
+                                                         uint32_t *__restrict__ wface, uint32_t *__restrict__ sface) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= P * 8) return;
     const int64_t e = t >> 3;
     const int f = (int)(t & 7);
     const uint32_t p = work[e];
-    uint32_t v;
+    uint32_t v, w;
     if (f < 6) {
         const uint32_t n = face[(int64_t)p * 8 + f];
-        v = n;
+        v = w = n;
         if (n >= 2u) {
             const uint32_t en = wpos[n];
             if ((int64_t)en / sgrid::kGroup == e / sgrid::kGroup) v = sgrid::kLocal | (en % sgrid::kGroup);
         }
     } else {
-        v = f == 6 ? p : 0u;
+        v = w = f == 6 ? p : 0u;
     }
+    wface[t] = w;
     sface[t] = v;
 }
 
@@ -456,7 +457,7 @@ __global__ __launch_bounds__(256) void nbr_kernel(const uint32_t *__restrict__ c
 void free_grid(sgrid_grid *g) {
     if (!g) return;
     void *ptrs[] = {g->cell_pkg, g->pkg_cell, g->pkg_type, g->nbr, g->face, g->core_list, g->workspace, g->work,
-                    g->sface, g->wpos};
+                    g->sface, g->wface, g->wpos};
     for (void *p : ptrs) sgrid::dev_free(p);
     delete g;
 }
@@ -578,6 +579,7 @@ extern "C" sgrid_status sgrid_build_packages(const sgrid_desc *desc, const float
     // every package in the worklist (kept with the handle)
     {
         SG_ALLOC(g->sface, (g->P > 0 ? g->P : 1) * 32, "sweep face table");
+        SG_ALLOC(g->wface, (g->P > 0 ? g->P : 1) * 32, "worklist face table");
         uint32_t *wpos = nullptr;
         SG_ALLOC(wpos, nt * 4, "worklist positions");
         if (g->P > 0) {
@@ -585,7 +587,7 @@ extern "C" sgrid_status sgrid_build_packages(const sgrid_desc *desc, const float
                                g->P, wpos);
             SG_HIP_OR_FREE(hipGetLastError());
             hipLaunchKernelGGL(sweep_face_kernel, dim3((unsigned)((g->P * 8 + 255) / 256)), dim3(256), 0, st, g->work,
-                               g->face, wpos, g->P, g->sface);
+                               g->face, wpos, g->P, g->wface, g->sface);
             SG_HIP_OR_FREE(hipGetLastError());
         }
         g->wpos = wpos;

@@ -55,6 +55,7 @@ struct sgrid_grid {
     uint32_t *face = nullptr;       // [P+2][8]: the six face slots of nbr, then two pads
     uint32_t *core_list = nullptr;  // [n_core]
     uint32_t *work = nullptr;       // [P]: activated package ids in Morton order of their cells
+    uint32_t *wface = nullptr;      // [P][8]: per worklist position: six face neighbours, own id, pad
     uint32_t *sface = nullptr;      // [P][8]: per worklist position: six face neighbours (package id, or
                                     // group slot | kLocal when in the same 64-package group), own id, pad
     uint32_t *wpos = nullptr;       // [P+2]: position of each package in the worklist

@@ -9,12 +9,13 @@
 //
 // The cut fraction V and the kernel taps are in fraction.hpp.
 #include "fraction.hpp"
+#include "window.hpp"
 
 namespace {
 
-constexpr int kWin = 9;       // phi window edge (-2..6)
+using sgrid::kWin;            // phi window edge (-2..6)
+using sgrid::kWinN;
 constexpr int kVol = 7;       // V window edge (-1..5)
-constexpr int kWinN = kWin * kWin * kWin;
 constexpr int kVolN = kVol * kVol * kVol;
 
 using sgrid::wendland_u;
@@ -34,14 +35,7 @@ __global__ __launch_bounds__(256) void integrals_plain_kernel(const float *__res
     const int64_t p = live ? core_list[ci] : 0;
     if (live && lane < 27) s_ids[w][lane] = nbr[p * 27 + lane];
     __syncthreads();
-    if (live) {
-        for (int v = lane; v < kWinN; v += 64) {
-            const int x = v % kWin - 2, y = (v / kWin) % kWin - 2, z = v / (kWin * kWin) - 2;
-            const int kx = (x + 4) >> 2, ky = (y + 4) >> 2, kz = (z + 4) >> 2;   // slot per axis
-            const int d = (x + 4 - 4 * kx) + 4 * (y + 4 - 4 * ky) + 16 * (z + 4 - 4 * kz);
-            s_phi[w][v] = phi[(int64_t)s_ids[w][kx + 3 * ky + 9 * kz] * 64 + d];
-        }
-    }
+    if (live) sgrid::stage_window_part<64>(phi, s_ids[w], lane, s_phi[w]);
     __syncthreads();
     if (live) {
         const float *f = s_phi[w];

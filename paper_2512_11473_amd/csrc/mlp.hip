@@ -23,6 +23,7 @@
 #include <vector>
 
 #include "fraction.hpp"
+#include "window.hpp"
 
 typedef __bf16 bf16;
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
@@ -569,7 +570,8 @@ extern "C" sgrid_status sgrid_mlp_train_step(sgrid_mlp *m, const float *x, const
 // ---------------------------------------------------------------------------
 namespace {
 
-constexpr int kWin = 9, kWinN = 729;   // phi window of a package, local -2..6
+using sgrid::kWin;                     // phi window of a package, local -2..6
+using sgrid::kWinN;
 constexpr int kVol = 7, kVolN = 343;   // points -1..5 whose cut fraction a tap may use
 
 // Stages the 9^3 phi window of core package p into LDS (all threads of the block).
@@ -577,12 +579,7 @@ __device__ __forceinline__ void stage_window(const float *__restrict__ phi, cons
                                              int64_t p, float *s_phi, uint32_t *s_ids) {
     if (threadIdx.x < 27) s_ids[threadIdx.x] = nbr[p * 27 + threadIdx.x];
     __syncthreads();
-    for (int v = threadIdx.x; v < kWinN; v += blockDim.x) {
-        const int x = v % kWin - 2, y = (v / kWin) % kWin - 2, z = v / (kWin * kWin) - 2;
-        const int kx = (x + 4) >> 2, ky = (y + 4) >> 2, kz = (z + 4) >> 2;
-        const int d = (x + 4 - 4 * kx) + 4 * (y + 4 - 4 * ky) + 16 * (z + 4 - 4 * kz);
-        s_phi[v] = phi[(int64_t)s_ids[kx + 3 * ky + 9 * kz] * 64 + d];
-    }
+    sgrid::stage_window_part<256>(phi, s_ids, threadIdx.x, s_phi);
     __syncthreads();
 }
 

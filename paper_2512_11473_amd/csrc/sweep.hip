@@ -160,11 +160,12 @@ __global__ __launch_bounds__(256) void reinit_dpp_kernel(const T *__restrict__ s
 // Worklist variant: the DPP sweep over the packages in Morton order of their
 // cells (the build's worklist), so the sixteen packages of a workgroup are
 // spatial neighbours and most halo rows come from lines the workgroup itself
-// brings into the caches.  G sets of four packages per wavefront.
+// brings into the caches.  The face rows are read in worklist order (wface:
+// six neighbours and the package's own id), one coalesced 32-byte row per
+// package.  G sets of four packages per wavefront.
 template <typename T, int G>
 __global__ __launch_bounds__(256) void reinit_work_kernel(const T *__restrict__ src, T *__restrict__ dst,
-                                                          const uint32_t *__restrict__ face,
-                                                          const uint32_t *__restrict__ work, int64_t P,
+                                                          const uint32_t *__restrict__ wface, int64_t P,
                                                           int64_t n_blocks, T h2, T inv_h, T dt) {
     const int64_t b = xcd_block(blockIdx.x, n_blocks);
     const int lane = threadIdx.x & 63;
@@ -175,8 +176,13 @@ __global__ __launch_bounds__(256) void reinit_work_kernel(const T *__restrict__ 
 #pragma unroll
     for (int g = 0; g < G; ++g) {
         const int64_t e = e0 + 4 * g;
-        p[g] = e < P ? (int64_t)work[e] : -1;
-        if (p[g] >= 0) issue_loads(src, face, p[g], r, l[g]);
+        p[g] = -1;
+        if (e < P) {
+            const uint4 f0 = *reinterpret_cast<const uint4 *>(wface + e * 8);
+            const uint4 f1 = *reinterpret_cast<const uint4 *>(wface + e * 8 + 4);
+            p[g] = (int64_t)f1.z;
+            issue_data(src, p[g], r, f0, make_uint2(f1.x, f1.y), l[g]);
+        }
     }
 #pragma unroll
     for (int g = 0; g < G; ++g) {
@@ -471,11 +477,11 @@ static sgrid_status launch_reinit_sweep(const sgrid_grid *g, const T *src, T *ds
                            g->P, ng, h2, inv_h, dt);
     } else if (cfg.variant == 3) {
         switch (cfg.groups) {
-            case 1: hipLaunchKernelGGL((reinit_work_kernel<T, 1>), grid, block, 0, st, src, dst, g->face, g->work, g->P, nb, h2, inv_h, dt); break;
-            case 2: hipLaunchKernelGGL((reinit_work_kernel<T, 2>), grid, block, 0, st, src, dst, g->face, g->work, g->P, nb, h2, inv_h, dt); break;
-            case 3: hipLaunchKernelGGL((reinit_work_kernel<T, 3>), grid, block, 0, st, src, dst, g->face, g->work, g->P, nb, h2, inv_h, dt); break;
-            case 4: hipLaunchKernelGGL((reinit_work_kernel<T, 4>), grid, block, 0, st, src, dst, g->face, g->work, g->P, nb, h2, inv_h, dt); break;
-            default: hipLaunchKernelGGL((reinit_work_kernel<T, 8>), grid, block, 0, st, src, dst, g->face, g->work, g->P, nb, h2, inv_h, dt); break;
+            case 1: hipLaunchKernelGGL((reinit_work_kernel<T, 1>), grid, block, 0, st, src, dst, g->wface, g->P, nb, h2, inv_h, dt); break;
+            case 2: hipLaunchKernelGGL((reinit_work_kernel<T, 2>), grid, block, 0, st, src, dst, g->wface, g->P, nb, h2, inv_h, dt); break;
+            case 3: hipLaunchKernelGGL((reinit_work_kernel<T, 3>), grid, block, 0, st, src, dst, g->wface, g->P, nb, h2, inv_h, dt); break;
+            case 4: hipLaunchKernelGGL((reinit_work_kernel<T, 4>), grid, block, 0, st, src, dst, g->wface, g->P, nb, h2, inv_h, dt); break;
+            default: hipLaunchKernelGGL((reinit_work_kernel<T, 8>), grid, block, 0, st, src, dst, g->wface, g->P, nb, h2, inv_h, dt); break;
         }
     } else if (cfg.variant == 2) {
         const int64_t n_sets = (g->P + 3) / 4;
@@ -525,6 +531,68 @@ extern "C" sgrid_status sgrid_set_sweep_config(int32_t variant, int32_t groups) 
     SG_REQUIRE(groups == 1 || groups == 2 || groups == 3 || groups == 4 || groups == 8, "groups must be 1, 2, 3, 4 or 8 (got %d)", groups);
     sgrid::set_sweep_config(variant, groups);
     return SGRID_OK;
+}
+
+// Candidates of the sweep autotuner: (variant, groups).
+static const int kTuneCandidates[6][2] = {{0, 1}, {0, 2}, {0, 4}, {3, 1}, {3, 2}, {5, 1}};
+
+template <typename T>
+static sgrid_status autotune_sweep(const sgrid_grid *g, const T *phi, T *scratch, int32_t reps, hipStream_t st,
+                                   int32_t *variant_out, int32_t *groups_out, float *us_table) {
+    hipEvent_t e0, e1;
+    SG_CHECK_HIP(hipEventCreate(&e0));
+    SG_CHECK_HIP(hipEventCreate(&e1));
+    float best = 1e30f;
+    sgrid::SweepConfig pick;
+    for (int c = 0; c < 6; ++c) {
+        sgrid::SweepConfig cfg;
+        cfg.variant = kTuneCandidates[c][0];
+        cfg.groups = kTuneCandidates[c][1];
+        // phi is only read: every timed sweep writes scratch
+        sgrid_status s = sgrid::launch_reinit_sweep<T>(g, phi, scratch, st, cfg);
+        if (s == SGRID_OK && hipEventRecord(e0, st) != hipSuccess) s = SGRID_E_HIP;
+        for (int32_t k = 0; s == SGRID_OK && k < reps; ++k) s = sgrid::launch_reinit_sweep<T>(g, phi, scratch, st, cfg);
+        float ms = 0.f;
+        if (s == SGRID_OK && (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                              hipEventElapsedTime(&ms, e0, e1) != hipSuccess)) {
+            sgrid::set_error("sweep autotune timing failed");
+            s = SGRID_E_HIP;
+        }
+        if (s != SGRID_OK) {
+            (void)hipEventDestroy(e0);
+            (void)hipEventDestroy(e1);
+            return s;
+        }
+        const float us = 1e3f * ms / reps;
+        if (us_table) us_table[c] = us;
+        if (us < best) {
+            best = us;
+            pick = cfg;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    sgrid::set_sweep_config(pick.variant, pick.groups);
+    if (variant_out) *variant_out = pick.variant;
+    if (groups_out) *groups_out = pick.groups;
+    return SGRID_OK;
+}
+
+extern "C" sgrid_status sgrid_autotune_sweep(const sgrid_grid *g, sgrid_dtype dtype, const void *phi, void *scratch,
+                                             int32_t reps, void *stream, int32_t *variant_out, int32_t *groups_out,
+                                             float *us_table) {
+    sgrid::clear_error();
+    SG_REQUIRE(g != nullptr && phi != nullptr && scratch != nullptr, "NULL argument");
+    SG_REQUIRE(phi != scratch, "phi and scratch must be distinct buffers");
+    SG_REQUIRE(sg_aligned(phi, 16) && sg_aligned(scratch, 16), "phi / scratch must be 16-byte aligned");
+    SG_REQUIRE(reps >= 1 && reps <= 1000, "reps must be in 1..1000");
+    SG_REQUIRE(dtype == SGRID_F32 || dtype == SGRID_F64, "unknown dtype %d", (int)dtype);
+    hipStream_t st = sg_stream(stream);
+    if (dtype == SGRID_F32)
+        return autotune_sweep<float>(g, (const float *)phi, (float *)scratch, reps, st, variant_out, groups_out,
+                                     us_table);
+    return autotune_sweep<double>(g, (const double *)phi, (double *)scratch, reps, st, variant_out, groups_out,
+                                  us_table);
 }
 
 extern "C" sgrid_status sgrid_fill_far_field(const sgrid_grid *g, sgrid_dtype dtype, void *phi, void *stream) {

@@ -41,7 +41,7 @@ def _singles(sg, bw, n_iter):
 @pytest.mark.parametrize("n_iter", [1, 6, 7])
 def test_batch_equals_single_grids(sg, bw, n_iter):
     ref = _singles(sg, bw, n_iter)
-    for variant, bpc in [(0, 1), (0, 4), (1, 2), (1, 8)]:
+    for variant, bpc in [(0, 1), (0, 4), (0, 0), (1, 2), (1, 8), (1, 0)]:
         bw.batch.set_config(variant, bpc)
         for use_graph in (False, True):
             bw.reset()
@@ -69,7 +69,8 @@ def test_graph_replays_match_eager(sg, bw):
 
 def test_autotune_keeps_results(sg, bw):
     v, b, table = bw.batch.autotune(bw.phi0, bw.scratch, reps=3)
-    assert v in (0, 1) and b in (1, 2, 4, 8, 16)
+    assert v in (0, 1) and b in (1, 2, 4, 8, 16, 0)
+    assert table.shape == (2, 6)
     assert np.all(table > 0)
     ref = _singles(sg, bw, 4)
     bw.reset()

@@ -267,6 +267,25 @@ def test_sweep_domain_edge(sg, dtype):
         assert np.max(np.abs(got - phi[wl.points.ravel()])) <= tol * run.h, n_iter
 
 
+def test_sweep_autotune(sg):
+    """The sweep autotuner times its candidates, leaves phi untouched, picks
+    one of them, and the tuned sweep gives the bits of the default one."""
+    cfg = synth.config_c1()
+    from paper_2512_11473_amd import workload
+    wl = workload.setup(cfg["shape"], cfg["N"], cfg["noise_amp"], cfg["noise_seed"])
+    sg.reinitialize(wl.grid, wl.phi, wl.scratch, 3)
+    ref = wl.phi.clone()
+    before = wl.phi.clone()
+    v, g, table = sg.autotune_sweep(wl.grid, wl.phi, wl.scratch, reps=2)
+    assert torch.equal(wl.phi, before)
+    assert (v, g) in sg.SWEEP_TUNE_CANDIDATES
+    assert np.all(table > 0)
+    wl.reset()
+    sg.reinitialize(wl.grid, wl.phi, wl.scratch, 3)
+    sg.set_sweep_config(0, 1)
+    assert torch.equal(wl.phi, ref)
+
+
 def test_determinism(sg):
     cfg = synth.config_c1()
     from paper_2512_11473_amd import workload
