@@ -2,17 +2,21 @@
 // Sec. 7.1 steps 1-3 and 5 of the paper), plus the handle lifecycle and error
 // reporting of the C ABI.
 //
-// Pipeline on the caller's stream:
-//   core_kernel     one lane per coarse cell: core flag |d| < l_c;
-//   tag_kernel      inner = not core with a core 26-neighbour; ballot-count
-//                   active and core cells per block of 1024 cells;
-//   scan_kernel     one workgroup: exclusive scan of the per-block counts;
+// Pipeline on the caller's stream (coarse cells held as bitmaps, 64 cells of a
+// row per word):
+//   bits_kernel     one wavefront per word: core flag |d| < l_c and sign of d,
+//                   one ballot each;
+//   dilate_kernel   one lane per word: activated = core dilated by one cell in
+//                   x, y, z (word shifts and ORs); per-group counts;
+//   scan_pair       exclusive scan of the counts (block sums, one workgroup
+//                   over them, block scans);
 //   (host)          read back P and n_core once, allocate the package tables;
-//   scatter_kernel  ballot + mbcnt rank inside each wavefront, wave offsets in
-//                   LDS, block offset from the scan: id = 2 + rank, in ascending
-//                   linear order, so no sort is needed;
+//   scatter_kernel  rank inside each word by popcount below the lane, word
+//                   offsets from the scan: id = 2 + rank in ascending linear
+//                   order, so no sort is needed;
 //   nbr_kernel      one lane per (package, slot): the 27-entry neighbour table and
-//                   the six face slots copied into a 32-byte row per package.
+//                   the six face slots copied into a 32-byte row per package;
+//   morton_*        the sweep worklist in Morton order of the cells.
 #include <stdarg.h>
 #include <stdlib.h>
 #include <string.h>
@@ -131,76 +135,113 @@ __device__ __forceinline__ uint64_t lanemask_lt() {
     return lane == 0 ? 0ull : (~0ull >> (64 - lane));
 }
 
-// Pass 1: core flag per coarse cell (|d| < l_c, compared in double so that a
-// non-representable l_c rounds the same way as the definition).
-__global__ __launch_bounds__(256) void core_kernel(const float *__restrict__ d, int64_t n_cells, double lc,
-                                                   uint8_t *__restrict__ type) {
-    const int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (c < n_cells) type[c] = fabs((double)d[c]) < lc ? 1 : 0;
-}
+// Bitmaps of the background grid.  Row r = y + M z holds its M cells in
+// W = ceil(M / 64) words; bit b of word r W + i is the cell x = 64 i + b.
+// Bits of x >= M are zero.  Word order is linear cell order.
 
-// Pass 2: cell type (0 inactive, 1 core, 2 inner = a core cell among the 26
-// neighbours) from the core bytes, and per-block ballot counts of active and
-// core cells.  Each thread handles kCellsPerThread consecutive cells.
-constexpr int kCellsPerThread = 4;
-constexpr int kCellsPerBlock = kTagBlock * kCellsPerThread;
-
-__device__ __forceinline__ uint8_t dilate(const uint8_t *__restrict__ core, int M, int64_t c) {
-    const int64_t MM = (int64_t)M * M;
-    const int x = (int)(c % M), y = (int)((c / M) % M), z = (int)(c / MM);
-    const int x0 = x > 0 ? x - 1 : x, x1 = x < M - 1 ? x + 1 : x;
-    const int y0 = y > 0 ? y - 1 : y, y1 = y < M - 1 ? y + 1 : y;
-    const int z0 = z > 0 ? z - 1 : z, z1 = z < M - 1 ? z + 1 : z;
-    uint32_t any = 0;
-    for (int zz = z0; zz <= z1; ++zz)
-        for (int yy = y0; yy <= y1; ++yy) {
-            const uint8_t *row = core + (int64_t)yy * M + (int64_t)zz * MM;
-            for (int xx = x0; xx <= x1; ++xx) any |= row[xx] & 1u;
-        }
-    return any ? 2 : 0;
-}
-
-// type[] holds the core flag in bit 0 on entry; inner cells get the value 2
-// written here.  Readers test bit 0 only, so a concurrent inner write never
-// changes what another block sees.
-__global__ __launch_bounds__(kTagBlock) void tag_kernel(int M, int64_t n_cells, uint8_t *__restrict__ type,
-                                                        uint32_t *__restrict__ cnt_active,
-                                                        uint32_t *__restrict__ cnt_core) {
-    __shared__ uint32_t s_act[kTagBlock / 64], s_core[kTagBlock / 64];
-    const int64_t c0 = (int64_t)blockIdx.x * kCellsPerBlock + threadIdx.x;
-    uint32_t na = 0, nc = 0;
-#pragma unroll
-    for (int q = 0; q < kCellsPerThread; ++q) {
-        const int64_t c = c0 + (int64_t)q * kTagBlock;
-        uint8_t t = 0;
-        if (c < n_cells) {
-            t = (type[c] & 1u) ? 1 : dilate(type, M, c);
-            if (t == 2) type[c] = 2;
-        }
-        na += (uint32_t)__popcll(__ballot(t != 0));
-        nc += (uint32_t)__popcll(__ballot(t == 1));
+// Pass 1: one wavefront per word: the core flag |d| < l_c (compared in double,
+// so that a non-representable l_c rounds as the definition does) and the sign
+// of d, each one ballot.
+__global__ __launch_bounds__(256) void bits_kernel(const float *__restrict__ d, int M, int W, int64_t n_words,
+                                                   double lc, uint64_t *__restrict__ core,
+                                                   uint64_t *__restrict__ neg) {
+    const int64_t w = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (w >= n_words) return;   // whole wavefronts
+    const int lane = threadIdx.x & 63;
+    const int64_t r = w / W;
+    const int x = (int)(w - r * W) * 64 + lane;
+    const float v = x < M ? d[r * M + x] : 1.0f;
+    const uint64_t bc = __ballot(x < M && fabs((double)v) < lc);
+    const uint64_t bn = __ballot(x < M && v < 0.0f);
+    if (lane == 0) {
+        core[w] = bc;
+        neg[w] = bn;
     }
-    const int w = threadIdx.x >> 6;
+}
+
+// Pass 2: one lane per word: the activated cells are the core cells dilated by
+// one cell along x, y and z (the cell and its 26 neighbours, Sec. 7.1 steps
+// 1-2: inner = not core with a core neighbour); per group of 16 words, the
+// counts of activated and of core cells feed the scan.
+__global__ __launch_bounds__(256) void dilate_kernel(const uint64_t *__restrict__ core, int M, int W,
+                                                     int64_t n_words, uint64_t *__restrict__ act,
+                                                     uint32_t *__restrict__ cnt_act,
+                                                     uint32_t *__restrict__ cnt_core) {
+    const int64_t w = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    uint64_t a = 0, own = 0;
+    if (w < n_words) {
+        const int64_t r = w / W;
+        const int i = (int)(w - r * W);
+        const int y = (int)(r % M), z = (int)(r / M);
+        for (int dz = -1; dz <= 1; ++dz) {
+            const int zz = z + dz;
+            if (zz < 0 || zz >= M) continue;
+            for (int dy = -1; dy <= 1; ++dy) {
+                const int yy = y + dy;
+                if (yy < 0 || yy >= M) continue;
+                const int64_t b = ((int64_t)yy + (int64_t)M * zz) * W + i;
+                const uint64_t c = core[b];
+                const uint64_t lo = i > 0 ? core[b - 1] : 0ull, hi = i < W - 1 ? core[b + 1] : 0ull;
+                a |= c | (c << 1) | (c >> 1) | (lo >> 63) | (hi << 63);
+            }
+        }
+        if (i == W - 1 && (M & 63)) a &= (1ull << (M & 63)) - 1ull;
+        own = core[w];
+    }
+    uint32_t na = (uint32_t)__popcll(a), nc = (uint32_t)__popcll(own);
+#pragma unroll
+    for (int off = 8; off >= 1; off >>= 1) {
+        na += __shfl_xor(na, off, 16);
+        nc += __shfl_xor(nc, off, 16);
+    }
+    if (w < n_words) {
+        act[w] = a;
+        if ((threadIdx.x & 15) == 0) {
+            cnt_act[w >> 4] = na;
+            cnt_core[w >> 4] = nc;
+        }
+    }
+}
+
+// Exclusive scan of two count arrays in three passes: per-block sums of
+// kScanBlock entries, one workgroup scanning the block sums (and writing the
+// totals), then every block scanning its entries from its offset.
+constexpr int kScanThreads = 1024;
+constexpr int kScanTile = kScanThreads * 4;
+constexpr int kScanBlock = 1024;   // entries per block of the first and last pass (256 lanes x 4)
+
+__global__ __launch_bounds__(256) void scan_reduce_kernel(const uint32_t *__restrict__ a, const uint32_t *__restrict__ b,
+                                                          int64_t n, uint32_t *__restrict__ sa,
+                                                          uint32_t *__restrict__ sb) {
+    __shared__ uint32_t ra[4], rb[4];
+    const int64_t base = (int64_t)blockIdx.x * kScanBlock + threadIdx.x * 4;
+    uint32_t xa = 0, xb = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+        if (base + k < n) {
+            xa += a[base + k];
+            xb += b[base + k];
+        }
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+        xa += __shfl_xor(xa, off);
+        xb += __shfl_xor(xb, off);
+    }
     if ((threadIdx.x & 63) == 0) {
-        s_act[w] = na;
-        s_core[w] = nc;
+        ra[threadIdx.x >> 6] = xa;
+        rb[threadIdx.x >> 6] = xb;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        uint32_t a = 0, k = 0;
-        for (int i = 0; i < kTagBlock / 64; ++i) { a += s_act[i]; k += s_core[i]; }
-        cnt_active[blockIdx.x] = a;
-        cnt_core[blockIdx.x] = k;
+        sa[blockIdx.x] = ra[0] + ra[1] + ra[2] + ra[3];
+        sb[blockIdx.x] = rb[0] + rb[1] + rb[2] + rb[3];
     }
 }
 
-// Exclusive scan of two count arrays by one workgroup, in tiles of
-// kScanThreads * 4 entries: coalesced loads into LDS, a sequential scan of 4
-// entries per thread, a Hillis-Steele scan of the thread sums, coalesced
-// stores, and a running carry between tiles.  totals = {P, n_core}.
-constexpr int kScanThreads = 1024;
-constexpr int kScanTile = kScanThreads * 4;
-
+// One workgroup, in tiles of kScanTile entries: coalesced loads into LDS, a
+// sequential scan of 4 entries per thread, a Hillis-Steele scan of the thread
+// sums, coalesced stores, and a running carry between tiles.  totals = the
+// two sums.
 __global__ __launch_bounds__(kScanThreads) void scan_kernel(uint32_t *__restrict__ a, uint32_t *__restrict__ b,
                                                             int64_t n, uint64_t *__restrict__ totals) {
     __shared__ uint32_t ta[kScanTile], tb[kScanTile];
@@ -252,52 +293,109 @@ __global__ __launch_bounds__(kScanThreads) void scan_kernel(uint32_t *__restrict
     }
 }
 
-// Numbering: within a block, cells are ranked q-major then by lane (cell
-// c0 + q * kTagBlock), which is ascending linear order because each q-slice
-// of the block covers kTagBlock consecutive cells.
-__global__ __launch_bounds__(kTagBlock) void scatter_kernel(const float *__restrict__ d, const uint8_t *__restrict__ type,
-                                                            int64_t n_cells, const uint32_t *__restrict__ off_active,
-                                                            const uint32_t *__restrict__ off_core,
-                                                            uint32_t *__restrict__ cell_pkg,
-                                                            uint32_t *__restrict__ pkg_cell,
-                                                            uint8_t *__restrict__ pkg_type,
-                                                            uint32_t *__restrict__ core_list) {
-    __shared__ uint32_t s_act[kCellsPerThread][kTagBlock / 64], s_core[kCellsPerThread][kTagBlock / 64];
-    const int64_t c0 = (int64_t)blockIdx.x * kCellsPerBlock + threadIdx.x;
-    const int w = threadIdx.x >> 6;
-    uint8_t t[kCellsPerThread];
-    uint64_t ba[kCellsPerThread], bc[kCellsPerThread];
+__global__ __launch_bounds__(256) void scan_apply_kernel(uint32_t *__restrict__ a, uint32_t *__restrict__ b, int64_t n,
+                                                         const uint32_t *__restrict__ off_a,
+                                                         const uint32_t *__restrict__ off_b) {
+    __shared__ uint32_t wa[4], wb[4];
+    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+    const int64_t base = (int64_t)blockIdx.x * kScanBlock + t * 4;
+    uint32_t va[4], vb[4], xa = 0, xb = 0;
 #pragma unroll
-    for (int q = 0; q < kCellsPerThread; ++q) {
-        const int64_t c = c0 + (int64_t)q * kTagBlock;
-        t[q] = c < n_cells ? type[c] : 0;
-        ba[q] = __ballot(t[q] != 0);
-        bc[q] = __ballot(t[q] == 1);
-        if ((threadIdx.x & 63) == 0) {
-            s_act[q][w] = (uint32_t)__popcll(ba[q]);
-            s_core[q][w] = (uint32_t)__popcll(bc[q]);
+    for (int k = 0; k < 4; ++k) {
+        va[k] = base + k < n ? a[base + k] : 0u;
+        vb[k] = base + k < n ? b[base + k] : 0u;
+        xa += va[k];
+        xb += vb[k];
+    }
+    // inclusive scan of the thread sums inside the wavefront
+    uint32_t ia = xa, ib = xb;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const uint32_t pa = __shfl_up(ia, off), pb = __shfl_up(ib, off);
+        if (lane >= off) {
+            ia += pa;
+            ib += pb;
         }
     }
+    if (lane == 63) {
+        wa[wv] = ia;
+        wb[wv] = ib;
+    }
     __syncthreads();
-    uint32_t wa = off_active[blockIdx.x], wc = off_core[blockIdx.x];
-    const uint64_t lt = lanemask_lt();
+    uint32_t ra = off_a[blockIdx.x] + ia - xa, rb = off_b[blockIdx.x] + ib - xb;
+    for (int k = 0; k < wv; ++k) {
+        ra += wa[k];
+        rb += wb[k];
+    }
 #pragma unroll
-    for (int q = 0; q < kCellsPerThread; ++q) {
-        uint32_t a = wa, k = wc;
-        for (int i = 0; i < w; ++i) { a += s_act[q][i]; k += s_core[q][i]; }
-        const int64_t c = c0 + (int64_t)q * kTagBlock;
-        if (c < n_cells) {
-            if (t[q] != 0) {
-                const uint32_t id = 2u + a + (uint32_t)__popcll(ba[q] & lt);
+    for (int k = 0; k < 4; ++k)
+        if (base + k < n) {
+            a[base + k] = ra;
+            b[base + k] = rb;
+            ra += va[k];
+            rb += vb[k];
+        }
+}
+
+// Exclusive scan of a[n] and b[n] in place; totals = {sum a, sum b}.  part
+// holds 2 * ceil(n / kScanBlock) words.
+static void scan_pair(uint32_t *a, uint32_t *b, int64_t n, uint32_t *part, uint64_t *totals, hipStream_t st) {
+    const int64_t nb = (n + kScanBlock - 1) / kScanBlock;
+    if (nb <= 1) {
+        hipLaunchKernelGGL(scan_kernel, dim3(1), dim3(kScanThreads), 0, st, a, b, n, totals);
+        return;
+    }
+    uint32_t *pa = part, *pb = part + nb;
+    hipLaunchKernelGGL(scan_reduce_kernel, dim3((unsigned)nb), dim3(256), 0, st, a, b, n, pa, pb);
+    hipLaunchKernelGGL(scan_kernel, dim3(1), dim3(kScanThreads), 0, st, pa, pb, nb, totals);
+    hipLaunchKernelGGL(scan_apply_kernel, dim3((unsigned)nb), dim3(256), 0, st, a, b, n, pa, pb);
+}
+
+// Pass 4: numbering.  One workgroup per group of 16 words, four words per
+// wavefront.  Cell x of word w gets id = 2 + (activated cells before the word:
+// the group's offset from the scan plus the words before it in the group) +
+// (activated cells of the word below x), which is ascending linear order, so
+// no sort is needed.  Cells not activated take the far-field package of their
+// sign.
+__global__ __launch_bounds__(256) void scatter_kernel(const uint64_t *__restrict__ act,
+                                                      const uint64_t *__restrict__ core,
+                                                      const uint64_t *__restrict__ neg, int M, int W,
+                                                      int64_t n_words, const uint32_t *__restrict__ off_act,
+                                                      const uint32_t *__restrict__ off_core,
+                                                      uint32_t *__restrict__ cell_pkg,
+                                                      uint32_t *__restrict__ pkg_cell,
+                                                      uint8_t *__restrict__ pkg_type,
+                                                      uint32_t *__restrict__ core_list) {
+    const int64_t grp = blockIdx.x;
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int64_t w0 = grp * 16 + wv * 4;
+    uint32_t pa = off_act[grp], pc = off_core[grp];
+    for (int64_t w = grp * 16; w < w0 && w < n_words; ++w) {
+        pa += (uint32_t)__popcll(act[w]);
+        pc += (uint32_t)__popcll(core[w]);
+    }
+    const uint64_t lt = lanemask_lt();
+    for (int k = 0; k < 4; ++k) {
+        const int64_t w = w0 + k;
+        if (w >= n_words) break;   // the same for the whole wavefront
+        const uint64_t a = act[w], cb = core[w], nb = neg[w];
+        const int64_t r = w / W;
+        const int x = (int)(w - r * W) * 64 + lane;
+        if (x < M) {
+            const int64_t c = r * M + x;
+            if ((a >> lane) & 1ull) {
+                const uint32_t id = 2u + pa + (uint32_t)__popcll(a & lt);
                 cell_pkg[c] = id;
                 pkg_cell[id] = (uint32_t)c;
-                pkg_type[id] = t[q];
-                if (t[q] == 1) core_list[k + (uint32_t)__popcll(bc[q] & lt)] = id;
+                const bool is_core = (cb >> lane) & 1ull;
+                pkg_type[id] = is_core ? 1 : 2;
+                if (is_core) core_list[pc + (uint32_t)__popcll(cb & lt)] = id;
             } else {
-                cell_pkg[c] = d[c] < 0.0f ? sgrid::kFarNeg : sgrid::kFarPos;
+                cell_pkg[c] = ((nb >> lane) & 1ull) ? sgrid::kFarNeg : sgrid::kFarPos;
             }
         }
-        for (int i = 0; i < kTagBlock / 64; ++i) { wa += s_act[q][i]; wc += s_core[q][i]; }
+        pa += (uint32_t)__popcll(a);
+        pc += (uint32_t)__popcll(cb);
     }
 }
 
@@ -305,6 +403,11 @@ __global__ __launch_bounds__(kTagBlock) void scatter_kernel(const float *__restr
 // their coarse cells, so the packages one workgroup sweeps together are
 // spatial neighbours and share their halo lines in the caches.  The codes run
 // over the enclosing power-of-two cube; codes outside the grid are skipped.
+// Each thread handles kCellsPerThread codes; activation is read from the
+// bitmap, the package id only for activated cells.
+constexpr int kCellsPerThread = 4;
+constexpr int kCellsPerBlock = kTagBlock * kCellsPerThread;
+
 __device__ __forceinline__ void morton_decode(int64_t code, int bits, int &x, int &y, int &z) {
     x = y = z = 0;
     for (int b = 0; b < bits; ++b) {
@@ -314,24 +417,36 @@ __device__ __forceinline__ void morton_decode(int64_t code, int bits, int &x, in
     }
 }
 
-__device__ __forceinline__ uint32_t morton_active(const uint32_t *__restrict__ cell_pkg, int M, int bits,
+__device__ __forceinline__ uint32_t morton_active(const uint32_t *__restrict__ cell_pkg,
+                                                  const uint64_t *__restrict__ act, int M, int W, int bits,
                                                   int64_t code, int64_t n_codes) {
     if (code >= n_codes) return 0u;
     int x, y, z;
     morton_decode(code, bits, x, y, z);
     if (x >= M || y >= M || z >= M) return 0u;
-    const uint32_t id = cell_pkg[x + (int64_t)M * (y + (int64_t)M * z)];
-    return id >= 2u ? id : 0u;
+    const int64_t r = (int64_t)y + (int64_t)M * z;
+    if (!((act[r * W + (x >> 6)] >> (x & 63)) & 1ull)) return 0u;
+    return cell_pkg[r * M + x];
 }
 
-__global__ __launch_bounds__(kTagBlock) void morton_count_kernel(const uint32_t *__restrict__ cell_pkg, int M, int bits,
-                                                                 int64_t n_codes, uint32_t *__restrict__ cnt) {
+__global__ __launch_bounds__(kTagBlock) void morton_count_kernel(const uint64_t *__restrict__ act, int M, int W,
+                                                                 int bits, int64_t n_codes,
+                                                                 uint32_t *__restrict__ cnt) {
     __shared__ uint32_t s_n[kTagBlock / 64];
     const int64_t c0 = (int64_t)blockIdx.x * kCellsPerBlock + threadIdx.x;
     uint32_t n = 0;
 #pragma unroll
-    for (int q = 0; q < kCellsPerThread; ++q)
-        n += (uint32_t)__popcll(__ballot(morton_active(cell_pkg, M, bits, c0 + (int64_t)q * kTagBlock, n_codes) != 0));
+    for (int q = 0; q < kCellsPerThread; ++q) {
+        const int64_t code = c0 + (int64_t)q * kTagBlock;
+        bool on = false;
+        if (code < n_codes) {
+            int x, y, z;
+            morton_decode(code, bits, x, y, z);
+            if (x < M && y < M && z < M)
+                on = (act[((int64_t)y + (int64_t)M * z) * W + (x >> 6)] >> (x & 63)) & 1ull;
+        }
+        n += (uint32_t)__popcll(__ballot(on));
+    }
     if ((threadIdx.x & 63) == 0) s_n[threadIdx.x >> 6] = n;
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -341,7 +456,8 @@ __global__ __launch_bounds__(kTagBlock) void morton_count_kernel(const uint32_t 
     }
 }
 
-__global__ __launch_bounds__(kTagBlock) void morton_scatter_kernel(const uint32_t *__restrict__ cell_pkg, int M,
+__global__ __launch_bounds__(kTagBlock) void morton_scatter_kernel(const uint32_t *__restrict__ cell_pkg,
+                                                                   const uint64_t *__restrict__ act, int M, int W,
                                                                    int bits, int64_t n_codes,
                                                                    const uint32_t *__restrict__ off,
                                                                    uint32_t *__restrict__ work) {
@@ -352,7 +468,7 @@ __global__ __launch_bounds__(kTagBlock) void morton_scatter_kernel(const uint32_
     uint64_t ba[kCellsPerThread];
 #pragma unroll
     for (int q = 0; q < kCellsPerThread; ++q) {
-        id[q] = morton_active(cell_pkg, M, bits, c0 + (int64_t)q * kTagBlock, n_codes);
+        id[q] = morton_active(cell_pkg, act, M, W, bits, c0 + (int64_t)q * kTagBlock, n_codes);
         ba[q] = __ballot(id[q] != 0);
         if ((threadIdx.x & 63) == 0) s_n[q][w] = (uint32_t)__popcll(ba[q]);
     }
@@ -513,24 +629,33 @@ extern "C" sgrid_status sgrid_build_packages(const sgrid_desc *desc, const float
     g->h = desc->h;
     SG_HIP_OR_FREE(hipGetDevice(&g->device));
 
-    // workspace: cell types (M^3 bytes), two count arrays, totals
-    const int64_t nb = (n_cells + kCellsPerBlock - 1) / kCellsPerBlock;
-    const size_t ws_types = ((size_t)n_cells + 255) / 256 * 256;
-    const size_t ws_counts = ((size_t)nb * 4 + 255) / 256 * 256;
-    SG_ALLOC(g->workspace, ws_types + 2 * ws_counts + 256, "build workspace");
-    uint8_t *types = (uint8_t *)g->workspace;
-    uint32_t *ca = (uint32_t *)(types + ws_types);
+    // workspace: three bitmaps (core, negative sign, activated), the per-group
+    // counts, the scan's block sums and the totals
+    const int64_t W = (M + 63) / 64;
+    const int64_t n_words = M * M * W;
+    const int64_t n_groups = (n_words + 15) / 16;
+    const int64_t n_sblocks = (n_groups + kScanBlock - 1) / kScanBlock;
+    const size_t ws_bits = ((size_t)n_words * 8 + 255) / 256 * 256;
+    const size_t ws_counts = ((size_t)n_groups * 4 + 255) / 256 * 256;
+    const size_t ws_part = ((size_t)n_sblocks * 8 + 255) / 256 * 256;
+    SG_ALLOC(g->workspace, 3 * ws_bits + 2 * ws_counts + ws_part + 256, "build workspace");
+    uint64_t *core_bits = (uint64_t *)g->workspace;
+    uint64_t *neg_bits = (uint64_t *)((uint8_t *)core_bits + ws_bits);
+    uint64_t *act_bits = (uint64_t *)((uint8_t *)neg_bits + ws_bits);
+    uint32_t *ca = (uint32_t *)((uint8_t *)act_bits + ws_bits);
     uint32_t *cc = (uint32_t *)((uint8_t *)ca + ws_counts);
-    uint64_t *totals = (uint64_t *)((uint8_t *)cc + ws_counts);
+    uint32_t *part = (uint32_t *)((uint8_t *)cc + ws_counts);
+    uint64_t *totals = (uint64_t *)((uint8_t *)part + ws_part);
     SG_ALLOC(g->cell_pkg, n_cells * 4, "cell_pkg");
 
     const double lc = 4.0 * desc->h;
-    hipLaunchKernelGGL(core_kernel, dim3((unsigned)((n_cells + 255) / 256)), dim3(256), 0, st, coarse_sdf, n_cells,
-                       lc, types);
+    hipLaunchKernelGGL(bits_kernel, dim3((unsigned)((n_words + 3) / 4)), dim3(256), 0, st, coarse_sdf, (int)M, (int)W,
+                       n_words, lc, core_bits, neg_bits);
     SG_HIP_OR_FREE(hipGetLastError());
-    hipLaunchKernelGGL(tag_kernel, dim3((unsigned)nb), dim3(kTagBlock), 0, st, (int)M, n_cells, types, ca, cc);
+    hipLaunchKernelGGL(dilate_kernel, dim3((unsigned)((n_words + 255) / 256)), dim3(256), 0, st, core_bits, (int)M,
+                       (int)W, n_words, act_bits, ca, cc);
     SG_HIP_OR_FREE(hipGetLastError());
-    hipLaunchKernelGGL(scan_kernel, dim3(1), dim3(kScanThreads), 0, st, ca, cc, nb, totals);
+    scan_pair(ca, cc, n_groups, part, totals, st);
     SG_HIP_OR_FREE(hipGetLastError());
     uint64_t *host = pinned_totals();
     uint64_t local[2] = {0, 0};
@@ -547,32 +672,35 @@ extern "C" sgrid_status sgrid_build_packages(const sgrid_desc *desc, const float
     SG_ALLOC(g->core_list, (g->n_core > 0 ? g->n_core : 1) * 4, "core_list");
     hipLaunchKernelGGL(far_rows_kernel, dim3(1), dim3(64), 0, st, g->pkg_cell, g->pkg_type);
     SG_HIP_OR_FREE(hipGetLastError());
-    hipLaunchKernelGGL(scatter_kernel, dim3((unsigned)nb), dim3(kTagBlock), 0, st, coarse_sdf, types, n_cells, ca, cc,
-                       g->cell_pkg, g->pkg_cell, g->pkg_type, g->core_list);
+    hipLaunchKernelGGL(scatter_kernel, dim3((unsigned)n_groups), dim3(256), 0, st, act_bits, core_bits, neg_bits,
+                       (int)M, (int)W, n_words, ca, cc, g->cell_pkg, g->pkg_cell, g->pkg_type, g->core_list);
     SG_HIP_OR_FREE(hipGetLastError());
     const int64_t nn = nt * 27;
     hipLaunchKernelGGL(nbr_kernel, dim3((unsigned)((nn + 255) / 256)), dim3(256), 0, st, g->cell_pkg, g->pkg_cell,
                        (int)M, nt, g->nbr, g->face);
     SG_HIP_OR_FREE(hipGetLastError());
-    // Morton-order sweep worklist (reuses the count buffers of the workspace
-    // when they are large enough, else a buffer of its own)
+    // Morton-order sweep worklist: count activated codes per block of
+    // kCellsPerBlock codes, scan, scatter (the counts and the scan's block sums
+    // live behind the worklist)
     {
         int bits = 0;
         while ((1ll << bits) < M) ++bits;
         const int64_t n_codes = (int64_t)1 << (3 * bits);
         const int64_t nbm = (n_codes + kCellsPerBlock - 1) / kCellsPerBlock;
-        SG_ALLOC(g->work, (g->P > 0 ? g->P : 1) * 4 + ((size_t)nbm * 8 + 256), "sweep worklist");
+        const int64_t nbs = (nbm + kScanBlock - 1) / kScanBlock;
+        SG_ALLOC(g->work, ((g->P > 0 ? g->P : 1) + 2 * nbm + 2 * nbs + 64) * 4, "sweep worklist");
         uint32_t *mc = g->work + (g->P > 0 ? g->P : 1);
         uint32_t *mz = mc + nbm;
+        uint32_t *mpart = mz + nbm;
         hipLaunchKernelGGL(fill_zero_kernel, dim3((unsigned)((nbm + 255) / 256)), dim3(256), 0, st, mz, nbm);
         SG_HIP_OR_FREE(hipGetLastError());
-        hipLaunchKernelGGL(morton_count_kernel, dim3((unsigned)nbm), dim3(kTagBlock), 0, st, g->cell_pkg, (int)M, bits,
-                           n_codes, mc);
+        hipLaunchKernelGGL(morton_count_kernel, dim3((unsigned)nbm), dim3(kTagBlock), 0, st, act_bits, (int)M, (int)W,
+                           bits, n_codes, mc);
         SG_HIP_OR_FREE(hipGetLastError());
-        hipLaunchKernelGGL(scan_kernel, dim3(1), dim3(kScanThreads), 0, st, mc, mz, nbm, totals);
+        scan_pair(mc, mz, nbm, mpart, totals, st);
         SG_HIP_OR_FREE(hipGetLastError());
-        hipLaunchKernelGGL(morton_scatter_kernel, dim3((unsigned)nbm), dim3(kTagBlock), 0, st, g->cell_pkg, (int)M,
-                           bits, n_codes, mc, g->work);
+        hipLaunchKernelGGL(morton_scatter_kernel, dim3((unsigned)nbm), dim3(kTagBlock), 0, st, g->cell_pkg, act_bits,
+                           (int)M, (int)W, bits, n_codes, mc, g->work);
         SG_HIP_OR_FREE(hipGetLastError());
     }
     // group-relative face rows of the sweep order, through the position of
