@@ -75,6 +75,11 @@ typedef struct {
     const uint32_t *core_list;   /* device [n_core]: ids of the core packages, ascending */
     const uint32_t *sweep_order; /* device [P]: activated package ids in Morton (Z-curve) order of their
                                     coarse cells; the order of sweep variant 3 */
+    const uint32_t *rank_map;    /* device [M * M * rank_row][4]: cell_pkg in compact form, one entry per
+                                    32 cells of a row (row y + M z, cells x = 32 e .. 32 e + 31):
+                                    {activated bits, negative-sign bits, activated cells before the
+                                    entry, 0}; bit b is cell 32 e + b.  The probe reads it. */
+    int32_t rank_row;            /* entries per row: ceil(M / 32) */
 } sgrid_info;
 
 /* Text of the last failure on this thread ("" if none). */
@@ -92,8 +97,8 @@ int32_t sgrid_version(void);
  * The result is bit-identical for identical inputs.  On success *out owns the
  * tables until sgrid_destroy.  Synchronises `stream` once (to learn P); the
  * tables are complete when `stream` reaches the end of the call, so work on
- * other streams must wait for it.  Memory comes from the device's
- * stream-ordered pool.
+ * other streams must wait for it.  Memory comes from the library's caching
+ * allocator (blocks of destroyed grids are reused).
  */
 sgrid_status sgrid_build_packages(const sgrid_desc *desc, const float *coarse_sdf_dev,
                                   void *stream, sgrid_grid **out);

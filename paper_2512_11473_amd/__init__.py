@@ -43,7 +43,8 @@ class _Desc(ctypes.Structure):
 class _Info(ctypes.Structure):
     _fields_ = [("n_coarse", ctypes.c_int32), ("h", ctypes.c_double), ("n_packages", ctypes.c_int64),
                 ("n_core", ctypes.c_int64), ("cell_pkg", _P), ("pkg_cell", _P), ("pkg_type", _P),
-                ("pkg_nbr", _P), ("core_list", _P), ("sweep_order", _P)]
+                ("pkg_nbr", _P), ("core_list", _P), ("sweep_order", _P), ("rank_map", _P),
+                ("rank_row", ctypes.c_int32)]
 
 
 _SIGNATURES = {
@@ -190,6 +191,7 @@ class Grid:
             "pkg_nbr": grab(info.pkg_nbr, nt * 27, torch.int32, 4).view(nt, 27),
             "core_list": grab(info.core_list, self.n_core, torch.int32, 4),
             "sweep_order": grab(info.sweep_order, self.n_packages, torch.int32, 4),
+            "rank_map": grab(info.rank_map, M * M * info.rank_row * 4, torch.int32, 4).view(M * M, info.rank_row, 4),
         }
 
     def empty_field(self, dtype=torch.float32, components: int = 1) -> torch.Tensor:

@@ -365,7 +365,8 @@ __global__ __launch_bounds__(256) void scatter_kernel(const uint64_t *__restrict
                                                       uint32_t *__restrict__ cell_pkg,
                                                       uint32_t *__restrict__ pkg_cell,
                                                       uint8_t *__restrict__ pkg_type,
-                                                      uint32_t *__restrict__ core_list) {
+                                                      uint32_t *__restrict__ core_list,
+                                                      uint4 *__restrict__ rank_map, int W32) {
     const int64_t grp = blockIdx.x;
     const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int64_t w0 = grp * 16 + wv * 4;
@@ -392,6 +393,15 @@ __global__ __launch_bounds__(256) void scatter_kernel(const uint64_t *__restrict
                 if (is_core) core_list[pc + (uint32_t)__popcll(cb & lt)] = id;
             } else {
                 cell_pkg[c] = ((nb >> lane) & 1ull) ? sgrid::kFarNeg : sgrid::kFarPos;
+            }
+        }
+        // the rank map entries of the word's two 32-cell halves
+        if (lane < 2) {
+            const int half = (int)(w - r * W) * 2 + lane;
+            if (half < W32) {
+                const uint32_t am = (uint32_t)(lane ? a >> 32 : a), nm = (uint32_t)(lane ? nb >> 32 : nb);
+                const uint32_t before = lane ? pa + (uint32_t)__popc((uint32_t)a) : pa;
+                rank_map[r * W32 + half] = make_uint4(am, nm, before, 0u);
             }
         }
         pa += (uint32_t)__popcll(a);
@@ -572,8 +582,8 @@ __global__ __launch_bounds__(256) void nbr_kernel(const uint32_t *__restrict__ c
 
 void free_grid(sgrid_grid *g) {
     if (!g) return;
-    void *ptrs[] = {g->cell_pkg, g->pkg_cell, g->pkg_type, g->nbr, g->face, g->core_list, g->workspace, g->work,
-                    g->sface, g->wface, g->wpos};
+    void *ptrs[] = {g->cell_pkg, g->pkg_cell, g->pkg_type, g->nbr,  g->face, g->core_list,
+                    g->workspace, g->rank_map, g->work, g->sface, g->wface,     g->wpos};
     for (void *p : ptrs) sgrid::dev_free(p);
     delete g;
 }
@@ -672,8 +682,11 @@ extern "C" sgrid_status sgrid_build_packages(const sgrid_desc *desc, const float
     SG_ALLOC(g->core_list, (g->n_core > 0 ? g->n_core : 1) * 4, "core_list");
     hipLaunchKernelGGL(far_rows_kernel, dim3(1), dim3(64), 0, st, g->pkg_cell, g->pkg_type);
     SG_HIP_OR_FREE(hipGetLastError());
+    g->W32 = (int32_t)((M + 31) / 32);
+    SG_ALLOC(g->rank_map, M * M * g->W32 * 16, "rank map");
     hipLaunchKernelGGL(scatter_kernel, dim3((unsigned)n_groups), dim3(256), 0, st, act_bits, core_bits, neg_bits,
-                       (int)M, (int)W, n_words, ca, cc, g->cell_pkg, g->pkg_cell, g->pkg_type, g->core_list);
+                       (int)M, (int)W, n_words, ca, cc, g->cell_pkg, g->pkg_cell, g->pkg_type, g->core_list,
+                       g->rank_map, g->W32);
     SG_HIP_OR_FREE(hipGetLastError());
     const int64_t nn = nt * 27;
     hipLaunchKernelGGL(nbr_kernel, dim3((unsigned)((nn + 255) / 256)), dim3(256), 0, st, g->cell_pkg, g->pkg_cell,
@@ -737,6 +750,8 @@ extern "C" sgrid_status sgrid_get_info(const sgrid_grid *g, sgrid_info *out) {
     out->pkg_nbr = g->nbr;
     out->core_list = g->core_list;
     out->sweep_order = g->work;
+    out->rank_map = (const uint32_t *)g->rank_map;
+    out->rank_row = g->W32;
     return SGRID_OK;
 }
 

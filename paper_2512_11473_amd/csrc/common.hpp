@@ -60,6 +60,10 @@ struct sgrid_grid {
                                     // group slot | kLocal when in the same 64-package group), own id, pad
     uint32_t *wpos = nullptr;       // [P+2]: position of each package in the worklist
     void *workspace = nullptr;      // build scratch, kept until destroy
+    // compact form of cell_pkg for position lookups: per 32 cells of a row,
+    // {activated bits, negative-sign bits, activated cells before them, 0}
+    uint4 *rank_map = nullptr;      // [M * M * W32]
+    int32_t W32 = 0;                // entries per row: ceil(M / 32)
     int64_t total() const { return P + 2; }
 };
 

@@ -7,6 +7,10 @@
 // the base corner's shift relative to that package lies in [-1, 3] per axis,
 // so the eight corners have shifts in [-1, 4] and the index shift
 // slot = (s + 4) / 4, data = s + 4 - 4 slot stays inside the 27 neighbours.
+// The packages of the home cell and its neighbours come from the rank map, a
+// compact form of the cell-to-package map (32 cells per 16-byte entry) that
+// the build writes beside it; the values are those of cell_pkg and of the
+// neighbour table.
 #include "common.hpp"
 
 namespace {
@@ -40,13 +44,12 @@ struct Corner {
     }
 };
 
-// Home package and base shift of one particle (per axis: u = x / h,
-// s = u - 1/2, i0 = clamp(floor(s), 0, N - 2), t = clamp(s - i0, 0, 1), home
-// cell = clamp(floor(u / 4), 0, M - 1), shift = i0 - 4 * cell in [-1, 3]).
+// Home cell and base shift of one particle (per axis: u = x / h, s = u - 1/2,
+// i0 = clamp(floor(s), 0, N - 2), t = clamp(s - i0, 0, 1), home cell =
+// clamp(floor(u / 4), 0, M - 1), shift = i0 - 4 * cell in [-1, 3]).
 template <typename T>
-__device__ __forceinline__ int64_t locate(const T *x, int M, T inv_h, int sh[3], T t[3]) {
+__device__ __forceinline__ void locate(const T *x, int M, T inv_h, int cc[3], int sh[3], T t[3]) {
     const int N = 4 * M;
-    int cc[3];
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         const T u = x[a] * inv_h;
@@ -56,18 +59,55 @@ __device__ __forceinline__ int64_t locate(const T *x, int M, T inv_h, int sh[3],
         cc[a] = (int)clampv(floor(u * T(0.25)), T(0), T(M - 1));
         sh[a] = (int)f - 4 * cc[a];
     }
-    return cc[0] + (int64_t)M * (cc[1] + (int64_t)M * cc[2]);
 }
 
-// Trilinear blend of phi and g over the eight corners reached from the home
-// package's neighbour row, then the normal.  The eight row reads are
-// unconditional so that they issue together (a read skipped per lane, e.g.
-// for the self slot, turns into a branch with a wait inside and serialises
-// the gathers).
+// Package ids from the rank map: entry {activated bits, negative bits, rank,
+// 0} of the 32 cells holding x gives id = 2 + rank + (activated cells of the
+// entry below x) for an activated cell, else the far-field package of its
+// sign; cells outside the domain belong to the positive far field (the
+// neighbour table's rule).  These are the values of cell_pkg, read from a
+// table 64 times smaller that stays in the caches.
+struct RankMap {
+    const uint4 *map;
+    int M, W32;
+    __device__ __forceinline__ int64_t entry(int x, int y, int z) const {
+        return ((int64_t)y + (int64_t)M * z) * W32 + (x >> 5);
+    }
+    __device__ __forceinline__ static uint32_t id(const uint4 &e, int x) {
+        const uint32_t bit = 1u << (x & 31);
+        if (e.x & bit) return 2u + e.z + (uint32_t)__popc(e.x & (bit - 1u));
+        return (e.y & bit) ? sgrid::kFarNeg : sgrid::kFarPos;
+    }
+};
+
+// Trilinear blend of phi and g over the eight corners, then the normal.  The
+// corners' packages are the home cell's package and, for corners past a face
+// of the home cell, those of the neighbouring cells (the index shift of
+// Sec. 5.2 per axis: slot = (s + 4) / 4, data = s + 4 - 4 slot).  A particle
+// whose home cell is far field reads the far-field constant at every corner,
+// as the far-field packages neighbour themselves.  All rank-map reads issue
+// before any is used, then all corner reads.
 template <typename T, bool PACKED>
-__device__ __forceinline__ void blend(const Corner<T, PACKED> &field, const uint32_t *__restrict__ row, const int sh[3],
-                                      const T t[3], T &v, T n[3]) {
-    // the eight package ids first, so the row reads issue back to back
+__device__ __forceinline__ void blend(const Corner<T, PACKED> &field, const RankMap &rm, const int cc[3],
+                                      const int sh[3], const T t[3], T &v, T n[3]) {
+    const int M = rm.M;
+    uint4 e[8];
+    int cx[8];
+    bool out[8];
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+        const int bx = b & 1, by = (b >> 1) & 1, bz = (b >> 2) & 1;
+        const int x = cc[0] + ((sh[0] + bx + 4) >> 2) - 1;
+        const int y = cc[1] + ((sh[1] + by + 4) >> 2) - 1;
+        const int z = cc[2] + ((sh[2] + bz + 4) >> 2) - 1;
+        out[b] = x < 0 || y < 0 || z < 0 || x >= M || y >= M || z >= M;
+        cx[b] = x;
+        e[b] = rm.map[out[b] ? 0 : rm.entry(x, y, z)];
+    }
+    // the home cell's own entry (one of the eight above, read again rather than
+    // picked by a per-lane index into the register array)
+    const uint4 eh = rm.map[rm.entry(cc[0], cc[1], cc[2])];
+    const uint32_t home = RankMap::id(eh, cc[0]);
     uint32_t pk[8];
     int d[8];
 #pragma unroll
@@ -77,7 +117,8 @@ __device__ __forceinline__ void blend(const Corner<T, PACKED> &field, const uint
         const int k0 = s0 >> 2, k1 = s1 >> 2, k2 = s2 >> 2;                        // neighbour slot per axis
         const int di = s0 - 4 * k0, dj = s1 - 4 * k1, dk = s2 - 4 * k2;            // data index
         d[b] = PACKED ? blocked_index(di, dj, dk) : di + 4 * dj + 16 * dk;
-        pk[b] = row[k0 + 3 * k1 + 9 * k2];
+        const uint32_t own = out[b] ? sgrid::kFarPos : RankMap::id(e[b], cx[b]);
+        pk[b] = home < 2u ? home : own;
     }
     v = T(0);
     T gx = T(0), gy = T(0), gz = T(0);
@@ -86,12 +127,12 @@ __device__ __forceinline__ void blend(const Corner<T, PACKED> &field, const uint
         const int bx = b & 1, by = (b >> 1) & 1, bz = (b >> 2) & 1;
         const int64_t idx = (int64_t)pk[b] * 64 + d[b];
         const T w = (bx ? t[0] : T(1) - t[0]) * (by ? t[1] : T(1) - t[1]) * (bz ? t[2] : T(1) - t[2]);
-        T cv, cx, cy, cz;
-        field.get(idx, cv, cx, cy, cz);
+        T cv, cx_, cy_, cz_;
+        field.get(idx, cv, cx_, cy_, cz_);
         v += w * cv;
-        gx += w * cx;
-        gy += w * cy;
-        gz += w * cz;
+        gx += w * cx_;
+        gy += w * cy_;
+        gz += w * cz_;
     }
     const T gn = sqrt(gx * gx + gy * gy + gz * gz);
     const T inv = gn > T(0) ? T(1) / gn : T(0);
@@ -101,16 +142,15 @@ __device__ __forceinline__ void blend(const Corner<T, PACKED> &field, const uint
 }
 
 template <typename T, bool PACKED>
-__global__ __launch_bounds__(256) void probe_kernel(Corner<T, PACKED> field, const uint32_t *__restrict__ cell_pkg,
-                                                    const uint32_t *__restrict__ nbr, const T *__restrict__ pos,
+__global__ __launch_bounds__(256) void probe_kernel(Corner<T, PACKED> field, RankMap rm, const T *__restrict__ pos,
                                                     int64_t n, T *__restrict__ phi_out, T *__restrict__ nrm_out,
-                                                    int M, T inv_h) {
+                                                    T inv_h) {
     const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (q >= n) return;
-    int sh[3];
+    int cc[3], sh[3];
     T t[3], v, nr[3];
-    const uint32_t home = cell_pkg[locate(pos + 3 * q, M, inv_h, sh, t)];
-    blend(field, nbr + (int64_t)home * 27, sh, t, v, nr);
+    locate(pos + 3 * q, rm.M, inv_h, cc, sh, t);
+    blend(field, rm, cc, sh, t, v, nr);
     phi_out[q] = v;
     nrm_out[3 * q] = nr[0];
     nrm_out[3 * q + 1] = nr[1];
@@ -136,16 +176,15 @@ static sgrid_status probe_entry(const sgrid_grid *g, sgrid_dtype dtype, const vo
     const int64_t nb = (n + 255) / 256;
     SG_REQUIRE(nb <= kMaxGrid, "too many particles for one launch");
     const int64_t stride = g->total() * 64;
+    const RankMap rm{g->rank_map, g->M, g->W32};
     if (dtype == SGRID_F32) {
         Corner<float, PACKED> f{(const float *)phi, (const float *)grad, stride};
-        hipLaunchKernelGGL((probe_kernel<float, PACKED>), dim3((unsigned)nb), dim3(256), 0, st, f, g->cell_pkg,
-                           g->nbr, (const float *)pos, n, (float *)phi_out, (float *)normal_out, g->M,
-                           (float)(1.0 / g->h));
+        hipLaunchKernelGGL((probe_kernel<float, PACKED>), dim3((unsigned)nb), dim3(256), 0, st, f, rm,
+                           (const float *)pos, n, (float *)phi_out, (float *)normal_out, (float)(1.0 / g->h));
     } else {
         Corner<double, PACKED> f{(const double *)phi, (const double *)grad, stride};
-        hipLaunchKernelGGL((probe_kernel<double, PACKED>), dim3((unsigned)nb), dim3(256), 0, st, f, g->cell_pkg,
-                           g->nbr, (const double *)pos, n, (double *)phi_out, (double *)normal_out, g->M,
-                           1.0 / g->h);
+        hipLaunchKernelGGL((probe_kernel<double, PACKED>), dim3((unsigned)nb), dim3(256), 0, st, f, rm,
+                           (const double *)pos, n, (double *)phi_out, (double *)normal_out, 1.0 / g->h);
     }
     SG_CHECK_LAUNCH("probe");
     return SGRID_OK;
