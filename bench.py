@@ -47,7 +47,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="prism512", choices=["prism512", "torus2048", "batch64"])
+    ap.add_argument("--workload", default="prism512", choices=["prism512", "torus2048", "batch64", "shell1024"])
     ap.add_argument("--n-iter", type=int, default=None)
     ap.add_argument("--sweep", default="auto",
                     help="sweep configuration 'variant,groups', or 'auto' to autotune it on the grid (default)")
@@ -378,6 +378,94 @@ def bench_batch(args, log):
     }
 
 
+# Tab. 1 of the paper: CPU timings of its timing test (unit not stated), context only
+PAPER_TAB1 = {"sequential_1_thread": 22.948, "sequential_4_threads": 7.429,
+              "stencil_1_thread": 59.972, "stencil_4_threads": 21.378,
+              "note": "SPHinXsys on an unnamed CPU; the paper gives no unit and no repetition count"}
+SHELL_CROPS = [(175, 96, 96), (96, 175, 96), (96, 96, 175), (17, 96, 96)]
+
+
+def bench_shell(args, log):
+    """The paper's timing test (Sec. 9, Tab. 1) on the shell at 1/1024: the
+    sequential update and the seven-point Laplacian over all activated data."""
+    import torch
+    import paper_2512_11473_amd as sg
+    import synth
+    from paper_2512_11473_amd import workload
+
+    cfg = synth.config_shell()
+    t0 = time.perf_counter()
+    wl = workload.setup(cfg["shape"], cfg["N"], cfg["noise_amp"], cfg["noise_seed"])
+    setup_s = time.perf_counter() - t0
+    g = wl.grid
+    P = g.n_packages
+    out = torch.empty_like(wl.phi)
+    stream = torch.cuda.current_stream()
+    # the sweep autotuner also fixes the package order of the stencil pass
+    tv, tg, _ = sg.autotune_sweep(g, wl.phi, wl.scratch, reps=10)
+    for _ in range(args.warmup):
+        sg.sequential_update(g, wl.phi, cfg["delta"])
+        sg.compute_laplacian(g, wl.phi, out)
+    torch.cuda.synchronize()
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.steps)]
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        ev[k][0].record(stream)
+        sg.sequential_update(g, wl.phi, cfg["delta"])
+        ev[k][1].record(stream)
+        sg.compute_laplacian(g, wl.phi, out)
+        ev[k][2].record(stream)
+    torch.cuda.synchronize()
+    total_s = time.perf_counter() - t0
+    K = args.steps
+    seq_ms = sum(e[0].elapsed_time(e[1]) for e in ev) / K
+    lap_ms = sum(e[1].elapsed_time(e[2]) for e in ev) / K
+    pts = 64 * P
+    lap_bytes = REINIT_BYTES_PER_UPDATE * pts
+    seq_bytes = 8.0 * pts
+    rec = {
+        "metric": "active points/s of the seven-point Laplacian (paper's timing test)",
+        "value": pts / (lap_ms * 1e-3), "unit": "points/s",
+        "n_gpus": 1, "steps": K, "warmup": args.warmup, "ms_per_step": 1e3 * total_s / K,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "shell1024: spherical shell of radii 0.3 and 0.31 about (0.5, 0.5, 0.5) at 1/1024, "
+                               "phi = its signed distance; one step = sequential update (phi += 1e-6) and "
+                               "seven-point Laplacian over all activated data",
+                   "N": cfg["N"], "n_packages": P, "points": pts},
+        "sequential_ms": seq_ms, "laplacian_ms": lap_ms,
+        "sweep_config": {"variant": tv, "groups": tg, "source": "autotuned"},
+        "sequential_points_per_s": pts / (seq_ms * 1e-3),
+        "roofline": {"bound": "hbm", "kernel": "laplacian", "achieved": lap_bytes / (lap_ms * 1e-3) / 1e9,
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": lap_bytes / (lap_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, "traffic": None,
+                     "algorithmic_bytes_per_launch": lap_bytes},
+        "sequential_roofline": {"achieved": seq_bytes / (seq_ms * 1e-3) / 1e9, "unit": "GB/s",
+                                "frac": seq_bytes / (seq_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                                "algorithmic_bytes_per_launch": seq_bytes},
+        "paper_tab1_cpu": PAPER_TAB1,
+        "setup_s": setup_s,
+    }
+    if not args.no_cpu_baseline:
+        import oracle
+        runs = [oracle.setup_crop(cfg["shape"], cfg["N"], o, 64, cfg["noise_amp"], cfg["noise_seed"])
+                for o in SHELL_CROPS]
+        dense = [oracle.dense_state(r.tab, r.active, r.phi0, r.B) for r in runs]
+        oracle.laplacian(runs[0].N, runs[0].h, runs[0].B, runs[0].active, dense[0])
+        done, secs, passes = 0, 0.0, 0
+        while secs < args.cpu_seconds:
+            r, d = runs[passes % len(runs)], dense[passes % len(runs)]
+            t1 = time.perf_counter()
+            oracle.laplacian(r.N, r.h, r.B, r.active, d)
+            secs += time.perf_counter() - t1
+            done += len(r.active)
+            passes += 1
+        threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+        rec["cpu_baseline"] = {"value": done / secs, "unit": "points/s", "cores": threads, "kind": "oracle",
+                               "sample": f"{passes} FP64 Laplacian passes of the oracle over 64^3-coarse-cell crops "
+                                         f"of the shell band in turn ({secs:.1f} s)"}
+    return rec
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -398,7 +486,12 @@ def main():
         b.copy_(a)
         torch.cuda.synchronize()
         del a, b
-    rec = bench_batch(args, log) if args.workload == "batch64" else bench_single(args, log)
+    if args.workload == "batch64":
+        rec = bench_batch(args, log)
+    elif args.workload == "shell1024":
+        rec = bench_shell(args, log)
+    else:
+        rec = bench_single(args, log)
     print(json.dumps(rec), flush=True)
 
 

@@ -284,6 +284,22 @@ sgrid_status sgrid_batch_reinitialize(sgrid_batch *batch, float *phi_dev, float 
                                       int32_t use_graph, void *stream);
 
 /*
+ * The two operations of the paper's timing test (Sec. 9, Tab. 1), over every
+ * data point of every activated package:
+ *   sgrid_sequential_update: phi += delta (the "small change to every active
+ *     value"); far-field rows 0 and 1 untouched.
+ *   sgrid_compute_laplacian: out = (sum of the six face neighbours - 6 phi) /
+ *     h^2, the seven-point Laplacian, neighbours through the neighbour table
+ *     (Sec. 5.2); out-of-band neighbours are their far-field constants; rows 0
+ *     and 1 of out get 0.  phi and out are distinct [P^][64] arrays.
+ * Asynchronous on `stream`; SGRID_E_INVALID for NULL or misaligned pointers.
+ */
+sgrid_status sgrid_sequential_update(const sgrid_grid *grid, sgrid_dtype dtype, void *phi_dev, double delta,
+                                     void *stream);
+sgrid_status sgrid_compute_laplacian(const sgrid_grid *grid, sgrid_dtype dtype, const void *phi_dev,
+                                     void *out_dev, void *stream);
+
+/*
  * Tuning knob for sgrid_reinitialize: sweep variant 0 exchanges the interior
  * neighbours between lanes (DPP row shifts), variant 1 stages each package
  * and its face halo in an LDS tile, variant 2 is variant 0 as a persistent
@@ -296,8 +312,9 @@ sgrid_status sgrid_batch_reinitialize(sgrid_batch *batch, float *phi_dev, float 
  * DPP (no workgroup barrier).  `groups` (1, 2, 3, 4 or 8) is, for variants 0,
  * 1, 3 and 5, the number of four-package sets one wavefront processes, for
  * variant 2 the number of workgroups per compute unit, and is ignored by
- * variant 4.  Process-wide; default (0, 1).  Results are identical for every
- * setting.
+ * variant 4.  With variant 3 or 4 the gradient and Laplacian passes also
+ * visit the packages in Morton order.  Process-wide; default (0, 1).  Results
+ * are identical for every setting.
  */
 sgrid_status sgrid_set_sweep_config(int32_t variant, int32_t groups);
 

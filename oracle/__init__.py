@@ -51,6 +51,7 @@ def lib():
             "orc_index_shift": (None, [i32, P, P]),
             "orc_reinit": (None, [i32, f64, f64, P, i64, P, P, i32]),
             "orc_gradient": (None, [i32, f64, f64, P, i64, P, P, P, P]),
+            "orc_laplacian": (None, [i32, f64, f64, P, i64, P, P]),
             "orc_probe": (None, [i32, f64, f64, P, P, P, P, P, P, i64, P, P, P]),
             "orc_plane_cube_fraction": (f64, [f64, f64, f64, f64]),
             "orc_wendland": (f64, [f64]),
@@ -173,6 +174,24 @@ def gradient(N: int, h: float, B: float, active: np.ndarray, phi: np.ndarray):
     act = np.ascontiguousarray(active, dtype=np.int64)
     lib().orc_gradient(N, h, B, _p(act), act.shape[0], _p(phi), _p(g[0]), _p(g[1]), _p(g[2]))
     return g
+
+
+def laplacian(N: int, h: float, B: float, active: np.ndarray, phi: np.ndarray) -> np.ndarray:
+    """Seven-point Laplacian at the active points of a dense field (0 elsewhere):
+    the stencil operation of the paper's timing test (Sec. 9, Tab. 1)."""
+    phi = np.ascontiguousarray(phi, dtype=np.float64)
+    out = np.zeros(N ** 3, dtype=np.float64)
+    act = np.ascontiguousarray(active, dtype=np.int64)
+    lib().orc_laplacian(N, h, B, _p(act), act.shape[0], _p(phi), _p(out))
+    return out
+
+
+def sequential_update(phi: np.ndarray, active: np.ndarray, delta: float) -> np.ndarray:
+    """The sequential operation of the paper's timing test (Sec. 9, Tab. 1): a
+    small change to every active value, here phi + delta."""
+    out = np.array(phi, dtype=np.float64, copy=True)
+    out[active] += delta
+    return out
 
 
 def probe(N: int, h: float, B: float, cell_pkg: np.ndarray, phi: np.ndarray, g: np.ndarray,

@@ -195,6 +195,26 @@ void orc_gradient(int32_t N, double h, double B, const int64_t *active, int64_t 
 }
 
 /* ------------------------------------------------------------------------ */
+/* The stencil operation of the paper's timing test (Sec. 9, Tab. 1): the     */
+/* seven-point Laplacian (sum of the six face neighbours - 6 phi) / h^2 at    */
+/* the listed active points; out-of-band neighbours read their far-field      */
+/* constant.  The caller zero-fills every other point.                        */
+/* ------------------------------------------------------------------------ */
+void orc_laplacian(int32_t N, double h, double B, const int64_t *active, int64_t n_active,
+                   const double *phi, double *out)
+{
+#pragma omp parallel for schedule(static)
+    for (int64_t q = 0; q < n_active; ++q) {
+        int64_t l = active[q];
+        int64_t i = l % N, j = (l / N) % N, k = l / ((int64_t)N * N);
+        double s = rd(phi, N, i - 1, j, k, B) + rd(phi, N, i + 1, j, k, B)
+                 + rd(phi, N, i, j - 1, k, B) + rd(phi, N, i, j + 1, k, B)
+                 + rd(phi, N, i, j, k - 1, B) + rd(phi, N, i, j, k + 1, B);
+        out[l] = (s - 6.0 * phi[l]) / (h * h);
+    }
+}
+
+/* ------------------------------------------------------------------------ */
 /* Grid-to-particle probe (Sec. 8): trilinear interpolation of phi and g over */
 /* the 8 data points around the particle, then n = g / |g| (0 when g = 0).    */
 /* Per axis: u = x / h, s = u - 1/2, i0 = clamp(floor(s), 0, N-2),            */

@@ -19,6 +19,7 @@ import torch
 __all__ = [
     "SgridError", "Grid", "load", "build_packages", "fill_far_field", "reinitialize",
     "compute_gradient", "compute_gradient_packed", "probe_particles", "probe_particles_packed", "compute_near_surface_integrals", "set_sweep_config",
+    "sequential_update", "compute_laplacian",
     "autotune_sweep", "SWEEP_TUNE_CANDIDATES",
     "Mlp", "gather_windows", "MLP_N_PARAMS", "Batch",
     "LIB_PATH", "FAR_FIELD_IN_H",
@@ -61,6 +62,8 @@ _SIGNATURES = {
     "sgrid_probe_particles": (ctypes.c_int, [_P, ctypes.c_int, _P, _P, _P, ctypes.c_int64, _P, _P, _P]),
     "sgrid_compute_near_surface_integrals": (ctypes.c_int, [_P, _P, _P, _P, _P, _P]),
     "sgrid_set_sweep_config": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32]),
+    "sgrid_sequential_update": (ctypes.c_int, [_P, ctypes.c_int, _P, ctypes.c_double, _P]),
+    "sgrid_compute_laplacian": (ctypes.c_int, [_P, ctypes.c_int, _P, _P, _P]),
     "sgrid_autotune_sweep": (ctypes.c_int, [_P, ctypes.c_int, _P, _P, ctypes.c_int32, _P,
                                             ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32), _P]),
     "sgrid_mlp_create": (ctypes.c_int, [_P, ctypes.POINTER(_P)]),
@@ -224,6 +227,22 @@ def reinitialize(grid: Grid, phi: torch.Tensor, scratch: torch.Tensor, n_iter: i
         raise ValueError("phi and scratch must both be [P+2, 64] of one dtype")
     _check(load().sgrid_reinitialize(grid.handle, _dtype_code(phi), _dev(phi, "phi"), _dev(scratch, "scratch"),
                                      int(n_iter), _stream(stream)))
+
+
+def sequential_update(grid: Grid, phi: torch.Tensor, delta: float, stream=None):
+    """phi += delta at every point of every activated package."""
+    if phi.numel() != grid.n_total * 64:
+        raise ValueError("phi must be [P+2, 64]")
+    _check(load().sgrid_sequential_update(grid.handle, _dtype_code(phi), _dev(phi, "phi"), float(delta),
+                                          _stream(stream)))
+
+
+def compute_laplacian(grid: Grid, phi: torch.Tensor, out: torch.Tensor, stream=None):
+    """Seven-point Laplacian of phi at every point of every activated package."""
+    if out.dtype != phi.dtype or out.numel() != phi.numel() or phi.numel() != grid.n_total * 64:
+        raise ValueError("phi and out must both be [P+2, 64] of one dtype")
+    _check(load().sgrid_compute_laplacian(grid.handle, _dtype_code(phi), _dev(phi, "phi"), _dev(out, "out"),
+                                          _stream(stream)))
 
 
 def compute_gradient(grid: Grid, phi: torch.Tensor, grad: torch.Tensor, stream=None):

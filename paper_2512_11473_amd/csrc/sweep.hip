@@ -368,20 +368,43 @@ __global__ __launch_bounds__(256) void reinit_lds_kernel(const T *__restrict__ s
     }
 }
 
+// Package of entry e of a stencil pass over all rows [0, P + 2): in id order
+// (WORK = false) entry e is package e; in worklist order entries 0 and 1 are
+// the far-field rows and entry e >= 2 is worklist position e - 2, whose face
+// row (wface: six neighbours, own id) comes in the same 32-byte load.
+template <bool WORK>
+__device__ __forceinline__ int64_t stencil_package(int64_t e, const uint32_t *__restrict__ face,
+                                                   const uint32_t *__restrict__ wface, uint4 &f0, uint2 &f1) {
+    if (e < 2) return e;
+    if (WORK) {
+        const uint4 a = *reinterpret_cast<const uint4 *>(wface + (e - 2) * 8);
+        const uint4 b = *reinterpret_cast<const uint4 *>(wface + (e - 2) * 8 + 4);
+        f0 = a;
+        f1 = make_uint2(b.x, b.y);
+        return (int64_t)b.z;
+    }
+    load_face(face, e, f0, f1);
+    return e;
+}
+
 // Central-difference gradient over packages [0, P + 2); far-field rows get 0.
 // PACKED = false writes the three components as separate [P^][64] arrays;
 // PACKED = true writes one [P^][64] array of (phi, gx, gy, gz) quadruples in
 // the blocked point order (blocked_index), the layout the packed probe gathers
 // with one 16-byte (FP32) load per corner.
-template <typename T, bool PACKED>
+template <typename T, bool PACKED, bool WORK>
 __global__ __launch_bounds__(256) void gradient_kernel(const T *__restrict__ phi, T *__restrict__ out,
-                                                       const uint32_t *__restrict__ face, int64_t n_total,
+                                                       const uint32_t *__restrict__ face,
+                                                       const uint32_t *__restrict__ wface, int64_t n_total,
                                                        int64_t n_blocks, T inv_2h) {
     const int64_t b = xcd_block(blockIdx.x, n_blocks);
     const int lane = threadIdx.x & 63;
     const int r = lane & 15;
-    const int64_t p = (b * 4 + (threadIdx.x >> 6)) * 4 + (lane >> 4);
-    if (p >= n_total) return;
+    const int64_t e = (b * 4 + (threadIdx.x >> 6)) * 4 + (lane >> 4);
+    if (e >= n_total) return;
+    uint4 f0;
+    uint2 f1;
+    const int64_t p = stencil_package<WORK>(e, face, wface, f0, f1);
     Row<T> c, ox, oy, oz;
     if (p < 2) {
         c = load_row(phi + p * 64 + r * 4);
@@ -389,7 +412,7 @@ __global__ __launch_bounds__(256) void gradient_kernel(const T *__restrict__ phi
         for (int i = 0; i < 4; ++i) ox.v[i] = oy.v[i] = oz.v[i] = T(0);
     } else {
         Loads<T> l;
-        issue_loads(phi, face, p, r, l);
+        issue_data(phi, p, r, f0, f1, l);
         const Stencil<T> s = assemble(r, l);
         c = s.c;
 #pragma unroll
@@ -415,6 +438,56 @@ __global__ __launch_bounds__(256) void gradient_kernel(const T *__restrict__ phi
     }
 }
 
+// The operations of the paper's timing test (Sec. 9, Tab. 1).  Sequential
+// access: a small change to every value of every activated package, phi +=
+// delta, streamed as 16-byte rows (rows 0 and 1, the far field, untouched).
+template <typename T>
+__global__ __launch_bounds__(256) void add_kernel(T *__restrict__ phi, int64_t n_rows, T delta) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= n_rows) return;
+    T *p = phi + 128 + i * 4;
+    Row<T> r = load_row(p);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) r.v[k] += delta;
+    store_row(p, r);
+}
+
+// Stencil: the seven-point Laplacian (sum of the six face neighbours - 6 phi)
+// / h^2 at every point of every activated package, neighbours through the
+// neighbour table as in the sweeps (the same lane mapping and halo loads);
+// the far-field rows get 0.
+template <typename T, bool WORK>
+__global__ __launch_bounds__(256) void laplacian_kernel(const T *__restrict__ phi, T *__restrict__ out,
+                                                        const uint32_t *__restrict__ face,
+                                                        const uint32_t *__restrict__ wface, int64_t n_total,
+                                                        int64_t n_blocks, T inv_h2) {
+    const int64_t b = xcd_block(blockIdx.x, n_blocks);
+    const int lane = threadIdx.x & 63;
+    const int r = lane & 15;
+    const int64_t e = (b * 4 + (threadIdx.x >> 6)) * 4 + (lane >> 4);
+    if (e >= n_total) return;
+    uint4 f0;
+    uint2 f1;
+    const int64_t p = stencil_package<WORK>(e, face, wface, f0, f1);
+    Row<T> o;
+    if (p < 2) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) o.v[i] = T(0);
+    } else {
+        Loads<T> l;
+        issue_data(phi, p, r, f0, f1, l);
+        const Stencil<T> s = assemble(r, l);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const T xm = i > 0 ? s.c.v[i - 1] : s.xm;
+            const T xp = i < 3 ? s.c.v[i + 1] : s.xp;
+            const T sum = (xm + xp) + (s.ym.v[i] + s.yp.v[i]) + (s.zm.v[i] + s.zp.v[i]);
+            o.v[i] = fma(T(-6), s.c.v[i], sum) * inv_h2;
+        }
+    }
+    store_row(out + p * 64 + r * 4, o);
+}
+
 template <typename T>
 __global__ void far_field_kernel(T *__restrict__ phi, T B) {
     const int t = threadIdx.x;   // 128 lanes: rows 0 and 1
@@ -438,6 +511,10 @@ void set_sweep_config(int variant, int groups) {
     g_sweep_cfg.variant = variant;
     g_sweep_cfg.groups = groups;
 }
+
+// The gradient and the Laplacian visit the packages in the sweep's order:
+// Morton (worklist) order when the configuration's sweep uses it.
+bool stencil_in_worklist_order() { return g_sweep_cfg.variant == 3 || g_sweep_cfg.variant == 4; }
 
 template <typename T>
 static void launch_dpp_range(const sgrid_grid *g, const T *src, T *dst, int64_t first, int64_t end, int groups,
@@ -636,12 +713,22 @@ static sgrid_status gradient_entry(const sgrid_grid *g, sgrid_dtype dtype, const
     hipStream_t st = sg_stream(stream);
     const int64_t nt = g->total();
     const int64_t nb = (nt + 15) / 16;
-    if (dtype == SGRID_F32)
-        hipLaunchKernelGGL((gradient_kernel<float, PACKED>), dim3((unsigned)nb), dim3(256), 0, st,
-                           (const float *)phi, (float *)out, g->face, nt, nb, (float)(0.5 / g->h));
-    else
-        hipLaunchKernelGGL((gradient_kernel<double, PACKED>), dim3((unsigned)nb), dim3(256), 0, st,
-                           (const double *)phi, (double *)out, g->face, nt, nb, 0.5 / g->h);
+    const bool work = sgrid::stencil_in_worklist_order();
+    if (dtype == SGRID_F32) {
+        if (work)
+            hipLaunchKernelGGL((gradient_kernel<float, PACKED, true>), dim3((unsigned)nb), dim3(256), 0, st,
+                               (const float *)phi, (float *)out, g->face, g->wface, nt, nb, (float)(0.5 / g->h));
+        else
+            hipLaunchKernelGGL((gradient_kernel<float, PACKED, false>), dim3((unsigned)nb), dim3(256), 0, st,
+                               (const float *)phi, (float *)out, g->face, g->wface, nt, nb, (float)(0.5 / g->h));
+    } else {
+        if (work)
+            hipLaunchKernelGGL((gradient_kernel<double, PACKED, true>), dim3((unsigned)nb), dim3(256), 0, st,
+                               (const double *)phi, (double *)out, g->face, g->wface, nt, nb, 0.5 / g->h);
+        else
+            hipLaunchKernelGGL((gradient_kernel<double, PACKED, false>), dim3((unsigned)nb), dim3(256), 0, st,
+                               (const double *)phi, (double *)out, g->face, g->wface, nt, nb, 0.5 / g->h);
+    }
     SG_CHECK_LAUNCH("gradient sweep");
     return SGRID_OK;
 }
@@ -654,4 +741,55 @@ extern "C" sgrid_status sgrid_compute_gradient(const sgrid_grid *g, sgrid_dtype 
 extern "C" sgrid_status sgrid_compute_gradient_packed(const sgrid_grid *g, sgrid_dtype dtype, const void *phi,
                                                       void *packed, void *stream) {
     return gradient_entry<true>(g, dtype, phi, packed, stream);
+}
+
+extern "C" sgrid_status sgrid_sequential_update(const sgrid_grid *g, sgrid_dtype dtype, void *phi, double delta,
+                                                void *stream) {
+    sgrid::clear_error();
+    SG_REQUIRE(g != nullptr && phi != nullptr, "NULL argument");
+    SG_REQUIRE(sg_aligned(phi, 16), "phi must be 16-byte aligned");
+    SG_REQUIRE(dtype == SGRID_F32 || dtype == SGRID_F64, "unknown dtype %d", (int)dtype);
+    if (g->P == 0) return SGRID_OK;
+    hipStream_t st = sg_stream(stream);
+    const int64_t n_rows = g->P * 16;
+    const int64_t nb = (n_rows + 255) / 256;
+    if (dtype == SGRID_F32)
+        hipLaunchKernelGGL(add_kernel<float>, dim3((unsigned)nb), dim3(256), 0, st, (float *)phi, n_rows,
+                           (float)delta);
+    else
+        hipLaunchKernelGGL(add_kernel<double>, dim3((unsigned)nb), dim3(256), 0, st, (double *)phi, n_rows, delta);
+    SG_CHECK_LAUNCH("sequential update");
+    return SGRID_OK;
+}
+
+extern "C" sgrid_status sgrid_compute_laplacian(const sgrid_grid *g, sgrid_dtype dtype, const void *phi, void *out,
+                                                void *stream) {
+    sgrid::clear_error();
+    SG_REQUIRE(g != nullptr && phi != nullptr && out != nullptr, "NULL argument");
+    SG_REQUIRE(phi != out, "phi and out must be distinct buffers");
+    SG_REQUIRE(sg_aligned(phi, 16) && sg_aligned(out, 16), "phi / out must be 16-byte aligned");
+    SG_REQUIRE(dtype == SGRID_F32 || dtype == SGRID_F64, "unknown dtype %d", (int)dtype);
+    hipStream_t st = sg_stream(stream);
+    const int64_t nt = g->total();
+    const int64_t nb = (nt + 15) / 16;
+    const bool work = sgrid::stencil_in_worklist_order();
+    if (dtype == SGRID_F32) {
+        if (work)
+            hipLaunchKernelGGL((laplacian_kernel<float, true>), dim3((unsigned)nb), dim3(256), 0, st,
+                               (const float *)phi, (float *)out, g->face, g->wface, nt, nb,
+                               (float)(1.0 / (g->h * g->h)));
+        else
+            hipLaunchKernelGGL((laplacian_kernel<float, false>), dim3((unsigned)nb), dim3(256), 0, st,
+                               (const float *)phi, (float *)out, g->face, g->wface, nt, nb,
+                               (float)(1.0 / (g->h * g->h)));
+    } else {
+        if (work)
+            hipLaunchKernelGGL((laplacian_kernel<double, true>), dim3((unsigned)nb), dim3(256), 0, st,
+                               (const double *)phi, (double *)out, g->face, g->wface, nt, nb, 1.0 / (g->h * g->h));
+        else
+            hipLaunchKernelGGL((laplacian_kernel<double, false>), dim3((unsigned)nb), dim3(256), 0, st,
+                               (const double *)phi, (double *)out, g->face, g->wface, nt, nb, 1.0 / (g->h * g->h));
+    }
+    SG_CHECK_LAUNCH("laplacian");
+    return SGRID_OK;
 }

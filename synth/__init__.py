@@ -33,7 +33,7 @@ __all__ = [
     "splitmix64", "unit_noise", "sdf", "coarse_sdf", "fine_points",
     "phi0_at", "sphere", "box", "prism", "torus", "displaced_torus", "union",
     "random_union", "batch_shapes", "shell_particles", "surface_particles",
-    "config_c1", "config_c2", "config_c3", "config_c5",
+    "config_c1", "config_c2", "config_c3", "config_c5", "config_shell", "shell",
 ]
 
 def _threads() -> int:
@@ -93,6 +93,11 @@ def unit_noise(seed: int, lin: np.ndarray) -> np.ndarray:
 
 def sphere(center=(0.5, 0.5, 0.5), radius=0.3) -> Dict:
     return {"kind": "sphere", "center": list(map(float, center)), "radius": float(radius)}
+
+
+def shell(center=(0.5, 0.5, 0.5), r_in=0.3, r_out=0.31) -> Dict:
+    """Spherical shell r_in <= |x - center| <= r_out (negative inside the shell)."""
+    return {"kind": "shell", "center": list(map(float, center)), "r_in": float(r_in), "r_out": float(r_out)}
 
 
 def box(center=(0.5, 0.5, 0.5), half=(0.2, 0.2, 0.2)) -> Dict:
@@ -178,6 +183,9 @@ def sdf(s: Dict, x: np.ndarray) -> np.ndarray:
     k = s["kind"]
     if k == "sphere":
         return np.linalg.norm(x - np.asarray(s["center"]), axis=1) - s["radius"]
+    if k == "shell":
+        r = np.linalg.norm(x - np.asarray(s["center"]), axis=1)
+        return np.maximum(r - s["r_out"], s["r_in"] - r)
     if k == "box":
         q = np.abs(x - np.asarray(s["center"])) - np.asarray(s["half"])
         outside = np.linalg.norm(np.maximum(q, 0.0), axis=1)
@@ -405,6 +413,13 @@ def config_c5() -> Dict:
     return {"name": "torus2048", "shape": displaced_torus(7), "N": 2048, "noise_amp": 0.0,
             "noise_seed": 0, "n_iter": 100, "n_particles": 50_000_000, "particle_seed": 8,
             "particles": "surface"}
+
+
+def config_shell() -> Dict:
+    """The paper's timing geometry (Sec. 9, Tab. 1): shell of radii 0.3 and 0.31
+    about (0.5, 0.5, 0.5) at resolution 1/1024; phi0 is its signed distance."""
+    return {"name": "shell1024", "shape": shell(), "N": 1024, "noise_amp": 0.0, "noise_seed": 0,
+            "delta": 1.0e-6}
 
 
 def particles_for(cfg: Dict, n: int | None = None) -> np.ndarray:

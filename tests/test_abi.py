@@ -63,6 +63,11 @@ def test_invalid_arguments_rejected_without_device(lib):
     lib.sgrid_set_sweep_config.argtypes = [ctypes.c_int32, ctypes.c_int32]
     assert lib.sgrid_set_sweep_config(6, 1) == E_INVALID
     assert lib.sgrid_set_sweep_config(0, 9) == E_INVALID
+    lib.sgrid_sequential_update.argtypes = [P, ctypes.c_int, P, ctypes.c_double, P]
+    assert lib.sgrid_sequential_update(None, 0, P(16), 1e-3, None) == E_INVALID
+    lib.sgrid_compute_laplacian.argtypes = [P, ctypes.c_int, P, P, P]
+    assert lib.sgrid_compute_laplacian(None, 0, P(16), P(32), None) == E_INVALID
+    assert lib.sgrid_compute_laplacian(P(64), 0, P(16), P(16), None) == E_INVALID
     lib.sgrid_autotune_sweep.argtypes = [P, ctypes.c_int, P, P, ctypes.c_int32, P, P, P, P]
     assert lib.sgrid_autotune_sweep(None, 0, P(16), P(32), 1, None, None, None, None) == E_INVALID
     assert lib.sgrid_autotune_sweep(P(64), 0, P(16), P(32), 0, None, None, None, None) == E_INVALID

@@ -187,3 +187,39 @@ def test_torus2048_full_size(sg):
     ref = oracle.integrals(n, h, crop.B, crop.phi, core_pts)
     assert np.max(np.abs(got[:, 0] - ref[:, 0])) <= 1e-5
     assert np.max(np.abs(got[:, 1:] - ref[:, 1:])) <= 1e-5 * G0
+
+
+# 64^3 coarse cells across the shell's outer surface at (0.81, 0.5, 0.5)
+SHELL_CROP = (175, 96, 96)
+SHELL_EXTENT = 64
+
+
+@pytest.mark.timeout(900)
+def test_shell1024_full_size(sg):
+    """The paper's timing geometry at its resolution: tables bit for bit, the
+    sequential update exactly, the Laplacian on an oracle crop."""
+    from paper_2512_11473_amd import workload
+    cfg = synth.config_shell()
+    N = cfg["N"]
+    M = N // 4
+    wl = workload.setup(cfg["shape"], N, cfg["noise_amp"], cfg["noise_seed"])
+    g = wl.grid
+    assert g.n_packages == 579128
+    out = torch.empty_like(wl.phi)
+    sg.compute_laplacian(g, wl.phi, out)
+    before = wl.phi.clone()
+    sg.sequential_update(g, wl.phi, cfg["delta"])
+    torch.cuda.synchronize()
+    assert torch.equal(wl.phi[2:], before[2:] + torch.tensor(cfg["delta"], dtype=torch.float32, device="cuda"))
+    t = {k: v.cpu().numpy() for k, v in g.tables().items()}
+    assert_tables_equal(t, oracle.build_tables(M, wl.coarse.cpu().numpy()))
+    crop = oracle.setup_crop(cfg["shape"], N, SHELL_CROP, SHELL_EXTENT, cfg["noise_amp"], cfg["noise_seed"])
+    n, h = 4 * SHELL_EXTENT, crop.h
+    dense = oracle.dense_state(crop.tab, crop.active, crop.phi0, crop.B)
+    ref = oracle.laplacian(n, h, crop.B, crop.active, dense)
+    act = crop.active[_interior(crop.active, n, 6)]
+    assert act.size > 200_000
+    pkg, loc = _global_rows(t, act, n, SHELL_CROP, M)
+    assert np.all(pkg >= 2)
+    got = out[torch.from_numpy(pkg).cuda(), torch.from_numpy(loc).cuda()].double().cpu().numpy()
+    assert np.max(np.abs(got - ref[act])) <= 3e-5 / h

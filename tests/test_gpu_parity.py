@@ -286,6 +286,64 @@ def test_sweep_autotune(sg):
     assert torch.equal(wl.phi, ref)
 
 
+LAP_TOL = 3e-5   # |dL| * h: FP32 sums of seven values of magnitude <= 16 h, times the exact 1 / h^2
+
+
+@pytest.mark.parametrize("dtype", [torch.float32, torch.float64], ids=["f32", "f64"])
+@pytest.mark.parametrize("which", ["sphere64", "shell128"])
+def test_timing_operations(sg, dtype, which):
+    """The two operations of the paper's timing test (Sec. 9, Tab. 1): the
+    sequential update is the same floating-point addition as on the host, the
+    seven-point Laplacian matches the oracle."""
+    from paper_2512_11473_amd import workload
+    if which == "sphere64":
+        cfg = synth.config_c1()
+        shape, N, amp, seed = cfg["shape"], cfg["N"], cfg["noise_amp"], cfg["noise_seed"]
+    else:
+        shape, N, amp, seed = synth.shell((0.5, 0.5, 0.5), 0.3, 0.34), 128, 0.05, 8
+    npd = np.float32 if dtype == torch.float32 else np.float64
+    wl = workload.setup(shape, N, amp, seed, dtype=dtype)
+    run = oracle.setup(shape, N, amp, seed, phi0_dtype=npd)
+    out = torch.empty_like(wl.phi)
+    sg.compute_laplacian(wl.grid, wl.phi, out)
+    dense = oracle.dense_state(run.tab, run.active, run.phi0, run.B)
+    ref = oracle.laplacian(run.N, run.h, run.B, run.active, dense)
+    got = out[2:].double().cpu().numpy().ravel()
+    tol = LAP_TOL / run.h if dtype == torch.float32 else 1e-9 / run.h
+    assert np.max(np.abs(got - ref[wl.points.ravel()])) <= tol
+    assert torch.all(out[:2] == 0)
+    # the far field is visible to part of the band
+    assert np.abs(ref[wl.points.ravel()]).max() > 10 / run.h
+    before = wl.phi.clone()
+    sg.sequential_update(wl.grid, wl.phi, 1e-6)
+    expect = before[2:] + torch.tensor(1e-6, dtype=dtype, device="cuda")
+    assert torch.equal(wl.phi[2:], expect)
+    assert torch.equal(wl.phi[:2], before[:2])
+
+
+def test_stencils_in_sweep_order(sg):
+    """With a Morton-order sweep configured, the gradient and the Laplacian
+    visit the packages in that order too; the results are the same bits."""
+    cfg = synth.config_c1()
+    from paper_2512_11473_amd import workload
+    wl = workload.setup(cfg["shape"], cfg["N"], cfg["noise_amp"], cfg["noise_seed"])
+    sg.reinitialize(wl.grid, wl.phi, wl.scratch, 4)
+    outs = []
+    for variant in (0, 3, 4):
+        sg.set_sweep_config(variant, 1)
+        grad = torch.empty((3,) + tuple(wl.phi.shape), device="cuda")
+        packed = torch.empty((wl.grid.n_total, 64, 4), device="cuda")
+        lap = torch.empty_like(wl.phi)
+        sg.compute_gradient(wl.grid, wl.phi, grad)
+        sg.compute_gradient_packed(wl.grid, wl.phi, packed)
+        sg.compute_laplacian(wl.grid, wl.phi, lap)
+        outs.append((grad, packed, lap))
+    sg.set_sweep_config(0, 1)
+    for o in outs[1:]:
+        for a, b in zip(outs[0], o):
+            assert torch.equal(a, b)
+
+
 def test_determinism(sg):
     cfg = synth.config_c1()
     from paper_2512_11473_amd import workload

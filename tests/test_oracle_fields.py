@@ -214,3 +214,48 @@ def test_probe_far_field_home_cell():
     val, nrm = oracle.probe(Nn, h, 16 * h, tab.cell_pkg, phi, g, pos)
     assert val[0] == -16 * h and val[1] == 16 * h and abs(val[2] - 99.0) < 1e-12
     assert np.all(nrm[:2] == 0)
+
+
+# --------------------------------------------------------------------------
+# The operations of the paper's timing test (Sec. 9, Tab. 1)
+# --------------------------------------------------------------------------
+
+def test_laplacian_exact_on_quadratics():
+    # The seven-point stencil is exact for quadratics: sum of 2 a_ii for any
+    # mixed and linear terms, here with dyadic coefficients so FP64 is exact.
+    act, x = _grid()
+    c = x - 0.5
+    phi = 0.75 * c[:, 0] ** 2 - 1.25 * c[:, 1] ** 2 + 2.5 * c[:, 2] ** 2 + 0.5 * c[:, 0] * c[:, 1] - c[:, 2] + 0.125
+    lap = oracle.laplacian(N, H, B, act, phi)
+    inner = _interior(x, 1)
+    assert np.max(np.abs(lap[inner] - 2 * (0.75 - 1.25 + 2.5))) < 1e-9
+    assert np.max(np.abs(oracle.laplacian(N, H, B, act, x @ np.array([0.3, -0.2, 0.7]))[inner])) < 1e-9
+
+
+def test_laplacian_brute_force_with_far_field():
+    # Against a padded numpy evaluation on a band that leaves far-field cells:
+    # the active list from the tables, every other point holding +-B.
+    s = synth.sphere((0.5, 0.5, 0.5), 0.3)
+    run = oracle.setup(s, N, 0.1, 3, phi0_dtype=np.float64)
+    phi = oracle.dense_state(run.tab, run.active, run.phi0, run.B)
+    lap = oracle.laplacian(N, H, B, run.active, phi)
+    P = np.pad(phi.reshape(N, N, N), 1, constant_values=B)
+    c = P[1:-1, 1:-1, 1:-1]
+    ref = (P[1:-1, 1:-1, :-2] + P[1:-1, 1:-1, 2:] + P[1:-1, :-2, 1:-1] + P[1:-1, 2:, 1:-1]
+           + P[:-2, 1:-1, 1:-1] + P[2:, 1:-1, 1:-1] - 6 * c) / H ** 2
+    mask = np.zeros(N ** 3, dtype=bool)
+    mask[run.active] = True
+    assert np.allclose(lap[mask], ref.ravel()[mask], rtol=1e-13, atol=1e-9)
+    assert np.all(lap[~mask] == 0.0)
+    # some active points see the far field across a face
+    assert (np.abs(ref.ravel()[mask]) > 100).any()
+
+
+def test_sequential_update():
+    act, x = _grid()
+    phi = np.sin(x[:, 0] * 7)
+    sel = act[::3]
+    out = oracle.sequential_update(phi, sel, 1e-3)
+    assert np.array_equal(out[sel], phi[sel] + 1e-3)
+    rest = np.setdiff1d(act, sel)
+    assert np.array_equal(out[rest], phi[rest])
