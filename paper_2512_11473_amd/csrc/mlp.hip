@@ -51,15 +51,23 @@ __device__ __forceinline__ floatx4 mfma(const bf16x8 &a, const bf16x8 &b, const 
 
 __device__ __forceinline__ bf16x8 ld8(const bf16 *p) { return *reinterpret_cast<const bf16x8 *>(p); }
 
-__device__ __forceinline__ float gelu(float z) {
+// GELU in its tanh form, 0.5 z (1 + tanh(u)) with u = sqrt(2/pi) (z + 0.044715
+// z^3), evaluated as z s with s = 0.5 (1 + tanh(u)) = 1 / (1 + exp(-2u)): the
+// same function, with the hardware exponential and reciprocal instead of a
+// library tanh (the activations dominate the network's vector work).  For
+// large |u| the exponential saturates to 0 or inf and s to 1 or 0.
+__device__ __forceinline__ float gelu_s(float z) {
     const float u = 0.7978845608028654f * (z + 0.044715f * z * z * z);
-    return 0.5f * z * (1.0f + tanhf(u));
+    return __frcp_rn(1.0f + __expf(-2.0f * u));
 }
 
+__device__ __forceinline__ float gelu(float z) { return z * gelu_s(z); }
+
+// d/dz [z s] = s + z s (1 - s) 2 u'(z), u' = sqrt(2/pi) (1 + 3 * 0.044715 z^2)
+// (the tanh form's 0.5 (1 + th) + 0.5 z (1 - th^2) u' with th = 2s - 1).
 __device__ __forceinline__ float gelu_grad(float z) {
-    const float u = 0.7978845608028654f * (z + 0.044715f * z * z * z);
-    const float th = tanhf(u);
-    return 0.5f * (1.0f + th) + 0.5f * z * (1.0f - th * th) * 0.7978845608028654f * (1.0f + 3.0f * 0.044715f * z * z);
+    const float s = gelu_s(z);
+    return s + 2.0f * z * s * (1.0f - s) * 0.7978845608028654f * (1.0f + 3.0f * 0.044715f * z * z);
 }
 
 struct Tile {
@@ -630,117 +638,232 @@ __device__ __forceinline__ Taps make_taps() {
 
 __global__ __launch_bounds__(256) void zero_u32_kernel(uint32_t *p) { *p = 0u; }
 
-// Learned-integral kernel: one workgroup per core package.  The 9^3 window is
-// staged, saturation flags are set, four wavefronts run the network on 16
-// points each (BF16 weights from L2), and four lanes per point evaluate the
-// exact saturated sum or the gate.
+// Learned-integral kernel: two core packages per workgroup, two wavefronts
+// per package.  A package's 128 lanes stage its 9^3 window and saturation
+// flags in the package's LDS region; each wavefront runs the network on 32 of
+// the 64 points as two 16-point MFMA tiles (each BF16 weight fragment read
+// from L2 feeds both tiles, hi and lo parts), and then two lanes per point
+// evaluate the exact saturated sum or the gate.  The MFMA accumulation order
+// is that of forward_tile, so the network outputs are the bits of
+// sgrid_mlp_forward on the gathered windows.
+constexpr int kLearnPkgs = 2;   // packages per workgroup
+constexpr int kLearnTiles = 2;  // 16-point tiles per wavefront
+
+struct LearnLds {
+    float phi[kWinN + 3];
+    uint32_t ids[28];
+    uint8_t sat[kVolN + 13];
+    __attribute__((aligned(16))) bf16 act[64 * kH];   // a1, then a2, then the outputs y (FP32 [64][4])
+};
+
 __global__ __launch_bounds__(256) void learned_kernel(MlpDev W, const float *__restrict__ phi,
                                                       const uint32_t *__restrict__ nbr,
                                                       const uint32_t *__restrict__ core_list, int64_t n_core,
                                                       float inv_h, float inv_2h, float tau, float kw_lo, float kw_hi,
                                                       float *__restrict__ out, uint32_t *__restrict__ fb_list,
                                                       uint32_t *__restrict__ fb_count) {
-    __shared__ float s_phi[kWinN];
-    __shared__ uint32_t s_ids[27];
-    __shared__ uint8_t s_sat[kVolN];
-    __shared__ __attribute__((aligned(16))) bf16 s_a1[64 * kH];
-    __shared__ __attribute__((aligned(16))) bf16 s_a2[64 * kH];
-    __shared__ float s_y[64][kOut];
+    __shared__ LearnLds lds[kLearnPkgs];
+    __shared__ int16_t s_off[kInPad];   // window offset of network input kk (ox + 9 oy + 81 oz), -1 past 215
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, r = lane & 15, q = lane >> 4;
+    if (threadIdx.x < kInPad) {
+        const int kk = threadIdx.x;
+        s_off[kk] = kk < kIn ? (int16_t)(kk % 6 + kWin * ((kk / 6) % 6) + kWin * kWin * (kk / 36)) : (int16_t)-1;
+    }
+    const int slot = w >> 1, half = w & 1, t128 = threadIdx.x & 127;
+    LearnLds &L = lds[slot];
+    const int64_t cw = (int64_t)blockIdx.x * kLearnPkgs + slot;
+    const bool live = cw < n_core;                 // a package slot past the end repeats the last package
+    const int64_t ci = live ? cw : n_core - 1;
+    const int64_t p = core_list[ci];
+    if (t128 < 27) L.ids[t128] = nbr[p * 27 + t128];
+    __syncthreads();
+    sgrid::stage_window_part<128>(phi, L.ids, t128, L.phi);
+    __syncthreads();
+    for (int v = t128; v < kVolN; v += 128) {
+        const int x = v % kVol + 1, y = (v / kVol) % kVol + 1, z = v / (kVol * kVol) + 1;
+        const int c = x + kWin * (y + kWin * z);
+        const float gx = (L.phi[c + 1] - L.phi[c - 1]) * inv_2h;
+        const float gy = (L.phi[c + kWin] - L.phi[c - kWin]) * inv_2h;
+        const float gz = (L.phi[c + kWin * kWin] - L.phi[c - kWin * kWin]) * inv_2h;
+        const float a = L.phi[c] * inv_h;
+        const bool sat = a != 0.f && fabsf(a) >= 0.5f * (fabsf(gx) + fabsf(gy) + fabsf(gz));
+        L.sat[v] = (uint8_t)((sat ? 1 : 0) | (a > 0.f ? 2 : 0));
+    }
+    const int cell0 = 32 * half;   // this wavefront's points: cell0 .. cell0 + 31
+    // layer 1: [32 x 224] (hi + lo BF16 parts of phi / h) x W1^T
+    floatx4 acc[kLearnTiles][8];
+#pragma unroll
+    for (int m = 0; m < kLearnTiles; ++m)
+#pragma unroll
+        for (int t = 0; t < 8; ++t) acc[m][t] = floatx4{0.f, 0.f, 0.f, 0.f};
+    // the weight fragments of step s + 1 load while step s multiplies
+    bf16x8 bw[8], bn[8];
+#pragma unroll
+    for (int t = 0; t < 8; ++t) bn[t] = ld8(W.w1b + (16 * t + r) * kInPad + 8 * q);
+    for (int s = 0; s < kInPad / 32; ++s) {
+#pragma unroll
+        for (int t = 0; t < 8; ++t) bw[t] = bn[t];
+        if (s + 1 < kInPad / 32) {
+#pragma unroll
+            for (int t = 0; t < 8; ++t) bn[t] = ld8(W.w1b + (16 * t + r) * kInPad + 32 * (s + 1) + 8 * q);
+        }
+#pragma unroll
+        for (int m = 0; m < kLearnTiles; ++m) {
+            float v[8];
+            const int c = cell0 + 16 * m + r;
+            const float *base = L.phi + (c & 3) + kWin * (((c >> 2) & 3) + kWin * (c >> 4));
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                const int off = s_off[32 * s + 8 * q + e];
+                v[e] = off >= 0 ? base[off] * inv_h : 0.f;
+            }
+            bf16x8 ah, al;
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                const bf16 hi = (bf16)v[j];
+                ah[j] = hi;
+                al[j] = (bf16)(v[j] - (float)hi);
+            }
+#pragma unroll
+            for (int t = 0; t < 8; ++t) {
+                acc[m][t] = mfma(ah, bw[t], acc[m][t]);
+                acc[m][t] = mfma(al, bw[t], acc[m][t]);
+            }
+        }
+    }
+    bf16 *act = L.act + cell0 * kH;
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+        const float bb = W.w[oB1 + 16 * t + r];
+#pragma unroll
+        for (int m = 0; m < kLearnTiles; ++m)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) act[(16 * m + 4 * q + i) * kH + 16 * t + r] = (bf16)gelu(acc[m][t][i] + bb);
+    }
+    __syncthreads();
+    // layer 2
+#pragma unroll
+    for (int m = 0; m < kLearnTiles; ++m)
+#pragma unroll
+        for (int t = 0; t < 8; ++t) acc[m][t] = floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int s = 0; s < kH / 32; ++s) {
+        bf16x8 bw[8];
+#pragma unroll
+        for (int t = 0; t < 8; ++t) bw[t] = ld8(W.w2b + (16 * t + r) * kH + 32 * s + 8 * q);
+#pragma unroll
+        for (int m = 0; m < kLearnTiles; ++m) {
+            const bf16x8 a = ld8(act + (16 * m + r) * kH + 32 * s + 8 * q);
+#pragma unroll
+            for (int t = 0; t < 8; ++t) acc[m][t] = mfma(a, bw[t], acc[m][t]);
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+        const float bb = W.w[oB2 + 16 * t + r];
+#pragma unroll
+        for (int m = 0; m < kLearnTiles; ++m)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) act[(16 * m + 4 * q + i) * kH + 16 * t + r] = (bf16)gelu(acc[m][t][i] + bb);
+    }
+    __syncthreads();
+    // layer 3
+    floatx4 y[kLearnTiles];
+#pragma unroll
+    for (int m = 0; m < kLearnTiles; ++m) y[m] = floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int s = 0; s < kH / 32; ++s) {
+        const bf16x8 b3 = ld8(W.w3b + r * kH + 32 * s + 8 * q);
+#pragma unroll
+        for (int m = 0; m < kLearnTiles; ++m) y[m] = mfma(ld8(act + (16 * m + r) * kH + 32 * s + 8 * q), b3, y[m]);
+    }
+    __syncthreads();
+    float *ys = reinterpret_cast<float *>(L.act);   // [64][4]
+    if (r < kOut) {
+        const float bb = W.w[oB3 + r];
+#pragma unroll
+        for (int m = 0; m < kLearnTiles; ++m)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) ys[(cell0 + 16 * m + 4 * q + i) * kOut + r] = y[m][i] + bb;
+    }
+    __syncthreads();
+    // epilogue: two lanes per point (adjacent lanes), taps and window rows split by parity
     const Taps tp = make_taps();
-    // point handled in the epilogue: c = threadIdx.x / 4, part = threadIdx.x % 4
-    const int c = threadIdx.x >> 2, part = threadIdx.x & 3;
+    const int c = cell0 + (lane >> 1), part = lane & 1;
     const int ci_ = c & 3, cj = (c >> 2) & 3, ck = c >> 4;
-    {
-        const int64_t ci = blockIdx.x;
-        stage_window(phi, nbr, core_list[ci], s_phi, s_ids);
-        saturation_flags(s_phi, inv_h, inv_2h, s_sat);
-        Tile T;
-        forward_tile(WindowX{s_phi, 16 * w, inv_h}, W, s_a1 + 16 * w * kH, s_a2 + 16 * w * kH, nullptr, T, lane);
-        if (r < kOut)
+    bool sat = true;
+    float kw = 0.f, kx = 0.f, ky = 0.f, kz = 0.f;
+    int tap = 0;
+    for (int oz = -1; oz <= 2; ++oz)
+        for (int oy = -1; oy <= 2; ++oy)
+            for (int ox = -1; ox <= 2; ++ox) {
+                const float dx = 0.5f - ox, dy = 0.5f - oy, dz = 0.5f - oz;
+                const float r2 = dx * dx + dy * dy + dz * dz;
+                if (r2 >= 4.0f) continue;
+                if ((tap++ & 1) != part) continue;
+                const uint8_t f = L.sat[(ci_ + ox + 1) + kVol * ((cj + oy + 1) + kVol * (ck + oz + 1))];
+                sat = sat && (f & 1);
+                const float vv = (f & 2) ? 1.f : 0.f;
+                const bool nearp = r2 < 1.0f;
+                const float Wt = nearp ? tp.Wn : tp.Wf, Dt = nearp ? tp.Dn : tp.Df;
+                kw += Wt * vv;
+                kx += Dt * dx * vv;
+                ky += Dt * dy * vv;
+                kz += Dt * dz * vv;
+            }
+    // non-planarity: mean squared residual after the window's least-squares
+    // affine fit.  The basis 1, ox, oy, oz (offsets centred at 2.5) is
+    // orthogonal on the window, so the residual is sum x^2 minus the squared
+    // projections: 216 c0^2 + 630 (cx^2 + cy^2 + cz^2).
+    float s0 = 0.f, s2 = 0.f, sx = 0.f, sy = 0.f, sz = 0.f;
+    for (int ez = 0; ez < 6; ++ez)
+        for (int ey = 0; ey < 6; ++ey) {
+            if (((ez * 6 + ey) & 1) != part) continue;
+            const float *row = L.phi + ci_ + kWin * ((cj + ey) + kWin * (ck + ez));
 #pragma unroll
-            for (int i = 0; i < 4; ++i) s_y[16 * w + 4 * q + i][r] = T.y[i];
-        __syncthreads();
-        // saturated taps: 32 taps split over the point's 4 lanes (taps t = part, part + 4, ...)
-        bool sat = true;
-        float kw = 0.f, kx = 0.f, ky = 0.f, kz = 0.f;
-        int tap = 0;
-        for (int oz = -1; oz <= 2; ++oz)
-            for (int oy = -1; oy <= 2; ++oy)
-                for (int ox = -1; ox <= 2; ++ox) {
-                    const float dx = 0.5f - ox, dy = 0.5f - oy, dz = 0.5f - oz;
-                    const float r2 = dx * dx + dy * dy + dz * dz;
-                    if (r2 >= 4.0f) continue;
-                    if ((tap++ & 3) != part) continue;
-                    const uint8_t f = s_sat[(ci_ + ox + 1) + kVol * ((cj + oy + 1) + kVol * (ck + oz + 1))];
-                    sat = sat && (f & 1);
-                    const float vv = (f & 2) ? 1.f : 0.f;
-                    const bool nearp = r2 < 1.0f;
-                    const float Wt = nearp ? tp.Wn : tp.Wf, Dt = nearp ? tp.Dn : tp.Df;
-                    kw += Wt * vv;
-                    kx += Dt * dx * vv;
-                    ky += Dt * dy * vv;
-                    kz += Dt * dz * vv;
-                }
-        // combine the 4 lanes of the point (adjacent lanes)
-#pragma unroll
-        for (int m = 1; m < 4; m <<= 1) {
-            kw += __shfl_xor(kw, m);
-            kx += __shfl_xor(kx, m);
-            ky += __shfl_xor(ky, m);
-            kz += __shfl_xor(kz, m);
-            const int other = __shfl_xor(sat ? 1 : 0, m);   // every lane takes part in the shuffle
-            sat = sat && other != 0;
+            for (int ex = 0; ex < 6; ++ex) {
+                const float v = row[ex] * inv_h;
+                s0 += v;
+                s2 += v * v;
+                sx += (ex - 2.5f) * v;
+                sy += (ey - 2.5f) * v;
+                sz += (ez - 2.5f) * v;
+            }
         }
-        // non-planarity: mean squared residual after the window's least-squares
-        // affine fit.  The basis 1, ox, oy, oz (offsets centred at 2.5) is
-        // orthogonal on the window, so the residual is sum x^2 minus the
-        // squared projections: 216 c0^2 + 630 (cx^2 + cy^2 + cz^2).
-        float s0 = 0.f, s2 = 0.f, sx = 0.f, sy = 0.f, sz = 0.f;
-        for (int ez = 0; ez < 6; ++ez)
-            for (int ey = 0; ey < 6; ++ey) {
-                if (((ez * 6 + ey) & 3) != part) continue;
-                const float *row = s_phi + ci_ + kWin * ((cj + ey) + kWin * (ck + ez));
-#pragma unroll
-                for (int ex = 0; ex < 6; ++ex) {
-                    const float v = row[ex] * inv_h;
-                    s0 += v;
-                    s2 += v * v;
-                    sx += (ex - 2.5f) * v;
-                    sy += (ey - 2.5f) * v;
-                    sz += (ez - 2.5f) * v;
-                }
+    // combine the two lanes of the point (every lane takes part in the shuffles)
+    kw += __shfl_xor(kw, 1);
+    kx += __shfl_xor(kx, 1);
+    ky += __shfl_xor(ky, 1);
+    kz += __shfl_xor(kz, 1);
+    const int other = __shfl_xor(sat ? 1 : 0, 1);
+    sat = sat && other != 0;
+    s0 += __shfl_xor(s0, 1);
+    s2 += __shfl_xor(s2, 1);
+    sx += __shfl_xor(sx, 1);
+    sy += __shfl_xor(sy, 1);
+    sz += __shfl_xor(sz, 1);
+    const float res = (s2 - s0 * s0 / 216.f - (sx * sx + sy * sy + sz * sz) / 630.f) * (1.0f / 216.f);
+    if (live && part == 0) {
+        const int64_t o = ci * 64 + c, stride = n_core * 64;
+        bool write = true;
+        if (!sat) {
+            const float y0 = ys[c * kOut];
+            if (res <= tau && y0 >= kw_lo && y0 <= kw_hi) {
+                kw = y0;
+                kx = ys[c * kOut + 1];
+                ky = ys[c * kOut + 2];
+                kz = ys[c * kOut + 3];
+            } else {
+                fb_list[atomicAdd(fb_count, 1u)] = (uint32_t)o;
+                write = false;
             }
-#pragma unroll
-        for (int m = 1; m < 4; m <<= 1) {
-            s0 += __shfl_xor(s0, m);
-            s2 += __shfl_xor(s2, m);
-            sx += __shfl_xor(sx, m);
-            sy += __shfl_xor(sy, m);
-            sz += __shfl_xor(sz, m);
         }
-        const float res = (s2 - s0 * s0 / 216.f - (sx * sx + sy * sy + sz * sz) / 630.f) * (1.0f / 216.f);
-        if (part == 0) {
-            const int64_t o = ci * 64 + c, stride = n_core * 64;
-            bool write = true;
-            if (!sat) {
-                const float y0 = s_y[c][0];
-                if (res <= tau && y0 >= kw_lo && y0 <= kw_hi) {
-                    kw = y0;
-                    kx = s_y[c][1];
-                    ky = s_y[c][2];
-                    kz = s_y[c][3];
-                } else {
-                    fb_list[atomicAdd(fb_count, 1u)] = (uint32_t)o;
-                    write = false;
-                }
-            }
-            if (write) {
-                out[o] = kw;
-                out[stride + o] = kx;
-                out[2 * stride + o] = ky;
-                out[3 * stride + o] = kz;
-            }
+        if (write) {
+            out[o] = kw;
+            out[stride + o] = kx;
+            out[2 * stride + o] = ky;
+            out[3 * stride + o] = kz;
         }
     }
 }
@@ -845,7 +968,8 @@ sgrid_status integrals_learned(const sgrid_grid *g, const float *phi, const sgri
     if (g->n_core == 0) return SGRID_OK;
     SG_REQUIRE(g->n_core <= kMaxGrid, "too many core packages");
     const float inv_h = (float)(1.0 / g->h), inv_2h = (float)(0.5 / g->h);
-    hipLaunchKernelGGL(learned_kernel, dim3((unsigned)g->n_core), dim3(256), 0, st, m->dev(), phi, g->nbr,
+    hipLaunchKernelGGL(learned_kernel, dim3((unsigned)((g->n_core + kLearnPkgs - 1) / kLearnPkgs)), dim3(256), 0,
+                       st, m->dev(), phi, g->nbr,
                        g->core_list, g->n_core, inv_h, inv_2h, m->gate_tau, m->kw_lo, m->kw_hi, out, m->fallback,
                        count);
     SG_CHECK_LAUNCH("learned integrals");
