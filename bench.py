@@ -59,7 +59,8 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
                     help="minimum oracle sweeping time of the CPU baseline")
     ap.add_argument("--train-cells", type=int, default=2_000_000)
-    ap.add_argument("--epochs", type=int, default=50)
+    ap.add_argument("--epochs", type=int, default=300)
+    ap.add_argument("--train-batch", type=int, default=2048)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one 256 MiB device copy first (counter calibration under rocprofv3)")
     return ap.parse_args()
@@ -134,7 +135,8 @@ def learned_vs_plain(sg, wl, args, log):
     tr = surrogate.generate(256, 101, args.train_cells)
     ho = surrogate.generate(128, 202, args.train_cells // 2)
     log(f"surrogate data: train {tuple(tr.x.shape)} in {tr.seconds:.1f}s, held-out {tuple(ho.x.shape)}")
-    res = surrogate.train(tr, epochs=args.epochs, log=log)
+    res = surrogate.train(tr, epochs=args.epochs, batch=args.train_batch, log=None)
+    log(f"surrogate trained: {res.steps} steps in {res.seconds:.1f}s, final loss {res.losses[-1]:.3e}")
     ev = surrogate.evaluate(res.model, ho, res.tau)
     n = wl.grid.n_core * 64
     out_p = torch.empty((4, n), device="cuda")
@@ -163,7 +165,7 @@ def learned_vs_plain(sg, wl, args, log):
         "heldout": ev,
         "bench_grid_error": surrogate.error_stats(e),
         "bench_grid_fallback_fraction": int(nf.item()) / n,
-        "train": {"points": int(tr.x.shape[0]), "shapes": tr.shapes, "epochs": args.epochs,
+        "train": {"points": int(tr.x.shape[0]), "shapes": tr.shapes, "epochs": args.epochs, "batch": args.train_batch,
                   "steps": res.steps, "seconds": res.seconds, "final_loss": res.losses[-1],
                   "gate_tau": res.tau},
     }

@@ -188,3 +188,68 @@ def test_learned_integrals_gate_extremes(sg):
     m = un.bool()
     assert torch.equal(out[:, m], y[m].t().contiguous())
     assert torch.max(torch.abs(out[:, ~m] - plain[:, ~m])).item() <= 1e-6
+
+
+def test_trained_surrogate_against_plain(sg):
+    """What the trained network gives over the method without it: trained by
+    the library's kernels on points of seeded shapes, it reproduces the plain
+    integrals of held-out shapes far better than before training, and the
+    gated learned path on a grid stays within the fallback contract.  The
+    timing of both paths is recorded (the plain kernel is the faster one)."""
+    from paper_2512_11473_amd import surrogate, workload
+    tr = surrogate.generate(16, 303, 200_000, resolutions=(64, 128))
+    ho = surrogate.generate(8, 404, 100_000, resolutions=(64, 128))
+    assert tr.x.shape[0] > 100_000 and ho.x.shape[0] > 50_000
+    res = surrogate.train(tr, epochs=30, batch=2048)
+    before = surrogate.evaluate(sg.Mlp(surrogate.init_params(0, float(tr.x.std()))), ho)["ungated"]["mean"]
+    after = surrogate.evaluate(res.model, ho, res.tau)
+    assert after["ungated"]["mean"] < before / 10
+    assert after["ungated"]["mean"] < 2e-2
+    assert after["fallback_fraction"] < 0.05
+    # on a grid: learned + fallback against plain
+    cfg = synth.config_c1()
+    wl = workload.setup(cfg["shape"], cfg["N"], cfg["noise_amp"], cfg["noise_seed"])
+    sg.reinitialize(wl.grid, wl.phi, wl.scratch, 20)
+    n = wl.grid.n_core * 64
+    plain = torch.empty((4, n), device="cuda")
+    learned = torch.empty_like(plain)
+    nf = torch.zeros(1, dtype=torch.int32, device="cuda")
+    e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    e[0].record()
+    sg.compute_near_surface_integrals(wl.grid, wl.phi, plain)
+    e[1].record()
+    sg.compute_near_surface_integrals(wl.grid, wl.phi, learned, model=res.model, n_fallback=nf)
+    e[2].record()
+    torch.cuda.synchronize()
+    err = surrogate.relative_error(learned.t(), plain.t())
+    assert float(err.mean()) < 2e-2
+    print(f"\nsurrogate: held-out mean error {before:.3e} -> {after['ungated']['mean']:.3e}; "
+          f"grid mean error {float(err.mean()):.3e}, fallback {int(nf.item())} of {n}; "
+          f"plain {e[0].elapsed_time(e[1]):.3f} ms, learned {e[1].elapsed_time(e[2]):.3f} ms")
+
+
+def test_checkpoint_resume_is_bit_identical(sg):
+    """Training resumed from a checkpoint (master weights, Adam moments, step
+    count) continues exactly as the uninterrupted run: the weight-gradient
+    reduction runs in a fixed order, so the same inputs give the same bits."""
+    rng = np.random.default_rng(11)
+    B = 1024
+    batches = [(torch.from_numpy((rng.standard_normal((B, 216)) * 1.5).astype(np.float32)).cuda(),
+                torch.from_numpy(rng.standard_normal((B, 4)).astype(np.float32)).cuda()) for _ in range(6)]
+    loss = torch.zeros(1, device="cuda")
+    lw = [1.0, 0.5, 2.0, 1.0]
+    a = sg.Mlp(init_params(12))
+    for x, t in batches:
+        a.train_step(x, t, lw, 1e-3, loss)
+    b = sg.Mlp(init_params(12))
+    for x, t in batches[:3]:
+        b.train_step(x, t, lw, 1e-3, loss)
+    w, m, v, step = b.state()
+    c = sg.Mlp(w)
+    c.set_state(m, v, step)
+    for x, t in batches[3:]:
+        c.train_step(x, t, lw, 1e-3, loss)
+    wa, ma, va, sa = a.state()
+    wc, mc, vc, sc = c.state()
+    assert sa == sc == 6
+    assert np.array_equal(wa, wc) and np.array_equal(ma, mc) and np.array_equal(va, vc)
