@@ -39,7 +39,9 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 REINIT_BYTES_PER_UPDATE = 8.375      # read + write one FP32 value, plus 6 face ids / 64 points
 PROBE_BYTES_PER_PARTICLE = 28.0      # 12 B position in, 16 B value + normal out
-SWEEP_SRC = os.path.join(ROOT, "paper_2512_11473_amd", "csrc", "sweep.hip")
+# the sources the sweep and stencil kernels are compiled from: a counter
+# summary counts only while they are unchanged
+SWEEP_SRCS = [os.path.join(ROOT, "paper_2512_11473_amd", "csrc", f) for f in ("sweep.hip", "common.hpp", "upwind.hpp")]
 
 
 def parse():
@@ -67,23 +69,23 @@ def parse():
 
 
 def sweep_source_hash() -> str:
-    return hashlib.sha256(open(SWEEP_SRC, "rb").read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for f in SWEEP_SRCS:
+        h.update(open(f, "rb").read())
+    return h.hexdigest()[:16]
 
 
-def measured_traffic(workload: str, sweep: tuple):
-    """HBM bytes per sweep launch from the committed counter summary of this
-    workload, when it was taken on the current sweep source and with the same
-    sweep configuration; else None."""
-    path = os.path.join(ROOT, "profiles", f"reinit_sweep_{workload}_counters.txt")
+def measured_traffic(summary: str, key: str):
+    """HBM bytes per launch of one kernel configuration (`key`) from a committed
+    rocprofv3 counter summary under profiles/, when the summary was taken on
+    the current sweep sources; else None."""
+    path = os.path.join(ROOT, "profiles", summary)
     if not os.path.exists(path):
         return None
     text = open(path).read()
-    m = re.search(r"sweep_source_sha256_16:\s*(\w+)", text)
-    c = re.search(r"sweep_config:\s*(\d+),(\d+)", text)
-    t = re.search(r"calibrated_bytes_per_launch:\s*([0-9.eE+]+)", text)
-    if not m or not t or not c or m.group(1) != sweep_source_hash():
-        return None
-    if (int(c.group(1)), int(c.group(2))) != tuple(sweep):
+    m = re.search(r"sweep_sources_sha256_16:\s*(\w+)", text)
+    t = re.search(r"calibrated_bytes_per_launch\[" + re.escape(key) + r"\]:\s*([0-9.eE+]+)", text)
+    if not m or not t or m.group(1) != sweep_source_hash():
         return None
     return float(t.group(1))
 
@@ -312,7 +314,7 @@ def bench_single(args, log):
         "integral_cells_per_s": n_core * 64 / (acc["integ"] / K * 1e-3),
         "roofline": {"bound": "hbm", "kernel": f"reinit sweep (variant {tv}, groups {tg})", "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": measured_traffic(cfg["name"], (tv, tg)),
+                     "traffic": measured_traffic(f"reinit_sweep_{cfg['name']}_counters.txt", f"v{tv}g{tg}"),
                      "avg_launch_us": sweep_ms * 1e3, "algorithmic_bytes_per_launch": bytes_launch,
                      "note": ("phi ping-pong of 64 MB is resident in the 256 MB Infinity Cache"
                               if cfg["name"] == "prism512" else
@@ -439,7 +441,9 @@ def bench_shell(args, log):
         "sequential_points_per_s": pts / (seq_ms * 1e-3),
         "roofline": {"bound": "hbm", "kernel": "laplacian", "achieved": lap_bytes / (lap_ms * 1e-3) / 1e9,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": lap_bytes / (lap_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, "traffic": None,
+                     "frac": lap_bytes / (lap_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                     "traffic": measured_traffic("laplacian_shell1024_counters.txt",
+                                                 "worklist" if tv in (3, 4) else "linear"),
                      "algorithmic_bytes_per_launch": lap_bytes},
         "sequential_roofline": {"achieved": seq_bytes / (seq_ms * 1e-3) / 1e9, "unit": "GB/s",
                                 "frac": seq_bytes / (seq_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,

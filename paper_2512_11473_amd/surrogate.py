@@ -11,6 +11,8 @@ points only; loss = sum_o (y_o - t_o)^2 / sigma_o^2 (targets standardised by
 their training-set spread); Adam with a cosine learning rate from 1e-3 to
 1e-5; Kaiming-uniform initialisation scaled by the input spread.  The gate
 threshold is the 99.9th percentile of the training windows' non-planarity.
+The benchmark trains 300 epochs of 2048-sample batches over 2e6 points, the
+best of the step counts and batch sizes tried (held-out mean error 2.5e-3).
 """
 from __future__ import annotations
 
