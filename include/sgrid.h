@@ -302,17 +302,18 @@ sgrid_status sgrid_compute_laplacian(const sgrid_grid *grid, sgrid_dtype dtype, 
 /*
  * Tuning knob for sgrid_reinitialize: sweep variant 0 exchanges the interior
  * neighbours between lanes (DPP row shifts), variant 1 stages each package
- * and its face halo in an LDS tile, variant 2 is variant 0 as a persistent
- * kernel whose wavefronts walk contiguous package ranges with the next face
- * row prefetched, variant 3 is variant 0 over the packages in Morton order of
- * their cells (spatial neighbours swept by the same workgroup), variant 4
+ * and its face halo in an LDS tile, variant 2 is variant 3 as a persistent
+ * kernel whose wavefronts walk the Morton worklist in grid-stride rounds
+ * with the next face row prefetched, variant 3 is variant 0 over the
+ * packages in Morton order of their cells (spatial neighbours swept by the
+ * same workgroup), variant 4
  * sweeps groups of 64 consecutive Morton-ordered packages per 1024-lane
  * workgroup and reads halo rows of in-group neighbours from LDS, variant 5
  * is variant 0 with the y / z neighbour rows exchanged through LDS instead of
  * DPP (no workgroup barrier).  `groups` (1, 2, 3, 4 or 8) is, for variants 0,
  * 1, 3 and 5, the number of four-package sets one wavefront processes, for
  * variant 2 the number of workgroups per compute unit, and is ignored by
- * variant 4.  With variant 3 or 4 the gradient and Laplacian passes also
+ * variant 4.  With variant 2, 3 or 4 the gradient and Laplacian passes also
  * visit the packages in Morton order.  Process-wide; default (0, 1).  Results
  * are identical for every setting.
  */
@@ -320,7 +321,7 @@ sgrid_status sgrid_set_sweep_config(int32_t variant, int32_t groups);
 
 /*
  * Autotuner of sgrid_reinitialize on the caller's grid: times the candidates
- * (variant, groups) = (0, 1), (0, 2), (0, 4), (3, 1), (3, 2), (5, 1) with
+ * (variant, groups) = (0, 1), (0, 2), (2, 4), (3, 1), (3, 2), (5, 1) with
  * `reps` sweeps each (1..1000) that read phi and write scratch (phi is not
  * modified; scratch rows 2.. are overwritten), makes the fastest the
  * process-wide configuration (as sgrid_set_sweep_config) and returns it.

@@ -289,37 +289,49 @@ __global__ __launch_bounds__(1024) void reinit_share_kernel(const T *__restrict_
     store_row(dst + p * 64 + r * 4, reinit_row(s, h2, inv_h, dt));
 }
 
-// Persistent variant: a fixed grid of a few workgroups per CU; each wavefront
-// walks a contiguous range of four-package sets and loads the face row of the
-// next set while the current set's data loads are in flight, so the
-// face-table -> halo dependency costs one memory round trip per range instead
-// of one per set.
+// Persistent worklist variant: a fixed grid of `groups` workgroups per CU
+// walks the Morton worklist in grid-stride rounds.  In each round the
+// wavefronts cover one contiguous stretch of the worklist (each XCD a
+// contiguous part of it), so halo rows come from lines the same round brings
+// into the caches, as in the one-shot worklist variant; and every wavefront
+// loads the face row of its next set while the current set's data loads are
+// in flight, which takes the face-row -> data dependency off the critical
+// path after a wavefront's first set.  The round loop is uniform over a
+// wavefront (all 64 lanes run the DPP exchange together).  The last set's
+// missing entries take the last entry again and store the same bytes to the
+// same package as its own lanes: the store stays unconditional, because a
+// conditional one lets the compiler sink the halo loads into the branch,
+// behind the DPP exchange, adding a memory round trip.
 template <typename T>
-__global__ __launch_bounds__(256) void reinit_stream_kernel(const T *__restrict__ src, T *__restrict__ dst,
-                                                            const uint32_t *__restrict__ face, int64_t P,
-                                                            int64_t n_blocks, int64_t sets_per_wave, T h2, T inv_h,
-                                                            T dt) {
+__global__ __launch_bounds__(256) void reinit_pipe_kernel(const T *__restrict__ src, T *__restrict__ dst,
+                                                          const uint32_t *__restrict__ wface, int64_t P,
+                                                          int64_t n_blocks, T h2, T inv_h, T dt) {
     const int64_t b = xcd_block(blockIdx.x, n_blocks);
     const int lane = threadIdx.x & 63;
     const int r = lane & 15;
-    const int64_t wave = b * 4 + (threadIdx.x >> 6);
     const int64_t n_sets = (P + 3) / 4;
-    const int64_t s0 = wave * sets_per_wave;
-    const int64_t s1 = s0 + sets_per_wave < n_sets ? s0 + sets_per_wave : n_sets;
-    if (s0 >= s1) return;
-    const int64_t end = P + 2;
-    uint4 f0n = make_uint4(0, 0, 0, 0);
-    uint2 f1n = make_uint2(0, 0);
-    int64_t p = 2 + 4 * s0 + (lane >> 4);
-    if (p < end) load_face(face, p, f0n, f1n);
-    for (int64_t s = s0; s < s1; ++s, p += 4) {
-        const uint4 f0 = f0n;
-        const uint2 f1 = f1n;
+    const int64_t stride = n_blocks * 4;
+    int64_t s = b * 4 + (threadIdx.x >> 6);
+    if (s >= n_sets) return;
+    auto entry = [&](int64_t set) {
+        const int64_t e = set * 4 + (lane >> 4);
+        return e < P ? e : P - 1;
+    };
+    int64_t e = entry(s);
+    uint4 f0 = *reinterpret_cast<const uint4 *>(wface + e * 8);
+    uint4 f1 = *reinterpret_cast<const uint4 *>(wface + e * 8 + 4);
+    for (; s < n_sets; s += stride) {
+        const uint4 c0 = f0;
+        const int64_t p = (int64_t)f1.z;
+        const uint2 cz = make_uint2(f1.x, f1.y);
+        // the next set's face row first, so that it is in flight for a whole set
+        e = entry(s + stride < n_sets ? s + stride : s);
+        f0 = *reinterpret_cast<const uint4 *>(wface + e * 8);
+        f1 = *reinterpret_cast<const uint4 *>(wface + e * 8 + 4);
         Loads<T> l;
-        if (p < end) issue_data(src, p, r, f0, f1, l);
-        if (s + 1 < s1 && p + 4 < end) load_face(face, p + 4, f0n, f1n);
+        issue_data(src, p, r, c0, cz, l);
         const Stencil<T> st = assemble(r, l);
-        if (p < end) store_row(dst + p * 64 + r * 4, reinit_row(st, h2, inv_h, dt));
+        store_row(dst + p * 64 + r * 4, reinit_row(st, h2, inv_h, dt));
     }
 }
 
@@ -514,7 +526,9 @@ void set_sweep_config(int variant, int groups) {
 
 // The gradient and the Laplacian visit the packages in the sweep's order:
 // Morton (worklist) order when the configuration's sweep uses it.
-bool stencil_in_worklist_order() { return g_sweep_cfg.variant == 3 || g_sweep_cfg.variant == 4; }
+bool stencil_in_worklist_order() {
+    return g_sweep_cfg.variant == 2 || g_sweep_cfg.variant == 3 || g_sweep_cfg.variant == 4;
+}
 
 template <typename T>
 static void launch_dpp_range(const sgrid_grid *g, const T *src, T *dst, int64_t first, int64_t end, int groups,
@@ -562,12 +576,9 @@ static sgrid_status launch_reinit_sweep(const sgrid_grid *g, const T *src, T *ds
         }
     } else if (cfg.variant == 2) {
         const int64_t n_sets = (g->P + 3) / 4;
-        int64_t nbp = (int64_t)cu_count() * cfg.groups;
-        const int64_t waves = nbp * 4;
-        const int64_t spw = (n_sets + waves - 1) / waves;
-        nbp = (n_sets + spw * 4 - 1) / (spw * 4);   // drop workgroups that would have no sets
-        hipLaunchKernelGGL(reinit_stream_kernel<T>, dim3((unsigned)nbp), block, 0, st, src, dst, g->face, g->P, nbp,
-                           spw, h2, inv_h, dt);
+        const int64_t nbp = std::min<int64_t>((int64_t)cu_count() * cfg.groups, (n_sets + 3) / 4);
+        hipLaunchKernelGGL(reinit_pipe_kernel<T>, dim3((unsigned)nbp), block, 0, st, src, dst, g->wface, g->P, nbp,
+                           h2, inv_h, dt);
     } else if (cfg.variant == 1) {
         hipLaunchKernelGGL(reinit_lds_kernel<T>, grid, block, 0, st, src, dst, g->face, g->P, nb, cfg.groups, h2,
                            inv_h, dt);
@@ -611,7 +622,7 @@ extern "C" sgrid_status sgrid_set_sweep_config(int32_t variant, int32_t groups) 
 }
 
 // Candidates of the sweep autotuner: (variant, groups).
-static const int kTuneCandidates[6][2] = {{0, 1}, {0, 2}, {0, 4}, {3, 1}, {3, 2}, {5, 1}};
+static const int kTuneCandidates[6][2] = {{0, 1}, {0, 2}, {2, 4}, {3, 1}, {3, 2}, {5, 1}};
 
 template <typename T>
 static sgrid_status autotune_sweep(const sgrid_grid *g, const T *phi, T *scratch, int32_t reps, hipStream_t st,

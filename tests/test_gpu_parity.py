@@ -227,6 +227,25 @@ def test_sweep_variants_identical(sg):
         assert torch.equal(r, results[0])
 
 
+def test_persistent_sweep_rounds(sg):
+    """The persistent worklist sweep over a grid that takes each wavefront
+    through several grid-stride rounds, with a ragged last set, gives the bits
+    of the one-shot sweeps."""
+    from paper_2512_11473_amd import workload
+    wl = workload.setup(synth.sphere((0.48, 0.51, 0.49), 0.33), 256, 0.1, 5)
+    P = wl.grid.n_packages
+    assert (P + 3) // 4 > 3 * 256 * 4 and P % 4 != 0      # more than three rounds at one workgroup per CU
+    results = []
+    for variant, groups in [(0, 1), (3, 1), (2, 1), (2, 2), (2, 3), (2, 8)]:
+        sg.set_sweep_config(variant, groups)
+        wl.reset()
+        sg.reinitialize(wl.grid, wl.phi, wl.scratch, 5)
+        results.append(wl.phi.clone())
+    sg.set_sweep_config(0, 1)
+    for r in results[1:]:
+        assert torch.equal(r, results[0])
+
+
 @pytest.mark.parametrize("dtype", [torch.float32, torch.float64], ids=["f32", "f64"])
 def test_sweep_domain_edge(sg, dtype):
     """A band cut by two domain faces (out-of-domain neighbours are the
@@ -329,7 +348,7 @@ def test_stencils_in_sweep_order(sg):
     wl = workload.setup(cfg["shape"], cfg["N"], cfg["noise_amp"], cfg["noise_seed"])
     sg.reinitialize(wl.grid, wl.phi, wl.scratch, 4)
     outs = []
-    for variant in (0, 3, 4):
+    for variant in (0, 2, 3, 4):
         sg.set_sweep_config(variant, 1)
         grad = torch.empty((3,) + tuple(wl.phi.shape), device="cuda")
         packed = torch.empty((wl.grid.n_total, 64, 4), device="cuda")
