@@ -277,8 +277,25 @@ def bench_single(args, log):
     e1.record(stream)
     torch.cuda.synchronize()
     probe_sorted_ms = e0.elapsed_time(e1) / 5
-    g.destroy()
     del pos_sorted
+    # grid-to-particle coupling of the integral field (Sec. 8), not part of the
+    # step: the field at every activated point, then its probe at the particles
+    field = torch.empty((g.n_total, 64, 4), device="cuda")
+    fout = torch.empty((int(wl.pos.shape[0]), 4), device="cuda")
+    sg.compute_integral_field(g, wl.phi, field)
+    sg.probe_integral_field(g, field, wl.pos, fout)
+    e2 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(5):
+        sg.compute_integral_field(g, wl.phi, field)
+    e1.record(stream)
+    for _ in range(5):
+        sg.probe_integral_field(g, field, wl.pos, fout)
+    e2.record(stream)
+    torch.cuda.synchronize()
+    field_ms, fprobe_ms = e0.elapsed_time(e1) / 5, e1.elapsed_time(e2) / 5
+    g.destroy()
+    del field, fout
 
     K = args.steps
     ms_step = 1e3 * total_s / K
@@ -312,6 +329,10 @@ def bench_single(args, log):
                       "cell_sorted_GBps": probe_bytes / (probe_sorted_ms * 1e-3) / 1e9,
                       "cell_sorted_frac": probe_bytes / (probe_sorted_ms * 1e-3) / 1e9 / HBM_PEAK_GBS},
         "integral_cells_per_s": n_core * 64 / (acc["integ"] / K * 1e-3),
+        "integral_field": {"field_ms": field_ms, "field_points_per_s": 64 * P / (field_ms * 1e-3),
+                           "probe_ms": fprobe_ms, "probes_per_s": n_part / (fprobe_ms * 1e-3),
+                           "note": "(K_W, h K_grad) at every activated point, then interpolated to the particles "
+                                   "(random order); measured outside the step"},
         "roofline": {"bound": "hbm", "kernel": f"reinit sweep (variant {tv}, groups {tg})", "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": measured_traffic(f"reinit_sweep_{cfg['name']}_counters.txt", f"v{tv}g{tg}"),

@@ -187,6 +187,33 @@ sgrid_status sgrid_compute_near_surface_integrals(const sgrid_grid *grid, const 
                                                   const sgrid_mlp *model, float *out_dev,
                                                   uint32_t *n_fallback_dev, void *stream);
 
+/*
+ * The integral field for grid-to-particle coupling (Sec. 8: the kernel
+ * integral evaluated on the sparse grid is interpolated trilinearly to the
+ * particles and drives them as a surface force).  The integrals above, at
+ * every data point of every activated package (core and inner), written to
+ * `field_dev` [P + 2][64] float4 (K_W, h K_grad x, y, z) in the packed
+ * blocked point order of sgrid_compute_gradient_packed.  Rows 0 and 1 are
+ * the far-field packages' constants: (0, 0, 0, 0) for the negative side,
+ * (c_full, 0, 0, 0) for the positive side, c_full = sum of the 32 kernel
+ * weights (K_W of a support wholly on the phi > 0 side).  Inner packages'
+ * windows reach into the far field, whose constant values they read like
+ * any other neighbour.  FP32; `phi_dev` with its far-field rows filled.
+ */
+sgrid_status sgrid_compute_integral_field(const sgrid_grid *grid, const float *phi_dev, float *field_dev,
+                                          void *stream);
+
+/*
+ * The integral field at particle positions: trilinear interpolation of the
+ * four components over the eight data points around each particle, with the
+ * home package and the index shift of sgrid_probe_particles (a particle
+ * whose home cell is far field reads that package's constants).  `pos_dev`
+ * [n][3] FP32, `out_dev` [n][4] float (16-byte aligned) receives
+ * (K_W, h K_grad) unnormalised.
+ */
+sgrid_status sgrid_probe_integral_field(const sgrid_grid *grid, const float *field_dev, const float *pos_dev,
+                                        int64_t n, float *out_dev, void *stream);
+
 /* ------------------------------------------------------------------------
  * Surrogate network for the near-surface integrals (not in the paper: a
  * learned replacement of the plain integral above).  216 -> 128 -> 128 -> 4

@@ -53,6 +53,7 @@ def lib():
             "orc_gradient": (None, [i32, f64, f64, P, i64, P, P, P, P]),
             "orc_laplacian": (None, [i32, f64, f64, P, i64, P, P]),
             "orc_probe": (None, [i32, f64, f64, P, P, P, P, P, P, i64, P, P, P]),
+            "orc_probe_field": (None, [i32, f64, P, P, P, P, i64, P]),
             "orc_plane_cube_fraction": (f64, [f64, f64, f64, f64]),
             "orc_wendland": (f64, [f64]),
             "orc_wendland_dr": (f64, [f64]),
@@ -208,6 +209,39 @@ def probe(N: int, h: float, B: float, cell_pkg: np.ndarray, phi: np.ndarray, g: 
     return (out, nrm, gout) if with_gradient else (out, nrm)
 
 
+def c_full() -> float:
+    """K_W of a support wholly on the phi > 0 side: the sum of the 32 kernel
+    weights of the dual-cell query (8 taps at sqrt(3)/2 h, 24 at sqrt(11)/2 h)."""
+    return 8.0 * wendland(0.5 * np.sqrt(3.0)) + 24.0 * wendland(0.5 * np.sqrt(11.0))
+
+
+def integral_field(N: int, h: float, B: float, tab: Tables, active: np.ndarray, phi: np.ndarray) -> np.ndarray:
+    """Dense [4][N^3] integral field (Sec. 8): the integrals at every
+    activated point; every other point holds the constants of its cell's
+    far-field package, (0, 0, 0, 0) inside and (c_full, 0, 0, 0) outside."""
+    f = np.zeros((4, N ** 3), dtype=np.float64)
+    M = N // 4
+    p = np.arange(N ** 3, dtype=np.int64)
+    i, j, k = p % N, (p // N) % N, p // (N * N)
+    cell = (i // 4) + M * ((j // 4) + M * (k // 4))
+    f[0] = np.where(np.asarray(tab.cell_pkg)[cell] == 1, c_full(), 0.0)
+    act = np.asarray(active, dtype=np.int64)
+    f[:, act] = integrals(N, h, B, phi, act).T
+    return f
+
+
+def probe_field(N: int, h: float, cell_pkg: np.ndarray, f: np.ndarray, pos: np.ndarray) -> np.ndarray:
+    """Trilinear interpolation of the dense [4][N^3] integral field at the
+    particles ([n][4]), with the probe's corner rules; a particle whose home
+    cell is far field takes that package's constants."""
+    pos = np.ascontiguousarray(pos, dtype=np.float64).reshape(-1, 3)
+    far = np.array([[0.0, 0.0, 0.0, 0.0], [c_full(), 0.0, 0.0, 0.0]])
+    out = np.empty((pos.shape[0], 4), dtype=np.float64)
+    lib().orc_probe_field(N, h, _p(np.ascontiguousarray(cell_pkg, dtype=np.uint32)),
+                          _p(np.ascontiguousarray(f, dtype=np.float64)), _p(far), _p(pos), pos.shape[0], _p(out))
+    return out
+
+
 def plane_cube_fraction(a: float, g) -> float:
     return lib().orc_plane_cube_fraction(float(a), float(g[0]), float(g[1]), float(g[2]))
 
@@ -228,8 +262,11 @@ def support_offsets() -> np.ndarray:
 
 def integrals(N: int, h: float, B: float, phi: np.ndarray, pts: np.ndarray) -> np.ndarray:
     pts = np.ascontiguousarray(pts, dtype=np.int64)
+    phi = np.ascontiguousarray(phi, dtype=np.float64)
+    if phi.shape != (N ** 3,):
+        raise ValueError(f"phi must be the dense field of N^3 = {N ** 3} values")
     out = np.empty((pts.shape[0], 4), dtype=np.float64)
-    lib().orc_integrals(N, h, B, _p(np.ascontiguousarray(phi, dtype=np.float64)), _p(pts),
+    lib().orc_integrals(N, h, B, _p(phi), _p(pts),
                         pts.shape[0], _p(out))
     return out
 

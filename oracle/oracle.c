@@ -272,6 +272,50 @@ void orc_probe(int32_t N, double h, double B, const uint32_t *cell_pkg,
 }
 
 /* ------------------------------------------------------------------------ */
+/* Grid-to-particle coupling of the integral field (Sec. 8): the field        */
+/* (K_W, h K_grad) is interpolated trilinearly to the particle position.      */
+/* Same corner and weight rules as orc_probe; f holds the four components as  */
+/* [4][N^3].  When the particle's home coarse cell is not activated, every    */
+/* corner reads the constants of that far-field package, far[4 * side]        */
+/* (side 0 negative, 1 positive).  out is [n][4].                             */
+/* ------------------------------------------------------------------------ */
+void orc_probe_field(int32_t N, double h, const uint32_t *cell_pkg, const double *f, const double *far,
+                     const double *pos, int64_t n, double *out)
+{
+    const int64_t M = N / 4, NN = (int64_t)N * N * N;
+#pragma omp parallel for schedule(static)
+    for (int64_t q = 0; q < n; ++q) {
+        int64_t i0[3], cc[3];
+        double t[3];
+        for (int a = 0; a < 3; ++a) {
+            double u = pos[3 * q + a] / h;
+            double s = u - 0.5;
+            double fl = floor(s);
+            if (fl < 0) fl = 0;
+            if (fl > N - 2) fl = N - 2;
+            i0[a] = (int64_t)fl;
+            double tt = s - fl;
+            t[a] = tt < 0 ? 0 : (tt > 1 ? 1 : tt);
+            double cf = floor(u / 4.0);
+            if (cf < 0) cf = 0;
+            if (cf > M - 1) cf = M - 1;
+            cc[a] = (int64_t)cf;
+        }
+        uint32_t home = cell_pkg[lin3(cc[0], cc[1], cc[2], M)];
+        for (int c = 0; c < 4; ++c) {
+            if (home < 2) { out[4 * q + c] = far[4 * home + c]; continue; }
+            double v = 0;
+            for (int b = 0; b < 8; ++b) {
+                int bx = b & 1, by = (b >> 1) & 1, bz = (b >> 2) & 1;
+                double w = (bx ? t[0] : 1 - t[0]) * (by ? t[1] : 1 - t[1]) * (bz ? t[2] : 1 - t[2]);
+                v += w * f[c * NN + lin3(i0[0] + bx, i0[1] + by, i0[2] + bz, N)];
+            }
+            out[4 * q + c] = v;
+        }
+    }
+}
+
+/* ------------------------------------------------------------------------ */
 /* Plane-cube volume fraction: the fraction of the cube u in [-1/2, 1/2]^3     */
 /* where a + g.u > 0, written as the iterated integral of the indicator and   */
 /* evaluated exactly: the innermost length is piecewise linear in the middle  */

@@ -19,6 +19,7 @@ import torch
 __all__ = [
     "SgridError", "Grid", "load", "build_packages", "fill_far_field", "reinitialize",
     "compute_gradient", "compute_gradient_packed", "probe_particles", "probe_particles_packed", "compute_near_surface_integrals", "set_sweep_config",
+    "compute_integral_field", "probe_integral_field",
     "sequential_update", "compute_laplacian",
     "autotune_sweep", "SWEEP_TUNE_CANDIDATES",
     "Mlp", "gather_windows", "MLP_N_PARAMS", "Batch",
@@ -61,6 +62,8 @@ _SIGNATURES = {
     "sgrid_probe_particles_packed": (ctypes.c_int, [_P, ctypes.c_int, _P, _P, ctypes.c_int64, _P, _P, _P]),
     "sgrid_probe_particles": (ctypes.c_int, [_P, ctypes.c_int, _P, _P, _P, ctypes.c_int64, _P, _P, _P]),
     "sgrid_compute_near_surface_integrals": (ctypes.c_int, [_P, _P, _P, _P, _P, _P]),
+    "sgrid_compute_integral_field": (ctypes.c_int, [_P, _P, _P, _P]),
+    "sgrid_probe_integral_field": (ctypes.c_int, [_P, _P, _P, ctypes.c_int64, _P, _P]),
     "sgrid_set_sweep_config": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32]),
     "sgrid_sequential_update": (ctypes.c_int, [_P, ctypes.c_int, _P, ctypes.c_double, _P]),
     "sgrid_compute_laplacian": (ctypes.c_int, [_P, ctypes.c_int, _P, _P, _P]),
@@ -300,6 +303,32 @@ def compute_near_surface_integrals(grid: Grid, phi: torch.Tensor, out: torch.Ten
     mh = model.handle if model is not None else None
     _check(load().sgrid_compute_near_surface_integrals(grid.handle, _dev(phi, "phi"), mh, _dev(out, "out"), nf,
                                                        _stream(stream)))
+
+
+def compute_integral_field(grid: Grid, phi: torch.Tensor, field: torch.Tensor, stream=None):
+    """(K_W, h K_grad) at every point of every activated package, packed
+    [P+2, 64, 4] like compute_gradient_packed; far-field rows hold the
+    one-sided constants."""
+    if phi.dtype != torch.float32 or field.dtype != torch.float32:
+        raise TypeError("the integral field is FP32")
+    if phi.numel() != grid.n_total * 64 or field.numel() != grid.n_total * 256:
+        raise ValueError("phi [P+2, 64] and field [P+2, 64, 4] expected")
+    _check(load().sgrid_compute_integral_field(grid.handle, _dev(phi, "phi"), _dev(field, "field"),
+                                               _stream(stream)))
+
+
+def probe_integral_field(grid: Grid, field: torch.Tensor, pos: torch.Tensor, out: torch.Tensor, stream=None):
+    """Trilinear interpolation of the integral field at particles: out [n, 4]."""
+    n = pos.numel() // 3
+    if pos.numel() != 3 * n or out.numel() != 4 * n:
+        raise ValueError("pos [n,3] and out [n,4] expected")
+    for t in (field, pos, out):
+        if t.dtype != torch.float32:
+            raise TypeError("the integral field probe is FP32")
+    if field.numel() != grid.n_total * 256:
+        raise ValueError("field must be [P+2, 64, 4]")
+    _check(load().sgrid_probe_integral_field(grid.handle, _dev(field, "field"), _dev(pos, "pos"), n,
+                                             _dev(out, "out"), _stream(stream)))
 
 
 MLP_N_PARAMS = 44804

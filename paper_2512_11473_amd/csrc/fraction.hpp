@@ -62,11 +62,11 @@ namespace sgrid {
 // Wendland C2 kernel in units of h (smoothing length h, support 2h): the two
 // tap distances of the dual-cell query are sqrt(3)/2 (8 taps) and sqrt(11)/2
 // (24 taps).  W(r) and W'(r) / r.
-__device__ __forceinline__ double wendland_u(double r) {
+__host__ __device__ __forceinline__ double wendland_u(double r) {
     const double e = 1.0 - 0.5 * r;
     return 21.0 / (16.0 * M_PI) * e * e * e * e * (1.0 + 2.0 * r);
 }
-__device__ __forceinline__ double wendland_dr_over_r_u(double r) {
+__host__ __device__ __forceinline__ double wendland_dr_over_r_u(double r) {
     const double e = 1.0 - 0.5 * r;
     return -105.0 / (16.0 * M_PI) * e * e * e;
 }

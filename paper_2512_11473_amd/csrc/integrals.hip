@@ -21,18 +21,23 @@ constexpr int kVolN = kVol * kVol * kVol;
 using sgrid::wendland_u;
 using sgrid::wendland_dr_over_r_u;
 
+// FIELD = false: the core packages of `list`, output [4][n * 64] in list
+// order.  FIELD = true: every activated package (ids 2 .. n + 1, `list`
+// unused), output one float4 (K_W, h K_grad) per data point in the packed
+// blocked layout of the probe fields.
+template <bool FIELD>
 __global__ __launch_bounds__(256) void integrals_plain_kernel(const float *__restrict__ phi,
                                                               const uint32_t *__restrict__ nbr,
-                                                              const uint32_t *__restrict__ core_list,
-                                                              int64_t n_core, float inv_h, float inv_2h,
+                                                              const uint32_t *__restrict__ list,
+                                                              int64_t n, float inv_h, float inv_2h,
                                                               float *__restrict__ out) {
     __shared__ float s_phi[4][kWinN];
     __shared__ float s_v[4][kVolN];
     __shared__ uint32_t s_ids[4][27];
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int64_t ci = (int64_t)blockIdx.x * 4 + w;
-    const bool live = ci < n_core;
-    const int64_t p = live ? core_list[ci] : 0;
+    const bool live = ci < n;
+    const int64_t p = live ? (FIELD ? ci + 2 : (int64_t)list[ci]) : 0;
     if (live && lane < 27) s_ids[w][lane] = nbr[p * 27 + lane];
     __syncthreads();
     if (live) sgrid::stage_window_part<64>(phi, s_ids[w], lane, s_phi[w]);
@@ -69,11 +74,25 @@ __global__ __launch_bounds__(256) void integrals_plain_kernel(const float *__res
                 ky += Dt * dy * vv;
                 kz += Dt * dz * vv;
             }
-    const int64_t o = ci * 64 + lane, stride = n_core * 64;
-    out[o] = kw;
-    out[stride + o] = kx;
-    out[2 * stride + o] = ky;
-    out[3 * stride + o] = kz;
+    if (FIELD) {
+        reinterpret_cast<float4 *>(out)[p * 64 + blocked_index(i, j, k)] = make_float4(kw, kx, ky, kz);
+    } else {
+        const int64_t o = ci * 64 + lane, stride = n * 64;
+        out[o] = kw;
+        out[stride + o] = kx;
+        out[2 * stride + o] = ky;
+        out[3 * stride + o] = kz;
+    }
+}
+
+// Rows 0 and 1 of the integral field: the far-field packages, whose points
+// have every cell of their support on one side of the surface.  Negative far
+// field (inside): all cut fractions 0, so (0, 0, 0, 0); positive far field:
+// all fractions 1, so K_W = the full kernel sum c_full and, by the symmetry of
+// the 32 taps about the query point, K_grad = 0.
+__global__ __launch_bounds__(128) void integral_far_rows_kernel(float4 *__restrict__ field, float c_full) {
+    const int t = threadIdx.x;
+    field[t] = t < 64 ? make_float4(0.f, 0.f, 0.f, 0.f) : make_float4(c_full, 0.f, 0.f, 0.f);
 }
 
 }  // namespace
@@ -83,8 +102,8 @@ namespace sgrid {
 sgrid_status launch_integrals_plain(const sgrid_grid *g, const float *phi, float *out, hipStream_t st) {
     if (g->n_core == 0) return SGRID_OK;
     const int64_t nb = (g->n_core + 3) / 4;
-    hipLaunchKernelGGL(integrals_plain_kernel, dim3((unsigned)nb), dim3(256), 0, st, phi, g->nbr, g->core_list,
-                       g->n_core, (float)(1.0 / g->h), (float)(0.5 / g->h), out);
+    hipLaunchKernelGGL(integrals_plain_kernel<false>, dim3((unsigned)nb), dim3(256), 0, st, phi, g->nbr,
+                       g->core_list, g->n_core, (float)(1.0 / g->h), (float)(0.5 / g->h), out);
     SG_CHECK_LAUNCH("plain integrals");
     return SGRID_OK;
 }
@@ -106,4 +125,24 @@ extern "C" sgrid_status sgrid_compute_near_surface_integrals(const sgrid_grid *g
     if (model) return sgrid::integrals_learned(g, phi, model, out, n_fallback, st);
     if (n_fallback) SG_CHECK_HIP(hipMemsetAsync(n_fallback, 0, sizeof(uint32_t), st));
     return sgrid::launch_integrals_plain(g, phi, out, st);
+}
+
+extern "C" sgrid_status sgrid_compute_integral_field(const sgrid_grid *g, const float *phi, float *field,
+                                                     void *stream) {
+    sgrid::clear_error();
+    SG_REQUIRE(g != nullptr, "grid is NULL");
+    SG_REQUIRE(phi != nullptr && field != nullptr, "phi or field is NULL");
+    SG_REQUIRE(phi != field, "phi and field must be distinct buffers");
+    SG_REQUIRE(sg_aligned(phi, 16) && sg_aligned(field, 16), "phi / field must be 16-byte aligned");
+    hipStream_t st = sg_stream(stream);
+    const double c_full = 8.0 * sgrid::wendland_u(0.5 * sqrt(3.0)) + 24.0 * sgrid::wendland_u(0.5 * sqrt(11.0));
+    hipLaunchKernelGGL(integral_far_rows_kernel, dim3(1), dim3(128), 0, st, (float4 *)field, (float)c_full);
+    SG_CHECK_LAUNCH("integral field far-field rows");
+    if (g->P == 0) return SGRID_OK;
+    const int64_t nb = (g->P + 3) / 4;
+    SG_REQUIRE(nb <= kMaxGrid, "too many packages for one launch");
+    hipLaunchKernelGGL(integrals_plain_kernel<true>, dim3((unsigned)nb), dim3(256), 0, st, phi, g->nbr,
+                       (const uint32_t *)nullptr, g->P, (float)(1.0 / g->h), (float)(0.5 / g->h), field);
+    SG_CHECK_LAUNCH("integral field");
+    return SGRID_OK;
 }

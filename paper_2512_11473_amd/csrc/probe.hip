@@ -80,7 +80,8 @@ struct RankMap {
     }
 };
 
-// Trilinear blend of phi and g over the eight corners, then the normal.  The
+// Trilinear blend of the four components (phi and g, or an integral field)
+// over the eight corners.  The
 // corners' packages are the home cell's package and, for corners past a face
 // of the home cell, those of the neighbouring cells (the index shift of
 // Sec. 5.2 per axis: slot = (s + 4) / 4, data = s + 4 - 4 slot).  A particle
@@ -89,7 +90,7 @@ struct RankMap {
 // before any is used, then all corner reads.
 template <typename T, bool PACKED>
 __device__ __forceinline__ void blend(const Corner<T, PACKED> &field, const RankMap &rm, const int cc[3],
-                                      const int sh[3], const T t[3], T &v, T n[3]) {
+                                      const int sh[3], const T t[3], T &v, T &gx, T &gy, T &gz) {
     const int M = rm.M;
     uint4 e[8];
     int cx[8];
@@ -121,7 +122,9 @@ __device__ __forceinline__ void blend(const Corner<T, PACKED> &field, const Rank
         pk[b] = home < 2u ? home : own;
     }
     v = T(0);
-    T gx = T(0), gy = T(0), gz = T(0);
+    gx = T(0);
+    gy = T(0);
+    gz = T(0);
 #pragma unroll
     for (int b = 0; b < 8; ++b) {
         const int bx = b & 1, by = (b >> 1) & 1, bz = (b >> 2) & 1;
@@ -134,11 +137,6 @@ __device__ __forceinline__ void blend(const Corner<T, PACKED> &field, const Rank
         gy += w * cy_;
         gz += w * cz_;
     }
-    const T gn = sqrt(gx * gx + gy * gy + gz * gz);
-    const T inv = gn > T(0) ? T(1) / gn : T(0);
-    n[0] = gx * inv;
-    n[1] = gy * inv;
-    n[2] = gz * inv;
 }
 
 template <typename T, bool PACKED>
@@ -148,13 +146,30 @@ __global__ __launch_bounds__(256) void probe_kernel(Corner<T, PACKED> field, Ran
     const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (q >= n) return;
     int cc[3], sh[3];
-    T t[3], v, nr[3];
+    T t[3], v, gx, gy, gz;
     locate(pos + 3 * q, rm.M, inv_h, cc, sh, t);
-    blend(field, rm, cc, sh, t, v, nr);
+    blend(field, rm, cc, sh, t, v, gx, gy, gz);
+    const T gn = sqrt(gx * gx + gy * gy + gz * gz);
+    const T inv = gn > T(0) ? T(1) / gn : T(0);
     phi_out[q] = v;
-    nrm_out[3 * q] = nr[0];
-    nrm_out[3 * q + 1] = nr[1];
-    nrm_out[3 * q + 2] = nr[2];
+    nrm_out[3 * q] = gx * inv;
+    nrm_out[3 * q + 1] = gy * inv;
+    nrm_out[3 * q + 2] = gz * inv;
+}
+
+// The integral field (K_W, h K_grad) at the particles (Sec. 8: the field is
+// interpolated trilinearly to the particle position and drives it as a
+// surface force): the same blend, no normalisation, one float4 per particle.
+__global__ __launch_bounds__(256) void probe_field_kernel(Corner<float, true> field, RankMap rm,
+                                                          const float *__restrict__ pos, int64_t n,
+                                                          float4 *__restrict__ out, float inv_h) {
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= n) return;
+    int cc[3], sh[3];
+    float t[3], v, gx, gy, gz;
+    locate(pos + 3 * q, rm.M, inv_h, cc, sh, t);
+    blend(field, rm, cc, sh, t, v, gx, gy, gz);
+    out[q] = make_float4(v, gx, gy, gz);
 }
 
 }  // namespace
@@ -200,4 +215,24 @@ extern "C" sgrid_status sgrid_probe_particles_packed(const sgrid_grid *g, sgrid_
                                                      const void *pos, int64_t n, void *phi_out, void *normal_out,
                                                      void *stream) {
     return probe_entry<true>(g, dtype, packed, nullptr, pos, n, phi_out, normal_out, stream);
+}
+
+extern "C" sgrid_status sgrid_probe_integral_field(const sgrid_grid *g, const float *field, const float *pos,
+                                                   int64_t n, float *out, void *stream) {
+    sgrid::clear_error();
+    SG_REQUIRE(g != nullptr, "grid is NULL");
+    SG_REQUIRE(n >= 0, "n must be >= 0");
+    if (n == 0) return SGRID_OK;
+    SG_REQUIRE(field && pos && out, "NULL field or particle array");
+    SG_REQUIRE(sg_aligned(field, 16) && sg_aligned(out, 16), "field / out must be 16-byte aligned");
+    SG_REQUIRE(sg_aligned(pos, 4), "pos must be 4-byte aligned");
+    hipStream_t st = sg_stream(stream);
+    const int64_t nb = (n + 255) / 256;
+    SG_REQUIRE(nb <= kMaxGrid, "too many particles for one launch");
+    const RankMap rm{g->rank_map, g->M, g->W32};
+    const Corner<float, true> f{field, nullptr, 0};
+    hipLaunchKernelGGL(probe_field_kernel, dim3((unsigned)nb), dim3(256), 0, st, f, rm, pos, n, (float4 *)out,
+                       (float)(1.0 / g->h));
+    SG_CHECK_LAUNCH("integral field probe");
+    return SGRID_OK;
 }
