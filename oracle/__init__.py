@@ -124,6 +124,36 @@ def build_tables(M: int, d: np.ndarray, lc: Optional[float] = None) -> Tables:
     return Tables(M, t, cell_pkg, pkg_cell, pkg_type, nbr)
 
 
+def refine_tables(M: int, d: np.ndarray, child_d: np.ndarray) -> Tables:
+    """The next layer of the multi-resolution construction (Sec. 7, Sec. 7.1
+    step 1): the layer of doubled resolution (2M)^3 whose distances are
+    evaluated only in the cells covered by core cells of the layer with
+    distances d[M^3].
+    child_d[i, b] is the distance at child b = bx + 2 by + 4 bz of the i-th
+    core cell in ascending cell order.  Every other fine cell carries its
+    parent's distance, which is at least the parent's cell size in magnitude
+    (the parent is not core) and so never tags it core, and gives it the
+    parent's sign.  Then tagging, numbering and neighbours as for any layer."""
+    d = np.ascontiguousarray(d, dtype=np.float32)
+    child_d = np.ascontiguousarray(child_d, dtype=np.float32).reshape(-1, 8)
+    Mf = 2 * M
+    t = classify(M, 1.0 / M, d)
+    core = np.nonzero(t == 1)[0]
+    if core.shape[0] != child_d.shape[0]:
+        raise ValueError(f"{core.shape[0]} core cells but {child_d.shape[0]} rows of child distances")
+    slot = np.full(M ** 3, -1, dtype=np.int64)
+    slot[core] = np.arange(core.shape[0])
+    f = np.arange(Mf ** 3, dtype=np.int64)
+    fi, fj, fk = f % Mf, (f // Mf) % Mf, f // (Mf * Mf)
+    parent = (fi // 2) + M * ((fj // 2) + M * (fk // 2))
+    child = (fi & 1) + 2 * (fj & 1) + 4 * (fk & 1)
+    sp = slot[parent]
+    under = sp >= 0
+    d_f = d[parent].copy()
+    d_f[under] = child_d[sp[under], child[under]]
+    return build_tables(Mf, d_f)
+
+
 def index_shift(s: int):
     slot, data = ctypes.c_int32(), ctypes.c_int32()
     lib().orc_index_shift(int(s), ctypes.byref(slot), ctypes.byref(data))

@@ -237,6 +237,29 @@ def coarse_sdf(s: Dict, n_coarse: int, chunk: int = 1 << 20, origin=(0, 0, 0),
     return out
 
 
+def child_sdf(s: Dict, parents: np.ndarray, M: int, chunk: int = 1 << 18) -> np.ndarray:
+    """float32 signed distance at the centres of the eight children of each
+    coarse cell in `parents` (linear indices on the M^3 grid) on the grid of
+    doubled resolution (2M)^3; shape (n, 8), child b = bx + 2 by + 4 bz,
+    evaluated in float64 and rounded once (the values the dense (2M)^3
+    sampling gives at those cells)."""
+    parents = np.asarray(parents, dtype=np.int64)
+    n = parents.shape[0]
+    out = np.empty((n, 8), dtype=np.float32)
+    b = np.arange(8)
+    off = np.stack([b & 1, (b >> 1) & 1, (b >> 2) & 1], axis=1)
+
+    def work(a, e):
+        c = parents[a:e]
+        ijk = np.stack([c % M, (c // M) % M, c // (M * M)], axis=1)
+        f = 2 * ijk[:, None, :] + off[None, :, :]
+        x = (f.reshape(-1, 3).astype(np.float64) + 0.5) / (2 * M)
+        out[a:e] = sdf(s, x).astype(np.float32).reshape(-1, 8)
+
+    _chunked(n, chunk, work)
+    return out
+
+
 def fine_points(lin: np.ndarray, N: int) -> np.ndarray:
     """Positions ((i, j, k) + 1/2) h of fine linear indices `lin` on an N^3 grid."""
     lin = np.asarray(lin, dtype=np.int64)
