@@ -103,6 +103,26 @@ int32_t sgrid_version(void);
 sgrid_status sgrid_build_packages(const sgrid_desc *desc, const float *coarse_sdf_dev,
                                   void *stream, sgrid_grid **out);
 
+/*
+ * The next layer of the multi-resolution construction (Sec. 7: layers of
+ * successively doubled resolution, each initialised from the one before;
+ * Sec. 7.1 step 1: a finer layer evaluates distances only in the cells that
+ * the coarser layer's core cells cover).  The new grid has 2M cells per axis
+ * and spacing h / 2.  `child_sdf_dev` [n_core][8] (FP32, device) holds the
+ * signed distance at the centres of the eight children of each core cell of
+ * `coarse`, rows in core_list order, child b = bx + 2 by + 4 bz.  A fine cell
+ * under a core parent is tagged with its own distance; any other fine cell
+ * is not core and takes its parent's sign (the parent's distance is at least
+ * the parent cell size).  Then inner tagging, numbering, neighbours and the
+ * sweep order as for sgrid_build_packages; for a signed distance function
+ * the tables equal those of sgrid_build_packages on the dense (2M)^3
+ * sampling.  `coarse` must stay alive until the call returns (it is only
+ * read).  Synchronises `stream` once.  child_sdf_dev may be NULL when
+ * `coarse` has no core cell.
+ */
+sgrid_status sgrid_build_packages_refined(const sgrid_grid *coarse, const float *child_sdf_dev, void *stream,
+                                          sgrid_grid **out);
+
 /* Sizes and device views of the tables (valid until sgrid_destroy). */
 sgrid_status sgrid_get_info(const sgrid_grid *grid, sgrid_info *out);
 

@@ -124,7 +124,7 @@ def build_tables(M: int, d: np.ndarray, lc: Optional[float] = None) -> Tables:
     return Tables(M, t, cell_pkg, pkg_cell, pkg_type, nbr)
 
 
-def refine_tables(M: int, d: np.ndarray, child_d: np.ndarray) -> Tables:
+def refine_tables(M: int, d: np.ndarray, child_d: np.ndarray):
     """The next layer of the multi-resolution construction (Sec. 7, Sec. 7.1
     step 1): the layer of doubled resolution (2M)^3 whose distances are
     evaluated only in the cells covered by core cells of the layer with
@@ -133,7 +133,9 @@ def refine_tables(M: int, d: np.ndarray, child_d: np.ndarray) -> Tables:
     core cell in ascending cell order.  Every other fine cell carries its
     parent's distance, which is at least the parent's cell size in magnitude
     (the parent is not core) and so never tags it core, and gives it the
-    parent's sign.  Then tagging, numbering and neighbours as for any layer."""
+    parent's sign.  Then tagging, numbering and neighbours as for any layer.
+    Returns the tables and the distances the layer holds per cell (the input
+    of the next refinement)."""
     d = np.ascontiguousarray(d, dtype=np.float32)
     child_d = np.ascontiguousarray(child_d, dtype=np.float32).reshape(-1, 8)
     Mf = 2 * M
@@ -148,10 +150,11 @@ def refine_tables(M: int, d: np.ndarray, child_d: np.ndarray) -> Tables:
     parent = (fi // 2) + M * ((fj // 2) + M * (fk // 2))
     child = (fi & 1) + 2 * (fj & 1) + 4 * (fk & 1)
     sp = slot[parent]
+    del fi, fj, fk
     under = sp >= 0
-    d_f = d[parent].copy()
+    d_f = d[parent]
     d_f[under] = child_d[sp[under], child[under]]
-    return build_tables(Mf, d_f)
+    return build_tables(Mf, d_f), d_f
 
 
 def index_shift(s: int):

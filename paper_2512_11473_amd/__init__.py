@@ -17,7 +17,7 @@ from typing import Optional
 import torch
 
 __all__ = [
-    "SgridError", "Grid", "load", "build_packages", "fill_far_field", "reinitialize",
+    "SgridError", "Grid", "load", "build_packages", "build_packages_refined", "fill_far_field", "reinitialize",
     "compute_gradient", "compute_gradient_packed", "probe_particles", "probe_particles_packed", "compute_near_surface_integrals", "set_sweep_config",
     "compute_integral_field", "probe_integral_field",
     "sequential_update", "compute_laplacian",
@@ -53,6 +53,7 @@ _SIGNATURES = {
     "sgrid_last_error": (ctypes.c_char_p, []),
     "sgrid_version": (ctypes.c_int32, []),
     "sgrid_build_packages": (ctypes.c_int, [ctypes.POINTER(_Desc), _P, _P, ctypes.POINTER(_P)]),
+    "sgrid_build_packages_refined": (ctypes.c_int, [_P, _P, _P, ctypes.POINTER(_P)]),
     "sgrid_get_info": (ctypes.c_int, [_P, ctypes.POINTER(_Info)]),
     "sgrid_destroy": (ctypes.c_int, [_P]),
     "sgrid_fill_far_field": (ctypes.c_int, [_P, ctypes.c_int, _P, _P]),
@@ -218,6 +219,21 @@ def build_packages(coarse_sdf: torch.Tensor, h: float, stream=None) -> Grid:
     out = ctypes.c_void_p()
     _check(load().sgrid_build_packages(ctypes.byref(desc), _dev(coarse_sdf, "coarse_sdf"), _stream(stream),
                                        ctypes.byref(out)))
+    return Grid(out)
+
+
+def build_packages_refined(coarse: Grid, child_sdf: Optional[torch.Tensor], stream=None) -> Grid:
+    """The layer of doubled resolution built from `coarse`: child_sdf holds
+    the distances at the eight children of each core cell of `coarse`
+    (float32 [n_core, 8], core_list order, child bx + 2 by + 4 bz)."""
+    if coarse.n_core > 0:
+        if child_sdf is None or child_sdf.dtype != torch.float32 or child_sdf.numel() != 8 * coarse.n_core:
+            raise ValueError(f"child_sdf must be float32 [{coarse.n_core}, 8]")
+        ptr = _dev(child_sdf, "child_sdf")
+    else:
+        ptr = None
+    out = ctypes.c_void_p()
+    _check(load().sgrid_build_packages_refined(coarse.handle, ptr, _stream(stream), ctypes.byref(out)))
     return Grid(out)
 
 

@@ -580,6 +580,59 @@ __global__ __launch_bounds__(256) void nbr_kernel(const uint32_t *__restrict__ c
     }
 }
 
+// Multi-resolution layers (Sec. 7, Sec. 7.1 step 1): the layer of doubled
+// resolution evaluates distances only in the cells its parent layer's core
+// cells cover.  core_slot[id] = position of core package `id` in the parent's
+// core list (the rows of the caller's child distances).
+__global__ __launch_bounds__(256) void core_slot_kernel(const uint32_t *__restrict__ core_list, int64_t n_core,
+                                                        uint32_t *__restrict__ core_slot) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n_core) core_slot[core_list[i]] = (uint32_t)i;
+}
+
+// Core and sign bits of the refined layer, one wavefront per 64-cell word as
+// in bits_kernel.  A fine cell under a core parent takes its own distance
+// (child b = bx + 2 by + 4 bz of the parent's row); any other cell takes the
+// parent's sign from the parent layer's rank map and is not core (the parent
+// is not core, so its distance is at least the parent cell size, twice the
+// fine one).
+__global__ __launch_bounds__(256) void refine_bits_kernel(const uint4 *__restrict__ rank_map, int W32c,
+                                                          const uint8_t *__restrict__ pkg_type,
+                                                          const uint32_t *__restrict__ core_slot,
+                                                          const float *__restrict__ child_d, int Mc, int W,
+                                                          int64_t n_words, double lc, uint64_t *__restrict__ core,
+                                                          uint64_t *__restrict__ neg) {
+    const int64_t w = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (w >= n_words) return;   // whole wavefronts
+    const int lane = threadIdx.x & 63;
+    const int Mf = 2 * Mc;
+    const int64_t r = w / W;
+    const int x = (int)(w - r * W) * 64 + lane;
+    const int y = (int)(r % Mf), z = (int)(r / Mf);
+    bool is_core = false, is_neg = false;
+    if (x < Mf) {
+        const int px = x >> 1, py = y >> 1, pz = z >> 1;
+        const uint4 e = rank_map[((int64_t)py + (int64_t)Mc * pz) * W32c + (px >> 5)];
+        const uint32_t bit = 1u << (px & 31);
+        is_neg = (e.y & bit) != 0u;
+        if (e.x & bit) {
+            const uint32_t id = 2u + e.z + (uint32_t)__popc(e.x & (bit - 1u));
+            if (pkg_type[id] == 1) {
+                const int b = (x & 1) + 2 * (y & 1) + 4 * (z & 1);
+                const float v = child_d[(int64_t)core_slot[id] * 8 + b];
+                is_core = fabs((double)v) < lc;
+                is_neg = v < 0.0f;
+            }
+        }
+    }
+    const uint64_t bc = __ballot(is_core);
+    const uint64_t bn = __ballot(is_neg);
+    if (lane == 0) {
+        core[w] = bc;
+        neg[w] = bn;
+    }
+}
+
 void free_grid(sgrid_grid *g) {
     if (!g) return;
     void *ptrs[] = {g->cell_pkg, g->pkg_cell, g->pkg_type, g->nbr,  g->face, g->core_list,
@@ -616,52 +669,55 @@ uint64_t *pinned_totals() {
         }                                                                             \
     } while (0)
 
-extern "C" sgrid_status sgrid_build_packages(const sgrid_desc *desc, const float *coarse_sdf, void *stream,
-                                             sgrid_grid **out) {
-    sgrid::clear_error();
-    SG_REQUIRE(out != nullptr, "out is NULL");
-    *out = nullptr;
-    SG_REQUIRE(desc != nullptr, "desc is NULL");
-    SG_REQUIRE(coarse_sdf != nullptr, "coarse_sdf is NULL");
-    SG_REQUIRE(sg_aligned(coarse_sdf, 4), "coarse_sdf is not 4-byte aligned");
-    SG_REQUIRE(desc->n_coarse >= 1, "n_coarse must be >= 1 (got %d)", desc->n_coarse);
-    SG_REQUIRE(desc->h > 0.0 && desc->h < 1e30, "h must be positive and finite");
-    const int64_t M = desc->n_coarse;
+namespace {
+
+// A new grid of M^3 cells at spacing h with its build workspace: three
+// bitmaps (core, negative sign, activated), the per-group counts, the scan's
+// block sums and the totals.
+struct BuildWs {
+    int64_t W, n_words, n_groups;
+    uint64_t *core_bits, *neg_bits, *act_bits, *totals;
+    uint32_t *ca, *cc, *part;
+};
+
+sgrid_status new_grid(int64_t M, double h, sgrid_grid **out, BuildWs &ws) {
     const int64_t n_cells = M * M * M;
     if (n_cells + 2 > (int64_t)0xFFFFFFFFll || (n_cells + 2) * 64 > ((int64_t)1 << 40)) {
         sgrid::set_error("n_coarse = %lld gives %lld coarse cells, beyond the 32-bit package ids",
                          (long long)M, (long long)n_cells);
         return SGRID_E_CAPACITY;
     }
-    hipStream_t st = sg_stream(stream);
     sgrid_grid *g = new sgrid_grid();
     g->M = (int32_t)M;
-    g->h = desc->h;
+    g->h = h;
     SG_HIP_OR_FREE(hipGetDevice(&g->device));
-
-    // workspace: three bitmaps (core, negative sign, activated), the per-group
-    // counts, the scan's block sums and the totals
-    const int64_t W = (M + 63) / 64;
-    const int64_t n_words = M * M * W;
-    const int64_t n_groups = (n_words + 15) / 16;
-    const int64_t n_sblocks = (n_groups + kScanBlock - 1) / kScanBlock;
-    const size_t ws_bits = ((size_t)n_words * 8 + 255) / 256 * 256;
-    const size_t ws_counts = ((size_t)n_groups * 4 + 255) / 256 * 256;
+    ws.W = (M + 63) / 64;
+    ws.n_words = M * M * ws.W;
+    ws.n_groups = (ws.n_words + 15) / 16;
+    const int64_t n_sblocks = (ws.n_groups + kScanBlock - 1) / kScanBlock;
+    const size_t ws_bits = ((size_t)ws.n_words * 8 + 255) / 256 * 256;
+    const size_t ws_counts = ((size_t)ws.n_groups * 4 + 255) / 256 * 256;
     const size_t ws_part = ((size_t)n_sblocks * 8 + 255) / 256 * 256;
     SG_ALLOC(g->workspace, 3 * ws_bits + 2 * ws_counts + ws_part + 256, "build workspace");
-    uint64_t *core_bits = (uint64_t *)g->workspace;
-    uint64_t *neg_bits = (uint64_t *)((uint8_t *)core_bits + ws_bits);
-    uint64_t *act_bits = (uint64_t *)((uint8_t *)neg_bits + ws_bits);
-    uint32_t *ca = (uint32_t *)((uint8_t *)act_bits + ws_bits);
-    uint32_t *cc = (uint32_t *)((uint8_t *)ca + ws_counts);
-    uint32_t *part = (uint32_t *)((uint8_t *)cc + ws_counts);
-    uint64_t *totals = (uint64_t *)((uint8_t *)part + ws_part);
+    ws.core_bits = (uint64_t *)g->workspace;
+    ws.neg_bits = (uint64_t *)((uint8_t *)ws.core_bits + ws_bits);
+    ws.act_bits = (uint64_t *)((uint8_t *)ws.neg_bits + ws_bits);
+    ws.ca = (uint32_t *)((uint8_t *)ws.act_bits + ws_bits);
+    ws.cc = (uint32_t *)((uint8_t *)ws.ca + ws_counts);
+    ws.part = (uint32_t *)((uint8_t *)ws.cc + ws_counts);
+    ws.totals = (uint64_t *)((uint8_t *)ws.part + ws_part);
     SG_ALLOC(g->cell_pkg, n_cells * 4, "cell_pkg");
+    *out = g;
+    return SGRID_OK;
+}
 
-    const double lc = 4.0 * desc->h;
-    hipLaunchKernelGGL(bits_kernel, dim3((unsigned)((n_words + 3) / 4)), dim3(256), 0, st, coarse_sdf, (int)M, (int)W,
-                       n_words, lc, core_bits, neg_bits);
-    SG_HIP_OR_FREE(hipGetLastError());
+// Everything after the core and sign bitmaps: dilation, numbering (one host
+// synchronisation learns P), tables, neighbours, the Morton worklist and the
+// worklist face rows.  Frees the grid on failure.
+sgrid_status finish_grid(sgrid_grid *g, const BuildWs &ws, hipStream_t st) {
+    const int64_t M = g->M, W = ws.W, n_words = ws.n_words, n_groups = ws.n_groups;
+    uint64_t *core_bits = ws.core_bits, *neg_bits = ws.neg_bits, *act_bits = ws.act_bits, *totals = ws.totals;
+    uint32_t *ca = ws.ca, *cc = ws.cc, *part = ws.part;
     hipLaunchKernelGGL(dilate_kernel, dim3((unsigned)((n_words + 255) / 256)), dim3(256), 0, st, core_bits, (int)M,
                        (int)W, n_words, act_bits, ca, cc);
     SG_HIP_OR_FREE(hipGetLastError());
@@ -733,6 +789,67 @@ extern "C" sgrid_status sgrid_build_packages(const sgrid_desc *desc, const float
         }
         g->wpos = wpos;
     }
+    return SGRID_OK;
+}
+
+}  // namespace
+
+extern "C" sgrid_status sgrid_build_packages(const sgrid_desc *desc, const float *coarse_sdf, void *stream,
+                                             sgrid_grid **out) {
+    sgrid::clear_error();
+    SG_REQUIRE(out != nullptr, "out is NULL");
+    *out = nullptr;
+    SG_REQUIRE(desc != nullptr, "desc is NULL");
+    SG_REQUIRE(coarse_sdf != nullptr, "coarse_sdf is NULL");
+    SG_REQUIRE(sg_aligned(coarse_sdf, 4), "coarse_sdf is not 4-byte aligned");
+    SG_REQUIRE(desc->n_coarse >= 1, "n_coarse must be >= 1 (got %d)", desc->n_coarse);
+    SG_REQUIRE(desc->h > 0.0 && desc->h < 1e30, "h must be positive and finite");
+    const int64_t M = desc->n_coarse;
+    hipStream_t st = sg_stream(stream);
+    sgrid_grid *g = nullptr;
+    BuildWs ws;
+    sgrid_status s = new_grid(M, desc->h, &g, ws);
+    if (s != SGRID_OK) return s;
+    const double lc = 4.0 * desc->h;
+    hipLaunchKernelGGL(bits_kernel, dim3((unsigned)((ws.n_words + 3) / 4)), dim3(256), 0, st, coarse_sdf, (int)M,
+                       (int)ws.W, ws.n_words, lc, ws.core_bits, ws.neg_bits);
+    SG_HIP_OR_FREE(hipGetLastError());
+    s = finish_grid(g, ws, st);
+    if (s != SGRID_OK) return s;
+    *out = g;
+    return SGRID_OK;
+}
+
+extern "C" sgrid_status sgrid_build_packages_refined(const sgrid_grid *coarse, const float *child_sdf, void *stream,
+                                                     sgrid_grid **out) {
+    sgrid::clear_error();
+    SG_REQUIRE(out != nullptr, "out is NULL");
+    *out = nullptr;
+    SG_REQUIRE(coarse != nullptr, "coarse grid is NULL");
+    SG_REQUIRE(child_sdf != nullptr || coarse->n_core == 0, "child_sdf is NULL");
+    SG_REQUIRE(child_sdf == nullptr || sg_aligned(child_sdf, 4), "child_sdf is not 4-byte aligned");
+    SG_REQUIRE(coarse->M <= (1 << 29), "the coarse grid is too large to refine");
+    const int64_t M = 2 * (int64_t)coarse->M;
+    hipStream_t st = sg_stream(stream);
+    sgrid_grid *g = nullptr;
+    BuildWs ws;
+    sgrid_status s = new_grid(M, 0.5 * coarse->h, &g, ws);
+    if (s != SGRID_OK) return s;
+    // the parent's core slots live in the new cell_pkg until it is written
+    static_assert(sizeof(uint32_t) == 4, "");
+    uint32_t *core_slot = g->cell_pkg;   // M^3 >= 8 (P_parent + 2) entries
+    if (coarse->n_core > 0) {
+        hipLaunchKernelGGL(core_slot_kernel, dim3((unsigned)((coarse->n_core + 255) / 256)), dim3(256), 0, st,
+                           coarse->core_list, coarse->n_core, core_slot);
+        SG_HIP_OR_FREE(hipGetLastError());
+    }
+    const double lc = 4.0 * g->h;
+    hipLaunchKernelGGL(refine_bits_kernel, dim3((unsigned)((ws.n_words + 3) / 4)), dim3(256), 0, st, coarse->rank_map,
+                       coarse->W32, coarse->pkg_type, core_slot, child_sdf, coarse->M, (int)ws.W, ws.n_words, lc,
+                       ws.core_bits, ws.neg_bits);
+    SG_HIP_OR_FREE(hipGetLastError());
+    s = finish_grid(g, ws, st);
+    if (s != SGRID_OK) return s;
     *out = g;
     return SGRID_OK;
 }

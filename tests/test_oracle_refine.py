@@ -30,7 +30,7 @@ SHAPES = [
 @pytest.mark.parametrize("name,shape,M", SHAPES, ids=[s[0] for s in SHAPES])
 def test_refined_layer_equals_dense_sampling(name, shape, M):
     d, child = _layers(shape, M)
-    ref = oracle.refine_tables(M, d, child)
+    ref, _ = oracle.refine_tables(M, d, child)
     dense = oracle.build_tables(2 * M, synth.coarse_sdf(shape, 2 * M))
     assert ref.n_packages == dense.n_packages > 0
     for a in ("cell_type", "cell_pkg", "pkg_cell", "pkg_type", "nbr"):
@@ -41,7 +41,7 @@ def test_refined_core_lies_under_coarse_core():
     shape = synth.union([synth.sphere((0.3, 0.4, 0.5), 0.15), synth.box((0.62, 0.6, 0.5), (0.2, 0.15, 0.2))])
     M = 16
     d, child = _layers(shape, M, scale=4.0)
-    ref = oracle.refine_tables(M, d, child)
+    ref, _ = oracle.refine_tables(M, d, child)
     coarse = oracle.build_tables(M, d)
     Mf = 2 * M
     f = np.nonzero(ref.cell_type == 1)[0]
@@ -60,7 +60,7 @@ def test_refined_far_field_sign_from_parent():
     shape = synth.sphere((0.5, 0.5, 0.5), 0.3)
     M = 16
     d, child = _layers(shape, M)
-    ref = oracle.refine_tables(M, d, child)
+    ref, _ = oracle.refine_tables(M, d, child)
     Mf = 2 * M
     f = np.arange(Mf ** 3)
     parent = (f % Mf) // 2 + M * (((f // Mf) % Mf) // 2 + M * ((f // (Mf * Mf)) // 2))
