@@ -193,6 +193,49 @@ def cell_sorted(pos, N):
     return np.ascontiguousarray(pos[np.argsort(key, kind="stable")])
 
 
+def multires_build(sg, synth, cfg, dense_grid, log, levels=2, reps=5):
+    """The multi-resolution construction of the same band (Sec. 7): the layer
+    at 1/2^levels of the resolution built from its dense distances, then
+    `levels` refinements that each evaluate distances only under the previous
+    layer's core cells.  The child distances are sampled on the host once
+    (they depend only on the core cells); the timed chain runs from device-
+    resident inputs, like the step's dense build, and must give its tables."""
+    import numpy as np
+    import torch
+    M = cfg["N"] // 4 >> levels
+    d0 = torch.from_numpy(synth.coarse_sdf(cfg["shape"], M)).cuda()
+    h0 = 1.0 / (4 * M)
+    g = sg.build_packages(d0, h0)
+    children = []
+    for lv in range(levels):
+        t = g.tables()
+        cells = t["pkg_cell"].cpu().numpy().view(np.uint32)[t["core_list"].cpu().numpy().astype(np.int64)]
+        ch = torch.from_numpy(synth.child_sdf(cfg["shape"], cells.astype(np.int64), M << lv)).cuda()
+        children.append(ch)
+        g_next = sg.build_packages_refined(g, ch)
+        g.destroy()
+        g = g_next
+    same = g.n_packages == dense_grid.n_packages and all(
+        torch.equal(a, b) for a, b in zip(g.tables().values(), dense_grid.tables().values()))
+    g.destroy()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        g = sg.build_packages(d0, h0)
+        for ch in children:
+            g_next = sg.build_packages_refined(g, ch)
+            g.destroy()
+            g = g_next
+        g.destroy()
+    torch.cuda.synchronize()
+    ms = 1e3 * (time.perf_counter() - t0) / reps
+    in_bytes = 4 * (M ** 3 + sum(int(c.numel()) for c in children))
+    log(f"multi-resolution build: {ms:.2f} ms, tables equal to the dense build: {same}")
+    return {"levels": levels + 1, "coarsest_n_coarse": M, "ms": ms, "tables_equal_dense": bool(same),
+            "distance_input_bytes": in_bytes, "dense_input_bytes": 4 * (cfg["N"] // 4) ** 3,
+            "note": "wall time of the whole chain (each build synchronises once to learn P), measured outside the step"}
+
+
 def bench_single(args, log):
     import numpy as np
     import torch
@@ -296,6 +339,7 @@ def bench_single(args, log):
     field_ms, fprobe_ms = e0.elapsed_time(e1) / 5, e1.elapsed_time(e2) / 5
     g.destroy()
     del field, fout
+    multires = multires_build(sg, synth, cfg, wl.grid, log)
 
     K = args.steps
     ms_step = 1e3 * total_s / K
@@ -329,6 +373,7 @@ def bench_single(args, log):
                       "cell_sorted_GBps": probe_bytes / (probe_sorted_ms * 1e-3) / 1e9,
                       "cell_sorted_frac": probe_bytes / (probe_sorted_ms * 1e-3) / 1e9 / HBM_PEAK_GBS},
         "integral_cells_per_s": n_core * 64 / (acc["integ"] / K * 1e-3),
+        "multires_build": multires,
         "integral_field": {"field_ms": field_ms, "field_points_per_s": 64 * P / (field_ms * 1e-3),
                            "probe_ms": fprobe_ms, "probes_per_s": n_part / (fprobe_ms * 1e-3),
                            "note": "(K_W, h K_grad) at every activated point, then interpolated to the particles "
