@@ -46,6 +46,7 @@ def lib():
         i32, i64, f64 = ctypes.c_int32, ctypes.c_int64, ctypes.c_double
         sig = {
             "orc_classify": (None, [i32, f64, P, P]),
+            "orc_correct_signs": (i32, [i32, f64, P, P]),
             "orc_number": (i64, [i32, P, P, P, P, P]),
             "orc_neighbours": (None, [i32, P, P, i64, P]),
             "orc_index_shift": (None, [i32, P, P]),
@@ -89,6 +90,16 @@ def classify(M: int, lc: float, d: np.ndarray) -> np.ndarray:
     t = np.zeros(M ** 3, dtype=np.uint8)
     lib().orc_classify(M, lc, _p(d), _p(t))
     return t
+
+
+def correct_signs(M: int, d: np.ndarray, lc: Optional[float] = None):
+    """Sign correction of coarse distances d[M^3] by diffusion from the core
+    cells (Sec. 7.2, coarse step); returns (corrected d, rounds)."""
+    d = np.ascontiguousarray(d, dtype=np.float32)
+    lc = 1.0 / M if lc is None else float(lc)
+    out = np.empty_like(d)
+    rounds = int(lib().orc_correct_signs(M, lc, _p(d), _p(out)))
+    return out, rounds
 
 
 @dataclass

@@ -66,6 +66,64 @@ void orc_classify(int32_t M, double lc, const float *d, uint8_t *type)
 }
 
 /* ------------------------------------------------------------------------ */
+/* Consistency (sign) correction of a layer's distances (Sec. 7.2), the coarse */
+/* step on the mesh cells: only the signs of cells near the surface (core,    */
+/* |d| < lc) are used as given; every other cell gets its sign by diffusion   */
+/* from them.  Rounds of simultaneous updates: a cell without a sign yet      */
+/* takes one when a face neighbour has one, positive if any such neighbour is */
+/* positive, else negative; rounds repeat until one changes nothing.  Output: */
+/* core cells keep d; cells that received a sign get |d| with it; cells no    */
+/* diffusion reaches keep d.  Returns the number of rounds that changed a    */
+/* cell.                                                                      */
+/* ------------------------------------------------------------------------ */
+int32_t orc_correct_signs(int32_t M, double lc, const float *d, float *out)
+{
+    const int64_t n = (int64_t)M * M * M;
+    uint8_t *state = (uint8_t *)malloc((size_t)n);    /* 0 no sign, 1 negative, 2 positive */
+    uint8_t *next = (uint8_t *)malloc((size_t)n);
+    for (int64_t c = 0; c < n; ++c)
+        state[c] = fabs((double)d[c]) < lc ? (d[c] < 0.0f ? 1 : 2) : 0;
+    int32_t rounds = 0;
+    for (;;) {
+        int changed = 0;
+#pragma omp parallel for schedule(static) reduction(| : changed)
+        for (int64_t z = 0; z < M; ++z)
+            for (int64_t y = 0; y < M; ++y)
+                for (int64_t x = 0; x < M; ++x) {
+                    const int64_t c = lin3(x, y, z, M);
+                    next[c] = state[c];
+                    if (state[c]) continue;
+                    int pos = 0, neg = 0;
+                    const int64_t nx[6] = {x - 1, x + 1, x, x, x, x}, ny[6] = {y, y, y - 1, y + 1, y, y},
+                                  nz[6] = {z, z, z, z, z - 1, z + 1};
+                    for (int f = 0; f < 6; ++f) {
+                        if (nx[f] < 0 || ny[f] < 0 || nz[f] < 0 || nx[f] >= M || ny[f] >= M || nz[f] >= M) continue;
+                        const uint8_t v = state[lin3(nx[f], ny[f], nz[f], M)];
+                        pos |= v == 2;
+                        neg |= v == 1;
+                    }
+                    if (pos || neg) {
+                        next[c] = pos ? 2 : 1;
+                        changed = 1;
+                    }
+                }
+        uint8_t *t = state;
+        state = next;
+        next = t;
+        if (!changed) break;
+        ++rounds;
+    }
+    for (int64_t c = 0; c < n; ++c) {
+        const int core = fabs((double)d[c]) < lc;
+        if (core || state[c] == 0) out[c] = d[c];
+        else out[c] = state[c] == 2 ? fabsf(d[c]) : -fabsf(d[c]);
+    }
+    free(state);
+    free(next);
+    return rounds;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Numbering (Sec. 5 and Sec. 7.1 step 3).  Returns P, the number of         */
 /* activated packages.  pkg_cell / pkg_type must hold M^3 + 2 entries.       */
 /* ------------------------------------------------------------------------ */

@@ -1,0 +1,106 @@
+"""Pins of the oracle's sign correction by diffusion (Sec. 7.2, the coarse
+step on the mesh cells): a distance function is left unchanged; signs flipped
+in regions away from the surface (a leaky inside/outside test) are restored;
+the result agrees with an independent labelling of the connected regions of
+uncertain cells; the number of rounds is the diffusion distance."""
+import numpy as np
+import pytest
+from scipy import ndimage
+
+import oracle
+import synth
+
+
+def _leaky(d, M, seed, n_boxes=6):
+    """d with the sign flipped inside random boxes, only at cells at least two
+    cell sizes from the surface (the near-surface signs stay right)."""
+    rng = np.random.default_rng(seed)
+    g = d.reshape(M, M, M).copy()      # [z, y, x]
+    far = np.abs(g) >= 2.0 / M
+    for _ in range(n_boxes):
+        lo = rng.integers(0, M - 4, 3)
+        hi = lo + rng.integers(2, max(3, M // 3), 3)
+        box = np.zeros_like(far)
+        box[lo[2]:hi[2], lo[1]:hi[1], lo[0]:hi[0]] = True
+        g[box & far] = -g[box & far]
+    return g.ravel()
+
+
+SHAPES = [
+    ("sphere", synth.sphere((0.5, 0.5, 0.5), 0.3), 24),
+    ("union", synth.union([synth.sphere((0.3, 0.4, 0.5), 0.15), synth.box((0.62, 0.6, 0.5), (0.2, 0.15, 0.2))]), 32),
+    ("shell", synth.shell((0.5, 0.5, 0.5), 0.25, 0.32), 32),
+]
+
+
+@pytest.mark.parametrize("name,shape,M", SHAPES, ids=[s[0] for s in SHAPES])
+def test_distance_function_unchanged(name, shape, M):
+    d = synth.coarse_sdf(shape, M)
+    out, rounds = oracle.correct_signs(M, d)
+    assert np.array_equal(out.view(np.uint32), d.view(np.uint32))
+    assert rounds > 0
+
+
+@pytest.mark.parametrize("name,shape,M", SHAPES, ids=[s[0] for s in SHAPES])
+def test_leaks_are_repaired(name, shape, M):
+    d = synth.coarse_sdf(shape, M)
+    for seed in range(3):
+        bad = _leaky(d, M, seed)
+        assert np.sum(np.sign(bad) != np.sign(d)) > 20
+        out, _ = oracle.correct_signs(M, bad)
+        assert np.array_equal(out, d)
+        assert np.array_equal(oracle.build_tables(M, out).cell_pkg, oracle.build_tables(M, d).cell_pkg)
+
+
+def test_agrees_with_region_labelling():
+    # every 6-connected region of non-core cells takes the sign of the core
+    # cells on its border (one sign per region for these inputs); regions that
+    # touch no core cell keep their input signs
+    M = 32
+    shape = synth.union([synth.sphere((0.3, 0.4, 0.5), 0.15), synth.box((0.62, 0.6, 0.5), (0.2, 0.15, 0.2))])
+    d = synth.coarse_sdf(shape, M)
+    bad = _leaky(d, M, 11, n_boxes=10)
+    out, _ = oracle.correct_signs(M, bad)
+    g = bad.reshape(M, M, M)
+    core = np.abs(g.astype(np.float64)) < 1.0 / M
+    lab, n = ndimage.label(~core)
+    pos_core = core & ~(g < 0)
+    neg_core = core & (g < 0)
+    want = g.copy()
+    st = ndimage.generate_binary_structure(3, 1)
+    for r in range(1, n + 1):
+        reg = lab == r
+        ring = ndimage.binary_dilation(reg, st) & ~reg
+        p, q = (ring & pos_core).any(), (ring & neg_core).any()
+        assert not (p and q)
+        if p:
+            want[reg] = np.abs(g[reg])
+        elif q:
+            want[reg] = -np.abs(g[reg])
+    assert np.array_equal(out.reshape(M, M, M), want)
+
+
+def test_rounds_are_the_diffusion_distance():
+    # a single core cell in a corner of an otherwise uncertain grid: the sign
+    # spreads one face step per round, so the far corner is reached after
+    # 3 (M - 1) rounds, and every cell takes the core cell's sign
+    M = 9
+    d = np.full(M ** 3, 5.0, dtype=np.float32)
+    d[0] = -0.01
+    out, rounds = oracle.correct_signs(M, d)
+    assert rounds == 3 * (M - 1)
+    assert np.all(out[1:] == -5.0) and out[0] == d[0]
+    # no core cell: nothing is decided, nothing changes
+    e = np.where(np.arange(M ** 3) % 2 == 0, 3.0, -3.0).astype(np.float32)
+    out, rounds = oracle.correct_signs(M, e)
+    assert rounds == 0 and np.array_equal(out, e)
+
+
+def test_positive_wins_a_tie():
+    # an uncertain cell between a positive and a negative core cell
+    M = 3
+    d = np.full(M ** 3, 7.0, dtype=np.float32)
+    d[0 + 3 * 1 + 9 * 1] = 0.1       # (0, 1, 1) positive core
+    d[2 + 3 * 1 + 9 * 1] = -0.1      # (2, 1, 1) negative core
+    out, _ = oracle.correct_signs(M, d, lc=0.5)
+    assert out[1 + 3 * 1 + 9 * 1] == 7.0
