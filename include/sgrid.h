@@ -104,6 +104,23 @@ sgrid_status sgrid_build_packages(const sgrid_desc *desc, const float *coarse_sd
                                   void *stream, sgrid_grid **out);
 
 /*
+ * Consistency (sign) correction of a layer's distances (Sec. 7.2: only the
+ * signs of cells very close to the surface are used directly; the others
+ * come from a diffusion outward from them), the coarse step on the mesh
+ * cells.  `d_dev` [M^3] (M = desc->n_coarse, x fastest, FP32): core cells
+ * (|d| < 4 desc->h) keep their value.  Every other cell gets its sign by
+ * rounds of simultaneous updates: a cell without a sign takes one when a face
+ * neighbour has one, positive if any such neighbour is positive, else
+ * negative, until a round changes nothing; such cells are written as |d| with
+ * that sign, and cells no diffusion reaches keep d.  `out_dev` [M^3] may be
+ * `d_dev` (in place).  *rounds_out (nullable) receives the number of rounds
+ * that decided a cell.  Synchronises `stream` once per 16 rounds; workspace
+ * M^3 / 2 bytes from the library's caching allocator.  M <= 4096.
+ */
+sgrid_status sgrid_correct_signs(const sgrid_desc *desc, const float *d_dev, float *out_dev, void *stream,
+                                 int32_t *rounds_out);
+
+/*
  * The next layer of the multi-resolution construction (Sec. 7: layers of
  * successively doubled resolution, each initialised from the one before;
  * Sec. 7.1 step 1: a finer layer evaluates distances only in the cells that

@@ -17,7 +17,8 @@ from typing import Optional
 import torch
 
 __all__ = [
-    "SgridError", "Grid", "load", "build_packages", "build_packages_refined", "fill_far_field", "reinitialize",
+    "SgridError", "Grid", "load", "build_packages", "build_packages_refined", "correct_signs", "fill_far_field",
+    "reinitialize",
     "compute_gradient", "compute_gradient_packed", "probe_particles", "probe_particles_packed", "compute_near_surface_integrals", "set_sweep_config",
     "compute_integral_field", "probe_integral_field",
     "sequential_update", "compute_laplacian",
@@ -54,6 +55,7 @@ _SIGNATURES = {
     "sgrid_version": (ctypes.c_int32, []),
     "sgrid_build_packages": (ctypes.c_int, [ctypes.POINTER(_Desc), _P, _P, ctypes.POINTER(_P)]),
     "sgrid_build_packages_refined": (ctypes.c_int, [_P, _P, _P, ctypes.POINTER(_P)]),
+    "sgrid_correct_signs": (ctypes.c_int, [ctypes.POINTER(_Desc), _P, _P, _P, ctypes.POINTER(ctypes.c_int32)]),
     "sgrid_get_info": (ctypes.c_int, [_P, ctypes.POINTER(_Info)]),
     "sgrid_destroy": (ctypes.c_int, [_P]),
     "sgrid_fill_far_field": (ctypes.c_int, [_P, ctypes.c_int, _P, _P]),
@@ -235,6 +237,24 @@ def build_packages_refined(coarse: Grid, child_sdf: Optional[torch.Tensor], stre
     out = ctypes.c_void_p()
     _check(load().sgrid_build_packages_refined(coarse.handle, ptr, _stream(stream), ctypes.byref(out)))
     return Grid(out)
+
+
+def correct_signs(coarse_sdf: torch.Tensor, h: float, out: Optional[torch.Tensor] = None, stream=None) -> int:
+    """Sign correction of coarse distances (float32, M^3 values) by diffusion
+    from the core cells; writes `out` (default: in place) and returns the
+    number of rounds that decided a cell."""
+    n = coarse_sdf.numel()
+    M = int(round(n ** (1.0 / 3.0)))
+    if M ** 3 != n:
+        raise ValueError(f"coarse_sdf has {n} values, not a cube")
+    if coarse_sdf.dtype != torch.float32 or (out is not None and (out.dtype != torch.float32 or out.numel() != n)):
+        raise TypeError("coarse_sdf and out must be float32 of the same size")
+    out = coarse_sdf if out is None else out
+    desc = _Desc(M, float(h))
+    rounds = ctypes.c_int32()
+    _check(load().sgrid_correct_signs(ctypes.byref(desc), _dev(coarse_sdf, "coarse_sdf"), _dev(out, "out"),
+                                      _stream(stream), ctypes.byref(rounds)))
+    return int(rounds.value)
 
 
 def fill_far_field(grid: Grid, phi: torch.Tensor, stream=None):

@@ -11,7 +11,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libsgrid.so")
 OBJ = os.path.join(os.path.dirname(HERE), "_build", "sgrid")
-SOURCES = ["build.hip", "sweep.hip", "probe.hip", "integrals.hip", "mlp.hip", "batch.hip"]
+SOURCES = ["build.hip", "sweep.hip", "probe.hip", "integrals.hip", "mlp.hip", "batch.hip", "signs.hip"]
 
 HIPCC = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
 FLAGS = [
