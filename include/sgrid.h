@@ -374,10 +374,12 @@ sgrid_status sgrid_compute_laplacian(const sgrid_grid *grid, sgrid_dtype dtype, 
  * sweeps groups of 64 consecutive Morton-ordered packages per 1024-lane
  * workgroup and reads halo rows of in-group neighbours from LDS, variant 5
  * is variant 0 with the y / z neighbour rows exchanged through LDS instead of
- * DPP (no workgroup barrier).  `groups` (1, 2, 3, 4 or 8) is, for variants 0,
- * 1, 3 and 5, the number of four-package sets one wavefront processes, for
- * variant 2 the number of workgroups per compute unit, and is ignored by
- * variant 4.  With variant 2, 3 or 4 the gradient and Laplacian passes also
+ * DPP (no workgroup barrier), variant 6 is variant 0 as a persistent
+ * grid-stride walk in package-id order with the next set's face row and own
+ * rows loaded ahead.  `groups` (1, 2, 3, 4 or 8) is, for variants 0, 1, 3 and
+ * 5, the number of four-package sets one wavefront processes, for variants 2
+ * and 6 the number of workgroups per compute unit, and is ignored by variant
+ * 4.  With variant 2, 3 or 4 the gradient and Laplacian passes also
  * visit the packages in Morton order.  Process-wide; default (0, 1).  Results
  * are identical for every setting.
  */

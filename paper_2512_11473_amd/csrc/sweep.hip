@@ -76,10 +76,9 @@ __device__ __forceinline__ void load_face(const uint32_t *__restrict__ face, int
 // would become branches, and the compiler then waits for every earlier load
 // before the branch's own, adding a memory round trip.
 template <typename T>
-__device__ __forceinline__ void issue_data(const T *__restrict__ src, int64_t p, int r, const uint4 &f0,
-                                           const uint2 &f1, Loads<T> &l) {
+__device__ __forceinline__ void issue_halos(const T *__restrict__ src, int64_t p, int r, const uint4 &f0,
+                                            const uint2 &f1, Loads<T> &l) {
     const int j = r & 3, k = r >> 2;
-    l.c = load_row(src + p * 64 + r * 4);
     l.xm = src[(int64_t)f0.x * 64 + r * 4 + 3];
     l.xp = src[(int64_t)f0.y * 64 + r * 4];
     const int64_t fy = j == 0 ? (int64_t)f0.z : j == 3 ? (int64_t)f0.w : p;
@@ -88,6 +87,13 @@ __device__ __forceinline__ void issue_data(const T *__restrict__ src, int64_t p,
     const int64_t fz = k == 0 ? (int64_t)f1.x : k == 3 ? (int64_t)f1.y : p;
     const int rz = k == 0 ? j + 12 : k == 3 ? j : r;
     l.zh = load_row(src + fz * 64 + rz * 4);
+}
+
+template <typename T>
+__device__ __forceinline__ void issue_data(const T *__restrict__ src, int64_t p, int r, const uint4 &f0,
+                                           const uint2 &f1, Loads<T> &l) {
+    l.c = load_row(src + p * 64 + r * 4);
+    issue_halos(src, p, r, f0, f1, l);
 }
 
 template <typename T>
@@ -335,6 +341,45 @@ __global__ __launch_bounds__(256) void reinit_pipe_kernel(const T *__restrict__ 
     }
 }
 
+// Persistent linear variant: the grid-stride walk of variant 2 over the
+// packages in id order, where a set's package ids are known without a table:
+// each wavefront loads the next set's face row and own rows while the current
+// set's halo rows are in flight, so a set costs one memory round trip.
+template <typename T>
+__global__ __launch_bounds__(256) void reinit_pipe_lin_kernel(const T *__restrict__ src, T *__restrict__ dst,
+                                                              const uint32_t *__restrict__ face, int64_t P,
+                                                              int64_t n_blocks, T h2, T inv_h, T dt) {
+    const int64_t b = xcd_block(blockIdx.x, n_blocks);
+    const int lane = threadIdx.x & 63;
+    const int r = lane & 15;
+    const int64_t n_sets = (P + 3) / 4;
+    const int64_t stride = n_blocks * 4;
+    int64_t s = b * 4 + (threadIdx.x >> 6);
+    if (s >= n_sets) return;
+    auto pkg = [&](int64_t set) {
+        const int64_t e = set * 4 + (lane >> 4);
+        return 2 + (e < P ? e : P - 1);
+    };
+    int64_t p = pkg(s);
+    uint4 f0;
+    uint2 f1;
+    load_face(face, p, f0, f1);
+    Row<T> own = load_row(src + p * 64 + r * 4);
+    for (; s < n_sets; s += stride) {
+        const int64_t pc = p;
+        const uint4 c0 = f0;
+        const uint2 c1 = f1;
+        Loads<T> l;
+        l.c = own;
+        p = pkg(s + stride < n_sets ? s + stride : s);
+        load_face(face, p, f0, f1);
+        own = load_row(src + p * 64 + r * 4);
+        issue_halos(src, pc, r, c0, c1, l);
+        const Stencil<T> st = assemble(r, l);
+        store_row(dst + pc * 64 + r * 4, reinit_row(st, h2, inv_h, dt));
+    }
+}
+
 // LDS-staged variant: the package rows and their face halo rows go into a
 // 6 x 6 x 6 tile per package (interior 4^3 plus one-cell faces) in LDS, and
 // each lane reads its stencil back from the tile.
@@ -554,7 +599,12 @@ static sgrid_status launch_reinit_sweep(const sgrid_grid *g, const T *src, T *ds
     const int64_t nb = (g->P + per_block - 1) / per_block;
     const T h2 = (T)(g->h * g->h), inv_h = (T)(1.0 / g->h), dt = (T)(0.5 * g->h);
     const dim3 grid((unsigned)nb), block(256);
-    if (cfg.variant == 5) {
+    if (cfg.variant == 6) {
+        const int64_t n_sets = (g->P + 3) / 4;
+        const int64_t nbp = std::min<int64_t>((int64_t)cu_count() * cfg.groups, (n_sets + 3) / 4);
+        hipLaunchKernelGGL(reinit_pipe_lin_kernel<T>, dim3((unsigned)nbp), block, 0, st, src, dst, g->face, g->P, nbp,
+                           h2, inv_h, dt);
+    } else if (cfg.variant == 5) {
         switch (cfg.groups) {
             case 1: hipLaunchKernelGGL((reinit_rows_kernel<T, 1>), grid, block, 0, st, src, dst, g->face, g->P, nb, h2, inv_h, dt); break;
             case 2: hipLaunchKernelGGL((reinit_rows_kernel<T, 2>), grid, block, 0, st, src, dst, g->face, g->P, nb, h2, inv_h, dt); break;
@@ -615,7 +665,7 @@ template sgrid_status reinit_impl<float>(const sgrid_grid *, float *, float *, i
 
 extern "C" sgrid_status sgrid_set_sweep_config(int32_t variant, int32_t groups) {
     sgrid::clear_error();
-    SG_REQUIRE(variant >= 0 && variant <= 5, "sweep variant must be 0..5 (got %d)", variant);
+    SG_REQUIRE(variant >= 0 && variant <= 6, "sweep variant must be 0..6 (got %d)", variant);
     SG_REQUIRE(groups == 1 || groups == 2 || groups == 3 || groups == 4 || groups == 8, "groups must be 1, 2, 3, 4 or 8 (got %d)", groups);
     sgrid::set_sweep_config(variant, groups);
     return SGRID_OK;

@@ -217,7 +217,7 @@ def test_sweep_variants_identical(sg):
     wl = workload.setup(cfg["shape"], cfg["N"], cfg["noise_amp"], cfg["noise_seed"])
     results = []
     for variant, groups in [(0, 1), (0, 2), (0, 3), (0, 4), (0, 8), (1, 1), (1, 2), (1, 3), (2, 1), (2, 2), (2, 4), (2, 8),
-                           (3, 1), (3, 2), (3, 4), (4, 1), (5, 1), (5, 2), (5, 4)]:
+                           (3, 1), (3, 2), (3, 4), (4, 1), (5, 1), (5, 2), (5, 4), (6, 1), (6, 3), (6, 8)]:
         sg.set_sweep_config(variant, groups)
         wl.reset()
         sg.reinitialize(wl.grid, wl.phi, wl.scratch, 7)
@@ -236,7 +236,7 @@ def test_persistent_sweep_rounds(sg):
     P = wl.grid.n_packages
     assert (P + 3) // 4 > 3 * 256 * 4 and P % 4 != 0      # more than three rounds at one workgroup per CU
     results = []
-    for variant, groups in [(0, 1), (3, 1), (2, 1), (2, 2), (2, 3), (2, 8)]:
+    for variant, groups in [(0, 1), (3, 1), (2, 1), (2, 2), (2, 3), (2, 8), (6, 1), (6, 4)]:
         sg.set_sweep_config(variant, groups)
         wl.reset()
         sg.reinitialize(wl.grid, wl.phi, wl.scratch, 5)
@@ -269,7 +269,7 @@ def test_sweep_domain_edge(sg, dtype):
     assert np.any(x == 0) and np.any(y == M - 1)           # the band reaches both faces
     assert np.any(nbr[2:] == 0) and np.any(nbr[2:] == 1)    # far field on both sides
     tol = 1e-5 if dtype == torch.float32 else 1e-12
-    configs = [(0, 1), (0, 4), (1, 1), (2, 1), (3, 1), (4, 1), (5, 1)]
+    configs = [(0, 1), (0, 4), (1, 1), (2, 1), (3, 1), (4, 1), (5, 1), (6, 2)]
     for n_iter in (1, 2, 5, 12):
         outs = []
         for variant, groups in configs:
