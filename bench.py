@@ -273,26 +273,39 @@ def bench_single(args, log):
           ("build", "reinit", "grad", "probe", "integ")}
     acc = {k: 0.0 for k in ev}
 
+    # a second stream (default priority) for work that does not depend on the
+    # main chain: the phi reset beside the build, the integrals (VALU-bound)
+    # beside the gradient and the probe (memory-bound)
+    side = torch.cuda.Stream()
+    ev_copy, ev_reinit, ev_integ = (torch.cuda.Event() for _ in range(3))
+
     def step(record):
-        def mark(k, i):
+        def mark(k, i, st=stream):
             if record:
-                ev[k][i].record(stream)
+                ev[k][i].record(st)
+        with torch.cuda.stream(side):
+            wl.phi.copy_(wl.phi0)
+            ev_copy.record(side)
         mark("build", 0)
         g = sg.build_packages(wl.coarse, wl.h)
         mark("build", 1)
-        wl.phi.copy_(wl.phi0)
+        stream.wait_event(ev_copy)
         mark("reinit", 0)
         sg.reinitialize(g, wl.phi, wl.scratch, cfg["n_iter"])
         mark("reinit", 1)
+        ev_reinit.record(stream)
+        side.wait_event(ev_reinit)
+        mark("integ", 0, side)
+        sg.compute_near_surface_integrals(g, wl.phi, integ, stream=side)
+        mark("integ", 1, side)
+        ev_integ.record(side)
         mark("grad", 0)
         sg.compute_gradient_packed(g, wl.phi, packed)
         mark("grad", 1)
         mark("probe", 0)
         sg.probe_particles_packed(g, packed, wl.pos, wl.phi_p, wl.nrm_p)
         mark("probe", 1)
-        mark("integ", 0)
-        sg.compute_near_surface_integrals(g, wl.phi, integ)
-        mark("integ", 1)
+        stream.wait_event(ev_integ)
         return g
 
     for _ in range(args.warmup):
