@@ -484,8 +484,14 @@ def bench_shell(args, log):
     P = g.n_packages
     out = torch.empty_like(wl.phi)
     stream = torch.cuda.current_stream()
-    # the sweep autotuner also fixes the package order of the stencil pass
-    tv, tg, _ = sg.autotune_sweep(g, wl.phi, wl.scratch, reps=10)
+    # the sweep configuration also fixes the package order of the stencil pass
+    if args.sweep == "auto":
+        tv, tg, _ = sg.autotune_sweep(g, wl.phi, wl.scratch, reps=10)
+        source = "autotuned"
+    else:
+        tv, tg = (int(x) for x in args.sweep.split(","))
+        sg.set_sweep_config(tv, tg)
+        source = "--sweep"
     for _ in range(args.warmup):
         sg.sequential_update(g, wl.phi, cfg["delta"])
         sg.compute_laplacian(g, wl.phi, out)
@@ -516,7 +522,7 @@ def bench_shell(args, log):
                                "seven-point Laplacian over all activated data",
                    "N": cfg["N"], "n_packages": P, "points": pts},
         "sequential_ms": seq_ms, "laplacian_ms": lap_ms,
-        "sweep_config": {"variant": tv, "groups": tg, "source": "autotuned"},
+        "sweep_config": {"variant": tv, "groups": tg, "source": source},
         "sequential_points_per_s": pts / (seq_ms * 1e-3),
         "roofline": {"bound": "hbm", "kernel": "laplacian", "achieved": lap_bytes / (lap_ms * 1e-3) / 1e9,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s",
