@@ -265,10 +265,13 @@ def integral_field(N: int, h: float, B: float, tab: Tables, active: np.ndarray, 
     far-field package, (0, 0, 0, 0) inside and (c_full, 0, 0, 0) outside."""
     f = np.zeros((4, N ** 3), dtype=np.float64)
     M = N // 4
-    p = np.arange(N ** 3, dtype=np.int64)
-    i, j, k = p % N, (p // N) % N, p // (N * N)
-    cell = (i // 4) + M * ((j // 4) + M * (k // 4))
-    f[0] = np.where(np.asarray(tab.cell_pkg)[cell] == 1, c_full(), 0.0)
+    cp = np.asarray(tab.cell_pkg)
+    i = np.arange(N, dtype=np.int64)
+    jj, ii = np.meshgrid(i, i, indexing="ij")                    # one z-layer, x fastest
+    layer = (ii // 4) + M * (jj // 4)
+    c = c_full()
+    for k in range(N):                                            # layer by layer: no N^3 index arrays
+        f[0, k * N * N:(k + 1) * N * N] = np.where(cp[layer.ravel() + M * M * (k // 4)] == 1, c, 0.0)
     act = np.asarray(active, dtype=np.int64)
     f[:, act] = integrals(N, h, B, phi, act).T
     return f

@@ -72,6 +72,22 @@ def test_prism512_full_pipeline(sg):
     got = integ.double().cpu().numpy().T
     assert np.max(np.abs(got[:, 0] - ref[:, 0])) <= 1e-5
     assert np.max(np.abs(got[:, 1:] - ref[:, 1:])) <= 1e-5 * G0
+    # the integral field at every activated point and its probe at all 1e7 particles (Sec. 8)
+    field = torch.empty((g.n_total, 64, 4), device="cuda")
+    sg.compute_integral_field(g, wl.phi, field)
+    fout = torch.empty((pos.shape[0], 4), device="cuda")
+    sg.probe_integral_field(g, field, wl.pos, fout)
+    torch.cuda.synchronize()
+    fref = oracle.integral_field(run.N, h, run.B, run.tab, run.active, run.phi)
+    fgot = field[2:, torch.from_numpy(_blocked()).cuda(), :].double().cpu().numpy().reshape(-1, 4)
+    fwant = fref[:, pts].T
+    assert np.max(np.abs(fgot[:, 0] - fwant[:, 0])) <= 1e-5
+    assert np.max(np.abs(fgot[:, 1:] - fwant[:, 1:])) <= 1e-5 * G0
+    del fgot, fwant
+    pref = oracle.probe_field(run.N, h, run.tab.cell_pkg, fref, pos.astype(np.float64))
+    pgot = fout.double().cpu().numpy()
+    assert np.max(np.abs(pgot[:, 0] - pref[:, 0])) <= 2e-5
+    assert np.max(np.abs(pgot[:, 1:] - pref[:, 1:])) <= 2e-5 * G0
 
 
 def test_batch64_full_size(sg):
