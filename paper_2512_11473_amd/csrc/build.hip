@@ -4,7 +4,7 @@
 //
 // Pipeline on the caller's stream (coarse cells held as bitmaps, 64 cells of a
 // row per word):
-//   bits_kernel     one wavefront per word: core flag |d| < l_c and sign of d,
+//   bits_kernel     one wavefront per four words: core flag |d| < l_c and sign of d,
 //                   one ballot each;
 //   dilate_kernel   one lane per word: activated = core dilated by one cell in
 //                   x, y, z (word shifts and ORs); per-group counts;
@@ -145,17 +145,29 @@ __device__ __forceinline__ uint64_t lanemask_lt() {
 __global__ __launch_bounds__(256) void bits_kernel(const float *__restrict__ d, int M, int W, int64_t n_words,
                                                    double lc, uint64_t *__restrict__ core,
                                                    uint64_t *__restrict__ neg) {
-    const int64_t w = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (w >= n_words) return;   // whole wavefronts
+    // four consecutive words per wavefront, their loads issued together
+    const int64_t w0 = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * 4;
+    if (w0 >= n_words) return;   // whole wavefronts
     const int lane = threadIdx.x & 63;
-    const int64_t r = w / W;
-    const int x = (int)(w - r * W) * 64 + lane;
-    const float v = x < M ? d[r * M + x] : 1.0f;
-    const uint64_t bc = __ballot(x < M && fabs((double)v) < lc);
-    const uint64_t bn = __ballot(x < M && v < 0.0f);
-    if (lane == 0) {
-        core[w] = bc;
-        neg[w] = bn;
+    float v[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int64_t w = w0 + k < n_words ? w0 + k : n_words - 1;
+        const int64_t r = w / W;
+        const int x = (int)(w - r * W) * 64 + lane;
+        v[k] = d[r * M + (x < M ? x : M - 1)];
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int64_t w = w0 + k;
+        const int64_t r = w / W;
+        const bool in = w < n_words && (int)(w - r * W) * 64 + lane < M;
+        const uint64_t bc = __ballot(in && fabs((double)v[k]) < lc);
+        const uint64_t bn = __ballot(in && v[k] < 0.0f);
+        if (lane == 0 && w < n_words) {
+            core[w] = bc;
+            neg[w] = bn;
+        }
     }
 }
 
@@ -367,45 +379,84 @@ __global__ __launch_bounds__(256) void scatter_kernel(const uint64_t *__restrict
                                                       uint8_t *__restrict__ pkg_type,
                                                       uint32_t *__restrict__ core_list,
                                                       uint4 *__restrict__ rank_map, int W32) {
+    // a wavefront owns four consecutive words; lane l the four cells of bits
+    // 4 (l mod 16) .. 4 (l mod 16) + 3 of word l / 16, stored with one 16-byte
+    // write where the row allows it
     const int64_t grp = blockIdx.x;
     const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int64_t w0 = grp * 16 + wv * 4;
+    if (w0 >= n_words) return;   // the same for the whole wavefront
     uint32_t pa = off_act[grp], pc = off_core[grp];
-    for (int64_t w = grp * 16; w < w0 && w < n_words; ++w) {
+    for (int64_t w = grp * 16; w < w0; ++w) {
         pa += (uint32_t)__popcll(act[w]);
         pc += (uint32_t)__popcll(core[w]);
     }
-    const uint64_t lt = lanemask_lt();
+    uint64_t a[4], cb[4], nb[4];
+#pragma unroll
     for (int k = 0; k < 4; ++k) {
+        const bool in = w0 + k < n_words;
+        a[k] = in ? act[w0 + k] : 0ull;
+        cb[k] = in ? core[w0 + k] : 0ull;
+        nb[k] = in ? neg[w0 + k] : 0ull;
+    }
+    // the rank map entries of the four words' 32-cell halves (lanes 0..7)
+    if (lane < 8) {
+        const int k = lane >> 1, hf = lane & 1;
         const int64_t w = w0 + k;
-        if (w >= n_words) break;   // the same for the whole wavefront
-        const uint64_t a = act[w], cb = core[w], nb = neg[w];
-        const int64_t r = w / W;
-        const int x = (int)(w - r * W) * 64 + lane;
-        if (x < M) {
-            const int64_t c = r * M + x;
-            if ((a >> lane) & 1ull) {
-                const uint32_t id = 2u + pa + (uint32_t)__popcll(a & lt);
-                cell_pkg[c] = id;
-                pkg_cell[id] = (uint32_t)c;
-                const bool is_core = (cb >> lane) & 1ull;
-                pkg_type[id] = is_core ? 1 : 2;
-                if (is_core) core_list[pc + (uint32_t)__popcll(cb & lt)] = id;
-            } else {
-                cell_pkg[c] = ((nb >> lane) & 1ull) ? sgrid::kFarNeg : sgrid::kFarPos;
-            }
-        }
-        // the rank map entries of the word's two 32-cell halves
-        if (lane < 2) {
-            const int half = (int)(w - r * W) * 2 + lane;
+        if (w < n_words) {
+            const int64_t r = w / W;
+            const int half = (int)(w - r * W) * 2 + hf;
             if (half < W32) {
-                const uint32_t am = (uint32_t)(lane ? a >> 32 : a), nm = (uint32_t)(lane ? nb >> 32 : nb);
-                const uint32_t before = lane ? pa + (uint32_t)__popc((uint32_t)a) : pa;
-                rank_map[r * W32 + half] = make_uint4(am, nm, before, 0u);
+                uint32_t before = pa;
+                for (int j = 0; j < k; ++j) before += (uint32_t)__popcll(a[j]);
+                if (hf) before += (uint32_t)__popc((uint32_t)a[k]);
+                rank_map[r * W32 + half] = make_uint4((uint32_t)(hf ? a[k] >> 32 : a[k]),
+                                                      (uint32_t)(hf ? nb[k] >> 32 : nb[k]), before, 0u);
             }
         }
-        pa += (uint32_t)__popcll(a);
-        pc += (uint32_t)__popcll(cb);
+    }
+    const int k = lane >> 4, b0 = 4 * (lane & 15);
+    const int64_t w = w0 + k;
+    if (w >= n_words) return;
+    uint32_t ra = pa, rc = pc;
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+        if (j < k) {
+            ra += (uint32_t)__popcll(a[j]);
+            rc += (uint32_t)__popcll(cb[j]);
+        }
+    const uint64_t ak = a[k], ck = cb[k], nk = nb[k];
+    const uint64_t below = (1ull << b0) - 1ull;
+    ra += (uint32_t)__popcll(ak & below);
+    rc += (uint32_t)__popcll(ck & below);
+    const int64_t r = w / W;
+    const int x0 = (int)(w - r * W) * 64 + b0;
+    if (x0 >= M) return;
+    uint32_t v[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int bit = b0 + i;
+        const int64_t c = r * M + x0 + i;
+        if ((ak >> bit) & 1ull) {
+            const uint32_t id = 2u + ra++;
+            v[i] = id;
+            if (x0 + i < M) {
+                pkg_cell[id] = (uint32_t)c;
+                const bool is_core = (ck >> bit) & 1ull;
+                pkg_type[id] = is_core ? 1 : 2;
+                if (is_core) core_list[rc++] = id;
+            }
+        } else {
+            v[i] = ((nk >> bit) & 1ull) ? sgrid::kFarNeg : sgrid::kFarPos;
+        }
+    }
+    uint32_t *dst = cell_pkg + r * M + x0;
+    if ((M & 3) == 0) {   // x0 and M multiples of 4: the four cells are in the row and 16-byte aligned
+        *reinterpret_cast<uint4 *>(dst) = make_uint4(v[0], v[1], v[2], v[3]);
+    } else {
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+            if (x0 + i < M) dst[i] = v[i];
     }
 }
 
@@ -413,10 +464,13 @@ __global__ __launch_bounds__(256) void scatter_kernel(const uint64_t *__restrict
 // their coarse cells, so the packages one workgroup sweeps together are
 // spatial neighbours and share their halo lines in the caches.  The codes run
 // over the enclosing power-of-two cube; codes outside the grid are skipped.
-// Each thread handles kCellsPerThread codes; activation is read from the
-// bitmap, the package id only for activated cells.
-constexpr int kCellsPerThread = 4;
-constexpr int kCellsPerBlock = kTagBlock * kCellsPerThread;
+// One lane per 64 consecutive codes, which cover a 4 x 4 x 4 box of cells:
+// the box's activation is 16 four-bit pieces of the bitmap (one per (y, z)
+// row, never straddling a word as the box is 4-aligned), gathered into one
+// 64-bit mask, bit lx + 4 ly + 16 lz.  Most boxes of a narrow band are empty
+// and cost 16 word reads; a box with activated cells is walked in Morton order
+// and reads the package id of its activated cells only.
+constexpr int kCodesPerBlock = kTagBlock * 64;
 
 __device__ __forceinline__ void morton_decode(int64_t code, int bits, int &x, int &y, int &z) {
     x = y = z = 0;
@@ -427,36 +481,42 @@ __device__ __forceinline__ void morton_decode(int64_t code, int bits, int &x, in
     }
 }
 
-__device__ __forceinline__ uint32_t morton_active(const uint32_t *__restrict__ cell_pkg,
-                                                  const uint64_t *__restrict__ act, int M, int W, int bits,
-                                                  int64_t code, int64_t n_codes) {
-    if (code >= n_codes) return 0u;
-    int x, y, z;
-    morton_decode(code, bits, x, y, z);
-    if (x >= M || y >= M || z >= M) return 0u;
-    const int64_t r = (int64_t)y + (int64_t)M * z;
-    if (!((act[r * W + (x >> 6)] >> (x & 63)) & 1ull)) return 0u;
-    return cell_pkg[r * M + x];
+// Activation mask of the box of codes 64 box .. 64 box + 63 and its origin
+// cell; 0 when the box lies past the codes or the grid.
+__device__ __forceinline__ uint64_t box_mask(const uint64_t *__restrict__ act, int M, int W, int bits,
+                                             int64_t box, int64_t n_codes, int &ox, int &oy, int &oz) {
+    ox = oy = oz = 0;
+    if (box * 64 >= n_codes) return 0ull;
+    if (bits > 2) {
+        morton_decode(box, bits - 2, ox, oy, oz);
+        ox *= 4;
+        oy *= 4;
+        oz *= 4;
+    }
+    if (ox >= M || oy >= M || oz >= M) return 0ull;
+    const int nx = M - ox;
+    const uint64_t xm = nx >= 4 ? 0xFull : ((1ull << nx) - 1ull);
+    uint64_t m = 0;
+#pragma unroll
+    for (int lz = 0; lz < 4; ++lz)
+#pragma unroll
+        for (int ly = 0; ly < 4; ++ly) {
+            const int y = oy + ly, z = oz + lz;
+            const uint64_t w = (y < M && z < M) ? act[((int64_t)y + (int64_t)M * z) * W + (ox >> 6)] : 0ull;
+            m |= ((w >> (ox & 63)) & xm) << (4 * (ly + 4 * lz));
+        }
+    return m;
 }
 
 __global__ __launch_bounds__(kTagBlock) void morton_count_kernel(const uint64_t *__restrict__ act, int M, int W,
                                                                  int bits, int64_t n_codes,
                                                                  uint32_t *__restrict__ cnt) {
     __shared__ uint32_t s_n[kTagBlock / 64];
-    const int64_t c0 = (int64_t)blockIdx.x * kCellsPerBlock + threadIdx.x;
-    uint32_t n = 0;
+    int ox, oy, oz;
+    const uint64_t m = box_mask(act, M, W, bits, (int64_t)blockIdx.x * kTagBlock + threadIdx.x, n_codes, ox, oy, oz);
+    uint32_t n = (uint32_t)__popcll(m);
 #pragma unroll
-    for (int q = 0; q < kCellsPerThread; ++q) {
-        const int64_t code = c0 + (int64_t)q * kTagBlock;
-        bool on = false;
-        if (code < n_codes) {
-            int x, y, z;
-            morton_decode(code, bits, x, y, z);
-            if (x < M && y < M && z < M)
-                on = (act[((int64_t)y + (int64_t)M * z) * W + (x >> 6)] >> (x & 63)) & 1ull;
-        }
-        n += (uint32_t)__popcll(__ballot(on));
-    }
+    for (int d = 32; d >= 1; d >>= 1) n += __shfl_xor(n, d);
     if ((threadIdx.x & 63) == 0) s_n[threadIdx.x >> 6] = n;
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -471,30 +531,31 @@ __global__ __launch_bounds__(kTagBlock) void morton_scatter_kernel(const uint32_
                                                                    int bits, int64_t n_codes,
                                                                    const uint32_t *__restrict__ off,
                                                                    uint32_t *__restrict__ work) {
-    __shared__ uint32_t s_n[kCellsPerThread][kTagBlock / 64];
-    const int64_t c0 = (int64_t)blockIdx.x * kCellsPerBlock + threadIdx.x;
-    const int w = threadIdx.x >> 6;
-    uint32_t id[kCellsPerThread];
-    uint64_t ba[kCellsPerThread];
+    __shared__ uint32_t s_n[kTagBlock / 64];
+    int ox, oy, oz;
+    const uint64_t m = box_mask(act, M, W, bits, (int64_t)blockIdx.x * kTagBlock + threadIdx.x, n_codes, ox, oy, oz);
+    // exclusive prefix of the boxes' counts over the workgroup (lane order is code order)
+    const uint32_t n = (uint32_t)__popcll(m);
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    uint32_t inc = n;
 #pragma unroll
-    for (int q = 0; q < kCellsPerThread; ++q) {
-        id[q] = morton_active(cell_pkg, act, M, W, bits, c0 + (int64_t)q * kTagBlock, n_codes);
-        ba[q] = __ballot(id[q] != 0);
-        if ((threadIdx.x & 63) == 0) s_n[q][w] = (uint32_t)__popcll(ba[q]);
+    for (int d = 1; d < 64; d <<= 1) {
+        const uint32_t v = __shfl_up(inc, d);
+        if (lane >= d) inc += v;
     }
+    if (lane == 63) s_n[wv] = inc;
     __syncthreads();
-    uint32_t base = off[blockIdx.x];
-    const uint64_t lt = lanemask_lt();
-#pragma unroll
-    for (int q = 0; q < kCellsPerThread; ++q) {
-        uint32_t a = base;
-        for (int i = 0; i < w; ++i) a += s_n[q][i];
-        if (id[q]) work[a + (uint32_t)__popcll(ba[q] & lt)] = id[q];
-        for (int i = 0; i < kTagBlock / 64; ++i) base += s_n[q][i];
+    uint32_t pos = off[blockIdx.x] + inc - n;
+    for (int i = 0; i < wv; ++i) pos += s_n[i];
+    if (!m) return;
+    // the box in Morton order: code t has lx = t0 + 2 t3, ly = t1 + 2 t4, lz = t2 + 2 t5
+    for (int t = 0; t < 64; ++t) {
+        const int lx = (t & 1) | ((t >> 2) & 2), ly = ((t >> 1) & 1) | ((t >> 3) & 2), lz = ((t >> 2) & 1) | ((t >> 4) & 2);
+        if ((m >> (lx + 4 * ly + 16 * lz)) & 1ull)
+            work[pos++] = cell_pkg[(ox + lx) + (int64_t)M * ((oy + ly) + (int64_t)M * (oz + lz))];
     }
 }
 
-// Position of every package in the sweep worklist.
 __global__ __launch_bounds__(256) void worklist_pos_kernel(const uint32_t *__restrict__ work, int64_t P,
                                                            uint32_t *__restrict__ wpos) {
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -749,13 +810,13 @@ sgrid_status finish_grid(sgrid_grid *g, const BuildWs &ws, hipStream_t st) {
                        (int)M, nt, g->nbr, g->face);
     SG_HIP_OR_FREE(hipGetLastError());
     // Morton-order sweep worklist: count activated codes per block of
-    // kCellsPerBlock codes, scan, scatter (the counts and the scan's block sums
+    // kCodesPerBlock codes, scan, scatter (the counts and the scan's block sums
     // live behind the worklist)
     {
         int bits = 0;
         while ((1ll << bits) < M) ++bits;
         const int64_t n_codes = (int64_t)1 << (3 * bits);
-        const int64_t nbm = (n_codes + kCellsPerBlock - 1) / kCellsPerBlock;
+        const int64_t nbm = (n_codes + kCodesPerBlock - 1) / kCodesPerBlock;
         const int64_t nbs = (nbm + kScanBlock - 1) / kScanBlock;
         SG_ALLOC(g->work, ((g->P > 0 ? g->P : 1) + 2 * nbm + 2 * nbs + 64) * 4, "sweep worklist");
         uint32_t *mc = g->work + (g->P > 0 ? g->P : 1);
@@ -811,7 +872,7 @@ extern "C" sgrid_status sgrid_build_packages(const sgrid_desc *desc, const float
     sgrid_status s = new_grid(M, desc->h, &g, ws);
     if (s != SGRID_OK) return s;
     const double lc = 4.0 * desc->h;
-    hipLaunchKernelGGL(bits_kernel, dim3((unsigned)((ws.n_words + 3) / 4)), dim3(256), 0, st, coarse_sdf, (int)M,
+    hipLaunchKernelGGL(bits_kernel, dim3((unsigned)((ws.n_words + 15) / 16)), dim3(256), 0, st, coarse_sdf, (int)M,
                        (int)ws.W, ws.n_words, lc, ws.core_bits, ws.neg_bits);
     SG_HIP_OR_FREE(hipGetLastError());
     s = finish_grid(g, ws, st);
