@@ -606,21 +606,26 @@ __global__ __launch_bounds__(256) void nbr_kernel(const uint32_t *__restrict__ c
                                                   const uint32_t *__restrict__ pkg_cell, int M,
                                                   int64_t n_total, uint32_t *__restrict__ nbr,
                                                   uint32_t *__restrict__ face) {
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= n_total * 27) return;
-    const int64_t p = t / 27;
-    const int s = (int)(t - p * 27);
+    // nine packages per workgroup, 27 lanes each (lanes 243.. idle): 32-bit
+    // index arithmetic, divisions by constants
+    const int tl = (int)threadIdx.x;
+    if (tl >= 9 * 27) return;
+    const int64_t p = (int64_t)blockIdx.x * 9 + tl / 27;
+    if (p >= n_total) return;
+    const int s = tl % 27;
+    const int64_t t = p * 27 + s;
     uint32_t v;
     if (p < 2) {
         v = (uint32_t)p;
     } else {
-        const int64_t c = pkg_cell[p];
-        const int64_t MM = (int64_t)M * M;
-        const int x = (int)(c % M) + s % 3 - 1;
-        const int y = (int)((c / M) % M) + (s / 3) % 3 - 1;
-        const int z = (int)(c / MM) + s / 9 - 1;
-        v = (x < 0 || y < 0 || z < 0 || x >= M || y >= M || z >= M) ? sgrid::kFarPos
-                                                                      : cell_pkg[x + (int64_t)M * y + MM * z];
+        const uint32_t c = pkg_cell[p], um = (uint32_t)M;
+        const uint32_t cyz = c / um;
+        const int x = (int)(c - cyz * um) + s % 3 - 1;
+        const int y = (int)(cyz % um) + (s / 3) % 3 - 1;
+        const int z = (int)(cyz / um) + s / 9 - 1;
+        v = (x < 0 || y < 0 || z < 0 || x >= M || y >= M || z >= M)
+                ? sgrid::kFarPos
+                : cell_pkg[x + (int64_t)M * y + (int64_t)M * M * z];
     }
     nbr[t] = v;
     // face row: -x, +x, -y, +y, -z, +z, then the package itself twice
@@ -805,8 +810,7 @@ sgrid_status finish_grid(sgrid_grid *g, const BuildWs &ws, hipStream_t st) {
                        (int)M, (int)W, n_words, ca, cc, g->cell_pkg, g->pkg_cell, g->pkg_type, g->core_list,
                        g->rank_map, g->W32);
     SG_HIP_OR_FREE(hipGetLastError());
-    const int64_t nn = nt * 27;
-    hipLaunchKernelGGL(nbr_kernel, dim3((unsigned)((nn + 255) / 256)), dim3(256), 0, st, g->cell_pkg, g->pkg_cell,
+    hipLaunchKernelGGL(nbr_kernel, dim3((unsigned)((nt + 8) / 9)), dim3(256), 0, st, g->cell_pkg, g->pkg_cell,
                        (int)M, nt, g->nbr, g->face);
     SG_HIP_OR_FREE(hipGetLastError());
     // Morton-order sweep worklist: count activated codes per block of
