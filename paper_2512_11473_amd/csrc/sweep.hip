@@ -51,6 +51,34 @@ __device__ __forceinline__ void store_row<double>(double *__restrict__ p, const 
     reinterpret_cast<double2 *>(p)[1] = make_double2(r.v[2], r.v[3]);
 }
 
+// The same row written with the streaming (non-temporal) hint: used by the
+// sweeps when the two field buffers do not fit in the last-level cache, where
+// the freshly written rows would only push out halo lines that the running
+// sweep still reads.  When the buffers fit, the hint would keep the written
+// rows out of the cache that the next sweep reads them from.
+typedef float f32x4v __attribute__((ext_vector_type(4)));
+typedef double f64x2v __attribute__((ext_vector_type(2)));
+template <typename T>
+__device__ __forceinline__ void store_row_nt(T *__restrict__ p, const Row<T> &r);
+template <>
+__device__ __forceinline__ void store_row_nt<float>(float *__restrict__ p, const Row<float> &r) {
+    const f32x4v v = {r.v[0], r.v[1], r.v[2], r.v[3]};
+    __builtin_nontemporal_store(v, reinterpret_cast<f32x4v *>(p));
+}
+template <>
+__device__ __forceinline__ void store_row_nt<double>(double *__restrict__ p, const Row<double> &r) {
+    const f64x2v a = {r.v[0], r.v[1]}, b = {r.v[2], r.v[3]};
+    __builtin_nontemporal_store(a, reinterpret_cast<f64x2v *>(p));
+    __builtin_nontemporal_store(b, reinterpret_cast<f64x2v *>(p) + 1);
+}
+template <typename T>
+__device__ __forceinline__ void store_row(T *__restrict__ p, const Row<T> &r, bool nt) {
+    if (nt)
+        store_row_nt(p, r);
+    else
+        store_row(p, r);
+}
+
 // A package row and its stencil neighbours.
 template <typename T>
 struct Stencil {
@@ -147,7 +175,7 @@ __device__ __forceinline__ Row<T> reinit_row(const Stencil<T> &s, T h2, T inv_h,
 template <typename T, int G>
 __global__ __launch_bounds__(256) void reinit_dpp_kernel(const T *__restrict__ src, T *__restrict__ dst,
                                                          const uint32_t *__restrict__ face, int64_t first,
-                                                         int64_t end, int64_t n_blocks, T h2, T inv_h, T dt) {
+                                                         int64_t end, int64_t n_blocks, T h2, T inv_h, T dt, bool nt) {
     const int64_t b = xcd_block(blockIdx.x, n_blocks);
     const int lane = threadIdx.x & 63;
     const int r = lane & 15;
@@ -159,7 +187,7 @@ __global__ __launch_bounds__(256) void reinit_dpp_kernel(const T *__restrict__ s
 #pragma unroll
     for (int g = 0; g < G; ++g) {
         const Stencil<T> s = assemble(r, l[g]);
-        if (p0 + 4 * g < end) store_row(dst + (p0 + 4 * g) * 64 + r * 4, reinit_row(s, h2, inv_h, dt));
+        if (p0 + 4 * g < end) store_row(dst + (p0 + 4 * g) * 64 + r * 4, reinit_row(s, h2, inv_h, dt), nt);
     }
 }
 
@@ -172,7 +200,7 @@ __global__ __launch_bounds__(256) void reinit_dpp_kernel(const T *__restrict__ s
 template <typename T, int G>
 __global__ __launch_bounds__(256) void reinit_work_kernel(const T *__restrict__ src, T *__restrict__ dst,
                                                           const uint32_t *__restrict__ wface, int64_t P,
-                                                          int64_t n_blocks, T h2, T inv_h, T dt) {
+                                                          int64_t n_blocks, T h2, T inv_h, T dt, bool nt) {
     const int64_t b = xcd_block(blockIdx.x, n_blocks);
     const int lane = threadIdx.x & 63;
     const int r = lane & 15;
@@ -193,7 +221,7 @@ __global__ __launch_bounds__(256) void reinit_work_kernel(const T *__restrict__ 
 #pragma unroll
     for (int g = 0; g < G; ++g) {
         const Stencil<T> s = assemble(r, l[g]);
-        if (p[g] >= 0) store_row(dst + p[g] * 64 + r * 4, reinit_row(s, h2, inv_h, dt));
+        if (p[g] >= 0) store_row(dst + p[g] * 64 + r * 4, reinit_row(s, h2, inv_h, dt), nt);
     }
 }
 
@@ -206,7 +234,7 @@ __global__ __launch_bounds__(256) void reinit_work_kernel(const T *__restrict__ 
 template <typename T, int G>
 __global__ __launch_bounds__(256) void reinit_rows_kernel(const T *__restrict__ src, T *__restrict__ dst,
                                                           const uint32_t *__restrict__ face, int64_t P,
-                                                          int64_t n_blocks, T h2, T inv_h, T dt) {
+                                                          int64_t n_blocks, T h2, T inv_h, T dt, bool nt) {
     __shared__ Row<T> rows[16][36];   // [package slot in block][(z+1) * 6 + (y+1)]
     const int64_t b = xcd_block(blockIdx.x, n_blocks);
     const int lane = threadIdx.x & 63;
@@ -236,7 +264,7 @@ __global__ __launch_bounds__(256) void reinit_rows_kernel(const T *__restrict__ 
         s.zm = R[k * 6 + (j + 1)];
         s.zp = R[(k + 2) * 6 + (j + 1)];
         __builtin_amdgcn_wave_barrier();
-        if (p < P + 2) store_row(dst + p * 64 + r * 4, reinit_row(s, h2, inv_h, dt));
+        if (p < P + 2) store_row(dst + p * 64 + r * 4, reinit_row(s, h2, inv_h, dt), nt);
     }
 }
 
@@ -311,7 +339,7 @@ __global__ __launch_bounds__(1024) void reinit_share_kernel(const T *__restrict_
 template <typename T>
 __global__ __launch_bounds__(256) void reinit_pipe_kernel(const T *__restrict__ src, T *__restrict__ dst,
                                                           const uint32_t *__restrict__ wface, int64_t P,
-                                                          int64_t n_blocks, T h2, T inv_h, T dt) {
+                                                          int64_t n_blocks, T h2, T inv_h, T dt, bool nt) {
     const int64_t b = xcd_block(blockIdx.x, n_blocks);
     const int lane = threadIdx.x & 63;
     const int r = lane & 15;
@@ -337,7 +365,7 @@ __global__ __launch_bounds__(256) void reinit_pipe_kernel(const T *__restrict__ 
         Loads<T> l;
         issue_data(src, p, r, c0, cz, l);
         const Stencil<T> st = assemble(r, l);
-        store_row(dst + p * 64 + r * 4, reinit_row(st, h2, inv_h, dt));
+        store_row(dst + p * 64 + r * 4, reinit_row(st, h2, inv_h, dt), nt);
     }
 }
 
@@ -575,19 +603,22 @@ bool stencil_in_worklist_order() {
     return g_sweep_cfg.variant == 2 || g_sweep_cfg.variant == 3 || g_sweep_cfg.variant == 4;
 }
 
+// MI355X's Infinity Cache (the last level before HBM)
+constexpr double kLastLevelCacheBytes = 256.0 * 1024 * 1024;
+
 template <typename T>
 static void launch_dpp_range(const sgrid_grid *g, const T *src, T *dst, int64_t first, int64_t end, int groups,
-                             hipStream_t st) {
+                             bool nt, hipStream_t st) {
     const int64_t per_block = 16 * (int64_t)groups;
     const int64_t nb = (end - first + per_block - 1) / per_block;
     const T h2 = (T)(g->h * g->h), inv_h = (T)(1.0 / g->h), dt = (T)(0.5 * g->h);
     const dim3 grid((unsigned)nb), block(256);
     switch (groups) {
-        case 1: hipLaunchKernelGGL((reinit_dpp_kernel<T, 1>), grid, block, 0, st, src, dst, g->face, first, end, nb, h2, inv_h, dt); break;
-        case 2: hipLaunchKernelGGL((reinit_dpp_kernel<T, 2>), grid, block, 0, st, src, dst, g->face, first, end, nb, h2, inv_h, dt); break;
-        case 3: hipLaunchKernelGGL((reinit_dpp_kernel<T, 3>), grid, block, 0, st, src, dst, g->face, first, end, nb, h2, inv_h, dt); break;
-        case 4: hipLaunchKernelGGL((reinit_dpp_kernel<T, 4>), grid, block, 0, st, src, dst, g->face, first, end, nb, h2, inv_h, dt); break;
-        default: hipLaunchKernelGGL((reinit_dpp_kernel<T, 8>), grid, block, 0, st, src, dst, g->face, first, end, nb, h2, inv_h, dt); break;
+        case 1: hipLaunchKernelGGL((reinit_dpp_kernel<T, 1>), grid, block, 0, st, src, dst, g->face, first, end, nb, h2, inv_h, dt, nt); break;
+        case 2: hipLaunchKernelGGL((reinit_dpp_kernel<T, 2>), grid, block, 0, st, src, dst, g->face, first, end, nb, h2, inv_h, dt, nt); break;
+        case 3: hipLaunchKernelGGL((reinit_dpp_kernel<T, 3>), grid, block, 0, st, src, dst, g->face, first, end, nb, h2, inv_h, dt, nt); break;
+        case 4: hipLaunchKernelGGL((reinit_dpp_kernel<T, 4>), grid, block, 0, st, src, dst, g->face, first, end, nb, h2, inv_h, dt, nt); break;
+        default: hipLaunchKernelGGL((reinit_dpp_kernel<T, 8>), grid, block, 0, st, src, dst, g->face, first, end, nb, h2, inv_h, dt, nt); break;
     }
 }
 
@@ -599,6 +630,8 @@ static sgrid_status launch_reinit_sweep(const sgrid_grid *g, const T *src, T *ds
     const int64_t nb = (g->P + per_block - 1) / per_block;
     const T h2 = (T)(g->h * g->h), inv_h = (T)(1.0 / g->h), dt = (T)(0.5 * g->h);
     const dim3 grid((unsigned)nb), block(256);
+    // streaming stores when the two field buffers exceed the last-level cache
+    const bool nt = 2.0 * (double)g->total() * 64.0 * sizeof(T) > kLastLevelCacheBytes;
     if (cfg.variant == 6) {
         const int64_t n_sets = (g->P + 3) / 4;
         const int64_t nbp = std::min<int64_t>((int64_t)cu_count() * cfg.groups, (n_sets + 3) / 4);
@@ -606,11 +639,11 @@ static sgrid_status launch_reinit_sweep(const sgrid_grid *g, const T *src, T *ds
                            h2, inv_h, dt);
     } else if (cfg.variant == 5) {
         switch (cfg.groups) {
-            case 1: hipLaunchKernelGGL((reinit_rows_kernel<T, 1>), grid, block, 0, st, src, dst, g->face, g->P, nb, h2, inv_h, dt); break;
-            case 2: hipLaunchKernelGGL((reinit_rows_kernel<T, 2>), grid, block, 0, st, src, dst, g->face, g->P, nb, h2, inv_h, dt); break;
-            case 3: hipLaunchKernelGGL((reinit_rows_kernel<T, 3>), grid, block, 0, st, src, dst, g->face, g->P, nb, h2, inv_h, dt); break;
-            case 4: hipLaunchKernelGGL((reinit_rows_kernel<T, 4>), grid, block, 0, st, src, dst, g->face, g->P, nb, h2, inv_h, dt); break;
-            default: hipLaunchKernelGGL((reinit_rows_kernel<T, 8>), grid, block, 0, st, src, dst, g->face, g->P, nb, h2, inv_h, dt); break;
+            case 1: hipLaunchKernelGGL((reinit_rows_kernel<T, 1>), grid, block, 0, st, src, dst, g->face, g->P, nb, h2, inv_h, dt, nt); break;
+            case 2: hipLaunchKernelGGL((reinit_rows_kernel<T, 2>), grid, block, 0, st, src, dst, g->face, g->P, nb, h2, inv_h, dt, nt); break;
+            case 3: hipLaunchKernelGGL((reinit_rows_kernel<T, 3>), grid, block, 0, st, src, dst, g->face, g->P, nb, h2, inv_h, dt, nt); break;
+            case 4: hipLaunchKernelGGL((reinit_rows_kernel<T, 4>), grid, block, 0, st, src, dst, g->face, g->P, nb, h2, inv_h, dt, nt); break;
+            default: hipLaunchKernelGGL((reinit_rows_kernel<T, 8>), grid, block, 0, st, src, dst, g->face, g->P, nb, h2, inv_h, dt, nt); break;
         }
     } else if (cfg.variant == 4) {
         const int64_t ng = (g->P + kGroup - 1) / kGroup;
@@ -618,22 +651,22 @@ static sgrid_status launch_reinit_sweep(const sgrid_grid *g, const T *src, T *ds
                            g->P, ng, h2, inv_h, dt);
     } else if (cfg.variant == 3) {
         switch (cfg.groups) {
-            case 1: hipLaunchKernelGGL((reinit_work_kernel<T, 1>), grid, block, 0, st, src, dst, g->wface, g->P, nb, h2, inv_h, dt); break;
-            case 2: hipLaunchKernelGGL((reinit_work_kernel<T, 2>), grid, block, 0, st, src, dst, g->wface, g->P, nb, h2, inv_h, dt); break;
-            case 3: hipLaunchKernelGGL((reinit_work_kernel<T, 3>), grid, block, 0, st, src, dst, g->wface, g->P, nb, h2, inv_h, dt); break;
-            case 4: hipLaunchKernelGGL((reinit_work_kernel<T, 4>), grid, block, 0, st, src, dst, g->wface, g->P, nb, h2, inv_h, dt); break;
-            default: hipLaunchKernelGGL((reinit_work_kernel<T, 8>), grid, block, 0, st, src, dst, g->wface, g->P, nb, h2, inv_h, dt); break;
+            case 1: hipLaunchKernelGGL((reinit_work_kernel<T, 1>), grid, block, 0, st, src, dst, g->wface, g->P, nb, h2, inv_h, dt, nt); break;
+            case 2: hipLaunchKernelGGL((reinit_work_kernel<T, 2>), grid, block, 0, st, src, dst, g->wface, g->P, nb, h2, inv_h, dt, nt); break;
+            case 3: hipLaunchKernelGGL((reinit_work_kernel<T, 3>), grid, block, 0, st, src, dst, g->wface, g->P, nb, h2, inv_h, dt, nt); break;
+            case 4: hipLaunchKernelGGL((reinit_work_kernel<T, 4>), grid, block, 0, st, src, dst, g->wface, g->P, nb, h2, inv_h, dt, nt); break;
+            default: hipLaunchKernelGGL((reinit_work_kernel<T, 8>), grid, block, 0, st, src, dst, g->wface, g->P, nb, h2, inv_h, dt, nt); break;
         }
     } else if (cfg.variant == 2) {
         const int64_t n_sets = (g->P + 3) / 4;
         const int64_t nbp = std::min<int64_t>((int64_t)cu_count() * cfg.groups, (n_sets + 3) / 4);
         hipLaunchKernelGGL(reinit_pipe_kernel<T>, dim3((unsigned)nbp), block, 0, st, src, dst, g->wface, g->P, nbp,
-                           h2, inv_h, dt);
+                           h2, inv_h, dt, nt);
     } else if (cfg.variant == 1) {
         hipLaunchKernelGGL(reinit_lds_kernel<T>, grid, block, 0, st, src, dst, g->face, g->P, nb, cfg.groups, h2,
                            inv_h, dt);
     } else {
-        launch_dpp_range<T>(g, src, dst, 2, 2 + g->P, cfg.groups, st);
+        launch_dpp_range<T>(g, src, dst, 2, 2 + g->P, cfg.groups, nt, st);
     }
     SG_CHECK_LAUNCH("reinit sweep");
     return SGRID_OK;
