@@ -38,8 +38,16 @@ __device__ __forceinline__ Row4<float> ld_row(const float *__restrict__ p) {
     const float4 a = *reinterpret_cast<const float4 *>(p);
     return Row4<float>{{a.x, a.y, a.z, a.w}};
 }
-__device__ __forceinline__ void st_row(float *__restrict__ p, const Row4<float> &r) {
-    *reinterpret_cast<float4 *>(p) = make_float4(r.v[0], r.v[1], r.v[2], r.v[3]);
+// nt: the streaming (non-temporal) hint, for ping-pong buffers larger than the
+// last-level cache (the written rows would only push out lines the running
+// sweep still reads)
+__device__ __forceinline__ void st_row(float *__restrict__ p, const Row4<float> &r, bool nt) {
+    typedef float f4v __attribute__((ext_vector_type(4)));
+    const f4v v = {r.v[0], r.v[1], r.v[2], r.v[3]};
+    if (nt)
+        __builtin_nontemporal_store(v, reinterpret_cast<f4v *>(p));
+    else
+        *reinterpret_cast<f4v *>(p) = v;
 }
 
 struct Halo {
@@ -92,7 +100,7 @@ __device__ __forceinline__ Row4<float> update_row_dpp(int r, const Halo &l, cons
 __global__ __launch_bounds__(256) void batch_dpp_kernel(const float *__restrict__ src, float *__restrict__ dst,
                                                         const uint32_t *__restrict__ wrow, int64_t n_work,
                                                         const sgrid::SweepParams<float> *__restrict__ params,
-                                                        int64_t n_blocks, int64_t spw) {
+                                                        int64_t n_blocks, int64_t spw, bool nt) {
     const int64_t b = xcd_block(blockIdx.x, n_blocks);
     const int lane = threadIdx.x & 63, r = lane & 15;
     const int64_t wave = b * 4 + (threadIdx.x >> 6);
@@ -107,7 +115,7 @@ __global__ __launch_bounds__(256) void batch_dpp_kernel(const float *__restrict_
         if (live) batch_loads(src, wrow, e, r, l, g, shape);
         const sgrid::SweepParams<float> sp = params[shape];
         const Row4<float> o = update_row_dpp(r, l, sp);
-        if (live) st_row(dst + g * 64 + r * 4, o);
+        if (live) st_row(dst + g * 64 + r * 4, o, nt);
     }
 }
 
@@ -115,7 +123,7 @@ __global__ __launch_bounds__(256) void batch_dpp_kernel(const float *__restrict_
 __global__ __launch_bounds__(256) void batch_lds_kernel(const float *__restrict__ src, float *__restrict__ dst,
                                                         const uint32_t *__restrict__ wrow, int64_t n_work,
                                                         const sgrid::SweepParams<float> *__restrict__ params,
-                                                        int64_t n_blocks, int64_t spw) {
+                                                        int64_t n_blocks, int64_t spw, bool nt) {
     __shared__ float tile[16][216];
     const int64_t b = xcd_block(blockIdx.x, n_blocks);
     const int lane = threadIdx.x & 63, r = lane & 15, j = r & 3, k = r >> 2;
@@ -156,7 +164,7 @@ __global__ __launch_bounds__(256) void batch_lds_kernel(const float *__restrict_
             for (int i = 0; i < 4; ++i)
                 o.v[i] = sgrid::upwind_update(t[at(i, j, k)], t[at(i - 1, j, k)], t[at(i + 1, j, k)], t[at(i, j - 1, k)],
                                 t[at(i, j + 1, k)], t[at(i, j, k - 1)], t[at(i, j, k + 1)], sp.h2, sp.inv_h, sp.dt);
-            st_row(dst + g * 64 + r * 4, o);
+            st_row(dst + g * 64 + r * 4, o, nt);
         }
         __syncthreads();
     }
@@ -216,12 +224,13 @@ sgrid_status launch_batch_sweep(const sgrid_batch *b, const float *src, float *d
     int64_t nb = bpc > 0 ? (int64_t)sgrid::cu_count() * bpc : (n_sets + 3) / 4;
     const int64_t spw = (n_sets + nb * 4 - 1) / (nb * 4);
     nb = (n_sets + spw * 4 - 1) / (spw * 4);
+    const bool nt = 2.0 * (double)b->n_total * 64.0 * sizeof(float) > 256.0 * 1024 * 1024;   // Infinity Cache
     if (variant == 1)
         hipLaunchKernelGGL(batch_lds_kernel, dim3((unsigned)nb), dim3(256), 0, st, src, dst, b->wrow, b->n_work,
-                           b->params, nb, spw);
+                           b->params, nb, spw, nt);
     else
         hipLaunchKernelGGL(batch_dpp_kernel, dim3((unsigned)nb), dim3(256), 0, st, src, dst, b->wrow, b->n_work,
-                           b->params, nb, spw);
+                           b->params, nb, spw, nt);
     SG_CHECK_LAUNCH("batch sweep");
     return SGRID_OK;
 }

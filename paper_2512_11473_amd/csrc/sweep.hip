@@ -481,7 +481,7 @@ template <typename T, bool PACKED, bool WORK>
 __global__ __launch_bounds__(256) void gradient_kernel(const T *__restrict__ phi, T *__restrict__ out,
                                                        const uint32_t *__restrict__ face,
                                                        const uint32_t *__restrict__ wface, int64_t n_total,
-                                                       int64_t n_blocks, T inv_2h) {
+                                                       int64_t n_blocks, T inv_2h, bool nt) {
     const int64_t b = xcd_block(blockIdx.x, n_blocks);
     const int lane = threadIdx.x & 63;
     const int r = lane & 15;
@@ -514,12 +514,12 @@ __global__ __launch_bounds__(256) void gradient_kernel(const T *__restrict__ phi
         T *o = out + p * 64 * 4;
 #pragma unroll
         for (int i = 0; i < 4; ++i)
-            store_row(o + 4 * blocked_index(i, j, k), Row<T>{{c.v[i], ox.v[i], oy.v[i], oz.v[i]}});
+            store_row(o + 4 * blocked_index(i, j, k), Row<T>{{c.v[i], ox.v[i], oy.v[i], oz.v[i]}}, nt);
     } else {
         T *gx = out + p * 64 + r * 4;
-        store_row(gx, ox);
-        store_row(gx + n_total * 64, oy);
-        store_row(gx + 2 * n_total * 64, oz);
+        store_row(gx, ox, nt);
+        store_row(gx + n_total * 64, oy, nt);
+        store_row(gx + 2 * n_total * 64, oz, nt);
     }
 }
 
@@ -545,7 +545,7 @@ template <typename T, bool WORK>
 __global__ __launch_bounds__(256) void laplacian_kernel(const T *__restrict__ phi, T *__restrict__ out,
                                                         const uint32_t *__restrict__ face,
                                                         const uint32_t *__restrict__ wface, int64_t n_total,
-                                                        int64_t n_blocks, T inv_h2) {
+                                                        int64_t n_blocks, T inv_h2, bool nt) {
     const int64_t b = xcd_block(blockIdx.x, n_blocks);
     const int lane = threadIdx.x & 63;
     const int r = lane & 15;
@@ -570,7 +570,7 @@ __global__ __launch_bounds__(256) void laplacian_kernel(const T *__restrict__ ph
             o.v[i] = fma(T(-6), s.c.v[i], sum) * inv_h2;
         }
     }
-    store_row(out + p * 64 + r * 4, o);
+    store_row(out + p * 64 + r * 4, o, nt);
 }
 
 template <typename T>
@@ -808,20 +808,23 @@ static sgrid_status gradient_entry(const sgrid_grid *g, sgrid_dtype dtype, const
     const int64_t nt = g->total();
     const int64_t nb = (nt + 15) / 16;
     const bool work = sgrid::stencil_in_worklist_order();
+    // streaming stores when phi and the output together exceed the last-level cache
+    const bool stream_out =
+        (double)nt * 64.0 * (dtype == SGRID_F32 ? 4.0 : 8.0) * (PACKED ? 5.0 : 4.0) > sgrid::kLastLevelCacheBytes;
     if (dtype == SGRID_F32) {
         if (work)
             hipLaunchKernelGGL((gradient_kernel<float, PACKED, true>), dim3((unsigned)nb), dim3(256), 0, st,
-                               (const float *)phi, (float *)out, g->face, g->wface, nt, nb, (float)(0.5 / g->h));
+                               (const float *)phi, (float *)out, g->face, g->wface, nt, nb, (float)(0.5 / g->h), stream_out);
         else
             hipLaunchKernelGGL((gradient_kernel<float, PACKED, false>), dim3((unsigned)nb), dim3(256), 0, st,
-                               (const float *)phi, (float *)out, g->face, g->wface, nt, nb, (float)(0.5 / g->h));
+                               (const float *)phi, (float *)out, g->face, g->wface, nt, nb, (float)(0.5 / g->h), stream_out);
     } else {
         if (work)
             hipLaunchKernelGGL((gradient_kernel<double, PACKED, true>), dim3((unsigned)nb), dim3(256), 0, st,
-                               (const double *)phi, (double *)out, g->face, g->wface, nt, nb, 0.5 / g->h);
+                               (const double *)phi, (double *)out, g->face, g->wface, nt, nb, 0.5 / g->h, stream_out);
         else
             hipLaunchKernelGGL((gradient_kernel<double, PACKED, false>), dim3((unsigned)nb), dim3(256), 0, st,
-                               (const double *)phi, (double *)out, g->face, g->wface, nt, nb, 0.5 / g->h);
+                               (const double *)phi, (double *)out, g->face, g->wface, nt, nb, 0.5 / g->h, stream_out);
     }
     SG_CHECK_LAUNCH("gradient sweep");
     return SGRID_OK;
@@ -867,22 +870,24 @@ extern "C" sgrid_status sgrid_compute_laplacian(const sgrid_grid *g, sgrid_dtype
     const int64_t nt = g->total();
     const int64_t nb = (nt + 15) / 16;
     const bool work = sgrid::stencil_in_worklist_order();
+    // streaming stores when phi and the output together exceed the last-level cache
+    const bool stream_out = (double)nt * 64.0 * (dtype == SGRID_F32 ? 4.0 : 8.0) * 2.0 > sgrid::kLastLevelCacheBytes;
     if (dtype == SGRID_F32) {
         if (work)
             hipLaunchKernelGGL((laplacian_kernel<float, true>), dim3((unsigned)nb), dim3(256), 0, st,
                                (const float *)phi, (float *)out, g->face, g->wface, nt, nb,
-                               (float)(1.0 / (g->h * g->h)));
+                               (float)(1.0 / (g->h * g->h)), stream_out);
         else
             hipLaunchKernelGGL((laplacian_kernel<float, false>), dim3((unsigned)nb), dim3(256), 0, st,
                                (const float *)phi, (float *)out, g->face, g->wface, nt, nb,
-                               (float)(1.0 / (g->h * g->h)));
+                               (float)(1.0 / (g->h * g->h)), stream_out);
     } else {
         if (work)
             hipLaunchKernelGGL((laplacian_kernel<double, true>), dim3((unsigned)nb), dim3(256), 0, st,
-                               (const double *)phi, (double *)out, g->face, g->wface, nt, nb, 1.0 / (g->h * g->h));
+                               (const double *)phi, (double *)out, g->face, g->wface, nt, nb, 1.0 / (g->h * g->h), stream_out);
         else
             hipLaunchKernelGGL((laplacian_kernel<double, false>), dim3((unsigned)nb), dim3(256), 0, st,
-                               (const double *)phi, (double *)out, g->face, g->wface, nt, nb, 1.0 / (g->h * g->h));
+                               (const double *)phi, (double *)out, g->face, g->wface, nt, nb, 1.0 / (g->h * g->h), stream_out);
     }
     SG_CHECK_LAUNCH("laplacian");
     return SGRID_OK;
