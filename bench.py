@@ -63,6 +63,8 @@ def parse():
     ap.add_argument("--train-cells", type=int, default=2_000_000)
     ap.add_argument("--epochs", type=int, default=300)
     ap.add_argument("--train-batch", type=int, default=2048)
+    ap.add_argument("--serial", action="store_true",
+                    help="run the whole step on one stream (no overlap of the integrals with the probe)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one 256 MiB device copy first (counter calibration under rocprofv3)")
     return ap.parse_args()
@@ -267,29 +269,29 @@ def bench_single(args, log):
     n_core = wl.grid.n_core
     integ = torch.empty((4, n_core * 64), device="cuda")
     packed = torch.empty((wl.grid.n_total, 64, 4), device="cuda")
+    # the step runs on a stream of its own rather than the legacy default
+    # stream, beside the second stream below
+    torch.cuda.synchronize()
+    torch.cuda.set_stream(torch.cuda.Stream())
     stream = torch.cuda.current_stream()
 
     ev = {k: [torch.cuda.Event(enable_timing=True) for _ in range(2)] for k in
           ("build", "reinit", "grad", "probe", "integ")}
     acc = {k: 0.0 for k in ev}
 
-    # a second stream (default priority) for work that does not depend on the
-    # main chain: the phi reset beside the build, the integrals (VALU-bound)
-    # beside the gradient and the probe (memory-bound)
-    side = torch.cuda.Stream()
-    ev_copy, ev_reinit, ev_integ = (torch.cuda.Event() for _ in range(3))
+    # a second stream (default priority) for the integrals (VALU-bound), which
+    # run beside the gradient and the probe (memory-bound)
+    side = stream if args.serial else torch.cuda.Stream()
+    ev_reinit, ev_integ = torch.cuda.Event(), torch.cuda.Event()
 
     def step(record):
         def mark(k, i, st=stream):
             if record:
                 ev[k][i].record(st)
-        with torch.cuda.stream(side):
-            wl.phi.copy_(wl.phi0)
-            ev_copy.record(side)
         mark("build", 0)
         g = sg.build_packages(wl.coarse, wl.h)
         mark("build", 1)
-        stream.wait_event(ev_copy)
+        wl.phi.copy_(wl.phi0)
         mark("reinit", 0)
         sg.reinitialize(g, wl.phi, wl.scratch, cfg["n_iter"])
         mark("reinit", 1)
