@@ -63,8 +63,9 @@ def parse():
     ap.add_argument("--train-cells", type=int, default=2_000_000)
     ap.add_argument("--epochs", type=int, default=300)
     ap.add_argument("--train-batch", type=int, default=2048)
-    ap.add_argument("--serial", action="store_true",
-                    help="run the whole step on one stream (no overlap of the integrals with the probe)")
+    ap.add_argument("--overlap", action="store_true",
+                    help="run the integrals on a second stream beside the gradient and the probe (a shorter step "
+                         "at torus2048, a slightly slower sweep at prism512)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one 256 MiB device copy first (counter calibration under rocprofv3)")
     return ap.parse_args()
@@ -269,8 +270,7 @@ def bench_single(args, log):
     n_core = wl.grid.n_core
     integ = torch.empty((4, n_core * 64), device="cuda")
     packed = torch.empty((wl.grid.n_total, 64, 4), device="cuda")
-    # the step runs on a stream of its own rather than the legacy default
-    # stream, beside the second stream below
+    # the step runs on a stream of its own rather than the legacy default stream
     torch.cuda.synchronize()
     torch.cuda.set_stream(torch.cuda.Stream())
     stream = torch.cuda.current_stream()
@@ -279,9 +279,10 @@ def bench_single(args, log):
           ("build", "reinit", "grad", "probe", "integ")}
     acc = {k: 0.0 for k in ev}
 
-    # a second stream (default priority) for the integrals (VALU-bound), which
-    # run beside the gradient and the probe (memory-bound)
-    side = stream if args.serial else torch.cuda.Stream()
+    # with --overlap a second stream (default priority) takes the integrals
+    # (VALU-bound), which then run beside the gradient and the probe (memory-
+    # bound); by default every step runs on one stream
+    side = torch.cuda.Stream() if args.overlap else stream
     ev_reinit, ev_integ = torch.cuda.Event(), torch.cuda.Event()
 
     def step(record):
