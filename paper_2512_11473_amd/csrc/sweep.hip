@@ -808,9 +808,11 @@ static sgrid_status gradient_entry(const sgrid_grid *g, sgrid_dtype dtype, const
     const int64_t nt = g->total();
     const int64_t nb = (nt + 15) / 16;
     const bool work = sgrid::stencil_in_worklist_order();
-    // streaming stores when phi and the output together exceed the last-level cache
+    // streaming stores when phi and the output together exceed the last-level
+    // cache; not for the packed layout, whose four stores per lane each fill
+    // only parts of lines (the cache merges them, streaming writes would not)
     const bool stream_out =
-        (double)nt * 64.0 * (dtype == SGRID_F32 ? 4.0 : 8.0) * (PACKED ? 5.0 : 4.0) > sgrid::kLastLevelCacheBytes;
+        !PACKED && (double)nt * 64.0 * (dtype == SGRID_F32 ? 4.0 : 8.0) * 4.0 > sgrid::kLastLevelCacheBytes;
     if (dtype == SGRID_F32) {
         if (work)
             hipLaunchKernelGGL((gradient_kernel<float, PACKED, true>), dim3((unsigned)nb), dim3(256), 0, st,
