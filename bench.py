@@ -270,9 +270,9 @@ def bench_single(args, log):
     n_core = wl.grid.n_core
     integ = torch.empty((4, n_core * 64), device="cuda")
     packed = torch.empty((wl.grid.n_total, 64, 4), device="cuda")
-    # the step runs on a stream of its own rather than the legacy default stream
-    torch.cuda.synchronize()
-    torch.cuda.set_stream(torch.cuda.Stream())
+    if args.overlap:   # the step on a stream of its own, the integrals on a second one
+        torch.cuda.synchronize()
+        torch.cuda.set_stream(torch.cuda.Stream())
     stream = torch.cuda.current_stream()
 
     ev = {k: [torch.cuda.Event(enable_timing=True) for _ in range(2)] for k in
