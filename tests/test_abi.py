@@ -71,6 +71,26 @@ def test_invalid_arguments_rejected_without_device(lib):
     lib.sgrid_autotune_sweep.argtypes = [P, ctypes.c_int, P, P, ctypes.c_int32, P, P, P, P]
     assert lib.sgrid_autotune_sweep(None, 0, P(16), P(32), 1, None, None, None, None) == E_INVALID
     assert lib.sgrid_autotune_sweep(P(64), 0, P(16), P(32), 0, None, None, None, None) == E_INVALID
+    # the multi-resolution layer, the sign correction and the integral field
+    lib.sgrid_build_packages_refined.argtypes = [P, P, P, P]
+    assert lib.sgrid_build_packages_refined(None, P(16), None, ctypes.byref(out)) == E_INVALID
+    assert lib.sgrid_build_packages_refined(P(64), P(16), None, None) == E_INVALID
+    lib.sgrid_correct_signs.argtypes = [P, P, P, P, P]
+    assert lib.sgrid_correct_signs(None, P(16), P(16), None, None) == E_INVALID
+    d = Desc(8, 0.1)
+    assert lib.sgrid_correct_signs(ctypes.byref(d), None, P(16), None, None) == E_INVALID
+    assert lib.sgrid_correct_signs(ctypes.byref(d), P(18), P(16), None, None) == E_INVALID   # misaligned
+    d = Desc(5000, 0.1)
+    assert lib.sgrid_correct_signs(ctypes.byref(d), P(16), P(16), None, None) == E_INVALID
+    d = Desc(8, 0.0)
+    assert lib.sgrid_correct_signs(ctypes.byref(d), P(16), P(16), None, None) == E_INVALID
+    lib.sgrid_compute_integral_field.argtypes = [P, P, P, P]
+    assert lib.sgrid_compute_integral_field(None, P(16), P(32), None) == E_INVALID
+    assert lib.sgrid_compute_integral_field(P(64), P(16), P(16), None) == E_INVALID   # aliased
+    lib.sgrid_probe_integral_field.argtypes = [P, P, P, ctypes.c_int64, P, P]
+    assert lib.sgrid_probe_integral_field(None, P(16), P(16), 1, P(16), None) == E_INVALID
+    assert lib.sgrid_probe_integral_field(P(64), P(16), P(16), -1, P(16), None) == E_INVALID
+    assert lib.sgrid_probe_integral_field(P(64), P(16), P(16), 0, P(16), None) == 0   # nothing to do
     lib.sgrid_destroy.argtypes = [P]
     assert lib.sgrid_destroy(None) == 0
     assert lib.sgrid_version() >= 10000
