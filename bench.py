@@ -356,6 +356,16 @@ def bench_single(args, log):
     g.destroy()
     del field, fout
     multires = multires_build(sg, synth, cfg, wl.grid, log)
+    # a plain device copy of one field buffer into another (the sweep's streams
+    # without its halos and face rows): the bandwidth this size reaches
+    copy_reps = 20
+    e0.record(stream)
+    for _ in range(copy_reps):
+        wl.scratch.copy_(wl.phi)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    copy_us = e0.elapsed_time(e1) * 1e3 / copy_reps
+    copy_gbps = 2 * wl.phi.numel() * wl.phi.element_size() / (copy_us * 1e-6) / 1e9
 
     K = args.steps
     ms_step = 1e3 * total_s / K
@@ -398,6 +408,7 @@ def bench_single(args, log):
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": measured_traffic(f"reinit_sweep_{cfg['name']}_counters.txt", f"v{tv}g{tg}"),
                      "avg_launch_us": sweep_ms * 1e3, "algorithmic_bytes_per_launch": bytes_launch,
+                     "copy_same_size_GBps": copy_gbps, "frac_of_copy": achieved / copy_gbps,
                      "note": ("phi ping-pong of 64 MB is resident in the 256 MB Infinity Cache"
                               if cfg["name"] == "prism512" else
                               "phi ping-pong of 0.9 GB streams from HBM")},
