@@ -11,12 +11,17 @@
 //   scan_pair       exclusive scan of the counts (block sums, one workgroup
 //                   over them, block scans);
 //   (host)          read back P and n_core once, allocate the package tables;
-//   scatter_kernel  rank inside each word by popcount below the lane, word
-//                   offsets from the scan: id = 2 + rank in ascending linear
-//                   order, so no sort is needed;
-//   nbr_kernel      one lane per (package, slot): the 27-entry neighbour table and
-//                   the six face slots copied into a 32-byte row per package;
-//   morton_*        the sweep worklist in Morton order of the cells.
+//   scatter_kernel  four words per wavefront, four cells per lane: rank by
+//                   popcount below the cell plus word offsets from the scan,
+//                   id = 2 + rank in ascending linear order (no sort needed);
+//                   the cell map in 16-byte stores, the rank map;
+//   nbr_kernel      27 lanes per package: the neighbour table and the six face
+//                   slots copied into a 32-byte row per package;
+//   morton_*        the sweep worklist in Morton order of the cells, one lane
+//                   per 4 x 4 x 4 box of codes.
+// The next layer of the multi-resolution construction replaces bits_kernel by
+// refine_bits_kernel (the parent layer's rank map and the children's
+// distances) and shares the rest.
 #include <stdarg.h>
 #include <stdlib.h>
 #include <string.h>
