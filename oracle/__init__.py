@@ -47,6 +47,7 @@ def lib():
         sig = {
             "orc_classify": (None, [i32, f64, P, P]),
             "orc_correct_signs": (i32, [i32, f64, P, P]),
+            "orc_correct_point_signs": (i32, [i32, P, i64, P, P]),
             "orc_number": (i64, [i32, P, P, P, P, P]),
             "orc_neighbours": (None, [i32, P, P, i64, P]),
             "orc_index_shift": (None, [i32, P, P]),
@@ -99,6 +100,20 @@ def correct_signs(M: int, d: np.ndarray, lc: Optional[float] = None):
     lc = 1.0 / M if lc is None else float(lc)
     out = np.empty_like(d)
     rounds = int(lib().orc_correct_signs(M, lc, _p(d), _p(out)))
+    return out, rounds
+
+
+def correct_point_signs(N: int, tab: "Tables", phi: np.ndarray):
+    """Sign correction of the inner packages' data points by diffusion from the
+    core packages and the far field (Sec. 7.2, refined step); phi is the dense
+    state (far-field constants outside the band).  Returns (corrected dense
+    phi, rounds)."""
+    inner = active_points(tab, pkg_types=(2,))
+    phi = np.ascontiguousarray(phi, dtype=np.float64)
+    if phi.shape != (N ** 3,):
+        raise ValueError(f"phi must be the dense field of N^3 = {N ** 3} values")
+    out = np.empty_like(phi)
+    rounds = int(lib().orc_correct_point_signs(N, _p(inner), inner.shape[0], _p(phi), _p(out)))
     return out, rounds
 
 

@@ -253,6 +253,65 @@ void orc_gradient(int32_t N, double h, double B, const int64_t *active, int64_t 
 }
 
 /* ------------------------------------------------------------------------ */
+/* Consistency (sign) correction, the refined step on the data packages      */
+/* (Sec. 7.2): on a refined layer the operation is limited to the inner       */
+/* packages.  The points of core packages keep their sign, like the core     */
+/* cells of the coarse step, and so do points outside the band (the far-field */
+/* constant of their cell; reads outside the domain are the positive far     */
+/* field).  The points of inner packages (`inner`, a list of linear indices)  */
+/* get their sign by diffusion over face neighbours, in rounds of            */
+/* simultaneous updates (positive if any decided neighbour is positive, else */
+/* negative), until a round changes nothing; they take |phi| with that sign, */
+/* or keep phi if no diffusion reaches them.  Returns the number of rounds   */
+/* that decided a point.                                                      */
+/* ------------------------------------------------------------------------ */
+int32_t orc_correct_point_signs(int32_t N, const int64_t *inner, int64_t n_inner, const double *phi, double *out)
+{
+    const int64_t n = (int64_t)N * N * N;
+    uint8_t *state = (uint8_t *)malloc((size_t)n), *next = (uint8_t *)malloc((size_t)n);
+    for (int64_t c = 0; c < n; ++c) state[c] = phi[c] < 0.0 ? 1 : 2;
+    for (int64_t q = 0; q < n_inner; ++q) state[inner[q]] = 0;
+    int32_t rounds = 0;
+    for (;;) {
+        int changed = 0;
+        memcpy(next, state, (size_t)n);
+#pragma omp parallel for schedule(static) reduction(| : changed)
+        for (int64_t q = 0; q < n_inner; ++q) {
+            const int64_t c = inner[q];
+            if (state[c]) continue;
+            const int64_t i = c % N, j = (c / N) % N, k = c / ((int64_t)N * N);
+            const int64_t nx[6] = {i - 1, i + 1, i, i, i, i}, ny[6] = {j, j, j - 1, j + 1, j, j},
+                          nz[6] = {k, k, k, k, k - 1, k + 1};
+            int pos = 0, neg = 0;
+            for (int f = 0; f < 6; ++f) {
+                uint8_t v;
+                if (nx[f] < 0 || ny[f] < 0 || nz[f] < 0 || nx[f] >= N || ny[f] >= N || nz[f] >= N) v = 2;
+                else v = state[lin3(nx[f], ny[f], nz[f], N)];
+                pos |= v == 2;
+                neg |= v == 1;
+            }
+            if (pos || neg) {
+                next[c] = pos ? 2 : 1;
+                changed = 1;
+            }
+        }
+        uint8_t *t = state;
+        state = next;
+        next = t;
+        if (!changed) break;
+        ++rounds;
+    }
+    memcpy(out, phi, (size_t)n * sizeof(double));
+    for (int64_t q = 0; q < n_inner; ++q) {
+        const int64_t c = inner[q];
+        if (state[c]) out[c] = state[c] == 2 ? fabs(phi[c]) : -fabs(phi[c]);
+    }
+    free(state);
+    free(next);
+    return rounds;
+}
+
+/* ------------------------------------------------------------------------ */
 /* The stencil operation of the paper's timing test (Sec. 9, Tab. 1): the     */
 /* seven-point Laplacian (sum of the six face neighbours - 6 phi) / h^2 at    */
 /* the listed active points; out-of-band neighbours read their far-field      */
