@@ -121,6 +121,22 @@ sgrid_status sgrid_correct_signs(const sgrid_desc *desc, const float *d_dev, flo
                                  int32_t *rounds_out);
 
 /*
+ * The refined step of the sign correction (Sec. 7.2: on a refined layer the
+ * correction is limited to inner cells or data packages), on phi_dev
+ * [P^][64] in place.  The points of core packages keep their sign, as the
+ * core cells do in sgrid_correct_signs, and so do the far-field packages
+ * (rows 0 and 1 must hold -B and +B; a neighbour outside the domain is the
+ * positive far field).  The points of inner packages get their sign by the
+ * same rounds of diffusion over face neighbours (positive if any decided
+ * neighbour is positive, else negative) and take |phi| with it; points no
+ * diffusion reaches keep phi.  *rounds_out (nullable) receives the number of
+ * rounds that decided a point.  Synchronises `stream` once per 16 rounds;
+ * workspace 2 bytes per point from the caching allocator.
+ */
+sgrid_status sgrid_correct_package_signs(const sgrid_grid *grid, sgrid_dtype dtype, void *phi_dev, void *stream,
+                                         int32_t *rounds_out);
+
+/*
  * The next layer of the multi-resolution construction (Sec. 7: layers of
  * successively doubled resolution, each initialised from the one before;
  * Sec. 7.1 step 1: a finer layer evaluates distances only in the cells that

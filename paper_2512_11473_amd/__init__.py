@@ -17,7 +17,8 @@ from typing import Optional
 import torch
 
 __all__ = [
-    "SgridError", "Grid", "load", "build_packages", "build_packages_refined", "correct_signs", "fill_far_field",
+    "SgridError", "Grid", "load", "build_packages", "build_packages_refined", "correct_signs",
+    "correct_package_signs", "fill_far_field",
     "reinitialize",
     "compute_gradient", "compute_gradient_packed", "probe_particles", "probe_particles_packed", "compute_near_surface_integrals", "set_sweep_config",
     "compute_integral_field", "probe_integral_field",
@@ -56,6 +57,7 @@ _SIGNATURES = {
     "sgrid_build_packages": (ctypes.c_int, [ctypes.POINTER(_Desc), _P, _P, ctypes.POINTER(_P)]),
     "sgrid_build_packages_refined": (ctypes.c_int, [_P, _P, _P, ctypes.POINTER(_P)]),
     "sgrid_correct_signs": (ctypes.c_int, [ctypes.POINTER(_Desc), _P, _P, _P, ctypes.POINTER(ctypes.c_int32)]),
+    "sgrid_correct_package_signs": (ctypes.c_int, [_P, ctypes.c_int, _P, _P, ctypes.POINTER(ctypes.c_int32)]),
     "sgrid_get_info": (ctypes.c_int, [_P, ctypes.POINTER(_Info)]),
     "sgrid_destroy": (ctypes.c_int, [_P]),
     "sgrid_fill_far_field": (ctypes.c_int, [_P, ctypes.c_int, _P, _P]),
@@ -254,6 +256,18 @@ def correct_signs(coarse_sdf: torch.Tensor, h: float, out: Optional[torch.Tensor
     rounds = ctypes.c_int32()
     _check(load().sgrid_correct_signs(ctypes.byref(desc), _dev(coarse_sdf, "coarse_sdf"), _dev(out, "out"),
                                       _stream(stream), ctypes.byref(rounds)))
+    return int(rounds.value)
+
+
+def correct_package_signs(grid: Grid, phi: torch.Tensor, stream=None) -> int:
+    """Sign correction of the inner packages' points of phi [P+2, 64] in place,
+    by diffusion from the core packages and the far field; returns the number
+    of rounds that decided a point."""
+    if phi.numel() != grid.n_total * 64:
+        raise ValueError("phi must be [P+2, 64]")
+    rounds = ctypes.c_int32()
+    _check(load().sgrid_correct_package_signs(grid.handle, _dtype_code(phi), _dev(phi, "phi"), _stream(stream),
+                                              ctypes.byref(rounds)))
     return int(rounds.value)
 
 

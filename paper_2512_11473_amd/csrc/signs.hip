@@ -184,3 +184,142 @@ extern "C" sgrid_status sgrid_correct_signs(const sgrid_desc *desc, const float 
     if (rounds_out) *rounds_out = rounds;
     return SGRID_OK;
 }
+
+// ---------------------------------------------------------------------------
+// The refined step on the data packages (Sec. 7.2: on a refined layer the
+// operation is limited to the inner packages).  The points of core packages
+// keep their sign, as the core cells do in the coarse step, and so do the
+// far-field packages (their constants; a neighbour outside the domain is the
+// positive far field, as in the neighbour table).  The points of inner
+// packages get their sign by the same rounds of diffusion over face
+// neighbours, reached through the six face slots of the package's face row;
+// state per point: 0 no sign, 1 negative, 2 positive.
+// ---------------------------------------------------------------------------
+namespace {
+
+template <typename T>
+__global__ __launch_bounds__(256) void point_sign_init_kernel(const T *__restrict__ phi,
+                                                              const uint8_t *__restrict__ pkg_type, int64_t n_points,
+                                                              uint8_t *__restrict__ state) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n_points) return;
+    const int64_t p = t >> 6;
+    state[t] = pkg_type[p] == 2 ? (uint8_t)0 : (phi[t] < T(0) ? (uint8_t)1 : (uint8_t)2);
+}
+
+__global__ __launch_bounds__(256) void point_sign_round_kernel(const uint8_t *__restrict__ state,
+                                                               const uint32_t *__restrict__ face, int64_t n_points,
+                                                               uint8_t *__restrict__ next,
+                                                               uint32_t *__restrict__ changed) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n_points) return;
+    const uint8_t s = state[t];
+    if (s) {
+        next[t] = s;
+        return;
+    }
+    const int64_t p = t >> 6;
+    const int l = (int)(t & 63), i = l & 3, j = (l >> 2) & 3, k = l >> 4;
+    const uint32_t *f = face + p * 8;
+    // the six face neighbours: inside the package, or across a face slot
+    const int64_t nb[6] = {
+        i > 0 ? t - 1 : (int64_t)f[0] * 64 + (l + 3),  i < 3 ? t + 1 : (int64_t)f[1] * 64 + (l - 3),
+        j > 0 ? t - 4 : (int64_t)f[2] * 64 + (l + 12), j < 3 ? t + 4 : (int64_t)f[3] * 64 + (l - 12),
+        k > 0 ? t - 16 : (int64_t)f[4] * 64 + (l + 48), k < 3 ? t + 16 : (int64_t)f[5] * 64 + (l - 48)};
+    bool pos = false, neg = false;
+#pragma unroll
+    for (int d = 0; d < 6; ++d) {
+        const uint8_t v = state[nb[d]];
+        pos = pos || v == 2;
+        neg = neg || v == 1;
+    }
+    const uint8_t o = pos ? 2 : (neg ? 1 : 0);
+    next[t] = o;
+    if (o) *changed = 1u;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void point_sign_apply_kernel(T *__restrict__ phi, const uint8_t *__restrict__ pkg_type,
+                                                               const uint8_t *__restrict__ state, int64_t n_points) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n_points) return;
+    const uint8_t s = state[t];
+    if (pkg_type[t >> 6] == 2 && s) phi[t] = s == 2 ? fabs(phi[t]) : -fabs(phi[t]);
+}
+
+template <typename T>
+sgrid_status correct_package_signs(const sgrid_grid *g, T *phi, hipStream_t st, int32_t *rounds_out) {
+    const int64_t n_points = g->total() * 64;
+    const int64_t nb = (n_points + 255) / 256;
+    uint8_t *mem = nullptr;
+    sgrid_status s = sgrid::dev_alloc((void **)&mem, (size_t)(2 * n_points + 256), "sign correction state");
+    if (s != SGRID_OK) return s;
+    uint8_t *state[2] = {mem, mem + n_points};
+    uint32_t *flags = reinterpret_cast<uint32_t *>(mem + ((2 * n_points + 3) / 4) * 4);
+    uint32_t *host = nullptr;
+    if (hipHostMalloc((void **)&host, kRoundsPerCheck * sizeof(uint32_t), hipHostMallocDefault) != hipSuccess) {
+        (void)hipGetLastError();
+        sgrid::dev_free(mem);
+        sgrid::set_error("pinned host flags could not be allocated");
+        return SGRID_E_NOMEM;
+    }
+    auto fail = [&](hipError_t e, const char *what) {
+        (void)hipStreamSynchronize(st);
+        sgrid::dev_free(mem);
+        (void)hipHostFree(host);
+        sgrid::set_error("%s failed: %s", what, hipGetErrorString(e));
+        return SGRID_E_HIP;
+    };
+    hipLaunchKernelGGL(point_sign_init_kernel<T>, dim3((unsigned)nb), dim3(256), 0, st, phi, g->pkg_type, n_points,
+                       state[0]);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(e, "point sign init");
+    int cur = 0;
+    int32_t rounds = 0;
+    bool done = false;
+    // every inner point lies within a few face steps of a core package, but
+    // the loop only ends on a round that changes nothing (or after as many
+    // rounds as there are points)
+    for (int64_t base = 0; !done && base < n_points + kRoundsPerCheck; base += kRoundsPerCheck) {
+        hipLaunchKernelGGL(clear_flags_kernel, dim3(1), dim3(64), 0, st, flags, kRoundsPerCheck);
+        for (int k = 0; k < kRoundsPerCheck; ++k) {
+            hipLaunchKernelGGL(point_sign_round_kernel, dim3((unsigned)nb), dim3(256), 0, st, state[cur], g->face,
+                               n_points, state[cur ^ 1], flags + k);
+            cur ^= 1;
+        }
+        e = hipGetLastError();
+        if (e != hipSuccess) return fail(e, "point sign rounds");
+        e = hipMemcpyAsync(host, flags, kRoundsPerCheck * sizeof(uint32_t), hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        if (e != hipSuccess) return fail(e, "point sign round flags");
+        for (int k = 0; k < kRoundsPerCheck; ++k) {
+            if (!host[k]) {
+                done = true;
+                break;
+            }
+            ++rounds;
+        }
+    }
+    hipLaunchKernelGGL(point_sign_apply_kernel<T>, dim3((unsigned)nb), dim3(256), 0, st, phi, g->pkg_type, state[cur],
+                       n_points);
+    e = hipGetLastError();
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return fail(e, "point sign apply");
+    sgrid::dev_free(mem);
+    (void)hipHostFree(host);
+    if (rounds_out) *rounds_out = rounds;
+    return SGRID_OK;
+}
+
+}  // namespace
+
+extern "C" sgrid_status sgrid_correct_package_signs(const sgrid_grid *g, sgrid_dtype dtype, void *phi, void *stream,
+                                                    int32_t *rounds_out) {
+    sgrid::clear_error();
+    SG_REQUIRE(g != nullptr && phi != nullptr, "NULL argument");
+    SG_REQUIRE(dtype == SGRID_F32 || dtype == SGRID_F64, "unknown dtype %d", (int)dtype);
+    SG_REQUIRE(sg_aligned(phi, dtype == SGRID_F32 ? 4 : 8), "phi is not aligned to its element size");
+    hipStream_t st = sg_stream(stream);
+    if (dtype == SGRID_F32) return correct_package_signs<float>(g, (float *)phi, st, rounds_out);
+    return correct_package_signs<double>(g, (double *)phi, st, rounds_out);
+}

@@ -84,6 +84,11 @@ def test_invalid_arguments_rejected_without_device(lib):
     assert lib.sgrid_correct_signs(ctypes.byref(d), P(16), P(16), None, None) == E_INVALID
     d = Desc(8, 0.0)
     assert lib.sgrid_correct_signs(ctypes.byref(d), P(16), P(16), None, None) == E_INVALID
+    lib.sgrid_correct_package_signs.argtypes = [P, ctypes.c_int, P, P, P]
+    assert lib.sgrid_correct_package_signs(None, 0, P(16), None, None) == E_INVALID
+    assert lib.sgrid_correct_package_signs(P(64), 0, None, None, None) == E_INVALID
+    assert lib.sgrid_correct_package_signs(P(64), 7, P(16), None, None) == E_INVALID
+    assert lib.sgrid_correct_package_signs(P(64), 1, P(20), None, None) == E_INVALID   # misaligned FP64
     lib.sgrid_compute_integral_field.argtypes = [P, P, P, P]
     assert lib.sgrid_compute_integral_field(None, P(16), P(32), None) == E_INVALID
     assert lib.sgrid_compute_integral_field(P(64), P(16), P(16), None) == E_INVALID   # aliased

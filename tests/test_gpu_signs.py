@@ -77,3 +77,47 @@ def test_torus2048_coarse_grid_repaired(sg):
     rounds = sg.correct_signs(x, 1.0 / cfg["N"])
     assert rounds > 10
     assert np.array_equal(x.cpu().numpy(), d)
+
+
+# the refined step on the data packages
+def _leaky_points(run, dense, seed, n_boxes=6):
+    N = run.N
+    rng = np.random.default_rng(seed)
+    bad = dense.copy()
+    inner = oracle.active_points(run.tab, pkg_types=(2,))
+    i, j, k = inner % N, (inner // N) % N, inner // (N * N)
+    for _ in range(n_boxes):
+        lo = rng.integers(0, N - 8, 3)
+        hi = lo + rng.integers(4, N // 3, 3)
+        sel = (i >= lo[0]) & (i < hi[0]) & (j >= lo[1]) & (j < hi[1]) & (k >= lo[2]) & (k < hi[2])
+        bad[inner[sel]] = -bad[inner[sel]]
+    return bad
+
+
+POINT_CASES = [
+    ("sphere64", synth.sphere((0.5, 0.5, 0.5), 0.3), 64, torch.float32),
+    ("union64-f64", synth.union([synth.sphere((0.3, 0.4, 0.5), 0.15),
+                                 synth.box((0.62, 0.6, 0.5), (0.2, 0.15, 0.2))]), 64, torch.float64),
+    ("shell128", synth.shell((0.5, 0.5, 0.5), 0.25, 0.32), 128, torch.float32),
+]
+
+
+@pytest.mark.parametrize("name,shape,N,dtype", POINT_CASES, ids=[c[0] for c in POINT_CASES])
+def test_package_sign_correction_matches_oracle(sg, name, shape, N, dtype):
+    from paper_2512_11473_amd import workload
+    npd = np.float32 if dtype == torch.float32 else np.float64
+    wl = workload.setup(shape, N, 0.1, 3, dtype=dtype)
+    run = oracle.setup(shape, N, 0.1, 3, phi0_dtype=npd)
+    dense = oracle.dense_state(run.tab, run.active, run.phi0, run.B)
+    pts = wl.points.ravel()
+    for seed in range(2):
+        bad = _leaky_points(run, dense, seed, n_boxes=8)
+        ref, ref_rounds = oracle.correct_point_signs(run.N, run.tab, bad)
+        phi = wl.phi.clone()
+        phi[2:] = torch.from_numpy(bad[pts].reshape(-1, 64).astype(npd)).cuda()
+        rounds = sg.correct_package_signs(wl.grid, phi)
+        assert rounds == ref_rounds > 0
+        got = phi[2:].double().cpu().numpy().ravel()
+        assert np.array_equal(got, ref[pts])
+        assert np.array_equal(ref, dense)                  # the leaks are repaired
+        assert torch.equal(phi[:2], wl.phi[:2])            # far-field rows untouched
