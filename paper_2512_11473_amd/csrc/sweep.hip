@@ -13,6 +13,8 @@
 // DPP row shifts (lane +-1 is y, lane +-4 is z; a package is exactly one
 // 16-lane DPP row).  The LDS-staged variant writes the same rows and halos
 // into a per-package tile in LDS and reads the neighbours back from there.
+#include <atomic>
+
 #include "common.hpp"
 #include "upwind.hpp"
 
@@ -583,24 +585,36 @@ __global__ void far_field_kernel(T *__restrict__ phi, T B) {
 
 namespace sgrid {
 
-// Sweep variants: 0 DPP exchange, 1 LDS tile, 2 persistent, 3 Morton
-// worklist, 4 group-shared LDS, 5 LDS row exchange.
+// Sweep variants: 0 DPP exchange, 1 LDS tile, 2 persistent Morton walk,
+// 3 Morton worklist, 4 group-shared LDS, 5 LDS row exchange, 6 persistent
+// walk in package-id order.
 struct SweepConfig {
     int variant = 0;
-    int groups = 1;   // sets of four packages per wavefront
+    int groups = 1;   // sets of four packages per wavefront, or workgroups per CU (2, 6)
 };
 
-static SweepConfig g_sweep_cfg;
+// The process-wide setting lives in one atomic word (variant in the high
+// half, groups in the low half), and every call reads it once, so a setting
+// changed by another thread never reaches a call half-applied.
+static std::atomic<uint32_t> g_sweep_word{(0u << 16) | 1u};
 
 void set_sweep_config(int variant, int groups) {
-    g_sweep_cfg.variant = variant;
-    g_sweep_cfg.groups = groups;
+    g_sweep_word.store(((uint32_t)variant << 16) | (uint32_t)groups, std::memory_order_relaxed);
+}
+
+SweepConfig current_sweep_config() {
+    const uint32_t w = g_sweep_word.load(std::memory_order_relaxed);
+    SweepConfig c;
+    c.variant = (int)(w >> 16);
+    c.groups = (int)(w & 0xFFFFu);
+    return c;
 }
 
 // The gradient and the Laplacian visit the packages in the sweep's order:
 // Morton (worklist) order when the configuration's sweep uses it.
 bool stencil_in_worklist_order() {
-    return g_sweep_cfg.variant == 2 || g_sweep_cfg.variant == 3 || g_sweep_cfg.variant == 4;
+    const int v = current_sweep_config().variant;
+    return v == 2 || v == 3 || v == 4;
 }
 
 // MI355X's Infinity Cache (the last level before HBM)
@@ -791,9 +805,10 @@ extern "C" sgrid_status sgrid_reinitialize(const sgrid_grid *g, sgrid_dtype dtyp
     SG_REQUIRE(n_iter >= 0, "n_iter must be >= 0 (got %d)", n_iter);
     SG_REQUIRE(dtype == SGRID_F32 || dtype == SGRID_F64, "unknown dtype %d", (int)dtype);
     hipStream_t st = sg_stream(stream);
+    const sgrid::SweepConfig cfg = sgrid::current_sweep_config();
     if (dtype == SGRID_F32)
-        return sgrid::reinit_impl<float>(g, (float *)phi, (float *)scratch, n_iter, st, sgrid::g_sweep_cfg);
-    return sgrid::reinit_impl<double>(g, (double *)phi, (double *)scratch, n_iter, st, sgrid::g_sweep_cfg);
+        return sgrid::reinit_impl<float>(g, (float *)phi, (float *)scratch, n_iter, st, cfg);
+    return sgrid::reinit_impl<double>(g, (double *)phi, (double *)scratch, n_iter, st, cfg);
 }
 
 template <bool PACKED>
