@@ -396,8 +396,10 @@ sgrid_status sgrid_compute_laplacian(const sgrid_grid *grid, sgrid_dtype dtype, 
  * 5, the number of four-package sets one wavefront processes, for variants 2
  * and 6 the number of workgroups per compute unit, and is ignored by variant
  * 4.  With variant 2, 3 or 4 the gradient and Laplacian passes also
- * visit the packages in Morton order.  Process-wide; default (0, 1).  Results
- * are identical for every setting.
+ * visit the packages in Morton order.  Process-wide; default (0, 1).  Safe to
+ * call from any thread: each sweep, gradient or Laplacian call reads the
+ * setting once, so a change reaches calls that start after it.  Results are
+ * identical for every setting.
  */
 sgrid_status sgrid_set_sweep_config(int32_t variant, int32_t groups);
 
