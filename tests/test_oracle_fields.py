@@ -52,6 +52,50 @@ def test_reinit_constant_field_one_step(c):
     assert np.allclose(out[inner], expect, rtol=0, atol=1e-15)
 
 
+def _kink(axis, c, sign, offset):
+    """phi = sign * (|x_axis - x_c| + offset) on the all-active grid: a field
+    of unit slope on both sides of the data-point plane x_axis = x_c, which
+    is a ridge (sign < 0 after the shift) or a valley (sign > 0)."""
+    act, x = _grid()
+    xc = (c + 0.5) * H
+    return act, x, sign * (np.abs(x[:, axis] - xc) + offset), np.isclose(x[:, axis], xc)
+
+
+@pytest.mark.parametrize("axis", [0, 1, 2])
+@pytest.mark.parametrize("sign", [1.0, -1.0])
+def test_reinit_kink_one_step_closed_form(axis, sign):
+    # Valley phi = |x - c| + h/2 (and its negative).  Away from the kink plane
+    # the field is linear with unit slope, so every branch gives G = 1 and the
+    # point is fixed.  On the plane D- = -1 and D+ = +1 (times the sign): the
+    # upwind branch of the sign of phi takes neither difference (both point
+    # away from the upwind side), G = 0, and the point moves by dt |S| in the
+    # direction of its sign, with S = (h/2) / sqrt(h^2/4 + h^2) = 1/sqrt(5).
+    # The downwind choice would take both, G = 1, and leave the point fixed.
+    act, x, phi, on = _kink(axis, 7, sign, 0.5 * H)
+    out = oracle.reinit(N, H, B, act, phi, 1)
+    inner = _interior(x, 1)
+    expect = phi.copy()
+    expect[on] = sign * (0.5 * H + 0.5 * H / np.sqrt(5.0))
+    assert on[inner].sum() == (N - 2) ** 2
+    assert np.max(np.abs(out[inner] - expect[inner])) < 1e-15
+
+
+@pytest.mark.parametrize("axis", [0, 1, 2])
+@pytest.mark.parametrize("sign", [1.0, -1.0])
+def test_reinit_ridge_is_stationary(axis, sign):
+    # Ridge phi = -|x - c| + 2.5h (and its negative): on the ridge plane the
+    # upwind branch takes both one-sided differences (each points towards the
+    # surface), G = 1, and the point is fixed; every other point lies on a
+    # unit-slope linear piece (no data point sits on phi = 0, which is 2.5h
+    # from the plane).  The downwind choice would give G = 0 and move the
+    # ridge by dt S.
+    act, x, phi, on = _kink(axis, 8, -sign, -2.5 * H)
+    out = oracle.reinit(N, H, B, act, phi, 1)
+    inner = _interior(x, 1)
+    assert not np.any(phi == 0.0)
+    assert np.max(np.abs(out[inner] - phi[inner])) < 1e-15
+
+
 def test_reinit_zero_is_stationary():
     act, x = _grid()
     out = oracle.reinit(N, H, B, act, np.zeros(N ** 3), 2)
