@@ -276,6 +276,13 @@ sgrid_status sgrid_probe_integral_field(const sgrid_grid *grid, const float *fie
  * values: W1[128][216], b1[128], W2[128][128], b2[128], W3[4][128], b3[4]
  * (row-major, y = W x + b).  Kernels use BF16 MFMA with FP32 accumulation;
  * the first layer splits its input into BF16 hi + lo parts.
+ *
+ * A model owns device buffers that its calls write (Adam moments, partial
+ * gradients, the fallback list of the learned integrals).  Calls with one
+ * model are ordered on the device: each records an event on its stream and a
+ * call on another stream first waits for the previous call's event, so the
+ * model can be used from several streams in turn.  The handle itself is not
+ * thread-safe: calls with one model must not run concurrently on the host.
  * ------------------------------------------------------------------------ */
 
 /* Creates a model on the current device from host parameters (copied). */
@@ -308,12 +315,18 @@ sgrid_status sgrid_mlp_forward(const sgrid_mlp *model, const float *x_dev, int64
 sgrid_status sgrid_mlp_backward(sgrid_mlp *model, const float *x_dev, const float *dy_dev, int64_t B,
                                 float *grad_dev, void *stream);
 
-/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected) on the
+/* One Adam step (beta1 and beta2 the FP32 numbers nearest 0.9 and 0.999, eps
+ * 1e-8, bias-corrected with the same betas) on the
  * loss sum_b sum_o w_o (y_bo - t_bo)^2 / B with w = loss_weights_host[4];
  * the loss before the step goes to *loss_dev (nullable, the sum over the
  * batch before dividing by B). */
 sgrid_status sgrid_mlp_train_step(sgrid_mlp *model, const float *x_dev, const float *t_dev, int64_t B,
                                   const float *loss_weights_host, float lr, float *loss_dev, void *stream);
+
+/* One Adam step (as in sgrid_mlp_train_step) on the model's parameters from
+ * a caller's gradient grad_dev [44804] (device, FP32), e.g. one reduced over
+ * several devices in data-parallel training.  Increments the step count. */
+sgrid_status sgrid_mlp_apply_gradient(sgrid_mlp *model, const float *grad_dev, float lr, void *stream);
 
 /* Network inputs of every core point in the integrals' output order:
  * x_dev [n_core * 64][216] (nullable) = window of phi / h; unsat_dev

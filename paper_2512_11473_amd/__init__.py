@@ -82,6 +82,7 @@ _SIGNATURES = {
     "sgrid_mlp_forward": (ctypes.c_int, [_P, _P, ctypes.c_int64, _P, _P]),
     "sgrid_mlp_backward": (ctypes.c_int, [_P, _P, _P, ctypes.c_int64, _P, _P]),
     "sgrid_mlp_train_step": (ctypes.c_int, [_P, _P, _P, ctypes.c_int64, _P, ctypes.c_float, _P, _P]),
+    "sgrid_mlp_apply_gradient": (ctypes.c_int, [_P, _P, ctypes.c_float, _P]),
     "sgrid_gather_windows": (ctypes.c_int, [_P, _P, _P, _P, _P]),
     "sgrid_batch_create": (ctypes.c_int, [_P, ctypes.c_int32, _P, ctypes.POINTER(_P)]),
     "sgrid_batch_destroy": (ctypes.c_int, [_P]),
@@ -135,6 +136,34 @@ def _dev(t: torch.Tensor, name: str):
     return ctypes.c_void_p(t.data_ptr())
 
 
+def _f32(t, name: str, numel: int):
+    """t must be a float32 tensor of exactly `numel` elements (the library
+    cannot check either)."""
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor")
+    if t.dtype != torch.float32:
+        raise TypeError(f"{name} must be float32 (got {t.dtype})")
+    if t.numel() != numel:
+        raise ValueError(f"{name} must hold {numel} values (got {t.numel()})")
+
+
+def _counter(t, name: str):
+    """A device counter the library writes one 32-bit unsigned value to."""
+    if t.dtype not in (torch.int32, torch.uint32) or t.numel() < 1:
+        raise TypeError(f"{name} must be an int32 or uint32 tensor of at least one element")
+    return _dev(t, name)
+
+
+def _hip_runtime():
+    """The HIP runtime this process already loaded (torch's), found by path."""
+    with open("/proc/self/maps") as f:
+        for line in f:
+            path = line.split()[-1] if len(line.split()) >= 6 else ""
+            if os.path.basename(path).startswith("libamdhip64.so"):
+                return ctypes.CDLL(path)
+    raise SgridError(3, "the HIP runtime is not loaded in this process")
+
+
 def _stream(stream=None):
     s = torch.cuda.current_stream() if stream is None else stream
     return ctypes.c_void_p(s.cuda_stream)
@@ -180,7 +209,7 @@ class Grid:
 
     def tables(self) -> dict:
         """Copies of the index tables as device tensors (for checks)."""
-        hip = ctypes.CDLL("libamdhip64.so.7")
+        hip = _hip_runtime()
         hip.hipMemcpy.argtypes = [_P, _P, ctypes.c_size_t, ctypes.c_int]
         hip.hipMemcpy.restype = ctypes.c_int
         info = self._info
@@ -349,7 +378,9 @@ def compute_near_surface_integrals(grid: Grid, phi: torch.Tensor, out: torch.Ten
         raise TypeError("integrals are FP32")
     if out.numel() != 4 * grid.n_core * 64 or phi.numel() != grid.n_total * 64:
         raise ValueError("out must be [4, n_core*64]")
-    nf = _dev(n_fallback, "n_fallback") if n_fallback is not None else None
+    nf = _counter(n_fallback, "n_fallback") if n_fallback is not None else None
+    if model is not None and not isinstance(model, Mlp):
+        raise TypeError("model must be an Mlp")
     mh = model.handle if model is not None else None
     _check(load().sgrid_compute_near_surface_integrals(grid.handle, _dev(phi, "phi"), mh, _dev(out, "out"), nf,
                                                        _stream(stream)))
@@ -433,14 +464,19 @@ class Mlp:
 
     def forward(self, x: torch.Tensor, y: torch.Tensor, stream=None):
         B = x.shape[0]
-        if x.dtype != torch.float32 or x.shape != (B, 216) or y.shape != (B, 4):
+        if x.shape != (B, 216) or y.shape != (B, 4):
             raise ValueError("x [B,216] and y [B,4] float32 expected")
+        _f32(x, "x", B * 216)
+        _f32(y, "y", B * 4)
         _check(load().sgrid_mlp_forward(self.handle, _dev(x, "x"), B, _dev(y, "y"), _stream(stream)))
 
     def backward(self, x: torch.Tensor, dy: torch.Tensor, grad: torch.Tensor, stream=None):
         B = x.shape[0]
-        if x.shape != (B, 216) or dy.shape != (B, 4) or grad.numel() != MLP_N_PARAMS:
+        if x.shape != (B, 216) or dy.shape != (B, 4):
             raise ValueError("x [B,216], dy [B,4], grad [44804] expected")
+        _f32(x, "x", B * 216)
+        _f32(dy, "dy", B * 4)
+        _f32(grad, "grad", MLP_N_PARAMS)
         _check(load().sgrid_mlp_backward(self.handle, _dev(x, "x"), _dev(dy, "dy"), B, _dev(grad, "grad"),
                                          _stream(stream)))
 
@@ -450,16 +486,28 @@ class Mlp:
         B = x.shape[0]
         if x.shape != (B, 216) or t.shape != (B, 4):
             raise ValueError("x [B,216] and t [B,4] expected")
+        _f32(x, "x", B * 216)
+        _f32(t, "t", B * 4)
         lw = np.ascontiguousarray(loss_weights, dtype=np.float32)
+        if lw.shape != (4,):
+            raise ValueError("loss_weights must hold exactly 4 values")
+        if loss is not None:
+            _f32(loss, "loss", 1)
         lp = _dev(loss, "loss") if loss is not None else None
         _check(load().sgrid_mlp_train_step(self.handle, _dev(x, "x"), _dev(t, "t"), B, lw.ctypes.data_as(_P),
                                            float(lr), lp, _stream(stream)))
+
+    def apply_gradient(self, grad: torch.Tensor, lr: float, stream=None):
+        """One Adam step from a caller's gradient [44804] (FP32, device)."""
+        _f32(grad, "grad", MLP_N_PARAMS)
+        _check(load().sgrid_mlp_apply_gradient(self.handle, _dev(grad, "grad"), float(lr), _stream(stream)))
 
 
 def gather_windows(grid: Grid, phi: torch.Tensor, x: Optional[torch.Tensor] = None,
                    unsat: Optional[torch.Tensor] = None, stream=None):
     """Windows of phi/h [n_core*64, 216] and unsaturated flags [n_core*64] of the core points."""
     n = grid.n_core * 64
+    _f32(phi, "phi", grid.n_total * 64)
     if x is not None and (x.shape != (n, 216) or x.dtype != torch.float32):
         raise ValueError("x must be [n_core*64, 216] float32")
     if unsat is not None and (unsat.numel() != n or unsat.dtype != torch.uint8):
@@ -507,6 +555,8 @@ class Batch:
         """Returns (variant, blocks_per_cu, table[2][6] of us per sweep for
         blocks_per_cu in (1, 2, 4, 8, 16, 0))."""
         import numpy as np
+        _f32(phi, "phi", self.n_total * 64)
+        _f32(scratch, "scratch", self.n_total * 64)
         v, b = ctypes.c_int32(), ctypes.c_int32()
         table = np.zeros(12, dtype=np.float32)
         _check(load().sgrid_batch_autotune(self.handle, _dev(phi, "phi"), _dev(scratch, "scratch"), int(reps),
@@ -516,8 +566,8 @@ class Batch:
 
     def reinitialize(self, phi: torch.Tensor, scratch: torch.Tensor, n_iter: int, use_graph: bool = True,
                      stream=None):
-        if phi.numel() != self.n_total * 64 or scratch.numel() != phi.numel() or phi.dtype != torch.float32:
-            raise ValueError("phi and scratch must be [n_total, 64] float32")
+        _f32(phi, "phi", self.n_total * 64)
+        _f32(scratch, "scratch", self.n_total * 64)
         _check(load().sgrid_batch_reinitialize(self.handle, _dev(phi, "phi"), _dev(scratch, "scratch"),
                                                int(n_iter), int(bool(use_graph)), _stream(stream)))
 

@@ -20,6 +20,7 @@
 #include <float.h>
 #include <string.h>
 
+#include <algorithm>
 #include <vector>
 
 #include "fraction.hpp"
@@ -387,6 +388,11 @@ struct sgrid_mlp {
     float kw_lo = -0.05f, kw_hi = 1.05f;
     uint32_t *fallback = nullptr;  // fallback cell list of the learned integrals
     int64_t fallback_cap = 0;
+    // Calls that use the model are ordered across streams: each records `done`
+    // on its stream, and a call on another stream first waits for it.
+    hipEvent_t done = nullptr;
+    hipStream_t last = nullptr;
+    bool used = false;
     MlpDev dev() const { return MlpDev{w, w1b, w2b, w2tb, w3b}; }
 };
 
@@ -397,11 +403,33 @@ static void free_mlp(sgrid_mlp *m) {
     void *ptrs[] = {m->w, m->m, m->v, m->grad, m->loss, m->w1b, m->w2b, m->w2tb, m->w3b, m->part, m->loss_part,
                     m->fallback};
     for (void *p : ptrs) dev_free(p);
+    if (m->done) (void)hipEventDestroy(m->done);
     delete m;
 }
 
+// Start of a call that uses the model's buffers on stream `st`: wait for the
+// model's previous call when that ran on another stream.
+static sgrid_status begin_use(const sgrid_mlp *mc, hipStream_t st) {
+    sgrid_mlp *m = const_cast<sgrid_mlp *>(mc);
+    if (m->used && m->last != st) SG_CHECK_HIP(hipStreamWaitEvent(st, m->done, 0));
+    return SGRID_OK;
+}
+
+// End of such a call: later calls on other streams wait for this point.
+static sgrid_status end_use(const sgrid_mlp *mc, hipStream_t st) {
+    sgrid_mlp *m = const_cast<sgrid_mlp *>(mc);
+    SG_CHECK_HIP(hipEventRecord(m->done, st));
+    m->last = st;
+    m->used = true;
+    return SGRID_OK;
+}
+
+// Growing a buffer frees the old block, which kernels queued by earlier calls
+// (on any stream) may still use: wait for the device before handing it back
+// to the allocator, which may give it to the next request of that size.
 static sgrid_status ensure_part(sgrid_mlp *m, int64_t rows) {
     if (rows <= m->part_rows) return SGRID_OK;
+    if (m->part || m->loss_part) SG_CHECK_HIP(hipDeviceSynchronize());
     dev_free(m->part);
     dev_free(m->loss_part);
     m->part = nullptr;
@@ -417,6 +445,7 @@ static sgrid_status ensure_part(sgrid_mlp *m, int64_t rows) {
 
 sgrid_status mlp_ensure_fallback(sgrid_mlp *m, int64_t cells) {
     if (cells <= m->fallback_cap) return SGRID_OK;
+    if (m->fallback) SG_CHECK_HIP(hipDeviceSynchronize());
     dev_free(m->fallback);
     m->fallback = nullptr;
     m->fallback_cap = 0;
@@ -448,7 +477,12 @@ extern "C" sgrid_status sgrid_mlp_create(const float *params_host, sgrid_mlp **o
     *out = nullptr;
     SG_REQUIRE(params_host != nullptr, "params is NULL");
     sgrid_mlp *m = new sgrid_mlp();
-    SG_CHECK_HIP(hipGetDevice(&m->device));
+    if (hipGetDevice(&m->device) != hipSuccess ||
+        hipEventCreateWithFlags(&m->done, hipEventDisableTiming) != hipSuccess) {
+        sgrid::set_error("MLP setup: no device or event");
+        sgrid::free_mlp(m);
+        return SGRID_E_HIP;
+    }
     struct A { void **p; size_t bytes; };
     A allocs[] = {{(void **)&m->w, kNParam * 4}, {(void **)&m->m, kNParam * 4}, {(void **)&m->v, kNParam * 4},
                   {(void **)&m->grad, kNParam * 4}, {(void **)&m->loss, 4},
@@ -533,9 +567,12 @@ extern "C" sgrid_status sgrid_mlp_forward(const sgrid_mlp *m, const float *x, in
     SG_REQUIRE(x && y && sg_aligned(x, 16) && sg_aligned(y, 16), "x / y NULL or not 16-byte aligned");
     const int64_t nwg = (B + 63) / 64;
     SG_REQUIRE(nwg <= kMaxGrid, "batch too large");
-    hipLaunchKernelGGL(forward_kernel, dim3((unsigned)nwg), dim3(256), 0, sg_stream(stream), m->dev(), x, B, y);
+    hipStream_t st = sg_stream(stream);
+    sgrid_status s = sgrid::begin_use(m, st);
+    if (s != SGRID_OK) return s;
+    hipLaunchKernelGGL(forward_kernel, dim3((unsigned)nwg), dim3(256), 0, st, m->dev(), x, B, y);
     SG_CHECK_LAUNCH("MLP forward");
-    return SGRID_OK;
+    return sgrid::end_use(m, st);
 }
 
 extern "C" sgrid_status sgrid_mlp_backward(sgrid_mlp *m, const float *x, const float *dy, int64_t B, float *grad,
@@ -545,13 +582,35 @@ extern "C" sgrid_status sgrid_mlp_backward(sgrid_mlp *m, const float *x, const f
     SG_REQUIRE(B >= 1, "B must be >= 1");
     SG_REQUIRE(x && dy && grad && sg_aligned(x, 16) && sg_aligned(dy, 16) && sg_aligned(grad, 4),
                "x / dy / grad NULL or misaligned");
+    SG_REQUIRE((B + kTrainRows - 1) / kTrainRows <= kMaxGrid, "batch too large");
     hipStream_t st = sg_stream(stream);
+    sgrid_status s = sgrid::begin_use(m, st);
+    if (s != SGRID_OK) return s;
     const float lw[4] = {0, 0, 0, 0};
-    sgrid_status s = sgrid::run_backward(m, x, B, nullptr, dy, lw, st);
+    s = sgrid::run_backward(m, x, B, nullptr, dy, lw, st);
     if (s != SGRID_OK) return s;
     SG_CHECK_HIP(hipMemcpyAsync(grad, m->grad, kNParam * 4, hipMemcpyDeviceToDevice, st));
+    return sgrid::end_use(m, st);
+}
+
+namespace sgrid {
+
+// One Adam step on the model's masters from the gradient in `g` (device,
+// kNParam values), then the BF16 copies.  The decay rates are the FP32
+// numbers nearest 0.9 and 0.999, and the bias corrections 1 - beta^t use
+// those same numbers, so the step is Adam with these rates.
+static sgrid_status adam_step(sgrid_mlp *m, const float *g, float lr, hipStream_t st) {
+    m->step += 1;
+    const float b1 = 0.9f, b2 = 0.999f;
+    const float c1 = (float)(1.0 - pow((double)b1, (double)m->step));
+    const float c2 = (float)(1.0 - pow((double)b2, (double)m->step));
+    hipLaunchKernelGGL(adam_kernel, dim3((kNParam + 255) / 256), dim3(256), 0, st, m->w, m->m, m->v, g, lr,
+                       b1, b2, 1e-8f, c1, c2, m->w1b, m->w2b, m->w2tb, m->w3b);
+    SG_CHECK_LAUNCH("Adam");
     return SGRID_OK;
 }
+
+}  // namespace sgrid
 
 extern "C" sgrid_status sgrid_mlp_train_step(sgrid_mlp *m, const float *x, const float *t, int64_t B,
                                              const float *loss_weights, float lr, float *loss_dev, void *stream) {
@@ -560,17 +619,29 @@ extern "C" sgrid_status sgrid_mlp_train_step(sgrid_mlp *m, const float *x, const
     SG_REQUIRE(B >= 1, "B must be >= 1");
     SG_REQUIRE(x && t && loss_weights && sg_aligned(x, 16) && sg_aligned(t, 16), "x / t / weights NULL or misaligned");
     SG_REQUIRE(lr >= 0.f, "lr must be >= 0");
+    SG_REQUIRE((B + kTrainRows - 1) / kTrainRows <= kMaxGrid, "batch too large");
     hipStream_t st = sg_stream(stream);
-    sgrid_status s = sgrid::run_backward(m, x, B, t, nullptr, loss_weights, st);
+    sgrid_status s = sgrid::begin_use(m, st);
     if (s != SGRID_OK) return s;
-    m->step += 1;
-    const double b1 = 0.9, b2 = 0.999;
-    const float c1 = (float)(1.0 - pow(b1, (double)m->step)), c2 = (float)(1.0 - pow(b2, (double)m->step));
-    hipLaunchKernelGGL(adam_kernel, dim3((kNParam + 255) / 256), dim3(256), 0, st, m->w, m->m, m->v, m->grad, lr,
-                       (float)b1, (float)b2, 1e-8f, c1, c2, m->w1b, m->w2b, m->w2tb, m->w3b);
-    SG_CHECK_LAUNCH("Adam");
+    s = sgrid::run_backward(m, x, B, t, nullptr, loss_weights, st);
+    if (s != SGRID_OK) return s;
+    s = sgrid::adam_step(m, m->grad, lr, st);
+    if (s != SGRID_OK) return s;
     if (loss_dev) SG_CHECK_HIP(hipMemcpyAsync(loss_dev, m->loss, 4, hipMemcpyDeviceToDevice, st));
-    return SGRID_OK;
+    return sgrid::end_use(m, st);
+}
+
+extern "C" sgrid_status sgrid_mlp_apply_gradient(sgrid_mlp *m, const float *grad_dev, float lr, void *stream) {
+    sgrid::clear_error();
+    SG_REQUIRE(m != nullptr, "model is NULL");
+    SG_REQUIRE(grad_dev != nullptr && sg_aligned(grad_dev, 4), "grad NULL or misaligned");
+    SG_REQUIRE(lr >= 0.f, "lr must be >= 0");
+    hipStream_t st = sg_stream(stream);
+    sgrid_status s = sgrid::begin_use(m, st);
+    if (s != SGRID_OK) return s;
+    s = sgrid::adam_step(m, grad_dev, lr, st);
+    if (s != SGRID_OK) return s;
+    return sgrid::end_use(m, st);
 }
 
 // ---------------------------------------------------------------------------
@@ -871,13 +942,9 @@ __global__ __launch_bounds__(256) void learned_kernel(MlpDev W, const float *__r
 // Plain integral of single cells (the fallback): the 32 taps of the cell's
 // dual-cell query, each with its own cut fraction from central differences,
 // in the same arithmetic and summation order as the plain package kernel.
-__global__ __launch_bounds__(256) void fallback_kernel(const float *__restrict__ phi, const uint32_t *__restrict__ nbr,
-                                                       const uint32_t *__restrict__ core_list, int64_t n_core,
-                                                       float inv_h, float inv_2h, const uint32_t *__restrict__ fb_list,
-                                                       const uint32_t *__restrict__ fb_count, float *__restrict__ out) {
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= (int64_t)*fb_count) return;
-    const int64_t o = fb_list[t];
+__device__ __forceinline__ void fallback_point(const float *__restrict__ phi, const uint32_t *__restrict__ nbr,
+                                               const uint32_t *__restrict__ core_list, int64_t n_core, float inv_h,
+                                               float inv_2h, int64_t o, float *__restrict__ out) {
     const int64_t ci = o / 64;
     const int c = (int)(o % 64);
     const int i = c & 3, j = (c >> 2) & 3, k = c >> 4;
@@ -912,6 +979,18 @@ __global__ __launch_bounds__(256) void fallback_kernel(const float *__restrict__
     out[stride + o] = kx;
     out[2 * stride + o] = ky;
     out[3 * stride + o] = kz;
+}
+
+// The listed points, `*fb_count` of them, read on the device: a persistent
+// grid strides over the list, so its size need not be known at launch.
+__global__ __launch_bounds__(256) void fallback_kernel(const float *__restrict__ phi, const uint32_t *__restrict__ nbr,
+                                                       const uint32_t *__restrict__ core_list, int64_t n_core,
+                                                       float inv_h, float inv_2h, const uint32_t *__restrict__ fb_list,
+                                                       const uint32_t *__restrict__ fb_count, float *__restrict__ out) {
+    const int64_t count = *fb_count;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < count;
+         t += (int64_t)gridDim.x * blockDim.x)
+        fallback_point(phi, nbr, core_list, n_core, inv_h, inv_2h, fb_list[t], out);
 }
 
 // Network inputs (windows of phi / h) and saturation of every core point, in
@@ -956,27 +1035,42 @@ __global__ __launch_bounds__(256) void gather_windows_kernel(const float *__rest
 
 namespace sgrid {
 
+// Gate + network over every core package, then the plain fallback over the
+// listed points.  `fb_list` holds n_core * 64 entries; `count` is reset here.
+// The fallback grid is a persistent one of at most four workgroups per
+// compute unit striding over the device-side count, so a launch costs little
+// when few points fall back.
+static sgrid_status learned_launch(const sgrid_grid *g, const float *phi, const sgrid_mlp *m, float *out,
+                                   uint32_t *fb_list, uint32_t *count, hipStream_t st) {
+    hipLaunchKernelGGL(zero_u32_kernel, dim3(1), dim3(1), 0, st, count);
+    SG_CHECK_LAUNCH("fallback counter reset");
+    if (g->n_core == 0) return SGRID_OK;
+    const int64_t cells = g->n_core * 64;
+    const float inv_h = (float)(1.0 / g->h), inv_2h = (float)(0.5 / g->h);
+    hipLaunchKernelGGL(learned_kernel, dim3((unsigned)((g->n_core + kLearnPkgs - 1) / kLearnPkgs)), dim3(256), 0,
+                       st, m->dev(), phi, g->nbr, g->core_list, g->n_core, inv_h, inv_2h, m->gate_tau, m->kw_lo,
+                       m->kw_hi, out, fb_list, count);
+    SG_CHECK_LAUNCH("learned integrals");
+    const int64_t fb_blocks = std::min<int64_t>((cells + 255) / 256, 4 * (int64_t)cu_count());
+    hipLaunchKernelGGL(fallback_kernel, dim3((unsigned)fb_blocks), dim3(256), 0, st, phi, g->nbr, g->core_list,
+                       g->n_core, inv_h, inv_2h, fb_list, count, out);
+    SG_CHECK_LAUNCH("fallback integrals");
+    return SGRID_OK;
+}
+
 sgrid_status integrals_learned(const sgrid_grid *g, const float *phi, const sgrid_mlp *model_c, float *out,
                                uint32_t *n_fallback, hipStream_t st) {
     sgrid_mlp *m = const_cast<sgrid_mlp *>(model_c);
     const int64_t cells = g->n_core * 64;
+    SG_REQUIRE(g->n_core <= kMaxGrid, "too many core packages");
     sgrid_status s = mlp_ensure_fallback(m, cells);
     if (s != SGRID_OK) return s;
+    s = begin_use(m, st);
+    if (s != SGRID_OK) return s;
     uint32_t *count = n_fallback ? n_fallback : m->fallback + m->fallback_cap;
-    hipLaunchKernelGGL(zero_u32_kernel, dim3(1), dim3(1), 0, st, count);
-    SG_CHECK_LAUNCH("fallback counter reset");
-    if (g->n_core == 0) return SGRID_OK;
-    SG_REQUIRE(g->n_core <= kMaxGrid, "too many core packages");
-    const float inv_h = (float)(1.0 / g->h), inv_2h = (float)(0.5 / g->h);
-    hipLaunchKernelGGL(learned_kernel, dim3((unsigned)((g->n_core + kLearnPkgs - 1) / kLearnPkgs)), dim3(256), 0,
-                       st, m->dev(), phi, g->nbr,
-                       g->core_list, g->n_core, inv_h, inv_2h, m->gate_tau, m->kw_lo, m->kw_hi, out, m->fallback,
-                       count);
-    SG_CHECK_LAUNCH("learned integrals");
-    hipLaunchKernelGGL(fallback_kernel, dim3((unsigned)((cells + 255) / 256)), dim3(256), 0, st, phi, g->nbr,
-                       g->core_list, g->n_core, inv_h, inv_2h, m->fallback, count, out);
-    SG_CHECK_LAUNCH("fallback integrals");
-    return SGRID_OK;
+    s = learned_launch(g, phi, m, out, m->fallback, count, st);
+    if (s != SGRID_OK) return s;
+    return end_use(m, st);
 }
 
 }  // namespace sgrid

@@ -99,3 +99,77 @@ def test_invalid_arguments_rejected_without_device(lib):
     lib.sgrid_destroy.argtypes = [P]
     assert lib.sgrid_destroy(None) == 0
     assert lib.sgrid_version() >= 10000
+
+
+def test_new_symbols_reject_invalid_arguments(lib):
+    P = ctypes.c_void_p
+    lib.sgrid_mlp_apply_gradient.argtypes = [P, P, ctypes.c_float, P]
+    assert lib.sgrid_mlp_apply_gradient(None, P(16), 1e-3, None) == E_INVALID
+    assert lib.sgrid_mlp_apply_gradient(P(64), None, 1e-3, None) == E_INVALID
+    assert lib.sgrid_mlp_apply_gradient(P(64), P(16), -1.0, None) == E_INVALID
+
+
+def _fake(cls, **attrs):
+    """An object of a binding class whose handle is never used: the binding's
+    own argument checks must reject the call before reaching the library."""
+    obj = cls.__new__(cls)
+    obj._h = ctypes.c_void_p(1)
+    for k, v in attrs.items():
+        setattr(obj, k, v)
+    return obj
+
+
+def test_binding_rejects_wrong_dtypes_and_sizes():
+    torch = pytest.importorskip("torch")
+    import paper_2512_11473_amd as sg
+    f32, bf16, f64, i64 = torch.float32, torch.bfloat16, torch.float64, torch.int64
+    m = _fake(sg.Mlp)
+    B = 8
+    x, y = torch.zeros(B, 216), torch.zeros(B, 4)
+    bad = [
+        lambda: m.forward(x, torch.zeros(B, 4, dtype=bf16)),              # y of half the bytes
+        lambda: m.forward(x.to(f64), y),
+        lambda: m.backward(x.to(bf16), y, torch.zeros(sg.MLP_N_PARAMS)),
+        lambda: m.backward(x, y.to(f64), torch.zeros(sg.MLP_N_PARAMS)),
+        lambda: m.backward(x, y, torch.zeros(sg.MLP_N_PARAMS, dtype=f64)),
+        lambda: m.backward(x, y, torch.zeros(sg.MLP_N_PARAMS - 1)),
+        lambda: m.train_step(x.to(f64), y, [1, 1, 1, 1], 1e-3),
+        lambda: m.train_step(x, y.to(bf16), [1, 1, 1, 1], 1e-3),
+        lambda: m.train_step(x, y, [1, 1, 1], 1e-3),                     # C reads 4 weights
+        lambda: m.train_step(x, y, [1, 1, 1, 1, 1], 1e-3),
+        lambda: m.train_step(x, y, [1, 1, 1, 1], 1e-3, torch.zeros(2)),   # loss is one float
+        lambda: m.train_step(x, y, [1, 1, 1, 1], 1e-3, torch.zeros(1, dtype=f64)),
+        lambda: m.apply_gradient(torch.zeros(sg.MLP_N_PARAMS, dtype=f64), 1e-3),
+        lambda: m.apply_gradient(torch.zeros(10), 1e-3),
+    ]
+    g = _fake(sg.Grid, n_coarse=4, h=1 / 16, n_packages=10, n_core=3)
+    nt = g.n_total
+    bad += [
+        lambda: sg.gather_windows(g, torch.zeros(nt, 64, dtype=f64)),
+        lambda: sg.gather_windows(g, torch.zeros(nt - 1, 64)),
+        lambda: sg.compute_near_surface_integrals(g, torch.zeros(nt, 64), torch.zeros(4, 3 * 64),
+                                                  n_fallback=torch.zeros(1, dtype=i64)),
+        lambda: sg.compute_near_surface_integrals(g, torch.zeros(nt, 64), torch.zeros(4, 3 * 64),
+                                                  n_fallback=torch.zeros(0, dtype=torch.int32)),
+        lambda: sg.compute_near_surface_integrals(g, torch.zeros(nt, 64), torch.zeros(4, 3 * 64), model=object()),
+    ]
+    b = _fake(sg.Batch, n_total=20)
+    bad += [
+        lambda: b.autotune(torch.zeros(20, 64), torch.zeros(19, 64)),
+        lambda: b.autotune(torch.zeros(20, 64, dtype=f64), torch.zeros(20, 64)),
+        lambda: b.autotune(torch.zeros(21, 64), torch.zeros(20, 64)),
+        lambda: b.reinitialize(torch.zeros(20, 64), torch.zeros(20, 64, dtype=f64), 1),
+        lambda: b.reinitialize(torch.zeros(20, 64), torch.zeros(19, 64), 1),
+    ]
+    try:
+        for call in bad:
+            with pytest.raises((TypeError, ValueError)) as e:
+                call()
+            # the dtype / size check fired, not the later device-tensor check
+            assert "device tensor" not in str(e.value), str(e.value)
+        # control: well-formed host tensors get past those checks to that one
+        with pytest.raises(ValueError, match="device tensor"):
+            m.train_step(x, y, [1, 1, 1, 1], 1e-3, torch.zeros(1))
+    finally:
+        for obj in (m, g, b):   # the fake handles must never reach destroy
+            obj._h = None

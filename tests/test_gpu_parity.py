@@ -254,8 +254,8 @@ def test_sweep_domain_edge(sg, dtype):
     faces: where an interior touches a face, its points see the +B far field
     across it, the update there jumps by several h per iteration, and FP32
     rounding is amplified beyond 1e-5 h within a few iterations (a property of
-    the iteration, shown by a correctly rounded FP32 emulation of it, not of
-    the kernels)."""
+    the iteration, not of the kernels: tests/test_fp32_domain_face.py shows it
+    with a correctly rounded FP32 evaluation of the update)."""
     from paper_2512_11473_amd import workload
     s = synth.union([synth.sphere((0.14, 0.5, 0.5), 0.12), synth.box((0.6, 0.8, 0.5), (0.25, 0.16, 0.25))])
     N = 64
