@@ -241,6 +241,20 @@ sgrid_status sgrid_compute_near_surface_integrals(const sgrid_grid *grid, const 
                                                   uint32_t *n_fallback_dev, void *stream);
 
 /*
+ * The plain integrals of sgrid_compute_near_surface_integrals in factorised
+ * form.  The cut fraction V_j depends on the point j alone (its value and its
+ * central-difference gradient), so a first pass writes V at every data point
+ * of every activated package into `vfrac_dev` ([P + 2][64] FP32, caller-owned
+ * workspace, contents on return unspecified), and a second pass sums each
+ * core point's 32 taps from it, so that no fraction is evaluated twice (the
+ * direct kernel evaluates 7^3 per package for 64 points).  The result has the
+ * bits of the direct plain kernel.  `out_dev` as there; phi, vfrac and out
+ * must be distinct.  Asynchronous on `stream`.
+ */
+sgrid_status sgrid_compute_near_surface_integrals_factorised(const sgrid_grid *grid, const float *phi_dev,
+                                                             float *vfrac_dev, float *out_dev, void *stream);
+
+/*
  * The integral field for grid-to-particle coupling (Sec. 8: the kernel
  * integral evaluated on the sparse grid is interpolated trilinearly to the
  * particles and drives them as a surface force).  The integrals above, at

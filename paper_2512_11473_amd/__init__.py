@@ -67,6 +67,7 @@ _SIGNATURES = {
     "sgrid_probe_particles_packed": (ctypes.c_int, [_P, ctypes.c_int, _P, _P, ctypes.c_int64, _P, _P, _P]),
     "sgrid_probe_particles": (ctypes.c_int, [_P, ctypes.c_int, _P, _P, _P, ctypes.c_int64, _P, _P, _P]),
     "sgrid_compute_near_surface_integrals": (ctypes.c_int, [_P, _P, _P, _P, _P, _P]),
+    "sgrid_compute_near_surface_integrals_factorised": (ctypes.c_int, [_P, _P, _P, _P, _P]),
     "sgrid_compute_integral_field": (ctypes.c_int, [_P, _P, _P, _P]),
     "sgrid_probe_integral_field": (ctypes.c_int, [_P, _P, _P, ctypes.c_int64, _P, _P]),
     "sgrid_set_sweep_config": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32]),
@@ -386,6 +387,21 @@ def compute_near_surface_integrals(grid: Grid, phi: torch.Tensor, out: torch.Ten
                                                        _stream(stream)))
 
 
+def compute_near_surface_integrals_factorised(grid: Grid, phi: torch.Tensor, vfrac: torch.Tensor,
+                                              out: torch.Tensor, stream=None):
+    """The plain integrals in two passes: cut fractions at every point into
+    `vfrac` ([P+2, 64] FP32 workspace), then the 32 taps per core point."""
+    for name, t in (("phi", phi), ("vfrac", vfrac), ("out", out)):
+        if t.dtype != torch.float32:
+            raise TypeError(f"{name} must be float32")
+    if phi.numel() != grid.n_total * 64 or vfrac.numel() != grid.n_total * 64:
+        raise ValueError("phi and vfrac must be [P+2, 64]")
+    if out.numel() != 4 * grid.n_core * 64:
+        raise ValueError("out must be [4, n_core*64]")
+    _check(load().sgrid_compute_near_surface_integrals_factorised(grid.handle, _dev(phi, "phi"), _dev(vfrac, "vfrac"),
+                                                                  _dev(out, "out"), _stream(stream)))
+
+
 def compute_integral_field(grid: Grid, phi: torch.Tensor, field: torch.Tensor, stream=None):
     """(K_W, h K_grad) at every point of every activated package, packed
     [P+2, 64, 4] like compute_gradient_packed; far-field rows hold the
@@ -480,8 +496,7 @@ class Mlp:
         _check(load().sgrid_mlp_backward(self.handle, _dev(x, "x"), _dev(dy, "dy"), B, _dev(grad, "grad"),
                                          _stream(stream)))
 
-    def train_step(self, x: torch.Tensor, t: torch.Tensor, loss_weights, lr: float,
-                   loss: Optional[torch.Tensor] = None, stream=None):
+    def _train_args(self, x, t, loss_weights, loss):
         import numpy as np
         B = x.shape[0]
         if x.shape != (B, 216) or t.shape != (B, 4):
@@ -494,6 +509,11 @@ class Mlp:
         if loss is not None:
             _f32(loss, "loss", 1)
         lp = _dev(loss, "loss") if loss is not None else None
+        return B, lw, lp
+
+    def train_step(self, x: torch.Tensor, t: torch.Tensor, loss_weights, lr: float,
+                   loss: Optional[torch.Tensor] = None, stream=None):
+        B, lw, lp = self._train_args(x, t, loss_weights, loss)
         _check(load().sgrid_mlp_train_step(self.handle, _dev(x, "x"), _dev(t, "t"), B, lw.ctypes.data_as(_P),
                                            float(lr), lp, _stream(stream)))
 

@@ -16,6 +16,7 @@
 #include <atomic>
 
 #include "common.hpp"
+#include "fraction.hpp"
 #include "upwind.hpp"
 
 using sgrid::kGroup;
@@ -525,6 +526,48 @@ __global__ __launch_bounds__(256) void gradient_kernel(const T *__restrict__ phi
     }
 }
 
+// First pass of the factorised near-surface integrals (Sec. 8 kernel
+// integral): the cut fraction V of every data point's cell, from the point's
+// value and its central-difference gradient, at every point of every
+// activated package, FP32.  V depends on the point alone, so a second pass
+// sums it over each core point's 32 taps without evaluating any fraction
+// again.  The expressions are those of the plain integral kernel, so the
+// fractions carry the same bits.  Far-field rows: phi = -B gives 0, +B gives 1.
+template <bool WORK>
+__global__ __launch_bounds__(256) void cut_fraction_kernel(const float *__restrict__ phi, float *__restrict__ vfrac,
+                                                           const uint32_t *__restrict__ face,
+                                                           const uint32_t *__restrict__ wface, int64_t n_total,
+                                                           int64_t n_blocks, float inv_h, float inv_2h, bool nt) {
+    const int64_t b = xcd_block(blockIdx.x, n_blocks);
+    const int lane = threadIdx.x & 63;
+    const int r = lane & 15;
+    const int64_t e = (b * 4 + (threadIdx.x >> 6)) * 4 + (lane >> 4);
+    if (e >= n_total) return;
+    uint4 f0;
+    uint2 f1;
+    const int64_t p = stencil_package<WORK>(e, face, wface, f0, f1);
+    Row<float> v;
+    if (p < 2) {
+        const Row<float> c = load_row(phi + p * 64 + r * 4);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) v.v[i] = sgrid::plane_cube_fraction(c.v[i] * inv_h, 0.f, 0.f, 0.f);
+    } else {
+        Loads<float> l;
+        issue_data(phi, p, r, f0, f1, l);
+        const Stencil<float> s = assemble(r, l);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const float xm = i > 0 ? s.c.v[i - 1] : s.xm;
+            const float xp = i < 3 ? s.c.v[i + 1] : s.xp;
+            const float gx = (xp - xm) * inv_2h;
+            const float gy = (s.yp.v[i] - s.ym.v[i]) * inv_2h;
+            const float gz = (s.zp.v[i] - s.zm.v[i]) * inv_2h;
+            v.v[i] = sgrid::plane_cube_fraction(s.c.v[i] * inv_h, gx, gy, gz);
+        }
+    }
+    store_row(vfrac + p * 64 + r * 4, v, nt);
+}
+
 // The operations of the paper's timing test (Sec. 9, Tab. 1).  Sequential
 // access: a small change to every value of every activated package, phi +=
 // delta, streamed as 16-byte rows (rows 0 and 1, the far field, untouched).
@@ -707,6 +750,28 @@ sgrid_status reinit_impl(const sgrid_grid *g, T *phi, T *scratch, int32_t n_iter
 
 template sgrid_status reinit_impl<float>(const sgrid_grid *, float *, float *, int32_t, hipStream_t,
                                          const SweepConfig &);
+
+
+// The first pass of the factorised integrals over all P + 2 packages.
+sgrid_status launch_cut_fractions(const sgrid_grid *g, const float *phi, float *vfrac, hipStream_t st) {
+    const int64_t nt = g->total();
+    const int64_t nb = (nt + 15) / 16;
+    if (nb > kMaxGrid) {
+        set_error("too many packages for one launch");
+        return SGRID_E_INVALID;
+    }
+    const bool work = stencil_in_worklist_order();
+    const bool nt_store = 2.0 * (double)nt * 64.0 * 4.0 > kLastLevelCacheBytes;
+    const float inv_h = (float)(1.0 / g->h), inv_2h = (float)(0.5 / g->h);
+    if (work)
+        hipLaunchKernelGGL(cut_fraction_kernel<true>, dim3((unsigned)nb), dim3(256), 0, st, phi, vfrac, g->face,
+                           g->wface, nt, nb, inv_h, inv_2h, nt_store);
+    else
+        hipLaunchKernelGGL(cut_fraction_kernel<false>, dim3((unsigned)nb), dim3(256), 0, st, phi, vfrac, g->face,
+                           g->wface, nt, nb, inv_h, inv_2h, nt_store);
+    SG_CHECK_LAUNCH("cut fractions");
+    return SGRID_OK;
+}
 
 }  // namespace sgrid
 

@@ -107,6 +107,14 @@ def test_new_symbols_reject_invalid_arguments(lib):
     assert lib.sgrid_mlp_apply_gradient(None, P(16), 1e-3, None) == E_INVALID
     assert lib.sgrid_mlp_apply_gradient(P(64), None, 1e-3, None) == E_INVALID
     assert lib.sgrid_mlp_apply_gradient(P(64), P(16), -1.0, None) == E_INVALID
+    f = lib.sgrid_compute_near_surface_integrals_factorised
+    f.argtypes = [P, P, P, P, P]
+    assert f(None, P(16), P(32), P(48), None) == E_INVALID
+    assert f(P(64), None, P(32), P(48), None) == E_INVALID
+    assert f(P(64), P(16), None, P(48), None) == E_INVALID
+    assert f(P(64), P(16), P(16), P(48), None) == E_INVALID    # phi and vfrac aliased
+    assert f(P(64), P(16), P(32), P(32), None) == E_INVALID    # vfrac and out aliased
+    assert f(P(64), P(16), P(36), P(48), None) == E_INVALID    # misaligned
 
 
 def _fake(cls, **attrs):
@@ -152,6 +160,12 @@ def test_binding_rejects_wrong_dtypes_and_sizes():
         lambda: sg.compute_near_surface_integrals(g, torch.zeros(nt, 64), torch.zeros(4, 3 * 64),
                                                   n_fallback=torch.zeros(0, dtype=torch.int32)),
         lambda: sg.compute_near_surface_integrals(g, torch.zeros(nt, 64), torch.zeros(4, 3 * 64), model=object()),
+        lambda: sg.compute_near_surface_integrals_factorised(g, torch.zeros(nt, 64), torch.zeros(nt - 1, 64),
+                                                             torch.zeros(4, 3 * 64)),
+        lambda: sg.compute_near_surface_integrals_factorised(g, torch.zeros(nt, 64), torch.zeros(nt, 64, dtype=f64),
+                                                             torch.zeros(4, 3 * 64)),
+        lambda: sg.compute_near_surface_integrals_factorised(g, torch.zeros(nt, 64), torch.zeros(nt, 64),
+                                                             torch.zeros(4, 2 * 64)),
     ]
     b = _fake(sg.Batch, n_total=20)
     bad += [

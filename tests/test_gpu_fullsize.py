@@ -1,5 +1,6 @@
 """Full-size parity (GPU): the prism512 workload exactly as bench.py runs it
-(default sweep configuration, packed gradient and probe, plain integrals),
+(default sweep configuration, packed gradient and probe, plain integrals
+direct and factorised),
 compared with the oracle on every point, every particle and every core
 point; the 64-shape batch in its autotuned, graph-replayed form against each
 member's own sweep; and the 2048^3 displaced torus, whose tables are checked
@@ -47,7 +48,12 @@ def test_prism512_full_pipeline(sg):
     sg.probe_particles_packed(g, packed, wl.pos, wl.phi_p, wl.nrm_p)
     integ = torch.empty((4, g.n_core * 64), device="cuda")
     sg.compute_near_surface_integrals(g, wl.phi, integ)
+    # the factorised form, as the benchmark runs it (fractions into the sweep's scratch)
+    integ_f = torch.empty_like(integ)
+    sg.compute_near_surface_integrals_factorised(g, wl.phi, wl.scratch, integ_f)
     torch.cuda.synchronize()
+    assert torch.equal(integ_f, integ)
+    del integ_f
 
     run = oracle.setup(cfg["shape"], cfg["N"], cfg["noise_amp"], cfg["noise_seed"])
     t = {k: v.cpu().numpy() for k, v in g.tables().items()}
@@ -153,7 +159,11 @@ def test_torus2048_full_size(sg):
     sg.probe_particles_packed(g, packed, wl.pos, wl.phi_p, wl.nrm_p)
     integ = torch.empty((4, g.n_core * 64), device="cuda")
     sg.compute_near_surface_integrals(g, wl.phi, integ)
+    integ_f = torch.empty_like(integ)
+    sg.compute_near_surface_integrals_factorised(g, wl.phi, wl.scratch, integ_f)
     torch.cuda.synchronize()
+    assert torch.equal(integ_f, integ)          # all 46 M core points; the crop below checks the values
+    del integ_f
 
     # tables: the whole 512^3 background grid, bit for bit
     t = {k: v.cpu().numpy() for k, v in g.tables().items()}

@@ -211,6 +211,95 @@ def test_sphere64_integrals(sg, n_iter):
     assert (ref[:, 0] > 0.01).mean() > 0.2 and (ref[:, 0] < 0.97).mean() > 0.2
 
 
+@pytest.mark.parametrize("n_iter", [0, 20])
+@pytest.mark.parametrize("variant", [0, 3], ids=["id-order", "morton-order"])
+def test_sphere64_integrals_factorised(sg, n_iter, variant):
+    """The two-pass integrals (cut fractions at every point, then the taps)
+    against the oracle, and bit for bit against the direct kernel; the first
+    pass runs in package-id or Morton order as the sweep setting says."""
+    cfg = synth.config_c1()
+    wl, run, _ = _run_both(sg, cfg, torch.float32, n_iter)
+    sg.reinitialize(wl.grid, wl.phi, wl.scratch, n_iter)
+    oracle.run_plain(run, n_iter)
+    n = wl.grid.n_core * 64
+    direct = torch.empty((4, n), device="cuda")
+    fact = torch.full((4, n), float("nan"), device="cuda")
+    vfrac = torch.full_like(wl.phi, float("nan"))
+    sg.set_sweep_config(variant, 1)
+    try:
+        sg.compute_near_surface_integrals(wl.grid, wl.phi, direct)
+        sg.compute_near_surface_integrals_factorised(wl.grid, wl.phi, vfrac, fact)
+        torch.cuda.synchronize()
+    finally:
+        sg.set_sweep_config(0, 1)
+    assert torch.equal(fact, direct)
+    ref = oracle.integrals(run.N, run.h, run.B, run.phi, _core_points(wl))
+    got = fact.double().cpu().numpy().T
+    assert np.max(np.abs(got[:, 0] - ref[:, 0])) <= 1e-5
+    assert np.max(np.abs(got[:, 1:] - ref[:, 1:])) <= 1e-5 * G0
+    # the fractions of the first pass: far-field rows 0 and 1, band points in [0, 1]
+    v = vfrac.cpu()
+    assert torch.all(v[0] == 0) and torch.all(v[1] == 1)
+    assert torch.all((v[2:] >= 0) & (v[2:] <= 1))
+
+
+def test_integrals_factorised_domain_faces(sg):
+    """Core packages whose window reaches out of the domain (far-field
+    neighbours) take the in-kernel fraction path; the result is still the
+    direct kernel's bits and the oracle's values."""
+    from paper_2512_11473_amd import workload
+    s = synth.union([synth.sphere((0.14, 0.5, 0.5), 0.12), synth.box((0.6, 0.8, 0.5), (0.25, 0.16, 0.25))])
+    N = 64
+    wl = workload.setup(s, N, 0.1, 21)
+    run = oracle.setup(s, N, 0.1, 21)
+    t = {k: v.cpu().numpy() for k, v in wl.grid.tables().items()}
+    nbr = t["pkg_nbr"].view(np.uint32)
+    core = t["core_list"].astype(np.int64)
+    assert np.any(np.any(nbr[core] < 2, axis=1))            # some core windows leave the domain
+    assert np.any(np.all(nbr[core] >= 2, axis=1))           # and some do not
+    n = wl.grid.n_core * 64
+    direct = torch.empty((4, n), device="cuda")
+    fact = torch.empty((4, n), device="cuda")
+    vfrac = torch.empty_like(wl.phi)
+    for n_iter in (0, 3):
+        if n_iter:
+            sg.reinitialize(wl.grid, wl.phi, wl.scratch, n_iter)
+            oracle.run_plain(run, n_iter)
+        sg.compute_near_surface_integrals(wl.grid, wl.phi, direct)
+        sg.compute_near_surface_integrals_factorised(wl.grid, wl.phi, vfrac, fact)
+        torch.cuda.synchronize()
+        assert torch.equal(fact, direct), n_iter
+        ref = oracle.integrals(run.N, run.h, run.B, run.phi, wl.points[core - 2].ravel())
+        got = fact.double().cpu().numpy().T
+        assert np.max(np.abs(got[:, 0] - ref[:, 0])) <= 1e-5, n_iter
+        assert np.max(np.abs(got[:, 1:] - ref[:, 1:])) <= 1e-5 * G0, n_iter
+
+
+def test_integrals_factorised_ragged_and_empty(sg):
+    """Core counts that leave the last workgroup partly empty, and a grid with
+    no core package at all (a call that launches nothing)."""
+    from paper_2512_11473_amd import workload
+    seen = set()
+    for r, seed in ((0.11, 3), (0.17, 4), (0.23, 5), (0.29, 6)):
+        wl = workload.setup(synth.sphere((0.5, 0.47, 0.52), r), 64, 0.1, seed)
+        n = wl.grid.n_core * 64
+        seen.add(wl.grid.n_core % 4)
+        direct = torch.empty((4, n), device="cuda")
+        fact = torch.empty((4, n), device="cuda")
+        sg.compute_near_surface_integrals(wl.grid, wl.phi, direct)
+        sg.compute_near_surface_integrals_factorised(wl.grid, wl.phi, torch.empty_like(wl.phi), fact)
+        torch.cuda.synchronize()
+        assert torch.equal(fact, direct)
+    assert seen - {0}
+    d = torch.full((8 ** 3,), 1.0, device="cuda")           # every coarse cell far outside: P = 0
+    g = sg.build_packages(d, 1.0 / 32)
+    assert g.n_core == 0
+    phi = torch.zeros((g.n_total, 64), device="cuda")
+    sg.compute_near_surface_integrals_factorised(g, phi, torch.zeros_like(phi), torch.empty((4, 0), device="cuda"))
+    torch.cuda.synchronize()
+    g.destroy()
+
+
 def test_sweep_variants_identical(sg):
     cfg = synth.config_c1()
     from paper_2512_11473_amd import workload
