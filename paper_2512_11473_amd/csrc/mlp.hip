@@ -883,11 +883,15 @@ __global__ __launch_bounds__(256) void learned_kernel(MlpDev W, const float *__r
                 ky += Dt * dy * vv;
                 kz += Dt * dz * vv;
             }
-    // non-planarity: mean squared residual after the window's least-squares
-    // affine fit.  The basis 1, ox, oy, oz (offsets centred at 2.5) is
-    // orthogonal on the window, so the residual is sum x^2 minus the squared
-    // projections: 216 c0^2 + 630 (cx^2 + cy^2 + cz^2).
-    float s0 = 0.f, s2 = 0.f, sx = 0.f, sy = 0.f, sz = 0.f;
+    // non-planarity: mean squared residual of the window after its
+    // least-squares affine fit.  The basis 1, ox, oy, oz (offsets centred at
+    // 2.5) is orthogonal on the window, so the fit's coefficients are the
+    // moments s0 / 216 and s_a / 630.  The residual is then summed over the
+    // window a second time, explicitly: the closed form s2 - 216 c0^2 -
+    // 630 |c|^2 subtracts nearly equal numbers for the near-planar windows the
+    // gate has to tell apart.  An error in the coefficients only moves the sum
+    // at second order (the residual is orthogonal to the basis).
+    float s0 = 0.f, sx = 0.f, sy = 0.f, sz = 0.f;
     for (int ez = 0; ez < 6; ++ez)
         for (int ey = 0; ey < 6; ++ey) {
             if (((ez * 6 + ey) & 1) != part) continue;
@@ -896,7 +900,6 @@ __global__ __launch_bounds__(256) void learned_kernel(MlpDev W, const float *__r
             for (int ex = 0; ex < 6; ++ex) {
                 const float v = row[ex] * inv_h;
                 s0 += v;
-                s2 += v * v;
                 sx += (ex - 2.5f) * v;
                 sy += (ey - 2.5f) * v;
                 sz += (ez - 2.5f) * v;
@@ -910,11 +913,24 @@ __global__ __launch_bounds__(256) void learned_kernel(MlpDev W, const float *__r
     const int other = __shfl_xor(sat ? 1 : 0, 1);
     sat = sat && other != 0;
     s0 += __shfl_xor(s0, 1);
-    s2 += __shfl_xor(s2, 1);
     sx += __shfl_xor(sx, 1);
     sy += __shfl_xor(sy, 1);
     sz += __shfl_xor(sz, 1);
-    const float res = (s2 - s0 * s0 / 216.f - (sx * sx + sy * sy + sz * sz) / 630.f) * (1.0f / 216.f);
+    const float c0 = s0 / 216.f, cx = sx / 630.f, cy = sy / 630.f, cz = sz / 630.f;
+    float rr = 0.f;
+    for (int ez = 0; ez < 6; ++ez)
+        for (int ey = 0; ey < 6; ++ey) {
+            if (((ez * 6 + ey) & 1) != part) continue;
+            const float *row = L.phi + ci_ + kWin * ((cj + ey) + kWin * (ck + ez));
+            const float pyz = c0 + cy * (ey - 2.5f) + cz * (ez - 2.5f);
+#pragma unroll
+            for (int ex = 0; ex < 6; ++ex) {
+                const float e = row[ex] * inv_h - (pyz + cx * (ex - 2.5f));
+                rr += e * e;
+            }
+        }
+    rr += __shfl_xor(rr, 1);
+    const float res = rr * (1.0f / 216.f);
     if (live && part == 0) {
         const int64_t o = ci * 64 + c, stride = n_core * 64;
         bool write = true;

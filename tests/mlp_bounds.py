@@ -160,13 +160,31 @@ def nonplanarity_f64(x):
 
 
 def nonplanarity_f32_bound(x):
-    """Bound of the FP32 evaluation error of the moment form
-    (s2 - s0^2 / 216 - (sx^2 + sy^2 + sz^2) / 630) / 216 with the moments
-    summed over 108 terms per lane and two lanes combined."""
+    """Bound of the FP32 evaluation error of the kernel's non-planarity: the
+    fit's coefficients c0 = s0 / 216 and c_a = s_a / 630 from moments summed
+    over 108 terms per lane and two lanes combined, then the explicit sum of
+    squared residuals r_i = v_i - (c0 + c . o_i) in a second pass.
+
+    With p~_i the plane through the computed coefficients, the computed sum
+    is sum (r_i + e_i)^2 up to the rounding of the sum, where e_i is the
+    plane's coefficient error at i (in the affine span, so sum r_i e_i = 0
+    exactly) plus the rounding of three fused steps of the plane's value and
+    of the subtraction.  Worst-case bounds: |ds0| <= 110 u sum |v|,
+    |ds_a| <= 110 u sum |o_a v|, each division one more rounding."""
     o = np.arange(6, dtype=np.float64) - 2.5
     oz, oy, ox = np.meshgrid(o, o, o, indexing="ij")
+    offs = [c.ravel() for c in (ox, oy, oz)]
+    u = U_F32
     ax = np.abs(x)
-    s0 = ax.sum(1)
-    mom = [(ax * np.abs(c.ravel())).sum(1) for c in (ox, oy, oz)]
-    k = 120 * U_F32
-    return k * ((x * x).sum(1) + 3 * s0 * s0 / 216 + 3 * sum(m * m for m in mom) / 630) / 216
+    c0 = x.mean(1)
+    cs = [(x * c).sum(1) / 630.0 for c in offs]
+    plane = c0[:, None] + sum(c[:, None] * oc[None, :] for c, oc in zip(cs, offs))
+    r = x - plane
+    d0 = 110 * u * ax.sum(1) / 216.0 + u * np.abs(c0)
+    ds = [110 * u * (ax * np.abs(oc)).sum(1) / 630.0 + u * np.abs(c) for c, oc in zip(cs, offs)]
+    dp = d0[:, None] + sum(d[:, None] * np.abs(oc)[None, :] for d, oc in zip(ds, offs))
+    amp = np.abs(c0)[:, None] + sum(np.abs(c)[:, None] * np.abs(oc)[None, :] for c, oc in zip(cs, offs))
+    ev = 3 * u * (amp + dp) + u * (np.abs(r) + dp + 3 * u * (amp + dp))
+    E = dp + ev
+    tot = 2 * (np.abs(r) * ev).sum(1) + (E * E).sum(1) + 110 * u * ((np.abs(r) + E) ** 2).sum(1)
+    return tot / 216.0 * (1 + 1e-6)

@@ -156,7 +156,7 @@ def test_gate_nonplanarity_decisions_match_fp64_fit(sg):
     """At thresholds across the distribution, a non-saturated point falls back
     exactly when the FP64 mean squared residual of its window's least-squares
     plane fit exceeds tau, except within the FP32 rounding of the kernel's
-    moment form around tau."""
+    explicit residual sum around tau."""
     model = sg.Mlp(init_params(9))
     x, un, y, fell = _windows_and_outputs(sg, model, 3.0e38, -1e30, 1e30)
     res = mb.nonplanarity_f64(x[un])

@@ -264,7 +264,7 @@ def test_integrals_factorised_domain_faces(sg):
     for n_iter in (0, 3):
         if n_iter:
             sg.reinitialize(wl.grid, wl.phi, wl.scratch, n_iter)
-            oracle.run_plain(run, n_iter)
+        oracle.run_plain(run, n_iter)
         sg.compute_near_surface_integrals(wl.grid, wl.phi, direct)
         sg.compute_near_surface_integrals_factorised(wl.grid, wl.phi, vfrac, fact)
         torch.cuda.synchronize()
