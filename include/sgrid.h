@@ -349,6 +349,28 @@ sgrid_status sgrid_mlp_apply_gradient(sgrid_mlp *model, const float *grad_dev, f
 sgrid_status sgrid_gather_windows(const sgrid_grid *grid, const float *phi_dev, float *x_dev,
                                   uint8_t *unsat_dev, void *stream);
 
+/*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops, harnesses that forbid allocation): the learned
+ * integrals of sgrid_compute_near_surface_integrals with a model, the same
+ * kernels and results (outputs and fallback count), calling no hipMalloc or
+ * hipFree.  Where that entry keeps its fallback list in a buffer the model
+ * allocates, this one uses a fixed array of the library in every GPU's
+ * memory: 8 MiB per device, held until the process ends, sized for one
+ * chunk of 32,768 core packages; grids with more core packages are processed
+ * in chunks, up to 2^26 core packages (32-bit point indices), beyond which the
+ * call fails with SGRID_E_INVALID.  `model` must be non-NULL (the plain
+ * integrals allocate nothing anyway); grid and model must live on the current
+ * device.  *n_fallback_dev (nullable, device) receives the number of fallback
+ * points.  Every call on one GPU shares that GPU's array: calls that overlap
+ * on one GPU (on different streams, or from several host threads) race and
+ * must be serialised by the caller.  The array's contents between calls are
+ * unspecified; a call clears its counters itself.
+ */
+sgrid_status sgrid_compute_near_surface_integrals_noalloc(const sgrid_grid *grid, const float *phi_dev,
+                                                          const sgrid_mlp *model, float *out_dev,
+                                                          uint32_t *n_fallback_dev, void *stream);
+
 /* ------------------------------------------------------------------------
  * Batched reinitialisation of many grids (shapes of uneven size) in one
  * persistent launch per iteration over a global package worklist, with the

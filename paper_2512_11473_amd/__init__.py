@@ -24,7 +24,7 @@ __all__ = [
     "compute_integral_field", "probe_integral_field",
     "sequential_update", "compute_laplacian",
     "autotune_sweep", "SWEEP_TUNE_CANDIDATES",
-    "Mlp", "gather_windows", "MLP_N_PARAMS", "Batch",
+    "Mlp", "gather_windows", "MLP_N_PARAMS", "Batch", "compute_near_surface_integrals_noalloc",
     "LIB_PATH", "FAR_FIELD_IN_H",
 ]
 
@@ -85,6 +85,7 @@ _SIGNATURES = {
     "sgrid_mlp_train_step": (ctypes.c_int, [_P, _P, _P, ctypes.c_int64, _P, ctypes.c_float, _P, _P]),
     "sgrid_mlp_apply_gradient": (ctypes.c_int, [_P, _P, ctypes.c_float, _P]),
     "sgrid_gather_windows": (ctypes.c_int, [_P, _P, _P, _P, _P]),
+    "sgrid_compute_near_surface_integrals_noalloc": (ctypes.c_int, [_P, _P, _P, _P, _P, _P]),
     "sgrid_batch_create": (ctypes.c_int, [_P, ctypes.c_int32, _P, ctypes.POINTER(_P)]),
     "sgrid_batch_destroy": (ctypes.c_int, [_P]),
     "sgrid_batch_info": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64), _P]),
@@ -385,6 +386,22 @@ def compute_near_surface_integrals(grid: Grid, phi: torch.Tensor, out: torch.Ten
     mh = model.handle if model is not None else None
     _check(load().sgrid_compute_near_surface_integrals(grid.handle, _dev(phi, "phi"), mh, _dev(out, "out"), nf,
                                                        _stream(stream)))
+
+
+def compute_near_surface_integrals_noalloc(grid: Grid, phi: torch.Tensor, out: torch.Tensor, model,
+                                           n_fallback: Optional[torch.Tensor] = None, stream=None):
+    """The learned integrals of compute_near_surface_integrals(model=...) with
+    the fallback list in the library's fixed per-device array: no device
+    allocation.  Calls that overlap on one GPU race."""
+    if phi.dtype != torch.float32 or out.dtype != torch.float32:
+        raise TypeError("integrals are FP32")
+    if out.numel() != 4 * grid.n_core * 64 or phi.numel() != grid.n_total * 64:
+        raise ValueError("out must be [4, n_core*64]")
+    if not isinstance(model, Mlp):
+        raise TypeError("model must be an Mlp")
+    nf = _counter(n_fallback, "n_fallback") if n_fallback is not None else None
+    _check(load().sgrid_compute_near_surface_integrals_noalloc(grid.handle, _dev(phi, "phi"), model.handle,
+                                                               _dev(out, "out"), nf, _stream(stream)))
 
 
 def compute_near_surface_integrals_factorised(grid: Grid, phi: torch.Tensor, vfrac: torch.Tensor,

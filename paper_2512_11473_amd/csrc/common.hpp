@@ -25,6 +25,9 @@ void dev_free(void *p);
 // Compute units of the current device (cached).
 int cu_count();
 
+// *p = 0 on `st` by a one-lane kernel (no memset node in a captured graph).
+sgrid_status launch_zero_u32(uint32_t *p, hipStream_t st);
+
 // Far-field package ids and the far-field constant in units of h.
 constexpr uint32_t kFarNeg = 0u;
 constexpr uint32_t kFarPos = 1u;

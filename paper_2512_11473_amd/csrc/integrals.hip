@@ -199,7 +199,10 @@ extern "C" sgrid_status sgrid_compute_near_surface_integrals(const sgrid_grid *g
     SG_REQUIRE(sg_aligned(phi, 16) && sg_aligned(out, 16), "phi / out must be 16-byte aligned");
     hipStream_t st = sg_stream(stream);
     if (model) return sgrid::integrals_learned(g, phi, model, out, n_fallback, st);
-    if (n_fallback) SG_CHECK_HIP(hipMemsetAsync(n_fallback, 0, sizeof(uint32_t), st));
+    if (n_fallback) {
+        sgrid_status s = sgrid::launch_zero_u32(n_fallback, st);
+        if (s != SGRID_OK) return s;
+    }
     return sgrid::launch_integrals_plain(g, phi, out, st);
 }
 

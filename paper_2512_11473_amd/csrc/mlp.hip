@@ -21,6 +21,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <vector>
 
 #include "fraction.hpp"
@@ -708,6 +709,7 @@ __device__ __forceinline__ Taps make_taps() {
 }
 
 __global__ __launch_bounds__(256) void zero_u32_kernel(uint32_t *p) { *p = 0u; }
+__global__ __launch_bounds__(64) void add_u32_kernel(uint32_t *total, const uint32_t *part) { *total += *part; }
 
 // Learned-integral kernel: two core packages per workgroup, two wavefronts
 // per package.  A package's 128 lanes stage its 9^3 window and saturation
@@ -730,8 +732,9 @@ struct LearnLds {
 __global__ __launch_bounds__(256) void learned_kernel(MlpDev W, const float *__restrict__ phi,
                                                       const uint32_t *__restrict__ nbr,
                                                       const uint32_t *__restrict__ core_list, int64_t n_core,
-                                                      float inv_h, float inv_2h, float tau, float kw_lo, float kw_hi,
-                                                      float *__restrict__ out, uint32_t *__restrict__ fb_list,
+                                                      int64_t ci0, int64_t ci_end, float inv_h, float inv_2h,
+                                                      float tau, float kw_lo, float kw_hi, float *__restrict__ out,
+                                                      uint32_t *__restrict__ fb_list,
                                                       uint32_t *__restrict__ fb_count) {
     __shared__ LearnLds lds[kLearnPkgs];
     __shared__ int16_t s_off[kInPad];   // window offset of network input kk (ox + 9 oy + 81 oz), -1 past 215
@@ -742,9 +745,10 @@ __global__ __launch_bounds__(256) void learned_kernel(MlpDev W, const float *__r
     }
     const int slot = w >> 1, half = w & 1, t128 = threadIdx.x & 127;
     LearnLds &L = lds[slot];
-    const int64_t cw = (int64_t)blockIdx.x * kLearnPkgs + slot;
-    const bool live = cw < n_core;                 // a package slot past the end repeats the last package
-    const int64_t ci = live ? cw : n_core - 1;
+    // core packages [ci0, ci_end) of the n_core (outputs are indexed over all)
+    const int64_t cw = ci0 + (int64_t)blockIdx.x * kLearnPkgs + slot;
+    const bool live = cw < ci_end;                 // a package slot past the end repeats the last package
+    const int64_t ci = live ? cw : ci_end - 1;
     const int64_t p = core_list[ci];
     if (t128 < 27) L.ids[t128] = nbr[p * 27 + t128];
     __syncthreads();
@@ -1051,21 +1055,21 @@ __global__ __launch_bounds__(256) void gather_windows_kernel(const float *__rest
 
 namespace sgrid {
 
-// Gate + network over every core package, then the plain fallback over the
-// listed points.  `fb_list` holds n_core * 64 entries; `count` is reset here.
-// The fallback grid is a persistent one of at most four workgroups per
-// compute unit striding over the device-side count, so a launch costs little
-// when few points fall back.
+// Gate + network over the core packages [ci0, ci_end), then the plain
+// fallback over the listed points.  `fb_list` holds (ci_end - ci0) * 64
+// entries; `count` is reset here.  The fallback grid is a persistent one of at
+// most four workgroups per compute unit striding over the device-side count,
+// so a launch costs little when few points fall back.
 static sgrid_status learned_launch(const sgrid_grid *g, const float *phi, const sgrid_mlp *m, float *out,
-                                   uint32_t *fb_list, uint32_t *count, hipStream_t st) {
+                                   uint32_t *fb_list, uint32_t *count, int64_t ci0, int64_t ci_end, hipStream_t st) {
     hipLaunchKernelGGL(zero_u32_kernel, dim3(1), dim3(1), 0, st, count);
     SG_CHECK_LAUNCH("fallback counter reset");
-    if (g->n_core == 0) return SGRID_OK;
-    const int64_t cells = g->n_core * 64;
+    if (ci_end <= ci0) return SGRID_OK;
+    const int64_t cells = (ci_end - ci0) * 64;
     const float inv_h = (float)(1.0 / g->h), inv_2h = (float)(0.5 / g->h);
-    hipLaunchKernelGGL(learned_kernel, dim3((unsigned)((g->n_core + kLearnPkgs - 1) / kLearnPkgs)), dim3(256), 0,
-                       st, m->dev(), phi, g->nbr, g->core_list, g->n_core, inv_h, inv_2h, m->gate_tau, m->kw_lo,
-                       m->kw_hi, out, fb_list, count);
+    hipLaunchKernelGGL(learned_kernel, dim3((unsigned)((ci_end - ci0 + kLearnPkgs - 1) / kLearnPkgs)), dim3(256), 0,
+                       st, m->dev(), phi, g->nbr, g->core_list, g->n_core, ci0, ci_end, inv_h, inv_2h, m->gate_tau,
+                       m->kw_lo, m->kw_hi, out, fb_list, count);
     SG_CHECK_LAUNCH("learned integrals");
     const int64_t fb_blocks = std::min<int64_t>((cells + 255) / 256, 4 * (int64_t)cu_count());
     hipLaunchKernelGGL(fallback_kernel, dim3((unsigned)fb_blocks), dim3(256), 0, st, phi, g->nbr, g->core_list,
@@ -1084,12 +1088,89 @@ sgrid_status integrals_learned(const sgrid_grid *g, const float *phi, const sgri
     s = begin_use(m, st);
     if (s != SGRID_OK) return s;
     uint32_t *count = n_fallback ? n_fallback : m->fallback + m->fallback_cap;
-    s = learned_launch(g, phi, m, out, m->fallback, count, st);
+    s = learned_launch(g, phi, m, out, m->fallback, count, 0, g->n_core, st);
     if (s != SGRID_OK) return s;
     return end_use(m, st);
 }
 
 }  // namespace sgrid
+
+// ---------------------------------------------------------------------------
+// Learned integrals without allocation
+// ---------------------------------------------------------------------------
+// The fallback list lives in a fixed array in every GPU's memory (8 MiB each,
+// held until the process ends): two counters padded to 256 bytes, then room
+// for one chunk of kNoAllocChunk core packages' points.  Host code reaches it
+// only through the address hipGetSymbolAddress returns on each device.
+constexpr int64_t kNoAllocChunk = 32768;
+constexpr int64_t kNoAllocWords = 64 + kNoAllocChunk * 64;
+static __device__ __align__(256) uint32_t scratch[kNoAllocWords];
+
+namespace {
+
+constexpr int kNoAllocDevices = 64;
+std::mutex g_scratch_mutex;
+uint32_t *g_scratch_ptr[kNoAllocDevices] = {};
+
+// The device address of `scratch` on the current device, looked up on the
+// first call there.
+sgrid_status scratch_address(int dev, uint32_t **out) {
+    SG_REQUIRE(dev >= 0 && dev < kNoAllocDevices, "device %d is beyond the %d devices the library tracks", dev,
+               kNoAllocDevices);
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        SG_CHECK_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        SG_REQUIRE(p != nullptr, "no device address for the fallback array on device %d", dev);
+        g_scratch_ptr[dev] = static_cast<uint32_t *>(p);
+    }
+    *out = g_scratch_ptr[dev];
+    return SGRID_OK;
+}
+
+}  // namespace
+
+extern "C" sgrid_status sgrid_compute_near_surface_integrals_noalloc(const sgrid_grid *g, const float *phi,
+                                                                     const sgrid_mlp *model, float *out,
+                                                                     uint32_t *n_fallback, void *stream) {
+    sgrid::clear_error();
+    SG_REQUIRE(g != nullptr, "grid is NULL");
+    SG_REQUIRE(model != nullptr, "model is NULL (the plain integrals allocate nothing: use "
+                                 "sgrid_compute_near_surface_integrals)");
+    SG_REQUIRE(phi != nullptr, "phi is NULL");
+    SG_REQUIRE(out != nullptr || g->n_core == 0, "out is NULL");
+    SG_REQUIRE(sg_aligned(phi, 16) && sg_aligned(out, 16), "phi / out must be 16-byte aligned");
+    SG_REQUIRE(g->n_core * 64 <= (int64_t)UINT32_MAX, "%lld core packages: point indices exceed 32 bits",
+               (long long)g->n_core);
+    int dev = 0;
+    SG_CHECK_HIP(hipGetDevice(&dev));
+    SG_REQUIRE(g->device == dev && model->device == dev,
+               "grid (device %d) and model (device %d) must live on the current device %d", g->device,
+               model->device, dev);
+    uint32_t *sc = nullptr;
+    sgrid_status s = scratch_address(dev, &sc);
+    if (s != SGRID_OK) return s;
+    hipStream_t st = sg_stream(stream);
+    s = sgrid::begin_use(model, st);
+    if (s != SGRID_OK) return s;
+    uint32_t *chunk_count = sc, *total = n_fallback ? n_fallback : sc + 1, *list = sc + 64;
+    hipLaunchKernelGGL(zero_u32_kernel, dim3(1), dim3(1), 0, st, total);
+    SG_CHECK_LAUNCH("fallback total reset");
+    for (int64_t ci0 = 0; ci0 < g->n_core; ci0 += kNoAllocChunk) {
+        const int64_t ci_end = std::min<int64_t>(ci0 + kNoAllocChunk, g->n_core);
+        s = sgrid::learned_launch(g, phi, model, out, list, chunk_count, ci0, ci_end, st);
+        if (s != SGRID_OK) return s;
+        hipLaunchKernelGGL(add_u32_kernel, dim3(1), dim3(1), 0, st, total, (const uint32_t *)chunk_count);
+        SG_CHECK_LAUNCH("fallback total");
+    }
+    return sgrid::end_use(model, st);
+}
+
+sgrid_status sgrid::launch_zero_u32(uint32_t *p, hipStream_t st) {
+    hipLaunchKernelGGL(zero_u32_kernel, dim3(1), dim3(1), 0, st, p);
+    SG_CHECK_LAUNCH("counter reset");
+    return SGRID_OK;
+}
 
 extern "C" sgrid_status sgrid_gather_windows(const sgrid_grid *g, const float *phi, float *x_dev, uint8_t *unsat_dev,
                                              void *stream) {
