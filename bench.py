@@ -1,27 +1,32 @@
 """Benchmark of the narrow-band sparse-grid hot path on one MI355X.
 
-Default workload (prism512): extruded triangular prism (edges 0.6, extrusion
-0.8) at 512^3 data points, 4^3 packages within about two package widths of
-the surface, phi0 = SDF * (1 + 0.05 u); 100 reinitialisation iterations, the
-central-difference gradient, 1e7 particles jittered N(0, 0.5h) about the
-surface, plain near-surface integrals on every core point.
+Default workload (torus2048): torus R = 0.35, r = 0.1 whose surface is
+displaced by 0.02 x a sum of 8 seeded sinusoidal modes, at 2048^3 data points
+(narrow band only: 4^3 packages within about two package widths of the
+surface), phi0 = SDF * (1 + 0.05 u); 100 reinitialisation iterations, the
+central-difference gradient, 5e7 particles jittered N(0, 0.5h) about the
+surface (sorted by home cell, then probed), and the near-surface integrals
+of every core point by the learned surrogate with its residual gate and
+plain fallback.
 
 One step = one pass of the whole hot path over resident inputs: package
 build from the coarse distances, phi reset from phi0 (device copy), 100
-reinitialisation sweeps, packed gradient, packed probe, plain integrals.
-Inputs are generated once and resident in HBM before timing starts.
+reinitialisation sweeps, packed gradient, sort of the particles by home
+cell (Morton order) and the probe of the sorted particles, learned
+integrals with gate and fallback.  Inputs are generated once and resident in HBM before timing
+starts; the surrogate is trained before timing (by the library's training
+kernels, on points of 256 other seeded shapes).
 
 `value` = package-cell updates (64 P n_iter per step) per second of
-whole-step time.  The learned-versus-plain comparison (surrogate trained by
-the library's kernels on points of seeded random shapes) and the oracle's CPU
-baseline are added to the same JSON line.
+whole-step time.  The plain integrals (direct and factorised) are timed
+beside the step, with the learned error against them; the probe in generated
+particle order, and the oracle's CPU baseline, are added to the same JSON
+line.
 
-Other workloads: --workload torus2048 (displaced torus R=0.35, r=0.1 at
-2048^3 data points, narrow band only: 100 iterations, gradient, 5e7 surface
-particles, plain and gated learned integrals on its 46 M core points; the
-CPU baseline is the oracle on a 100^3-coarse-cell crop of the band) and
---workload batch64 (64 random unions, one persistent launch per iteration,
-graph replay, autotuned configuration).
+Other workloads: --workload prism512 (extruded triangular prism, edges 0.6,
+extrusion 0.8, at 512^3: the same step with 1e7 particles), batch64 (64
+random unions, one persistent launch per iteration, graph replay, autotuned
+configuration) and shell1024 (the paper's timing test).
 """
 from __future__ import annotations
 
@@ -49,13 +54,14 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="prism512", choices=["prism512", "torus2048", "batch64", "shell1024"])
+    ap.add_argument("--workload", default="torus2048", choices=["prism512", "torus2048", "batch64", "shell1024"])
     ap.add_argument("--n-iter", type=int, default=None)
     ap.add_argument("--sweep", default="auto",
                     help="sweep configuration 'variant,groups', or 'auto' to autotune it on the grid (default)")
     ap.add_argument("--particles", type=int, default=None, help="default: the workload's count")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-learned", action="store_true")
+    ap.add_argument("--no-learned", action="store_true",
+                    help="no surrogate: the step takes the plain integrals (factorised) instead")
     ap.add_argument("--cpu-iters", type=int, default=None,
                     help="oracle sweeps per CPU-baseline pass (default: the workload's iteration count)")
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
@@ -99,11 +105,32 @@ TORUS_CROPS = [(385, 206, 257), (206, 385, 257), (26, 206, 257), (206, 26, 257)]
 TORUS_CROP_EXTENT = 100
 
 
-def cpu_baseline(cfg, n_iter, min_seconds=10.0):
+def _omp():
+    """The OpenMP runtime the oracle's library uses (libgomp, already loaded)."""
+    import ctypes
+    gomp = ctypes.CDLL("libgomp.so.1")
+    gomp.omp_get_max_threads.restype = ctypes.c_int
+    gomp.omp_set_num_threads.argtypes = [ctypes.c_int]
+    return gomp
+
+
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(cfg, n_iter, min_seconds=10.0, one_thread_seconds=4.0):
     """The oracle (FP64, dense grid, OpenMP) timed on the host on a bounded
     sample of the workload: passes of `n_iter` reinitialisation sweeps from
     phi0 over the full band (or, at 2048^3 where the dense grid would not fit,
-    over crops of it in turn), repeated until `min_seconds` of sweeping."""
+    over crops of it in turn), repeated until `min_seconds` of sweeping with
+    every thread the runtime gives it; then the same on one thread for at
+    least `one_thread_seconds` (fewer sweeps per pass)."""
     import oracle
     t0 = time.perf_counter()
     if cfg["N"] > 1024:
@@ -116,26 +143,40 @@ def cpu_baseline(cfg, n_iter, min_seconds=10.0):
     dense = [oracle.dense_state(r.tab, r.active, r.phi0, r.B) for r in runs]
     setup_s = time.perf_counter() - t0
     oracle.reinit(runs[0].N, runs[0].h, runs[0].B, runs[0].active, dense[0], 1)       # warm-up
-    updates, secs, passes = 0, 0.0, 0
-    while secs < min_seconds:
-        r, d = runs[passes % len(runs)], dense[passes % len(runs)]
-        t0 = time.perf_counter()
-        oracle.reinit(r.N, r.h, r.B, r.active, d, n_iter)
-        secs += time.perf_counter() - t0
-        updates += len(r.active) * n_iter
-        passes += 1
-    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+
+    def timed(iters, seconds):
+        updates, secs, passes = 0, 0.0, 0
+        while secs < seconds:
+            r, d = runs[passes % len(runs)], dense[passes % len(runs)]
+            t1 = time.perf_counter()
+            oracle.reinit(r.N, r.h, r.B, r.active, d, iters)
+            secs += time.perf_counter() - t1
+            updates += len(r.active) * iters
+            passes += 1
+        return updates / secs, secs, passes
+
+    gomp = _omp()
+    threads = gomp.omp_get_max_threads()
+    rate, secs, passes = timed(n_iter, min_seconds)
+    gomp.omp_set_num_threads(1)
+    try:
+        one_iters = max(1, n_iter // 10)
+        rate1, secs1, passes1 = timed(one_iters, one_thread_seconds)
+    finally:
+        gomp.omp_set_num_threads(threads)
     pts = sum(len(r.active) for r in runs) // len(runs)
-    return {"value": updates / secs, "unit": "package-cell updates/s", "cores": threads, "kind": "oracle",
-            "sample": f"{passes} pass{'es' if passes != 1 else ''} of {n_iter} FP64 reinitialisation sweeps of the oracle over {where} "
-                      f"({pts} points per pass, {secs:.1f} s of sweeping; dense-grid setup {setup_s:.1f} s)"}
+    return {"value": rate, "unit": "package-cell updates/s", "cores": threads, "kind": "oracle",
+            "cpu_model": cpu_model(), "host_cpus": os.cpu_count(),
+            "one_thread_value": rate1,
+            "sample": f"{passes} pass{'es' if passes != 1 else ''} of {n_iter} FP64 reinitialisation sweeps of the "
+                      f"oracle over {where} ({pts} points per pass, {secs:.1f} s of sweeping on {threads} threads; "
+                      f"one thread: {passes1} passes of {one_iters} sweeps, {secs1:.1f} s; dense-grid setup "
+                      f"{setup_s:.1f} s)"}
 
 
-def learned_vs_plain(sg, wl, args, log):
-    """Train the surrogate on method-generated points, score it on held-out
-    points, and time learned (gated, with fallback) against plain integrals on
-    the benchmark grid's core points."""
-    import torch
+def train_surrogate(args, log):
+    """The surrogate trained by the library's kernels on points of 256 seeded
+    random shapes, with a held-out score on points of 128 others."""
     from paper_2512_11473_amd import surrogate
     tr = surrogate.generate(256, 101, args.train_cells)
     ho = surrogate.generate(128, 202, args.train_cells // 2)
@@ -143,12 +184,26 @@ def learned_vs_plain(sg, wl, args, log):
     res = surrogate.train(tr, epochs=args.epochs, batch=args.train_batch, log=None)
     log(f"surrogate trained: {res.steps} steps in {res.seconds:.1f}s, final loss {res.losses[-1]:.3e}")
     ev = surrogate.evaluate(res.model, ho, res.tau)
-    n = wl.grid.n_core * 64
-    out_p = torch.empty((4, n), device="cuda")
-    out_l = torch.empty((4, n), device="cuda")
-    nf = torch.zeros(1, dtype=torch.int32, device="cuda")
+    info = {"heldout": ev,
+            "train": {"points": int(tr.x.shape[0]), "shapes": tr.shapes, "epochs": args.epochs,
+                      "batch": args.train_batch, "steps": res.steps, "seconds": res.seconds,
+                      "final_loss": res.losses[-1], "gate_tau": res.tau}}
+    del tr, ho
+    return res.model, info
 
-    def t(fn, reps=10):
+
+def integrals_report(sg, g, wl, model, log):
+    """Learned (gated, with fallback) against both plain forms on the
+    benchmark grid's core points after the step: rates and the learned error
+    against the plain values."""
+    import torch
+    from paper_2512_11473_amd import surrogate
+    n = g.n_core * 64
+    out_p = torch.empty((4, n), device="cuda")
+    out_f = torch.empty((4, n), device="cuda")
+    vfrac = torch.empty_like(wl.phi)
+
+    def t(fn, reps=5):
         fn()
         torch.cuda.synchronize()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -159,41 +214,36 @@ def learned_vs_plain(sg, wl, args, log):
         torch.cuda.synchronize()
         return e0.elapsed_time(e1) / reps
 
-    ms_plain = t(lambda: sg.compute_near_surface_integrals(wl.grid, wl.phi, out_p))
-    ms_learn = t(lambda: sg.compute_near_surface_integrals(wl.grid, wl.phi, out_l, model=res.model, n_fallback=nf))
-    e = surrogate.relative_error(out_l.t(), out_p.t())
-    return {
-        "plain_cells_per_s": n / (ms_plain * 1e-3),
-        "learned_cells_per_s": n / (ms_learn * 1e-3),
-        "learned_over_plain": ms_plain / ms_learn,
-        "target_rel_error": 1e-3,
-        "heldout": ev,
-        "bench_grid_error": surrogate.error_stats(e),
-        "bench_grid_fallback_fraction": int(nf.item()) / n,
-        "train": {"points": int(tr.x.shape[0]), "shapes": tr.shapes, "epochs": args.epochs, "batch": args.train_batch,
-                  "steps": res.steps, "seconds": res.seconds, "final_loss": res.losses[-1],
-                  "gate_tau": res.tau},
-    }
+    ms_direct = t(lambda: sg.compute_near_surface_integrals(g, wl.phi, out_p))
+    ms_fact = t(lambda: sg.compute_near_surface_integrals_factorised(g, wl.phi, vfrac, out_f))
+    same = bool(torch.equal(out_p, out_f))
+    del out_f, vfrac
+    rec = {"plain_direct_cells_per_s": n / (ms_direct * 1e-3),
+           "plain_factorised_cells_per_s": n / (ms_fact * 1e-3),
+           "factorised_equals_direct": same}
+    if model is not None:
+        out_l = torch.empty((4, n), device="cuda")
+        nf = torch.zeros(1, dtype=torch.int32, device="cuda")
+        ms_learn = t(lambda: sg.compute_near_surface_integrals(g, wl.phi, out_l, model=model, n_fallback=nf))
+        e = surrogate.relative_error(out_l.t(), out_p.t())
+        rec.update({"learned_cells_per_s": n / (ms_learn * 1e-3),
+                    "learned_over_plain_direct": ms_direct / ms_learn,
+                    "learned_over_plain_factorised": ms_fact / ms_learn,
+                    "target_rel_error": 1e-3,
+                    "bench_grid_error": surrogate.error_stats(e),
+                    "bench_grid_fallback_fraction": int(nf.item()) / n})
+        log(f"integrals: plain direct {ms_direct:.2f} ms, factorised {ms_fact:.2f} ms, learned {ms_learn:.2f} ms")
+    return rec
 
 
 WORKLOAD_TEXT = {
     "prism512": "prism512: extruded triangular prism (edges 0.6, extrusion 0.8) at 512^3, 5% noise, "
-                "100 reinitialisation iterations, gradient, 1e7 jittered particles, plain integrals on all "
-                "core points",
+                "100 reinitialisation iterations, gradient, sort and probe of 1e7 jittered particles, "
+                "near-surface integrals on all core points",
     "torus2048": "torus2048: torus R=0.35, r=0.1 displaced by 0.02 x 8 seeded modes at 2048^3 (narrow band "
-                 "only), 100 reinitialisation iterations, gradient, 5e7 jittered particles, plain integrals "
-                 "on all core points; learned integrals with gate and fallback timed beside the step",
+                 "only), 100 reinitialisation iterations, gradient, sort and probe of 5e7 jittered particles, "
+                 "near-surface integrals on all core points",
 }
-
-
-def cell_sorted(pos, N):
-    """The particles reordered by the linear index of their home coarse cell
-    (for the sorted-order probe figure)."""
-    import numpy as np
-    M = N // 4
-    c = np.clip(np.floor(pos.astype(np.float64) * M).astype(np.int64), 0, M - 1)
-    key = c[:, 0] + M * (c[:, 1] + M * c[:, 2])
-    return np.ascontiguousarray(pos[np.argsort(key, kind="stable")])
 
 
 def multires_build(sg, synth, cfg, dense_grid, log, levels=2, reps=5):
@@ -291,7 +341,6 @@ def sign_correction(sg, cfg, wl, log):
 
 
 def bench_single(args, log):
-    import numpy as np
     import torch
     import paper_2512_11473_amd as sg
     import synth
@@ -303,10 +352,10 @@ def bench_single(args, log):
     t0 = time.perf_counter()
     pos = synth.particles_for(cfg, args.particles)
     wl = workload.setup(cfg["shape"], cfg["N"], cfg["noise_amp"], cfg["noise_seed"], particles=pos)
-    pos_sorted = torch.from_numpy(cell_sorted(pos, cfg["N"])).cuda()
     del pos
     setup_s = time.perf_counter() - t0
     log(f"{cfg['name']} set up in {setup_s:.1f}s: {wl.grid.n_packages} packages, {wl.grid.n_core} core")
+    model, learned_info = (None, None) if args.no_learned else train_surrogate(args, log)
     # sweep configuration: tuned once on this grid (phi0 is only read), or fixed
     if args.sweep == "auto":
         tv, tg, ttab = sg.autotune_sweep(wl.grid, wl.phi0, wl.scratch, reps=10)
@@ -319,19 +368,24 @@ def bench_single(args, log):
     log(f"sweep configuration: variant {tv}, groups {tg}")
     P = wl.grid.n_packages
     n_core = wl.grid.n_core
+    n_part = int(wl.pos.shape[0])
     integ = torch.empty((4, n_core * 64), device="cuda")
     packed = torch.empty((wl.grid.n_total, 64, 4), device="cuda")
+    pos_sorted = torch.empty_like(wl.pos)
+    perm = torch.empty(n_part, dtype=torch.int32, device="cuda")
+    sort_ws = torch.empty(sg.sort_workspace_bytes(wl.grid, n_part), dtype=torch.uint8, device="cuda")
+    n_fb = torch.zeros(1, dtype=torch.int32, device="cuda")
     if args.overlap:   # the step on a stream of its own, the integrals on a second one
         torch.cuda.synchronize()
         torch.cuda.set_stream(torch.cuda.Stream())
     stream = torch.cuda.current_stream()
 
     ev = {k: [torch.cuda.Event(enable_timing=True) for _ in range(2)] for k in
-          ("build", "reinit", "grad", "probe", "integ")}
+          ("build", "reinit", "grad", "sort", "probe", "integ")}
     acc = {k: 0.0 for k in ev}
 
-    # with --overlap a second stream (default priority) takes the integrals
-    # (VALU-bound), which then run beside the gradient and the probe (memory-
+    # with --overlap a second stream (default priority) takes the integrals,
+    # which then run beside the gradient, the sort and the probe (memory-
     # bound); by default every step runs on one stream
     side = torch.cuda.Stream() if args.overlap else stream
     ev_reinit, ev_integ = torch.cuda.Event(), torch.cuda.Event()
@@ -350,14 +404,20 @@ def bench_single(args, log):
         ev_reinit.record(stream)
         side.wait_event(ev_reinit)
         mark("integ", 0, side)
-        sg.compute_near_surface_integrals(g, wl.phi, integ, stream=side)
+        if model is not None:
+            sg.compute_near_surface_integrals(g, wl.phi, integ, model=model, n_fallback=n_fb, stream=side)
+        else:   # plain, factorised (its fractions go to the sweep's scratch)
+            sg.compute_near_surface_integrals_factorised(g, wl.phi, wl.scratch, integ, stream=side)
         mark("integ", 1, side)
         ev_integ.record(side)
         mark("grad", 0)
         sg.compute_gradient_packed(g, wl.phi, packed)
         mark("grad", 1)
+        mark("sort", 0)
+        sg.sort_particles(g, wl.pos, pos_sorted, perm, workspace=sort_ws)
+        mark("sort", 1)
         mark("probe", 0)
-        sg.probe_particles_packed(g, packed, wl.pos, wl.phi_p, wl.nrm_p)
+        sg.probe_particles_packed(g, packed, pos_sorted, wl.phi_p, wl.nrm_p)
         mark("probe", 1)
         stream.wait_event(ev_integ)
         return g
@@ -374,24 +434,28 @@ def bench_single(args, log):
         g.destroy()
     torch.cuda.synchronize()
     total_s = time.perf_counter() - t0
+    fb_fraction = int(n_fb.item()) / max(1, n_core * 64) if model is not None else None
 
-    # the same probe over cell-sorted particles (not part of the step)
+    # the same probe over the particles in generated order (not part of the step)
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     g = sg.build_packages(wl.coarse, wl.h)
     sg.reinitialize(g, wl.phi, wl.scratch, cfg["n_iter"])
     sg.compute_gradient_packed(g, wl.phi, packed)
-    sg.probe_particles_packed(g, packed, pos_sorted, wl.phi_p, wl.nrm_p)
+    sg.probe_particles_packed(g, packed, wl.pos, wl.phi_p, wl.nrm_p)
     e0.record(stream)
     for _ in range(5):
-        sg.probe_particles_packed(g, packed, pos_sorted, wl.phi_p, wl.nrm_p)
+        sg.probe_particles_packed(g, packed, wl.pos, wl.phi_p, wl.nrm_p)
     e1.record(stream)
     torch.cuda.synchronize()
-    probe_sorted_ms = e0.elapsed_time(e1) / 5
-    del pos_sorted
+    probe_random_ms = e0.elapsed_time(e1) / 5
+    del pos_sorted, perm, sort_ws
+    integrals = integrals_report(sg, g, wl, model, log)
+    if learned_info is not None:
+        integrals.update(learned_info)
     # grid-to-particle coupling of the integral field (Sec. 8), not part of the
     # step: the field at every activated point, then its probe at the particles
     field = torch.empty((g.n_total, 64, 4), device="cuda")
-    fout = torch.empty((int(wl.pos.shape[0]), 4), device="cuda")
+    fout = torch.empty((n_part, 4), device="cuda")
     sg.compute_integral_field(g, wl.phi, field)
     sg.probe_integral_field(g, field, wl.pos, fout)
     e2 = torch.cuda.Event(enable_timing=True)
@@ -422,8 +486,7 @@ def bench_single(args, log):
     K = args.steps
     ms_step = 1e3 * total_s / K
     upd_step = 64 * P * cfg["n_iter"]
-    n_part = int(wl.pos.shape[0])
-    probe_ms = acc["probe"] / K
+    sort_ms, probe_ms = acc["sort"] / K, acc["probe"] / K
     probe_bytes = PROBE_BYTES_PER_PARTICLE * n_part + 16.0 * 64 * P
     reinit_ms = acc["reinit"] / K
     sweep_ms = reinit_ms / cfg["n_iter"]
@@ -438,25 +501,31 @@ def bench_single(args, log):
         "dtype": "f32", "data": "synthetic",
         "config": {"workload": WORKLOAD_TEXT[cfg["name"]],
                    "N": cfg["N"], "n_packages": P, "n_core": n_core, "n_iter": cfg["n_iter"],
-                   "particles": n_part},
+                   "particles": n_part,
+                   "integrals_in_step": "learned, gated, plain fallback" if model is not None
+                   else "plain (factorised)"},
         "breakdown_ms": {k: acc[k] / K for k in acc},
         "reinit_updates_per_s": upd_step / (reinit_ms * 1e-3),
         "sweep_config": tuned,
-        "probes_per_s": n_part / (probe_ms * 1e-3),
-        "probe_particle_order": "as generated (random over the surface)",
-        "probes_per_s_cell_sorted": n_part / (probe_sorted_ms * 1e-3),
+        "probes_per_s": n_part / ((sort_ms + probe_ms) * 1e-3),
+        "probe_particle_order": "sorted by home cell (Morton order) inside the step: sort + probe of the sorted particles",
+        "probe_only_per_s": n_part / (probe_ms * 1e-3),
+        "probes_per_s_generated_order": n_part / (probe_random_ms * 1e-3),
         "probe_hbm": {"algorithmic_bytes_per_launch": probe_bytes,
                       "note": "28 B per particle (position in, value and normal out) plus the packed field once",
-                      "random_order_GBps": probe_bytes / (probe_ms * 1e-3) / 1e9,
-                      "cell_sorted_GBps": probe_bytes / (probe_sorted_ms * 1e-3) / 1e9,
-                      "cell_sorted_frac": probe_bytes / (probe_sorted_ms * 1e-3) / 1e9 / HBM_PEAK_GBS},
-        "integral_cells_per_s": n_core * 64 / (acc["integ"] / K * 1e-3),
+                      "sorted_probe_GBps": probe_bytes / (probe_ms * 1e-3) / 1e9,
+                      "sorted_probe_frac": probe_bytes / (probe_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                      "sort_plus_probe_GBps": probe_bytes / ((sort_ms + probe_ms) * 1e-3) / 1e9,
+                      "generated_order_GBps": probe_bytes / (probe_random_ms * 1e-3) / 1e9},
+        "integral_cells_per_s_in_step": n_core * 64 / (acc["integ"] / K * 1e-3),
+        "step_fallback_fraction": fb_fraction,
+        "integrals": integrals,
         "multires_build": multires,
         "sign_correction": signs,
         "integral_field": {"field_ms": field_ms, "field_points_per_s": 64 * P / (field_ms * 1e-3),
                            "probe_ms": fprobe_ms, "probes_per_s": n_part / (fprobe_ms * 1e-3),
                            "note": "(K_W, h K_grad) at every activated point, then interpolated to the particles "
-                                   "(random order); measured outside the step"},
+                                   "(generated order); measured outside the step"},
         "roofline": {"bound": "hbm", "kernel": f"reinit sweep (variant {tv}, groups {tg})", "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": measured_traffic(f"reinit_sweep_{cfg['name']}_counters.txt", f"v{tv}g{tg}"),
@@ -468,9 +537,6 @@ def bench_single(args, log):
         "setup_s": setup_s,
     }
     log(f"timed {K} steps: {ms_step:.2f} ms per step")
-    if not args.no_learned:
-        rec["learned"] = learned_vs_plain(sg, wl, args, log)
-        log("learned vs plain done")
     if not args.no_cpu_baseline:
         rec["cpu_baseline"] = cpu_baseline(cfg, args.cpu_iters or cfg["n_iter"], args.cpu_seconds)
         log("cpu baseline done")

@@ -222,6 +222,25 @@ sgrid_status sgrid_probe_particles_packed(const sgrid_grid *grid, sgrid_dtype dt
                                           void *normal_out_dev, void *stream);
 
 /*
+ * Particle reordering for the probe (Sec. 8 probing is position-based random
+ * access; the reordering is not in the paper).  Stable sort of n FP32
+ * particles `pos_dev` [n][3] by the Morton (Z-order) code of their home
+ * coarse cell (the probe's cell clamp(floor(x / 4h), 0, M - 1) per axis, bit
+ * b of x, y, z at bits 3b, 3b + 1, 3b + 2), the order of the sweep worklist,
+ * so that particles of one package are adjacent and neighbouring packages
+ * close.  Writes pos_sorted_dev [n][3] with pos_sorted[i] = pos[perm[i]] and
+ * perm_dev [n] (uint32): keys non-decreasing, equal keys in input order, so
+ * the result is unique.  Probing pos_sorted gives each particle's values in
+ * sorted order; perm maps them back.  `workspace_dev` (caller-owned,
+ * 256-byte aligned, contents on return unspecified) of at least the bytes
+ * sgrid_sort_particles_workspace_size returns (about 16 n + 0.25 n bytes).
+ * n in [0, 2^32 - 1]; pos and pos_sorted distinct.  Asynchronous on `stream`.
+ */
+sgrid_status sgrid_sort_particles_workspace_size(const sgrid_grid *grid, int64_t n, int64_t *bytes);
+sgrid_status sgrid_sort_particles(const sgrid_grid *grid, const float *pos_dev, int64_t n, float *pos_sorted_dev,
+                                  uint32_t *perm_dev, void *workspace_dev, int64_t workspace_bytes, void *stream);
+
+/*
  * Near-surface kernel integrals (Sec. 8 names the integral with an SPH
  * smoothing kernel over the sparse grid).  At every data point p of every
  * core package, with query point q = x_p + (h/2)(1,1,1) and the 32 data points

@@ -25,6 +25,7 @@ __all__ = [
     "sequential_update", "compute_laplacian",
     "autotune_sweep", "SWEEP_TUNE_CANDIDATES",
     "Mlp", "gather_windows", "MLP_N_PARAMS", "Batch", "compute_near_surface_integrals_noalloc",
+    "sort_particles", "sort_workspace_bytes",
     "LIB_PATH", "FAR_FIELD_IN_H",
 ]
 
@@ -86,6 +87,8 @@ _SIGNATURES = {
     "sgrid_mlp_apply_gradient": (ctypes.c_int, [_P, _P, ctypes.c_float, _P]),
     "sgrid_gather_windows": (ctypes.c_int, [_P, _P, _P, _P, _P]),
     "sgrid_compute_near_surface_integrals_noalloc": (ctypes.c_int, [_P, _P, _P, _P, _P, _P]),
+    "sgrid_sort_particles_workspace_size": (ctypes.c_int, [_P, ctypes.c_int64, ctypes.POINTER(ctypes.c_int64)]),
+    "sgrid_sort_particles": (ctypes.c_int, [_P, _P, ctypes.c_int64, _P, _P, _P, ctypes.c_int64, _P]),
     "sgrid_batch_create": (ctypes.c_int, [_P, ctypes.c_int32, _P, ctypes.POINTER(_P)]),
     "sgrid_batch_destroy": (ctypes.c_int, [_P]),
     "sgrid_batch_info": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64), _P]),
@@ -357,6 +360,32 @@ def probe_particles_packed(grid: Grid, packed: torch.Tensor, pos: torch.Tensor, 
     _check(load().sgrid_probe_particles_packed(grid.handle, _dtype_code(packed), _dev(packed, "packed"),
                                                _dev(pos, "pos"), n, _dev(phi_out, "phi_out"),
                                                _dev(normal_out, "normal_out"), _stream(stream)))
+
+
+def sort_workspace_bytes(grid: Grid, n: int) -> int:
+    out = ctypes.c_int64()
+    _check(load().sgrid_sort_particles_workspace_size(grid.handle, int(n), ctypes.byref(out)))
+    return int(out.value)
+
+
+def sort_particles(grid: Grid, pos: torch.Tensor, pos_sorted: torch.Tensor, perm: torch.Tensor,
+                   workspace: Optional[torch.Tensor] = None, stream=None):
+    """Counting sort of the particles by home package (Morton worklist order):
+    pos_sorted[i] = pos[perm[i]].  `workspace` is a device tensor of at least
+    sort_workspace_bytes(grid, n) bytes (allocated here when None)."""
+    n = pos.numel() // 3
+    _f32(pos, "pos", 3 * n)
+    _f32(pos_sorted, "pos_sorted", 3 * n)
+    if perm.dtype not in (torch.int32, torch.uint32) or perm.numel() != n:
+        raise TypeError("perm must be an int32 or uint32 tensor of n elements")
+    need = sort_workspace_bytes(grid, n)
+    if workspace is None:
+        workspace = torch.empty(max(need, 4), dtype=torch.uint8, device="cuda")
+    have = workspace.numel() * workspace.element_size()
+    if have < need:
+        raise ValueError(f"workspace holds {have} bytes, the sort needs {need}")
+    _check(load().sgrid_sort_particles(grid.handle, _dev(pos, "pos"), n, _dev(pos_sorted, "pos_sorted"),
+                                       _dev(perm, "perm"), _dev(workspace, "workspace"), have, _stream(stream)))
 
 
 def probe_particles(grid: Grid, phi: torch.Tensor, grad: torch.Tensor, pos: torch.Tensor,

@@ -55,12 +55,14 @@ __device__ __forceinline__ bf16x8 ld8(const bf16 *p) { return *reinterpret_cast<
 
 // GELU in its tanh form, 0.5 z (1 + tanh(u)) with u = sqrt(2/pi) (z + 0.044715
 // z^3), evaluated as z s with s = 0.5 (1 + tanh(u)) = 1 / (1 + exp(-2u)): the
-// same function, with the hardware exponential and reciprocal instead of a
-// library tanh (the activations dominate the network's vector work).  For
+// same function.  exp(-2u) = 2^(k z (1 + 0.044715 z^2)) with k = -2 sqrt(2/pi)
+// / ln 2 folded into the polynomial, on the hardware's base-2 exponential and
+// reciprocal (each within one ulp; the activations dominate the network's
+// vector work, and an IEEE division would cost ten instructions more).  For
 // large |u| the exponential saturates to 0 or inf and s to 1 or 0.
 __device__ __forceinline__ float gelu_s(float z) {
-    const float u = 0.7978845608028654f * (z + 0.044715f * z * z * z);
-    return __frcp_rn(1.0f + __expf(-2.0f * u));
+    const float a = z * __builtin_fmaf(-0.1029432395800235f, z * z, -2.302208198144325f);
+    return __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(a));
 }
 
 __device__ __forceinline__ float gelu(float z) { return z * gelu_s(z); }
@@ -86,8 +88,12 @@ template <class XSrc>
 __device__ __forceinline__ void forward_tile(const XSrc &xs, const MlpDev &W, bf16 *a1, bf16 *a2, bf16 *xh, Tile &T,
                                              int lane) {
     const int r = lane & 15, q = lane >> 4;
+    // every accumulator starts from its bias (the column's hidden unit)
 #pragma unroll
-    for (int t = 0; t < 8; ++t) T.z1[t] = floatx4{0.f, 0.f, 0.f, 0.f};
+    for (int t = 0; t < 8; ++t) {
+        const float bb = W.w[oB1 + 16 * t + r];
+        T.z1[t] = floatx4{bb, bb, bb, bb};
+    }
     for (int s = 0; s < kInPad / 32; ++s) {
         float v[8];
         xs(r, 32 * s + 8 * q, v);
@@ -107,17 +113,15 @@ __device__ __forceinline__ void forward_tile(const XSrc &xs, const MlpDev &W, bf
         }
     }
 #pragma unroll
-    for (int t = 0; t < 8; ++t) {
-        const float bb = W.w[oB1 + 16 * t + r];
+    for (int t = 0; t < 8; ++t)
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            T.z1[t][i] += bb;
-            a1[(4 * q + i) * kH + 16 * t + r] = (bf16)gelu(T.z1[t][i]);
-        }
-    }
+        for (int i = 0; i < 4; ++i) a1[(4 * q + i) * kH + 16 * t + r] = (bf16)gelu(T.z1[t][i]);
     __syncthreads();
 #pragma unroll
-    for (int t = 0; t < 8; ++t) T.z2[t] = floatx4{0.f, 0.f, 0.f, 0.f};
+    for (int t = 0; t < 8; ++t) {
+        const float bb = W.w[oB2 + 16 * t + r];
+        T.z2[t] = floatx4{bb, bb, bb, bb};
+    }
 #pragma unroll
     for (int s = 0; s < kH / 32; ++s) {
         const bf16x8 a = ld8(a1 + r * kH + 32 * s + 8 * q);
@@ -125,24 +129,15 @@ __device__ __forceinline__ void forward_tile(const XSrc &xs, const MlpDev &W, bf
         for (int t = 0; t < 8; ++t) T.z2[t] = mfma(a, ld8(W.w2b + (16 * t + r) * kH + 32 * s + 8 * q), T.z2[t]);
     }
 #pragma unroll
-    for (int t = 0; t < 8; ++t) {
-        const float bb = W.w[oB2 + 16 * t + r];
+    for (int t = 0; t < 8; ++t)
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            T.z2[t][i] += bb;
-            a2[(4 * q + i) * kH + 16 * t + r] = (bf16)gelu(T.z2[t][i]);
-        }
-    }
+        for (int i = 0; i < 4; ++i) a2[(4 * q + i) * kH + 16 * t + r] = (bf16)gelu(T.z2[t][i]);
     __syncthreads();
-    T.y = floatx4{0.f, 0.f, 0.f, 0.f};
+    const float b3 = r < kOut ? W.w[oB3 + r] : 0.f;
+    T.y = floatx4{b3, b3, b3, b3};
 #pragma unroll
     for (int s = 0; s < kH / 32; ++s)
         T.y = mfma(ld8(a2 + r * kH + 32 * s + 8 * q), ld8(W.w3b + r * kH + 32 * s + 8 * q), T.y);
-    if (r < kOut) {
-        const float bb = W.w[oB3 + r];
-#pragma unroll
-        for (int i = 0; i < 4; ++i) T.y[i] += bb;
-    }
 }
 
 // ---------------------------------------------------------------------------
@@ -703,6 +698,28 @@ struct Taps {
     float Wn, Wf, Dn, Df;
 };
 
+// The 32 taps of a point's query: offsets o in {-1, 0, 1, 2}^3 with
+// |(1/2, 1/2, 1/2) - o| < 2, in the order oz, oy, ox.
+struct TapOffset {
+    int x, y, z;
+};
+constexpr int tap_r2x4(int ox, int oy, int oz) {   // 4 |(1/2, 1/2, 1/2) - o|^2
+    return (1 - 2 * ox) * (1 - 2 * ox) + (1 - 2 * oy) * (1 - 2 * oy) + (1 - 2 * oz) * (1 - 2 * oz);
+}
+struct TapTable {
+    TapOffset t[32];
+    constexpr TapTable() : t() {
+        int n = 0;
+        for (int oz = -1; oz <= 2; ++oz)
+            for (int oy = -1; oy <= 2; ++oy)
+                for (int ox = -1; ox <= 2; ++ox)
+                    if (tap_r2x4(ox, oy, oz) < 16) t[n++] = TapOffset{ox, oy, oz};
+    }
+};
+constexpr TapTable kTapTable{};
+constexpr const TapOffset *kTapOffsets = kTapTable.t;
+static_assert(tap_r2x4(-1, 0, 0) == 11 && kTapTable.t[31].z == 2, "tap table");
+
 __device__ __forceinline__ Taps make_taps() {
     return Taps{(float)sgrid::wendland_u(sqrt(0.75)), (float)sgrid::wendland_u(sqrt(2.75)),
                 (float)sgrid::wendland_dr_over_r_u(sqrt(0.75)), (float)sgrid::wendland_dr_over_r_u(sqrt(2.75))};
@@ -721,12 +738,16 @@ __global__ __launch_bounds__(64) void add_u32_kernel(uint32_t *total, const uint
 // sgrid_mlp_forward on the gathered windows.
 constexpr int kLearnPkgs = 2;   // packages per workgroup
 constexpr int kLearnTiles = 2;  // 16-point tiles per wavefront
+constexpr int kActStride = kH + 8;   // bf16 per activation row in LDS
 
 struct LearnLds {
     float phi[kWinN + 3];
+    bf16 xh[kWinN + 7], xl[kWinN + 7];   // BF16 hi and lo parts of the window's phi / h
     uint32_t ids[28];
     uint8_t sat[kVolN + 13];
-    __attribute__((aligned(16))) bf16 act[64 * kH];   // a1, then a2, then the outputs y (FP32 [64][4])
+    // a1, then a2, then the outputs y (FP32 [64][4]); rows padded by 16 bytes,
+    // so that the sixteen rows of an A-fragment read start in different banks
+    __attribute__((aligned(16))) bf16 act[64 * kActStride];
 };
 
 __global__ __launch_bounds__(256) void learned_kernel(MlpDev W, const float *__restrict__ phi,
@@ -737,11 +758,14 @@ __global__ __launch_bounds__(256) void learned_kernel(MlpDev W, const float *__r
                                                       uint32_t *__restrict__ fb_list,
                                                       uint32_t *__restrict__ fb_count) {
     __shared__ LearnLds lds[kLearnPkgs];
-    __shared__ int16_t s_off[kInPad];   // window offset of network input kk (ox + 9 oy + 81 oz), -1 past 215
+    // window offset of network input kk (ox + 9 oy + 81 oz); the padding
+    // inputs 216..223 meet zero columns of W1, so they read any finite window
+    // value (offset 0) and add exactly zero, without a branch per input
+    __shared__ int16_t s_off[kInPad];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, r = lane & 15, q = lane >> 4;
     if (threadIdx.x < kInPad) {
         const int kk = threadIdx.x;
-        s_off[kk] = kk < kIn ? (int16_t)(kk % 6 + kWin * ((kk / 6) % 6) + kWin * kWin * (kk / 36)) : (int16_t)-1;
+        s_off[kk] = kk < kIn ? (int16_t)(kk % 6 + kWin * ((kk / 6) % 6) + kWin * kWin * (kk / 36)) : (int16_t)0;
     }
     const int slot = w >> 1, half = w & 1, t128 = threadIdx.x & 127;
     LearnLds &L = lds[slot];
@@ -764,13 +788,23 @@ __global__ __launch_bounds__(256) void learned_kernel(MlpDev W, const float *__r
         const bool sat = a != 0.f && fabsf(a) >= 0.5f * (fabsf(gx) + fabsf(gy) + fabsf(gz));
         L.sat[v] = (uint8_t)((sat ? 1 : 0) | (a > 0.f ? 2 : 0));
     }
+    // the network inputs' BF16 hi + lo parts, once per window value
+    for (int v = t128; v < kWinN; v += 128) {
+        const float x = L.phi[v] * inv_h;
+        const bf16 hi = (bf16)x;
+        L.xh[v] = hi;
+        L.xl[v] = (bf16)(x - (float)hi);
+    }
+    __syncthreads();
     const int cell0 = 32 * half;   // this wavefront's points: cell0 .. cell0 + 31
     // layer 1: [32 x 224] (hi + lo BF16 parts of phi / h) x W1^T
     floatx4 acc[kLearnTiles][8];
 #pragma unroll
-    for (int m = 0; m < kLearnTiles; ++m)
+    for (int t = 0; t < 8; ++t) {   // accumulators start from the biases, as in forward_tile
+        const float bb = W.w[oB1 + 16 * t + r];
 #pragma unroll
-        for (int t = 0; t < 8; ++t) acc[m][t] = floatx4{0.f, 0.f, 0.f, 0.f};
+        for (int m = 0; m < kLearnTiles; ++m) acc[m][t] = floatx4{bb, bb, bb, bb};
+    }
     // the weight fragments of step s + 1 load while step s multiplies
     bf16x8 bw[8], bn[8];
 #pragma unroll
@@ -784,20 +818,14 @@ __global__ __launch_bounds__(256) void learned_kernel(MlpDev W, const float *__r
         }
 #pragma unroll
         for (int m = 0; m < kLearnTiles; ++m) {
-            float v[8];
             const int c = cell0 + 16 * m + r;
-            const float *base = L.phi + (c & 3) + kWin * (((c >> 2) & 3) + kWin * (c >> 4));
-#pragma unroll
-            for (int e = 0; e < 8; ++e) {
-                const int off = s_off[32 * s + 8 * q + e];
-                v[e] = off >= 0 ? base[off] * inv_h : 0.f;
-            }
+            const int base = (c & 3) + kWin * (((c >> 2) & 3) + kWin * (c >> 4));
             bf16x8 ah, al;
 #pragma unroll
-            for (int j = 0; j < 8; ++j) {
-                const bf16 hi = (bf16)v[j];
-                ah[j] = hi;
-                al[j] = (bf16)(v[j] - (float)hi);
+            for (int e = 0; e < 8; ++e) {
+                const int off = base + s_off[32 * s + 8 * q + e];
+                ah[e] = L.xh[off];
+                al[e] = L.xl[off];
             }
 #pragma unroll
             for (int t = 0; t < 8; ++t) {
@@ -806,21 +834,21 @@ __global__ __launch_bounds__(256) void learned_kernel(MlpDev W, const float *__r
             }
         }
     }
-    bf16 *act = L.act + cell0 * kH;
+    bf16 *act = L.act + cell0 * kActStride;
 #pragma unroll
-    for (int t = 0; t < 8; ++t) {
-        const float bb = W.w[oB1 + 16 * t + r];
+    for (int t = 0; t < 8; ++t)
 #pragma unroll
         for (int m = 0; m < kLearnTiles; ++m)
 #pragma unroll
-            for (int i = 0; i < 4; ++i) act[(16 * m + 4 * q + i) * kH + 16 * t + r] = (bf16)gelu(acc[m][t][i] + bb);
-    }
+            for (int i = 0; i < 4; ++i) act[(16 * m + 4 * q + i) * kActStride + 16 * t + r] = (bf16)gelu(acc[m][t][i]);
     __syncthreads();
     // layer 2
 #pragma unroll
-    for (int m = 0; m < kLearnTiles; ++m)
+    for (int t = 0; t < 8; ++t) {
+        const float bb = W.w[oB2 + 16 * t + r];
 #pragma unroll
-        for (int t = 0; t < 8; ++t) acc[m][t] = floatx4{0.f, 0.f, 0.f, 0.f};
+        for (int m = 0; m < kLearnTiles; ++m) acc[m][t] = floatx4{bb, bb, bb, bb};
+    }
 #pragma unroll
     for (int s = 0; s < kH / 32; ++s) {
         bf16x8 bw[8];
@@ -828,65 +856,63 @@ __global__ __launch_bounds__(256) void learned_kernel(MlpDev W, const float *__r
         for (int t = 0; t < 8; ++t) bw[t] = ld8(W.w2b + (16 * t + r) * kH + 32 * s + 8 * q);
 #pragma unroll
         for (int m = 0; m < kLearnTiles; ++m) {
-            const bf16x8 a = ld8(act + (16 * m + r) * kH + 32 * s + 8 * q);
+            const bf16x8 a = ld8(act + (16 * m + r) * kActStride + 32 * s + 8 * q);
 #pragma unroll
             for (int t = 0; t < 8; ++t) acc[m][t] = mfma(a, bw[t], acc[m][t]);
         }
     }
     __syncthreads();
 #pragma unroll
-    for (int t = 0; t < 8; ++t) {
-        const float bb = W.w[oB2 + 16 * t + r];
+    for (int t = 0; t < 8; ++t)
 #pragma unroll
         for (int m = 0; m < kLearnTiles; ++m)
 #pragma unroll
-            for (int i = 0; i < 4; ++i) act[(16 * m + 4 * q + i) * kH + 16 * t + r] = (bf16)gelu(acc[m][t][i] + bb);
-    }
+            for (int i = 0; i < 4; ++i) act[(16 * m + 4 * q + i) * kActStride + 16 * t + r] = (bf16)gelu(acc[m][t][i]);
     __syncthreads();
     // layer 3
     floatx4 y[kLearnTiles];
+    const float b3 = r < kOut ? W.w[oB3 + r] : 0.f;
 #pragma unroll
-    for (int m = 0; m < kLearnTiles; ++m) y[m] = floatx4{0.f, 0.f, 0.f, 0.f};
+    for (int m = 0; m < kLearnTiles; ++m) y[m] = floatx4{b3, b3, b3, b3};
 #pragma unroll
     for (int s = 0; s < kH / 32; ++s) {
         const bf16x8 b3 = ld8(W.w3b + r * kH + 32 * s + 8 * q);
 #pragma unroll
-        for (int m = 0; m < kLearnTiles; ++m) y[m] = mfma(ld8(act + (16 * m + r) * kH + 32 * s + 8 * q), b3, y[m]);
+        for (int m = 0; m < kLearnTiles; ++m) y[m] = mfma(ld8(act + (16 * m + r) * kActStride + 32 * s + 8 * q), b3, y[m]);
     }
     __syncthreads();
     float *ys = reinterpret_cast<float *>(L.act);   // [64][4]
     if (r < kOut) {
-        const float bb = W.w[oB3 + r];
 #pragma unroll
         for (int m = 0; m < kLearnTiles; ++m)
 #pragma unroll
-            for (int i = 0; i < 4; ++i) ys[(cell0 + 16 * m + 4 * q + i) * kOut + r] = y[m][i] + bb;
+            for (int i = 0; i < 4; ++i) ys[(cell0 + 16 * m + 4 * q + i) * kOut + r] = y[m][i];
     }
     __syncthreads();
-    // epilogue: two lanes per point (adjacent lanes), taps and window rows split by parity
+    // epilogue: two lanes per point (adjacent lanes), taps and window rows
+    // split by parity: lane `part` takes the taps 2i + part of the 32 (in the
+    // order oz, oy, ox) and the window rows 2i + part of the 36 (ez, ey); the
+    // choice between the two is a select of constants, not a branch
     const Taps tp = make_taps();
     const int c = cell0 + (lane >> 1), part = lane & 1;
     const int ci_ = c & 3, cj = (c >> 2) & 3, ck = c >> 4;
     bool sat = true;
     float kw = 0.f, kx = 0.f, ky = 0.f, kz = 0.f;
-    int tap = 0;
-    for (int oz = -1; oz <= 2; ++oz)
-        for (int oy = -1; oy <= 2; ++oy)
-            for (int ox = -1; ox <= 2; ++ox) {
-                const float dx = 0.5f - ox, dy = 0.5f - oy, dz = 0.5f - oz;
-                const float r2 = dx * dx + dy * dy + dz * dz;
-                if (r2 >= 4.0f) continue;
-                if ((tap++ & 1) != part) continue;
-                const uint8_t f = L.sat[(ci_ + ox + 1) + kVol * ((cj + oy + 1) + kVol * (ck + oz + 1))];
-                sat = sat && (f & 1);
-                const float vv = (f & 2) ? 1.f : 0.f;
-                const bool nearp = r2 < 1.0f;
-                const float Wt = nearp ? tp.Wn : tp.Wf, Dt = nearp ? tp.Dn : tp.Df;
-                kw += Wt * vv;
-                kx += Dt * dx * vv;
-                ky += Dt * dy * vv;
-                kz += Dt * dz * vv;
-            }
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+        const TapOffset a = kTapOffsets[2 * i], b = kTapOffsets[2 * i + 1];
+        const int ox = part ? b.x : a.x, oy = part ? b.y : a.y, oz = part ? b.z : a.z;
+        const float dx = 0.5f - ox, dy = 0.5f - oy, dz = 0.5f - oz;
+        const uint8_t f = L.sat[(ci_ + ox + 1) + kVol * ((cj + oy + 1) + kVol * (ck + oz + 1))];
+        sat = sat && (f & 1);
+        const float vv = (f & 2) ? 1.f : 0.f;
+        const bool nearp = dx * dx + dy * dy + dz * dz < 1.0f;
+        const float Wt = nearp ? tp.Wn : tp.Wf, Dt = nearp ? tp.Dn : tp.Df;
+        kw += Wt * vv;
+        kx += Dt * dx * vv;
+        ky += Dt * dy * vv;
+        kz += Dt * dz * vv;
+    }
     // non-planarity: mean squared residual of the window after its
     // least-squares affine fit.  The basis 1, ox, oy, oz (offsets centred at
     // 2.5) is orthogonal on the window, so the fit's coefficients are the
@@ -895,20 +921,23 @@ __global__ __launch_bounds__(256) void learned_kernel(MlpDev W, const float *__r
     // 630 |c|^2 subtracts nearly equal numbers for the near-planar windows the
     // gate has to tell apart.  An error in the coefficients only moves the sum
     // at second order (the residual is orthogonal to the basis).
+    // Both passes sum phi itself and apply 1/h to the result (for h a power of
+    // two the bits of summing phi / h).  Rows 2i + part: ez = 2i / 6 for both
+    // parities (6 is even), ey = 2i % 6 + part.
     float s0 = 0.f, sx = 0.f, sy = 0.f, sz = 0.f;
-    for (int ez = 0; ez < 6; ++ez)
-        for (int ey = 0; ey < 6; ++ey) {
-            if (((ez * 6 + ey) & 1) != part) continue;
-            const float *row = L.phi + ci_ + kWin * ((cj + ey) + kWin * (ck + ez));
+#pragma unroll 1
+    for (int i = 0; i < 18; ++i) {
+        const int ez = (2 * i) / 6, ey = (2 * i) % 6 + part;
+        const float *row = L.phi + ci_ + kWin * ((cj + ey) + kWin * (ck + ez));
 #pragma unroll
-            for (int ex = 0; ex < 6; ++ex) {
-                const float v = row[ex] * inv_h;
-                s0 += v;
-                sx += (ex - 2.5f) * v;
-                sy += (ey - 2.5f) * v;
-                sz += (ez - 2.5f) * v;
-            }
+        for (int ex = 0; ex < 6; ++ex) {
+            const float v = row[ex];
+            s0 += v;
+            sx += (ex - 2.5f) * v;
+            sy += (ey - 2.5f) * v;
+            sz += (ez - 2.5f) * v;
         }
+    }
     // combine the two lanes of the point (every lane takes part in the shuffles)
     kw += __shfl_xor(kw, 1);
     kx += __shfl_xor(kx, 1);
@@ -920,21 +949,21 @@ __global__ __launch_bounds__(256) void learned_kernel(MlpDev W, const float *__r
     sx += __shfl_xor(sx, 1);
     sy += __shfl_xor(sy, 1);
     sz += __shfl_xor(sz, 1);
-    const float c0 = s0 / 216.f, cx = sx / 630.f, cy = sy / 630.f, cz = sz / 630.f;
+    const float c0 = s0 / 216.f, cx = sx / 630.f, cy = sy / 630.f, cz = sz / 630.f;   // units of phi
     float rr = 0.f;
-    for (int ez = 0; ez < 6; ++ez)
-        for (int ey = 0; ey < 6; ++ey) {
-            if (((ez * 6 + ey) & 1) != part) continue;
-            const float *row = L.phi + ci_ + kWin * ((cj + ey) + kWin * (ck + ez));
-            const float pyz = c0 + cy * (ey - 2.5f) + cz * (ez - 2.5f);
+#pragma unroll 1
+    for (int i = 0; i < 18; ++i) {
+        const int ez = (2 * i) / 6, ey = (2 * i) % 6 + part;
+        const float *row = L.phi + ci_ + kWin * ((cj + ey) + kWin * (ck + ez));
+        const float pyz = c0 + cy * (ey - 2.5f) + cz * (ez - 2.5f);
 #pragma unroll
-            for (int ex = 0; ex < 6; ++ex) {
-                const float e = row[ex] * inv_h - (pyz + cx * (ex - 2.5f));
-                rr += e * e;
-            }
+        for (int ex = 0; ex < 6; ++ex) {
+            const float e = row[ex] - (pyz + cx * (ex - 2.5f));
+            rr += e * e;
         }
+    }
     rr += __shfl_xor(rr, 1);
-    const float res = rr * (1.0f / 216.f);
+    const float res = rr * inv_h * inv_h * (1.0f / 216.f);
     if (live && part == 0) {
         const int64_t o = ci * 64 + c, stride = n_core * 64;
         bool write = true;

@@ -11,6 +11,8 @@
 // compact form of the cell-to-package map (32 cells per 16-byte entry) that
 // the build writes beside it; the values are those of cell_pkg and of the
 // neighbour table.
+#include <algorithm>
+
 #include "common.hpp"
 
 namespace {
@@ -48,6 +50,9 @@ struct Corner {
 // i0 = clamp(floor(s), 0, N - 2), t = clamp(s - i0, 0, 1), home cell =
 // clamp(floor(u / 4), 0, M - 1), shift = i0 - 4 * cell in [-1, 3]).
 template <typename T>
+__device__ __forceinline__ int home_coord(T u, int M) { return (int)clampv(floor(u * T(0.25)), T(0), T(M - 1)); }
+
+template <typename T>
 __device__ __forceinline__ void locate(const T *x, int M, T inv_h, int cc[3], int sh[3], T t[3]) {
     const int N = 4 * M;
 #pragma unroll
@@ -56,7 +61,7 @@ __device__ __forceinline__ void locate(const T *x, int M, T inv_h, int cc[3], in
         const T s = u - T(0.5);
         const T f = clampv(floor(s), T(0), T(N - 2));
         t[a] = clampv(s - f, T(0), T(1));
-        cc[a] = (int)clampv(floor(u * T(0.25)), T(0), T(M - 1));
+        cc[a] = home_coord(u, M);
         sh[a] = (int)f - 4 * cc[a];
     }
 }
@@ -143,7 +148,9 @@ template <typename T, bool PACKED>
 __global__ __launch_bounds__(256) void probe_kernel(Corner<T, PACKED> field, RankMap rm, const T *__restrict__ pos,
                                                     int64_t n, T *__restrict__ phi_out, T *__restrict__ nrm_out,
                                                     T inv_h) {
-    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    // each XCD takes one contiguous stretch of the particles: when they are
+    // sorted by home package, its L2 then holds the packages it gathers from
+    const int64_t q = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     if (q >= n) return;
     int cc[3], sh[3];
     T t[3], v, gx, gy, gz;
@@ -163,13 +170,236 @@ __global__ __launch_bounds__(256) void probe_kernel(Corner<T, PACKED> field, Ran
 __global__ __launch_bounds__(256) void probe_field_kernel(Corner<float, true> field, RankMap rm,
                                                           const float *__restrict__ pos, int64_t n,
                                                           float4 *__restrict__ out, float inv_h) {
-    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t q = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     if (q >= n) return;
     int cc[3], sh[3];
     float t[3], v, gx, gy, gz;
     locate(pos + 3 * q, rm.M, inv_h, cc, sh, t);
     blend(field, rm, cc, sh, t, v, gx, gy, gz);
     out[q] = make_float4(v, gx, gy, gz);
+}
+
+// ---------------------------------------------------------------------------
+// Particle sort by home cell
+// ---------------------------------------------------------------------------
+// Probing is position-based random access (Sec. 8): in generated order the
+// lanes of a wavefront gather from unrelated packages, about five cache lines
+// each.  Sorted by the Morton (Z-order) code of the home coarse cell, the
+// particles of one package are adjacent and neighbouring packages close, so a
+// wavefront's corners fall on a few shared lines and the packages a stretch of
+// particles gathers from stay in the L2 of the XCD that probes them.
+//
+// LSD radix sort, 8 bits per pass, stable, so the result is unique: keys
+// non-decreasing, equal keys in their input order.  Per pass, one kernel
+// counts each 4096-element tile's digits in LDS, a scan turns the
+// digit-major [256][tiles] counts into output offsets, and a second kernel
+// ranks the tile's elements stably (wavefront ballots over the digit bits,
+// then per-wavefront running counts in LDS), reorders the tile by digit in
+// LDS and writes each digit's run contiguously.  The first pass computes the
+// keys from the positions; the last writes the permutation and gathers the
+// sorted positions.
+
+constexpr int kScanItems = 4096;    // entries per scan block: 1024 lanes x 4
+constexpr int kRadixBits = 8, kRadixBins = 1 << kRadixBits;
+constexpr int kSortTile = 4096;     // elements per tile: 4 wavefronts x 16 rounds x 64
+constexpr int kSortRounds = 16;
+
+__device__ __forceinline__ uint32_t spread3(uint32_t v) {   // bit b of v (b < 10) to bit 3b
+    v &= 0x3FFu;
+    v = (v | (v << 16)) & 0x030000FFu;
+    v = (v | (v << 8)) & 0x0300F00Fu;
+    v = (v | (v << 4)) & 0x030C30C3u;
+    v = (v | (v << 2)) & 0x09249249u;
+    return v;
+}
+
+// Morton code of the particle's home coarse cell (x in the lowest bit).
+__device__ __forceinline__ uint32_t home_key(const float *x, int M, float inv_h) {
+    const int cx = home_coord(x[0] * inv_h, M), cy = home_coord(x[1] * inv_h, M), cz = home_coord(x[2] * inv_h, M);
+    return spread3((uint32_t)cx) | (spread3((uint32_t)cy) << 1) | (spread3((uint32_t)cz) << 2);
+}
+
+template <bool FIRST>
+__device__ __forceinline__ uint32_t sort_key_at(const float *__restrict__ pos, const uint32_t *__restrict__ keys,
+                                                int64_t e, int M, float inv_h) {
+    return FIRST ? home_key(pos + 3 * e, M, inv_h) : keys[e];
+}
+
+// counts[d * n_tiles + tile] = elements of the tile whose digit is d.
+template <bool FIRST>
+__global__ __launch_bounds__(256) void radix_count_kernel(const float *__restrict__ pos,
+                                                          const uint32_t *__restrict__ keys, int64_t n, int M,
+                                                          float inv_h, int shift, uint32_t *__restrict__ counts,
+                                                          int64_t n_tiles) {
+    __shared__ uint32_t s_hist[kRadixBins];
+    s_hist[threadIdx.x] = 0u;
+    __syncthreads();
+    const int64_t t0 = (int64_t)blockIdx.x * kSortTile;
+#pragma unroll 4
+    for (int k = 0; k < kSortTile / 256; ++k) {
+        const int64_t e = t0 + k * 256 + threadIdx.x;
+        if (e < n) atomicAdd(&s_hist[(sort_key_at<FIRST>(pos, keys, e, M, inv_h) >> shift) & (kRadixBins - 1)], 1u);
+    }
+    __syncthreads();
+    counts[(int64_t)threadIdx.x * n_tiles + blockIdx.x] = s_hist[threadIdx.x];
+}
+
+// Exclusive scan of one block of kScanItems entries in place; the block's
+// total goes to sums[blockIdx.x].
+__global__ __launch_bounds__(1024) void scan_block_kernel(uint32_t *__restrict__ v, int64_t n,
+                                                          uint32_t *__restrict__ sums) {
+    __shared__ uint32_t s_wave[16];
+    const int64_t base = (int64_t)blockIdx.x * kScanItems + 4 * threadIdx.x;
+    uint32_t a[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) a[k] = base + k < n ? v[base + k] : 0u;
+    const uint32_t own = a[0] + a[1] + a[2] + a[3];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    uint32_t inc = own;                       // inclusive scan over the wavefront
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const uint32_t o = __shfl_up(inc, d);
+        if (lane >= d) inc += o;
+    }
+    if (lane == 63) s_wave[w] = inc;
+    __syncthreads();
+    uint32_t before = 0;
+    for (int k = 0; k < w; ++k) before += s_wave[k];
+    uint32_t run = before + inc - own;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const uint32_t c = a[k];
+        if (base + k < n) v[base + k] = run;
+        run += c;
+    }
+    if (threadIdx.x == 1023) sums[blockIdx.x] = run;
+}
+
+// Exclusive scan of the block totals by one workgroup, in chunks of 1024.
+__global__ __launch_bounds__(1024) void scan_sums_kernel(uint32_t *__restrict__ sums, int64_t nb) {
+    __shared__ uint32_t s_wave[16];
+    __shared__ uint32_t s_carry;
+    if (threadIdx.x == 0) s_carry = 0;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    for (int64_t c0 = 0; c0 < nb; c0 += 1024) {
+        __syncthreads();
+        const int64_t i = c0 + threadIdx.x;
+        const uint32_t own = i < nb ? sums[i] : 0u;
+        uint32_t inc = own;
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            const uint32_t o = __shfl_up(inc, d);
+            if (lane >= d) inc += o;
+        }
+        if (lane == 63) s_wave[w] = inc;
+        __syncthreads();
+        uint32_t before = s_carry;
+        for (int k = 0; k < w; ++k) before += s_wave[k];
+        if (i < nb) sums[i] = before + inc - own;
+        __syncthreads();
+        if (threadIdx.x == 1023) s_carry = before + inc;
+    }
+}
+
+// One stable pass over a tile: rank, reorder in LDS, write runs.  Element
+// order inside the tile: wavefront w holds elements [1024 w, 1024 (w + 1)),
+// taken in rounds of 64 consecutive ones.
+template <bool FIRST, bool LAST>
+__global__ __launch_bounds__(256) void radix_scatter_kernel(const float *__restrict__ pos,
+                                                            const uint32_t *__restrict__ keys_in,
+                                                            const uint32_t *__restrict__ idx_in, int64_t n, int M,
+                                                            float inv_h, int shift,
+                                                            const uint32_t *__restrict__ offs,
+                                                            const uint32_t *__restrict__ sums, int64_t n_tiles,
+                                                            uint32_t *__restrict__ keys_out,
+                                                            uint32_t *__restrict__ idx_out,
+                                                            float *__restrict__ pos_out) {
+    __shared__ uint32_t s_cnt[4][kRadixBins];   // running count per wavefront, then its base
+    __shared__ uint32_t s_start[kRadixBins];    // first tile position of each digit
+    __shared__ uint32_t s_goff[kRadixBins];     // output position of each digit's run
+    __shared__ uint32_t s_key[kSortTile], s_idx[kSortTile];
+    __shared__ uint32_t s_wsum[4];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) s_cnt[k][threadIdx.x] = 0u;
+    __syncthreads();
+    const int64_t tile0 = (int64_t)blockIdx.x * kSortTile;
+    const int64_t w0 = tile0 + 1024 * w;
+    const uint64_t below = (1ull << lane) - 1ull;
+    uint32_t key[kSortRounds], idx[kSortRounds], rank[kSortRounds];
+#pragma unroll
+    for (int j = 0; j < kSortRounds; ++j) {
+        const int64_t e = w0 + 64 * j + lane;
+        const bool valid = e < n;
+        const int64_t ec = valid ? e : n - 1;
+        key[j] = sort_key_at<FIRST>(pos, keys_in, ec, M, inv_h);
+        idx[j] = FIRST ? (uint32_t)ec : idx_in[ec];
+        const uint32_t d = (key[j] >> shift) & (kRadixBins - 1);
+        // lanes of this round with the same digit (the valid ones)
+        uint64_t peers = __ballot(valid);
+#pragma unroll
+        for (int b = 0; b < kRadixBits; ++b) {
+            const uint64_t ones = __ballot((d >> b) & 1u);
+            peers &= ((d >> b) & 1u) ? ones : ~ones;
+        }
+        const uint32_t lower = (uint32_t)__popcll(peers & below);
+        const uint32_t pre = s_cnt[w][d];
+        if (valid && lower == 0) s_cnt[w][d] = pre + (uint32_t)__popcll(peers);
+        rank[j] = pre + lower;
+    }
+    __syncthreads();
+    // thread d: the digit's counts in the four wavefronts, its tile start
+    // (exclusive scan over the digits) and each wavefront's base
+    const int d = threadIdx.x;
+    const uint32_t c0 = s_cnt[0][d], c1 = s_cnt[1][d], c2 = s_cnt[2][d], c3 = s_cnt[3][d];
+    const uint32_t tot = c0 + c1 + c2 + c3;
+    uint32_t inc = tot;
+#pragma unroll
+    for (int k = 1; k < 64; k <<= 1) {
+        const uint32_t o = __shfl_up(inc, k);
+        if (lane >= k) inc += o;
+    }
+    if (lane == 63) s_wsum[w] = inc;
+    __syncthreads();
+    uint32_t start = inc - tot;
+    for (int k = 0; k < w; ++k) start += s_wsum[k];
+    s_start[d] = start;
+    s_cnt[0][d] = start;
+    s_cnt[1][d] = start + c0;
+    s_cnt[2][d] = start + c0 + c1;
+    s_cnt[3][d] = start + c0 + c1 + c2;
+    const int64_t oi = (int64_t)d * n_tiles + blockIdx.x;
+    s_goff[d] = offs[oi] + sums[oi / kScanItems];
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < kSortRounds; ++j) {
+        const int64_t e = w0 + 64 * j + lane;
+        if (e < n) {
+            const uint32_t p = s_cnt[w][(key[j] >> shift) & (kRadixBins - 1)] + rank[j];
+            s_key[p] = key[j];
+            s_idx[p] = idx[j];
+        }
+    }
+    __syncthreads();
+    const int64_t n_tile = n - tile0 < kSortTile ? n - tile0 : kSortTile;
+#pragma unroll 4
+    for (int k = 0; k < kSortTile / 256; ++k) {
+        const int p = k * 256 + threadIdx.x;
+        if (p < n_tile) {
+            const uint32_t kp = s_key[p], ip = s_idx[p];
+            const uint32_t dd = (kp >> shift) & (kRadixBins - 1);
+            const int64_t dest = (int64_t)s_goff[dd] + (p - (int64_t)s_start[dd]);
+            if (LAST) {
+                idx_out[dest] = ip;
+                pos_out[3 * dest] = pos[3 * (int64_t)ip];
+                pos_out[3 * dest + 1] = pos[3 * (int64_t)ip + 1];
+                pos_out[3 * dest + 2] = pos[3 * (int64_t)ip + 2];
+            } else {
+                keys_out[dest] = kp;
+                idx_out[dest] = ip;
+            }
+        }
+    }
 }
 
 }  // namespace
@@ -235,4 +465,105 @@ extern "C" sgrid_status sgrid_probe_integral_field(const sgrid_grid *g, const fl
                        (float)(1.0 / g->h));
     SG_CHECK_LAUNCH("integral field probe");
     return SGRID_OK;
+}
+
+namespace {
+constexpr int64_t kSortMaxParticles = 0xFFFFFFFFll;   // 32-bit permutation entries
+
+// Layout of the sort's workspace for n particles: key and index ping-pong
+// buffers (when there is more than one pass), the digit counts of every tile
+// and the scan's block totals, each 256-byte aligned.
+struct SortPlan {
+    int passes = 0;
+    int64_t n_tiles = 0, n_counts = 0, n_sums = 0;
+    int64_t off_keys[2] = {0, 0}, off_idx[2] = {0, 0}, off_counts = 0, off_sums = 0, bytes = 0;
+};
+
+int64_t align256(int64_t b) { return (b + 255) / 256 * 256; }
+
+SortPlan sort_plan(const sgrid_grid *g, int64_t n) {
+    SortPlan s;
+    int bits_axis = 0;
+    while ((1 << bits_axis) < g->M) ++bits_axis;
+    s.passes = std::max(1, (3 * bits_axis + kRadixBits - 1) / kRadixBits);
+    s.n_tiles = (n + kSortTile - 1) / kSortTile;
+    s.n_counts = (int64_t)kRadixBins * s.n_tiles;
+    s.n_sums = (s.n_counts + kScanItems - 1) / kScanItems;
+    int64_t b = 0;
+    if (s.passes > 1)
+        for (int k = 0; k < 2; ++k) {
+            s.off_keys[k] = b;
+            b += align256(4 * n);
+            s.off_idx[k] = b;
+            b += align256(4 * n);
+        }
+    s.off_counts = b;
+    b += align256(4 * s.n_counts);
+    s.off_sums = b;
+    b += align256(4 * std::max<int64_t>(1, s.n_sums));
+    s.bytes = b;
+    return s;
+}
+
+template <bool FIRST, bool LAST>
+sgrid_status radix_pass(const sgrid_grid *g, const float *pos, const uint32_t *keys_in, const uint32_t *idx_in,
+                        int64_t n, int shift, const SortPlan &sp, uint32_t *counts, uint32_t *sums,
+                        uint32_t *keys_out, uint32_t *idx_out, float *pos_out, hipStream_t st) {
+    const float inv_h = (float)(1.0 / g->h);
+    hipLaunchKernelGGL(radix_count_kernel<FIRST>, dim3((unsigned)sp.n_tiles), dim3(256), 0, st, pos, keys_in, n, g->M,
+                       inv_h, shift, counts, sp.n_tiles);
+    SG_CHECK_LAUNCH("sort digit counts");
+    hipLaunchKernelGGL(scan_block_kernel, dim3((unsigned)sp.n_sums), dim3(1024), 0, st, counts, sp.n_counts, sums);
+    SG_CHECK_LAUNCH("sort scan");
+    hipLaunchKernelGGL(scan_sums_kernel, dim3(1), dim3(1024), 0, st, sums, sp.n_sums);
+    SG_CHECK_LAUNCH("sort scan of block totals");
+    hipLaunchKernelGGL((radix_scatter_kernel<FIRST, LAST>), dim3((unsigned)sp.n_tiles), dim3(256), 0, st, pos,
+                       keys_in, idx_in, n, g->M, inv_h, shift, (const uint32_t *)counts, (const uint32_t *)sums,
+                       sp.n_tiles, keys_out, idx_out, pos_out);
+    SG_CHECK_LAUNCH("sort scatter");
+    return SGRID_OK;
+}
+}  // namespace
+
+extern "C" sgrid_status sgrid_sort_particles_workspace_size(const sgrid_grid *g, int64_t n, int64_t *bytes) {
+    sgrid::clear_error();
+    SG_REQUIRE(g != nullptr && bytes != nullptr, "grid or bytes is NULL");
+    SG_REQUIRE(n >= 0 && n <= kSortMaxParticles, "n = %lld is outside [0, 2^32 - 1]", (long long)n);
+    *bytes = sort_plan(g, n).bytes;
+    return SGRID_OK;
+}
+
+extern "C" sgrid_status sgrid_sort_particles(const sgrid_grid *g, const float *pos, int64_t n, float *pos_sorted,
+                                             uint32_t *perm, void *workspace, int64_t workspace_bytes,
+                                             void *stream) {
+    sgrid::clear_error();
+    SG_REQUIRE(g != nullptr, "grid is NULL");
+    SG_REQUIRE(n >= 0 && n <= kSortMaxParticles, "n = %lld is outside [0, 2^32 - 1]", (long long)n);
+    if (n == 0) return SGRID_OK;
+    SG_REQUIRE(pos && pos_sorted && perm && workspace, "NULL particle array or workspace");
+    SG_REQUIRE(pos != pos_sorted, "pos and pos_sorted must be distinct");
+    SG_REQUIRE(sg_aligned(pos, 4) && sg_aligned(pos_sorted, 4) && sg_aligned(perm, 4) && sg_aligned(workspace, 256),
+               "arrays must be 4-byte aligned, the workspace 256-byte aligned");
+    const SortPlan sp = sort_plan(g, n);
+    SG_REQUIRE(workspace_bytes >= sp.bytes, "workspace holds %lld bytes, the sort needs %lld",
+               (long long)workspace_bytes, (long long)sp.bytes);
+    SG_REQUIRE(sp.n_tiles <= kMaxGrid, "too many particles for one launch");
+    hipStream_t st = sg_stream(stream);
+    char *ws = static_cast<char *>(workspace);
+    uint32_t *keys[2] = {(uint32_t *)(ws + sp.off_keys[0]), (uint32_t *)(ws + sp.off_keys[1])};
+    uint32_t *idx[2] = {(uint32_t *)(ws + sp.off_idx[0]), (uint32_t *)(ws + sp.off_idx[1])};
+    uint32_t *counts = (uint32_t *)(ws + sp.off_counts), *sums = (uint32_t *)(ws + sp.off_sums);
+    sgrid_status s;
+    if (sp.passes == 1)
+        return radix_pass<true, true>(g, pos, nullptr, nullptr, n, 0, sp, counts, sums, nullptr, perm, pos_sorted, st);
+    s = radix_pass<true, false>(g, pos, nullptr, nullptr, n, 0, sp, counts, sums, keys[0], idx[0], nullptr, st);
+    if (s != SGRID_OK) return s;
+    int cur = 0;
+    for (int p = 1; p + 1 < sp.passes; ++p, cur ^= 1) {
+        s = radix_pass<false, false>(g, pos, keys[cur], idx[cur], n, p * kRadixBits, sp, counts, sums, keys[cur ^ 1],
+                                     idx[cur ^ 1], nullptr, st);
+        if (s != SGRID_OK) return s;
+    }
+    return radix_pass<false, true>(g, pos, keys[cur], idx[cur], n, (sp.passes - 1) * kRadixBits, sp, counts, sums,
+                                   nullptr, perm, pos_sorted, st);
 }

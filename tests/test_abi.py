@@ -115,6 +115,29 @@ def test_new_symbols_reject_invalid_arguments(lib):
     assert f(P(64), P(16), P(16), P(48), None) == E_INVALID    # phi and vfrac aliased
     assert f(P(64), P(16), P(32), P(32), None) == E_INVALID    # vfrac and out aliased
     assert f(P(64), P(16), P(36), P(48), None) == E_INVALID    # misaligned
+    # the particle sort: checks before any use of the grid
+    ws = lib.sgrid_sort_particles_workspace_size
+    ws.argtypes = [P, ctypes.c_int64, P]
+    nb = ctypes.c_int64(-1)
+    assert ws(None, 10, ctypes.byref(nb)) == E_INVALID
+    assert ws(P(64), 10, None) == E_INVALID
+    assert ws(P(64), -1, ctypes.byref(nb)) == E_INVALID
+    assert ws(P(64), 1 << 32, ctypes.byref(nb)) == E_INVALID
+    srt = lib.sgrid_sort_particles
+    srt.argtypes = [P, P, ctypes.c_int64, P, P, P, ctypes.c_int64, P]
+    assert srt(None, P(16), 4, P(32), P(48), P(64), 1 << 20, None) == E_INVALID
+    assert srt(P(64), P(16), -1, P(32), P(48), P(64), 1 << 20, None) == E_INVALID
+    assert srt(P(64), None, 4, P(32), P(48), P(64), 1 << 20, None) == E_INVALID
+    assert srt(P(64), P(16), 4, P(32), P(48), None, 1 << 20, None) == E_INVALID   # no workspace
+    assert srt(P(64), P(16), 4, P(16), P(48), P(64), 1 << 20, None) == E_INVALID  # pos aliased
+    assert srt(P(64), P(18), 4, P(32), P(48), P(64), 1 << 20, None) == E_INVALID  # misaligned
+    # the allocation-free learned integrals: checks before any use of the grid
+    na = lib.sgrid_compute_near_surface_integrals_noalloc
+    na.argtypes = [P, P, P, P, P, P]
+    assert na(None, P(16), P(64), P(32), None, None) == E_INVALID
+    assert na(P(64), P(16), None, P(32), None, None) == E_INVALID                # no model
+    assert na(P(64), None, P(64), P(32), None, None) == E_INVALID
+    assert na(P(64), P(20), P(64), P(32), None, None) == E_INVALID               # misaligned
 
 
 def _fake(cls, **attrs):

@@ -11,6 +11,7 @@ import pytest
 
 import oracle
 import synth
+from sort_check import assert_sorted
 from tables_check import assert_tables_equal
 
 torch = pytest.importorskip("torch")
@@ -73,6 +74,7 @@ def test_prism512_full_pipeline(sg):
     ok = np.linalg.norm(ref_g, axis=1) > 0.25
     assert ok.mean() > 0.95
     assert np.max(np.abs(wl.nrm_p.double().cpu().numpy()[ok] - ref_nrm[ok])) <= 1e-5
+    _check_sorted_probe(sg, g, packed, wl, t, pos)
     core = t["core_list"].astype(np.int64)
     ref = oracle.integrals(run.N, h, run.B, run.phi, wl.points[core - 2].ravel())
     got = integ.double().cpu().numpy().T
@@ -139,6 +141,21 @@ def _global_rows(t, local, n, origin, M):
     return pkg, loc
 
 
+def _check_sorted_probe(sg, g, packed, wl, t, pos):
+    """The particle sort as the benchmark step runs it, then the probe of the
+    sorted particles: every particle's bits of the generated-order probe."""
+    ps = torch.empty_like(wl.pos)
+    perm = torch.empty(wl.pos.shape[0], dtype=torch.int32, device="cuda")
+    sg.sort_particles(g, wl.pos, ps, perm)
+    php, nrp = torch.empty_like(wl.phi_p), torch.empty_like(wl.nrm_p)
+    sg.probe_particles_packed(g, packed, ps, php, nrp)
+    torch.cuda.synchronize()
+    p = perm.long()
+    assert torch.equal(php.view(torch.int32), wl.phi_p[p].view(torch.int32))
+    assert torch.equal(nrp.view(torch.int32), wl.nrm_p[p].view(torch.int32))
+    assert_sorted(g.n_coarse, wl.h, pos, ps.cpu().numpy(), perm.cpu().numpy())
+
+
 def _interior(local, n, m):
     i, j, k = local % n, (local // n) % n, local // (n * n)
     return (i >= m) & (i < n - m) & (j >= m) & (j < n - m) & (k >= m) & (k < n - m)
@@ -200,6 +217,7 @@ def test_torus2048_full_size(sg):
     ok = np.linalg.norm(ref_g, axis=1) > 0.25
     assert ok.mean() > 0.95
     assert np.max(np.abs(wl.nrm_p[sel_d].double().cpu().numpy()[ok] - ref_nrm[ok])) <= 1e-5
+    _check_sorted_probe(sg, g, packed, wl, t, pos)
 
     # integrals of the core points whose 9^3 window lies inside the checked region
     core_pts = oracle.active_points(crop.tab, (1,))
