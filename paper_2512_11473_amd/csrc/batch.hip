@@ -67,13 +67,14 @@ __device__ __forceinline__ void batch_loads(const float *__restrict__ src, const
     l.c = ld_row(src + g * 64 + r * 4);
     l.xm = src[(int64_t)f0.x * 64 + r * 4 + 3];
     l.xp = src[(int64_t)f0.y * 64 + r * 4];
-    // unconditional (a lane without a y / z halo re-reads its own row), so the
-    // halo loads issue together instead of behind a branch that waits
-    const int64_t fy = j == 0 ? (int64_t)f0.z : j == 3 ? (int64_t)f0.w : g;
-    const int ry = j == 0 ? 3 + 4 * k : j == 3 ? 4 * k : r;
+    // unconditional, so the halo loads issue together instead of behind a
+    // branch that waits: a lane without a y / z halo loads that of its
+    // neighbour lane on the same side (unused), touching no other lines
+    const int64_t fy = j < 2 ? (int64_t)f0.z : (int64_t)f0.w;
+    const int ry = j < 2 ? 3 + 4 * k : 4 * k;
     l.yh = ld_row(src + fy * 64 + ry * 4);
-    const int64_t fz = k == 0 ? (int64_t)f1.x : k == 3 ? (int64_t)f1.y : g;
-    const int rz = k == 0 ? j + 12 : k == 3 ? j : r;
+    const int64_t fz = k < 2 ? (int64_t)f1.x : (int64_t)f1.y;
+    const int rz = k < 2 ? j + 12 : j;
     l.zh = ld_row(src + fz * 64 + rz * 4);
 }
 

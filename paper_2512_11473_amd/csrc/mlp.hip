@@ -728,16 +728,25 @@ __device__ __forceinline__ Taps make_taps() {
 __global__ __launch_bounds__(256) void zero_u32_kernel(uint32_t *p) { *p = 0u; }
 __global__ __launch_bounds__(64) void add_u32_kernel(uint32_t *total, const uint32_t *part) { *total += *part; }
 
-// Learned-integral kernel: two core packages per workgroup, two wavefronts
-// per package.  A package's 128 lanes stage its 9^3 window and saturation
-// flags in the package's LDS region; each wavefront runs the network on 32 of
-// the 64 points as two 16-point MFMA tiles (each BF16 weight fragment read
-// from L2 feeds both tiles, hi and lo parts), and then two lanes per point
-// evaluate the exact saturated sum or the gate.  The MFMA accumulation order
-// is that of forward_tile, so the network outputs are the bits of
-// sgrid_mlp_forward on the gathered windows.
+// Learned-integral kernel: two core packages (128 points) per workgroup of
+// four wavefronts.
+//  1. Each package's 128 lanes stage its 9^3 window, the saturation flags of
+//     the 7^3 tap points and the BF16 hi + lo parts of the network inputs.
+//  2. Two lanes per point sum the 32 taps' saturated fractions.  A point
+//     whose taps are all saturated takes that exact sum (the plain value);
+//     the others are listed, in LDS, for the network.
+//  3. The listed points go through the network in 16-point MFMA tiles, tile
+//     T on wavefront T mod 4 (each BF16 weight fragment read from L2 feeds
+//     both of a wavefront's tiles, hi and lo parts).  A wavefront reads back
+//     only activation rows it wrote, so the layers need no barrier.
+//  4. The same wavefront evaluates the gate of its tiles' points, two lanes
+//     per point, and writes the network's value or lists the point for the
+//     plain fallback.
+// Every listed point's network row is computed in the MFMA accumulation
+// order of forward_tile, so the outputs are the bits of sgrid_mlp_forward on
+// the gathered windows.
 constexpr int kLearnPkgs = 2;   // packages per workgroup
-constexpr int kLearnTiles = 2;  // 16-point tiles per wavefront
+constexpr int kLearnPts = 64 * kLearnPkgs;
 constexpr int kActStride = kH + 8;   // bf16 per activation row in LDS
 
 struct LearnLds {
@@ -745,29 +754,139 @@ struct LearnLds {
     bf16 xh[kWinN + 7], xl[kWinN + 7];   // BF16 hi and lo parts of the window's phi / h
     uint32_t ids[28];
     uint8_t sat[kVolN + 13];
-    // a1, then a2, then the outputs y (FP32 [64][4]); rows padded by 16 bytes,
-    // so that the sixteen rows of an A-fragment read start in different banks
-    __attribute__((aligned(16))) bf16 act[64 * kActStride];
 };
 
-__global__ __launch_bounds__(256) void learned_kernel(MlpDev W, const float *__restrict__ phi,
-                                                      const uint32_t *__restrict__ nbr,
-                                                      const uint32_t *__restrict__ core_list, int64_t n_core,
-                                                      int64_t ci0, int64_t ci_end, float inv_h, float inv_2h,
-                                                      float tau, float kw_lo, float kw_hi, float *__restrict__ out,
-                                                      uint32_t *__restrict__ fb_list,
-                                                      uint32_t *__restrict__ fb_count) {
+// The network over the listed points of TILES tiles (rows 16 tile + r of the
+// list): layer outputs through the wavefront's own activation rows, the
+// outputs y to s_y[row][4].
+template <int TILES>
+__device__ __forceinline__ void learned_network(const MlpDev &W, const LearnLds *lds, const int16_t *s_off,
+                                                const uint8_t *s_list, int n_list, const int tile[2], bf16 *s_act,
+                                                float *s_y, int lane) {
+    const int r = lane & 15, q = lane >> 4;
+    int base[TILES];
+    const LearnLds *win[TILES];
+#pragma unroll
+    for (int m = 0; m < TILES; ++m) {
+        const int row = 16 * tile[m] + r;
+        const int pt = s_list[row < n_list ? row : n_list - 1];   // rows past the list repeat its last point
+        const int c = pt & 63;
+        win[m] = lds + (pt >> 6);
+        base[m] = (c & 3) + kWin * (((c >> 2) & 3) + kWin * (c >> 4));
+    }
+    // layer 1: [16 x 224] (hi + lo BF16 parts of phi / h) x W1^T per tile;
+    // accumulators start from the biases, as in forward_tile
+    floatx4 acc[TILES][8];
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+        const float bb = W.w[oB1 + 16 * t + r];
+#pragma unroll
+        for (int m = 0; m < TILES; ++m) acc[m][t] = floatx4{bb, bb, bb, bb};
+    }
+    // the weight fragments of step s + 1 load while step s multiplies
+    bf16x8 bw[8], bn[8];
+#pragma unroll
+    for (int t = 0; t < 8; ++t) bn[t] = ld8(W.w1b + (16 * t + r) * kInPad + 8 * q);
+    for (int s = 0; s < kInPad / 32; ++s) {
+#pragma unroll
+        for (int t = 0; t < 8; ++t) bw[t] = bn[t];
+        if (s + 1 < kInPad / 32) {
+#pragma unroll
+            for (int t = 0; t < 8; ++t) bn[t] = ld8(W.w1b + (16 * t + r) * kInPad + 32 * (s + 1) + 8 * q);
+        }
+#pragma unroll
+        for (int m = 0; m < TILES; ++m) {
+            bf16x8 ah, al;
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                const int off = base[m] + s_off[32 * s + 8 * q + e];
+                ah[e] = win[m]->xh[off];
+                al[e] = win[m]->xl[off];
+            }
+#pragma unroll
+            for (int t = 0; t < 8; ++t) {
+                acc[m][t] = mfma(ah, bw[t], acc[m][t]);
+                acc[m][t] = mfma(al, bw[t], acc[m][t]);
+            }
+        }
+    }
+#pragma unroll
+    for (int t = 0; t < 8; ++t)
+#pragma unroll
+        for (int m = 0; m < TILES; ++m)
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+                s_act[(16 * tile[m] + 4 * q + i) * kActStride + 16 * t + r] = (bf16)gelu(acc[m][t][i]);
+    // layer 2
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+        const float bb = W.w[oB2 + 16 * t + r];
+#pragma unroll
+        for (int m = 0; m < TILES; ++m) acc[m][t] = floatx4{bb, bb, bb, bb};
+    }
+#pragma unroll
+    for (int s = 0; s < kH / 32; ++s) {
+        bf16x8 bv[8];
+#pragma unroll
+        for (int t = 0; t < 8; ++t) bv[t] = ld8(W.w2b + (16 * t + r) * kH + 32 * s + 8 * q);
+#pragma unroll
+        for (int m = 0; m < TILES; ++m) {
+            const bf16x8 a = ld8(s_act + (16 * tile[m] + r) * kActStride + 32 * s + 8 * q);
+#pragma unroll
+            for (int t = 0; t < 8; ++t) acc[m][t] = mfma(a, bv[t], acc[m][t]);
+        }
+    }
+#pragma unroll
+    for (int t = 0; t < 8; ++t)
+#pragma unroll
+        for (int m = 0; m < TILES; ++m)
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+                s_act[(16 * tile[m] + 4 * q + i) * kActStride + 16 * t + r] = (bf16)gelu(acc[m][t][i]);
+    // layer 3
+    floatx4 y[TILES];
+    const float b3 = r < kOut ? W.w[oB3 + r] : 0.f;
+#pragma unroll
+    for (int m = 0; m < TILES; ++m) y[m] = floatx4{b3, b3, b3, b3};
+#pragma unroll
+    for (int s = 0; s < kH / 32; ++s) {
+        const bf16x8 w3 = ld8(W.w3b + r * kH + 32 * s + 8 * q);
+#pragma unroll
+        for (int m = 0; m < TILES; ++m)
+            y[m] = mfma(ld8(s_act + (16 * tile[m] + r) * kActStride + 32 * s + 8 * q), w3, y[m]);
+    }
+    if (r < kOut) {
+#pragma unroll
+        for (int m = 0; m < TILES; ++m)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) s_y[(16 * tile[m] + 4 * q + i) * kOut + r] = y[m][i];
+    }
+}
+
+__global__ __launch_bounds__(256, 3) void learned_kernel(MlpDev W, const float *__restrict__ phi,
+                                                         const uint32_t *__restrict__ nbr,
+                                                         const uint32_t *__restrict__ core_list, int64_t n_core,
+                                                         int64_t ci0, int64_t ci_end, float inv_h, float inv_2h,
+                                                         float tau, float kw_lo, float kw_hi,
+                                                         float *__restrict__ out, uint32_t *__restrict__ fb_list,
+                                                         uint32_t *__restrict__ fb_count) {
     __shared__ LearnLds lds[kLearnPkgs];
     // window offset of network input kk (ox + 9 oy + 81 oz); the padding
     // inputs 216..223 meet zero columns of W1, so they read any finite window
     // value (offset 0) and add exactly zero, without a branch per input
     __shared__ int16_t s_off[kInPad];
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, r = lane & 15, q = lane >> 4;
+    __shared__ __attribute__((aligned(16))) bf16 s_act[kLearnPts * kActStride];   // rows padded by 16 bytes
+    __shared__ float s_y[kLearnPts * kOut];
+    __shared__ uint8_t s_list[kLearnPts];   // listed points: slot * 64 + local index
+    __shared__ uint32_t s_n;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     if (threadIdx.x < kInPad) {
         const int kk = threadIdx.x;
         s_off[kk] = kk < kIn ? (int16_t)(kk % 6 + kWin * ((kk / 6) % 6) + kWin * kWin * (kk / 36)) : (int16_t)0;
     }
-    const int slot = w >> 1, half = w & 1, t128 = threadIdx.x & 127;
+    if (threadIdx.x == 0) s_n = 0u;
+    // 1. staging, per package: 128 lanes each
+    const int slot = w >> 1, t128 = threadIdx.x & 127;
     LearnLds &L = lds[slot];
     // core packages [ci0, ci_end) of the n_core (outputs are indexed over all)
     const int64_t cw = ci0 + (int64_t)blockIdx.x * kLearnPkgs + slot;
@@ -788,163 +907,101 @@ __global__ __launch_bounds__(256) void learned_kernel(MlpDev W, const float *__r
         const bool sat = a != 0.f && fabsf(a) >= 0.5f * (fabsf(gx) + fabsf(gy) + fabsf(gz));
         L.sat[v] = (uint8_t)((sat ? 1 : 0) | (a > 0.f ? 2 : 0));
     }
-    // the network inputs' BF16 hi + lo parts, once per window value
-    for (int v = t128; v < kWinN; v += 128) {
+    for (int v = t128; v < kWinN; v += 128) {   // the network inputs, once per window value
         const float x = L.phi[v] * inv_h;
         const bf16 hi = (bf16)x;
         L.xh[v] = hi;
         L.xl[v] = (bf16)(x - (float)hi);
     }
     __syncthreads();
-    const int cell0 = 32 * half;   // this wavefront's points: cell0 .. cell0 + 31
-    // layer 1: [32 x 224] (hi + lo BF16 parts of phi / h) x W1^T
-    floatx4 acc[kLearnTiles][8];
+    const int64_t stride = n_core * 64;
+    // 2. exact sums of saturated points; two lanes per point, lane `part`
+    // takes the taps 2i + part of the 32 (in the order oz, oy, ox), chosen by
+    // a select of constants rather than a branch
+    {
+        const Taps tp = make_taps();
+        const int c = t128 >> 1, part = t128 & 1;
+        const int ci_ = c & 3, cj = (c >> 2) & 3, ck = c >> 4;
+        bool sat = true;
+        float kw = 0.f, kx = 0.f, ky = 0.f, kz = 0.f;
 #pragma unroll
-    for (int t = 0; t < 8; ++t) {   // accumulators start from the biases, as in forward_tile
-        const float bb = W.w[oB1 + 16 * t + r];
-#pragma unroll
-        for (int m = 0; m < kLearnTiles; ++m) acc[m][t] = floatx4{bb, bb, bb, bb};
-    }
-    // the weight fragments of step s + 1 load while step s multiplies
-    bf16x8 bw[8], bn[8];
-#pragma unroll
-    for (int t = 0; t < 8; ++t) bn[t] = ld8(W.w1b + (16 * t + r) * kInPad + 8 * q);
-    for (int s = 0; s < kInPad / 32; ++s) {
-#pragma unroll
-        for (int t = 0; t < 8; ++t) bw[t] = bn[t];
-        if (s + 1 < kInPad / 32) {
-#pragma unroll
-            for (int t = 0; t < 8; ++t) bn[t] = ld8(W.w1b + (16 * t + r) * kInPad + 32 * (s + 1) + 8 * q);
+        for (int i = 0; i < 16; ++i) {
+            const TapOffset a = kTapOffsets[2 * i], b = kTapOffsets[2 * i + 1];
+            const int ox = part ? b.x : a.x, oy = part ? b.y : a.y, oz = part ? b.z : a.z;
+            const float dx = 0.5f - ox, dy = 0.5f - oy, dz = 0.5f - oz;
+            const uint8_t f = L.sat[(ci_ + ox + 1) + kVol * ((cj + oy + 1) + kVol * (ck + oz + 1))];
+            sat = sat && (f & 1);
+            const float vv = (f & 2) ? 1.f : 0.f;
+            const bool nearp = dx * dx + dy * dy + dz * dz < 1.0f;
+            const float Wt = nearp ? tp.Wn : tp.Wf, Dt = nearp ? tp.Dn : tp.Df;
+            kw += Wt * vv;
+            kx += Dt * dx * vv;
+            ky += Dt * dy * vv;
+            kz += Dt * dz * vv;
         }
-#pragma unroll
-        for (int m = 0; m < kLearnTiles; ++m) {
-            const int c = cell0 + 16 * m + r;
-            const int base = (c & 3) + kWin * (((c >> 2) & 3) + kWin * (c >> 4));
-            bf16x8 ah, al;
-#pragma unroll
-            for (int e = 0; e < 8; ++e) {
-                const int off = base + s_off[32 * s + 8 * q + e];
-                ah[e] = L.xh[off];
-                al[e] = L.xl[off];
+        kw += __shfl_xor(kw, 1);
+        kx += __shfl_xor(kx, 1);
+        ky += __shfl_xor(ky, 1);
+        kz += __shfl_xor(kz, 1);
+        const int other = __shfl_xor(sat ? 1 : 0, 1);
+        sat = sat && other != 0;
+        if (live && part == 0) {
+            if (sat) {
+                const int64_t o = ci * 64 + c;
+                out[o] = kw;
+                out[stride + o] = kx;
+                out[2 * stride + o] = ky;
+                out[3 * stride + o] = kz;
+            } else {
+                s_list[atomicAdd(&s_n, 1u)] = (uint8_t)(slot * 64 + c);
             }
-#pragma unroll
-            for (int t = 0; t < 8; ++t) {
-                acc[m][t] = mfma(ah, bw[t], acc[m][t]);
-                acc[m][t] = mfma(al, bw[t], acc[m][t]);
-            }
-        }
-    }
-    bf16 *act = L.act + cell0 * kActStride;
-#pragma unroll
-    for (int t = 0; t < 8; ++t)
-#pragma unroll
-        for (int m = 0; m < kLearnTiles; ++m)
-#pragma unroll
-            for (int i = 0; i < 4; ++i) act[(16 * m + 4 * q + i) * kActStride + 16 * t + r] = (bf16)gelu(acc[m][t][i]);
-    __syncthreads();
-    // layer 2
-#pragma unroll
-    for (int t = 0; t < 8; ++t) {
-        const float bb = W.w[oB2 + 16 * t + r];
-#pragma unroll
-        for (int m = 0; m < kLearnTiles; ++m) acc[m][t] = floatx4{bb, bb, bb, bb};
-    }
-#pragma unroll
-    for (int s = 0; s < kH / 32; ++s) {
-        bf16x8 bw[8];
-#pragma unroll
-        for (int t = 0; t < 8; ++t) bw[t] = ld8(W.w2b + (16 * t + r) * kH + 32 * s + 8 * q);
-#pragma unroll
-        for (int m = 0; m < kLearnTiles; ++m) {
-            const bf16x8 a = ld8(act + (16 * m + r) * kActStride + 32 * s + 8 * q);
-#pragma unroll
-            for (int t = 0; t < 8; ++t) acc[m][t] = mfma(a, bw[t], acc[m][t]);
         }
     }
     __syncthreads();
-#pragma unroll
-    for (int t = 0; t < 8; ++t)
-#pragma unroll
-        for (int m = 0; m < kLearnTiles; ++m)
-#pragma unroll
-            for (int i = 0; i < 4; ++i) act[(16 * m + 4 * q + i) * kActStride + 16 * t + r] = (bf16)gelu(acc[m][t][i]);
-    __syncthreads();
-    // layer 3
-    floatx4 y[kLearnTiles];
-    const float b3 = r < kOut ? W.w[oB3 + r] : 0.f;
-#pragma unroll
-    for (int m = 0; m < kLearnTiles; ++m) y[m] = floatx4{b3, b3, b3, b3};
-#pragma unroll
-    for (int s = 0; s < kH / 32; ++s) {
-        const bf16x8 b3 = ld8(W.w3b + r * kH + 32 * s + 8 * q);
-#pragma unroll
-        for (int m = 0; m < kLearnTiles; ++m) y[m] = mfma(ld8(act + (16 * m + r) * kActStride + 32 * s + 8 * q), b3, y[m]);
-    }
-    __syncthreads();
-    float *ys = reinterpret_cast<float *>(L.act);   // [64][4]
-    if (r < kOut) {
-#pragma unroll
-        for (int m = 0; m < kLearnTiles; ++m)
-#pragma unroll
-            for (int i = 0; i < 4; ++i) ys[(cell0 + 16 * m + 4 * q + i) * kOut + r] = y[m][i];
-    }
-    __syncthreads();
-    // epilogue: two lanes per point (adjacent lanes), taps and window rows
-    // split by parity: lane `part` takes the taps 2i + part of the 32 (in the
-    // order oz, oy, ox) and the window rows 2i + part of the 36 (ez, ey); the
-    // choice between the two is a select of constants, not a branch
-    const Taps tp = make_taps();
-    const int c = cell0 + (lane >> 1), part = lane & 1;
-    const int ci_ = c & 3, cj = (c >> 2) & 3, ck = c >> 4;
-    bool sat = true;
-    float kw = 0.f, kx = 0.f, ky = 0.f, kz = 0.f;
-#pragma unroll
-    for (int i = 0; i < 16; ++i) {
-        const TapOffset a = kTapOffsets[2 * i], b = kTapOffsets[2 * i + 1];
-        const int ox = part ? b.x : a.x, oy = part ? b.y : a.y, oz = part ? b.z : a.z;
-        const float dx = 0.5f - ox, dy = 0.5f - oy, dz = 0.5f - oz;
-        const uint8_t f = L.sat[(ci_ + ox + 1) + kVol * ((cj + oy + 1) + kVol * (ck + oz + 1))];
-        sat = sat && (f & 1);
-        const float vv = (f & 2) ? 1.f : 0.f;
-        const bool nearp = dx * dx + dy * dy + dz * dz < 1.0f;
-        const float Wt = nearp ? tp.Wn : tp.Wf, Dt = nearp ? tp.Dn : tp.Df;
-        kw += Wt * vv;
-        kx += Dt * dx * vv;
-        ky += Dt * dy * vv;
-        kz += Dt * dz * vv;
-    }
-    // non-planarity: mean squared residual of the window after its
+    const int n_list = (int)s_n;
+    const int n_tiles = (n_list + 15) / 16;
+    const int tile[2] = {w, w + 4};
+    const int mine = (w < n_tiles ? 1 : 0) + (w + 4 < n_tiles ? 1 : 0);
+    if (mine == 0) return;
+    // 3. the network over this wavefront's tiles
+    if (mine == 2)
+        learned_network<2>(W, lds, s_off, s_list, n_list, tile, s_act, s_y, lane);
+    else
+        learned_network<1>(W, lds, s_off, s_list, n_list, tile, s_act, s_y, lane);
+    // 4. the gate of this wavefront's points, two lanes per point: lanes
+    // 0..31 the rows of tile w, lanes 32..63 those of tile w + 4.
+    // Non-planarity: mean squared residual of the window after its
     // least-squares affine fit.  The basis 1, ox, oy, oz (offsets centred at
     // 2.5) is orthogonal on the window, so the fit's coefficients are the
     // moments s0 / 216 and s_a / 630.  The residual is then summed over the
     // window a second time, explicitly: the closed form s2 - 216 c0^2 -
     // 630 |c|^2 subtracts nearly equal numbers for the near-planar windows the
     // gate has to tell apart.  An error in the coefficients only moves the sum
-    // at second order (the residual is orthogonal to the basis).
-    // Both passes sum phi itself and apply 1/h to the result (for h a power of
-    // two the bits of summing phi / h).  Rows 2i + part: ez = 2i / 6 for both
-    // parities (6 is even), ey = 2i % 6 + part.
+    // at second order (the residual is orthogonal to the basis).  Both passes
+    // sum phi itself and apply 1/h to the result (for h a power of two the
+    // bits of summing phi / h).  Lane `part` takes the window rows 2i + part
+    // of the 36 (ez = 2i / 6 for both parities, 6 being even, ey = 2i % 6 +
+    // part).
+    const int row = 16 * tile[lane >> 5] + ((lane >> 1) & 15), part = lane & 1;
+    const bool valid = row < n_list;
+    const int pt = s_list[valid ? row : n_list - 1];
+    const LearnLds &Lp = lds[pt >> 6];
+    const int c = pt & 63;
+    const int ci_ = c & 3, cj = (c >> 2) & 3, ck = c >> 4;
     float s0 = 0.f, sx = 0.f, sy = 0.f, sz = 0.f;
 #pragma unroll 1
     for (int i = 0; i < 18; ++i) {
         const int ez = (2 * i) / 6, ey = (2 * i) % 6 + part;
-        const float *row = L.phi + ci_ + kWin * ((cj + ey) + kWin * (ck + ez));
+        const float *wrow = Lp.phi + ci_ + kWin * ((cj + ey) + kWin * (ck + ez));
 #pragma unroll
         for (int ex = 0; ex < 6; ++ex) {
-            const float v = row[ex];
+            const float v = wrow[ex];
             s0 += v;
             sx += (ex - 2.5f) * v;
             sy += (ey - 2.5f) * v;
             sz += (ez - 2.5f) * v;
         }
     }
-    // combine the two lanes of the point (every lane takes part in the shuffles)
-    kw += __shfl_xor(kw, 1);
-    kx += __shfl_xor(kx, 1);
-    ky += __shfl_xor(ky, 1);
-    kz += __shfl_xor(kz, 1);
-    const int other = __shfl_xor(sat ? 1 : 0, 1);
-    sat = sat && other != 0;
     s0 += __shfl_xor(s0, 1);
     sx += __shfl_xor(sx, 1);
     sy += __shfl_xor(sy, 1);
@@ -954,36 +1011,26 @@ __global__ __launch_bounds__(256) void learned_kernel(MlpDev W, const float *__r
 #pragma unroll 1
     for (int i = 0; i < 18; ++i) {
         const int ez = (2 * i) / 6, ey = (2 * i) % 6 + part;
-        const float *row = L.phi + ci_ + kWin * ((cj + ey) + kWin * (ck + ez));
+        const float *wrow = Lp.phi + ci_ + kWin * ((cj + ey) + kWin * (ck + ez));
         const float pyz = c0 + cy * (ey - 2.5f) + cz * (ez - 2.5f);
 #pragma unroll
         for (int ex = 0; ex < 6; ++ex) {
-            const float e = row[ex] - (pyz + cx * (ex - 2.5f));
+            const float e = wrow[ex] - (pyz + cx * (ex - 2.5f));
             rr += e * e;
         }
     }
     rr += __shfl_xor(rr, 1);
     const float res = rr * inv_h * inv_h * (1.0f / 216.f);
-    if (live && part == 0) {
-        const int64_t o = ci * 64 + c, stride = n_core * 64;
-        bool write = true;
-        if (!sat) {
-            const float y0 = ys[c * kOut];
-            if (res <= tau && y0 >= kw_lo && y0 <= kw_hi) {
-                kw = y0;
-                kx = ys[c * kOut + 1];
-                ky = ys[c * kOut + 2];
-                kz = ys[c * kOut + 3];
-            } else {
-                fb_list[atomicAdd(fb_count, 1u)] = (uint32_t)o;
-                write = false;
-            }
-        }
-        if (write) {
-            out[o] = kw;
-            out[stride + o] = kx;
-            out[2 * stride + o] = ky;
-            out[3 * stride + o] = kz;
+    if (valid && part == 0) {
+        const int64_t o = (ci0 + (int64_t)blockIdx.x * kLearnPkgs + (pt >> 6)) * 64 + c;
+        const float *yv = s_y + row * kOut;
+        if (res <= tau && yv[0] >= kw_lo && yv[0] <= kw_hi) {
+            out[o] = yv[0];
+            out[stride + o] = yv[1];
+            out[2 * stride + o] = yv[2];
+            out[3 * stride + o] = yv[3];
+        } else {
+            fb_list[atomicAdd(fb_count, 1u)] = (uint32_t)o;
         }
     }
 }

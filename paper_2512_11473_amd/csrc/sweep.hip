@@ -102,21 +102,24 @@ __device__ __forceinline__ void load_face(const uint32_t *__restrict__ face, int
     f1 = *reinterpret_cast<const uint2 *>(face + p * 8 + 4);
 }
 
-// Every lane issues all five loads: a lane with no y (z) halo row re-reads its
-// own row, which the caches already hold.  Loads under a per-lane condition
-// would become branches, and the compiler then waits for every earlier load
-// before the branch's own, adding a memory round trip.
+// Every lane issues all five loads.  A lane with no y (z) halo row loads the
+// halo row of its neighbour lane on the same side (j = 1 that of j = 0, j = 2
+// that of j = 3, and likewise for k), so each halo load touches only the
+// neighbour packages' lines; the interior lanes' values are not used.  Loads
+// under a per-lane condition would become branches, and the compiler then
+// waits for every earlier load before the branch's own, adding a memory round
+// trip.
 template <typename T>
 __device__ __forceinline__ void issue_halos(const T *__restrict__ src, int64_t p, int r, const uint4 &f0,
                                             const uint2 &f1, Loads<T> &l) {
     const int j = r & 3, k = r >> 2;
     l.xm = src[(int64_t)f0.x * 64 + r * 4 + 3];
     l.xp = src[(int64_t)f0.y * 64 + r * 4];
-    const int64_t fy = j == 0 ? (int64_t)f0.z : j == 3 ? (int64_t)f0.w : p;
-    const int ry = j == 0 ? 3 + 4 * k : j == 3 ? 4 * k : r;
+    const int64_t fy = j < 2 ? (int64_t)f0.z : (int64_t)f0.w;
+    const int ry = j < 2 ? 3 + 4 * k : 4 * k;
     l.yh = load_row(src + fy * 64 + ry * 4);
-    const int64_t fz = k == 0 ? (int64_t)f1.x : k == 3 ? (int64_t)f1.y : p;
-    const int rz = k == 0 ? j + 12 : k == 3 ? j : r;
+    const int64_t fz = k < 2 ? (int64_t)f1.x : (int64_t)f1.y;
+    const int rz = k < 2 ? j + 12 : j;
     l.zh = load_row(src + fz * 64 + rz * 4);
 }
 
