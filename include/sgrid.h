@@ -460,10 +460,13 @@ sgrid_status sgrid_compute_laplacian(const sgrid_grid *grid, sgrid_dtype dtype, 
  * is variant 0 with the y / z neighbour rows exchanged through LDS instead of
  * DPP (no workgroup barrier), variant 6 is variant 0 as a persistent
  * grid-stride walk in package-id order with the next set's face row and own
- * rows loaded ahead.  `groups` (1, 2, 3, 4 or 8) is, for variants 0, 1, 3 and
+ * rows loaded ahead, variant 7 holds the field in Morton (worklist) order
+ * between the first and the last sweep of a call (the first sweep gathers it
+ * from package-id order, the last scatters it back), so each sweep streams
+ * contiguous rows.  `groups` (1, 2, 3, 4 or 8) is, for variants 0, 1, 3 and
  * 5, the number of four-package sets one wavefront processes, for variants 2
- * and 6 the number of workgroups per compute unit, and is ignored by variant
- * 4.  With variant 2, 3 or 4 the gradient and Laplacian passes also
+ * and 6 the number of workgroups per compute unit, and is ignored by variants
+ * 4 and 7.  With variant 2, 3, 4 or 7 the gradient and Laplacian passes also
  * visit the packages in Morton order.  Process-wide; default (0, 1).  Safe to
  * call from any thread: each sweep, gradient or Laplacian call reads the
  * setting once, so a change reaches calls that start after it.  Results are
@@ -473,11 +476,12 @@ sgrid_status sgrid_set_sweep_config(int32_t variant, int32_t groups);
 
 /*
  * Autotuner of sgrid_reinitialize on the caller's grid: times the candidates
- * (variant, groups) = (0, 1), (0, 2), (2, 4), (3, 1), (3, 2), (5, 1) with
- * `reps` sweeps each (1..1000) that read phi and write scratch (phi is not
- * modified; scratch rows 2.. are overwritten), makes the fastest the
- * process-wide configuration (as sgrid_set_sweep_config) and returns it.
- * us_table [6] (nullable) receives the microseconds per sweep in that order.
+ * (variant, groups) = (0, 1), (0, 2), (2, 4), (3, 1), (3, 2), (5, 1), (7, 1)
+ * with `reps` sweeps each (1..1000) that read phi and write scratch (phi is
+ * not modified; scratch rows 2.. are overwritten; variant 7 is timed on its
+ * steady-state sweep, worklist order to worklist order), makes the fastest
+ * the process-wide configuration (as sgrid_set_sweep_config) and returns it.
+ * us_table [7] (nullable) receives the microseconds per sweep in that order.
  * Synchronises the stream.  Results are identical for every candidate, so
  * tuning changes only speed.
  */

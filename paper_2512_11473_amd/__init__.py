@@ -638,7 +638,7 @@ class Batch:
                                                int(n_iter), int(bool(use_graph)), _stream(stream)))
 
 
-SWEEP_TUNE_CANDIDATES = ((0, 1), (0, 2), (2, 4), (3, 1), (3, 2), (5, 1))
+SWEEP_TUNE_CANDIDATES = ((0, 1), (0, 2), (2, 4), (3, 1), (3, 2), (5, 1), (7, 1))
 
 
 def autotune_sweep(grid: "Grid", phi: torch.Tensor, scratch: torch.Tensor, reps: int = 10, stream=None):

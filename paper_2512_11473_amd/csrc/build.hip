@@ -595,6 +595,19 @@ __global__ __launch_bounds__(256) void sweep_face_kernel(const uint32_t *__restr
     sface[t] = v;
 }
 
+// Face rows of the worklist-ordered copy of a field (row 2 + e holds the
+// package at worklist position e, rows 0 and 1 the far fields): the six face
+// neighbours' rows in that copy, then the package's own id.
+__global__ __launch_bounds__(256) void morton_face_kernel(const uint32_t *__restrict__ wface,
+                                                          const uint32_t *__restrict__ wpos, int64_t P,
+                                                          uint32_t *__restrict__ mface) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= P * 8) return;
+    const int f = (int)(t & 7);
+    const uint32_t n = wface[t];
+    mface[t] = f < 6 ? (n < 2u ? n : 2u + wpos[n]) : (f == 6 ? n : 0u);
+}
+
 __global__ __launch_bounds__(256) void fill_zero_kernel(uint32_t *__restrict__ p, int64_t n) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) p[i] = 0u;
@@ -708,7 +721,8 @@ __global__ __launch_bounds__(256) void refine_bits_kernel(const uint4 *__restric
 void free_grid(sgrid_grid *g) {
     if (!g) return;
     void *ptrs[] = {g->cell_pkg, g->pkg_cell, g->pkg_type, g->nbr,  g->face, g->core_list,
-                    g->workspace, g->rank_map, g->work, g->sface, g->wface,     g->wpos};
+                    g->workspace, g->rank_map, g->work, g->sface, g->wface,     g->wpos,
+                    g->mface};
     for (void *p : ptrs) sgrid::dev_free(p);
     delete g;
 }
@@ -859,6 +873,12 @@ sgrid_status finish_grid(sgrid_grid *g, const BuildWs &ws, hipStream_t st) {
             SG_HIP_OR_FREE(hipGetLastError());
         }
         g->wpos = wpos;
+        SG_ALLOC(g->mface, (g->P > 0 ? g->P : 1) * 32, "worklist-ordered face table");
+        if (g->P > 0) {
+            hipLaunchKernelGGL(morton_face_kernel, dim3((unsigned)((g->P * 8 + 255) / 256)), dim3(256), 0, st,
+                               g->wface, wpos, g->P, g->mface);
+            SG_HIP_OR_FREE(hipGetLastError());
+        }
     }
     return SGRID_OK;
 }

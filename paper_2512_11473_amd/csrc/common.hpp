@@ -62,6 +62,8 @@ struct sgrid_grid {
     uint32_t *sface = nullptr;      // [P][8]: per worklist position: six face neighbours (package id, or
                                     // group slot | kLocal when in the same 64-package group), own id, pad
     uint32_t *wpos = nullptr;       // [P+2]: position of each package in the worklist
+    uint32_t *mface = nullptr;      // [P][8]: per worklist position e: the six face neighbours' rows in the
+                                    // worklist-ordered field copy (2 + position, far fields 0 and 1), own id, pad
     void *workspace = nullptr;      // build scratch, kept until destroy
     // compact form of cell_pkg for position lookups: per 32 cells of a row,
     // {activated bits, negative-sign bits, activated cells before them, 0}

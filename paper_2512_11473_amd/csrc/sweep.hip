@@ -231,6 +231,44 @@ __global__ __launch_bounds__(256) void reinit_work_kernel(const T *__restrict__ 
     }
 }
 
+// Worklist-ordered storage variant (7).  During the iterations the field is
+// held in a copy ordered by the worklist: row 2 + e is the package at
+// worklist position e, rows 0 and 1 the far fields, and the face rows of that
+// copy (mface) give each position's neighbours as rows of the copy.  A sweep
+// then streams contiguous rows in Morton order, with its halos in Morton-near
+// rows, and a wavefront's own rows no longer wait for its face row.  The
+// first sweep of a call reads the field in package-id order (wface) and
+// writes the copy (MODE 0); the following ones go copy to copy (MODE 1); the
+// last writes package-id order again (MODE 2).  The values are those of every
+// other variant.
+template <typename T, int MODE>
+__global__ __launch_bounds__(256) void reinit_morton_kernel(const T *__restrict__ src, T *__restrict__ dst,
+                                                            const uint32_t *__restrict__ wface,
+                                                            const uint32_t *__restrict__ mface, int64_t P,
+                                                            int64_t n_blocks, T h2, T inv_h, T dt, bool nt) {
+    const int64_t b = xcd_block(blockIdx.x, n_blocks);
+    const int lane = threadIdx.x & 63;
+    const int r = lane & 15;
+    const int64_t e = (b * 4 + (threadIdx.x >> 6)) * 4 + (lane >> 4);
+    if (e >= P) return;   // whole 16-lane rows (one package each) leave together
+    Loads<T> l;
+    int64_t out_row;
+    if (MODE == 0) {
+        const uint4 f0 = *reinterpret_cast<const uint4 *>(wface + e * 8);
+        const uint4 f1 = *reinterpret_cast<const uint4 *>(wface + e * 8 + 4);
+        issue_data(src, (int64_t)f1.z, r, f0, make_uint2(f1.x, f1.y), l);
+        out_row = 2 + e;
+    } else {
+        l.c = load_row(src + (2 + e) * 64 + r * 4);
+        const uint4 f0 = *reinterpret_cast<const uint4 *>(mface + e * 8);
+        const uint4 f1 = *reinterpret_cast<const uint4 *>(mface + e * 8 + 4);
+        issue_halos(src, 2 + e, r, f0, make_uint2(f1.x, f1.y), l);
+        out_row = MODE == 1 ? 2 + e : (int64_t)f1.z;
+    }
+    const Stencil<T> st = assemble(r, l);
+    store_row(dst + out_row * 64 + r * 4, reinit_row(st, h2, inv_h, dt), nt);
+}
+
 // Row-exchange variant: the y / z neighbour rows move through LDS instead of
 // DPP, which takes the exchange off the VALU.  Every wavefront writes its own
 // four packages' rows (and their y / z halo rows) into a 6 x 6 grid of rows
@@ -660,7 +698,7 @@ SweepConfig current_sweep_config() {
 // Morton (worklist) order when the configuration's sweep uses it.
 bool stencil_in_worklist_order() {
     const int v = current_sweep_config().variant;
-    return v == 2 || v == 3 || v == 4;
+    return v == 2 || v == 3 || v == 4 || v == 7;
 }
 
 // MI355X's Infinity Cache (the last level before HBM)
@@ -682,9 +720,12 @@ static void launch_dpp_range(const sgrid_grid *g, const T *src, T *dst, int64_t 
     }
 }
 
+// One sweep src -> dst.  For variant 7, `mode` says which orders the two
+// buffers hold: 0 package-id order -> worklist order, 1 worklist -> worklist
+// (the autotuner times this one), 2 worklist -> package-id order.
 template <typename T>
 static sgrid_status launch_reinit_sweep(const sgrid_grid *g, const T *src, T *dst, hipStream_t st,
-                                        const SweepConfig &cfg) {
+                                        const SweepConfig &cfg, int mode = 1) {
     if (g->P == 0) return SGRID_OK;
     const int64_t per_block = 16 * (int64_t)cfg.groups;
     const int64_t nb = (g->P + per_block - 1) / per_block;
@@ -692,7 +733,19 @@ static sgrid_status launch_reinit_sweep(const sgrid_grid *g, const T *src, T *ds
     const dim3 grid((unsigned)nb), block(256);
     // streaming stores when the two field buffers exceed the last-level cache
     const bool nt = 2.0 * (double)g->total() * 64.0 * sizeof(T) > kLastLevelCacheBytes;
-    if (cfg.variant == 6) {
+    if (cfg.variant == 7) {
+        const int64_t nb7 = (g->P + 15) / 16;
+        const dim3 grid7((unsigned)nb7);
+        if (mode == 0)
+            hipLaunchKernelGGL((reinit_morton_kernel<T, 0>), grid7, block, 0, st, src, dst, g->wface, g->mface, g->P,
+                               nb7, h2, inv_h, dt, nt);
+        else if (mode == 1)
+            hipLaunchKernelGGL((reinit_morton_kernel<T, 1>), grid7, block, 0, st, src, dst, g->wface, g->mface, g->P,
+                               nb7, h2, inv_h, dt, nt);
+        else
+            hipLaunchKernelGGL((reinit_morton_kernel<T, 2>), grid7, block, 0, st, src, dst, g->wface, g->mface, g->P,
+                               nb7, h2, inv_h, dt, nt);
+    } else if (cfg.variant == 6) {
         const int64_t n_sets = (g->P + 3) / 4;
         const int64_t nbp = std::min<int64_t>((int64_t)cu_count() * cfg.groups, (n_sets + 3) / 4);
         hipLaunchKernelGGL(reinit_pipe_lin_kernel<T>, dim3((unsigned)nbp), block, 0, st, src, dst, g->face, g->P, nbp,
@@ -739,8 +792,13 @@ sgrid_status reinit_impl(const sgrid_grid *g, T *phi, T *scratch, int32_t n_iter
     // far-field rows of the second buffer: read as halo, never written
     SG_CHECK_HIP(hipMemcpyAsync(scratch, phi, 2 * 64 * sizeof(T), hipMemcpyDeviceToDevice, st));
     T *a = phi, *b = scratch;
+    // variant 7 holds the field in worklist order between its first and last
+    // sweep; a single sweep goes id order to id order (variant 3)
+    SweepConfig one = cfg;
+    if (cfg.variant == 7 && n_iter == 1) one.variant = 3;
     for (int32_t it = 0; it < n_iter; ++it) {
-        sgrid_status s = launch_reinit_sweep<T>(g, a, b, st, cfg);
+        const int mode = it == 0 ? 0 : (it == n_iter - 1 ? 2 : 1);
+        sgrid_status s = launch_reinit_sweep<T>(g, a, b, st, one, mode);
         if (s != SGRID_OK) return s;
         T *t = a;
         a = b;
@@ -780,14 +838,15 @@ sgrid_status launch_cut_fractions(const sgrid_grid *g, const float *phi, float *
 
 extern "C" sgrid_status sgrid_set_sweep_config(int32_t variant, int32_t groups) {
     sgrid::clear_error();
-    SG_REQUIRE(variant >= 0 && variant <= 6, "sweep variant must be 0..6 (got %d)", variant);
+    SG_REQUIRE(variant >= 0 && variant <= 7, "sweep variant must be 0..7 (got %d)", variant);
     SG_REQUIRE(groups == 1 || groups == 2 || groups == 3 || groups == 4 || groups == 8, "groups must be 1, 2, 3, 4 or 8 (got %d)", groups);
     sgrid::set_sweep_config(variant, groups);
     return SGRID_OK;
 }
 
 // Candidates of the sweep autotuner: (variant, groups).
-static const int kTuneCandidates[6][2] = {{0, 1}, {0, 2}, {2, 4}, {3, 1}, {3, 2}, {5, 1}};
+constexpr int kNumTune = 7;
+static const int kTuneCandidates[kNumTune][2] = {{0, 1}, {0, 2}, {2, 4}, {3, 1}, {3, 2}, {5, 1}, {7, 1}};
 
 template <typename T>
 static sgrid_status autotune_sweep(const sgrid_grid *g, const T *phi, T *scratch, int32_t reps, hipStream_t st,
@@ -797,7 +856,7 @@ static sgrid_status autotune_sweep(const sgrid_grid *g, const T *phi, T *scratch
     SG_CHECK_HIP(hipEventCreate(&e1));
     float best = 1e30f;
     sgrid::SweepConfig pick;
-    for (int c = 0; c < 6; ++c) {
+    for (int c = 0; c < kNumTune; ++c) {
         sgrid::SweepConfig cfg;
         cfg.variant = kTuneCandidates[c][0];
         cfg.groups = kTuneCandidates[c][1];

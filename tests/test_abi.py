@@ -61,7 +61,7 @@ def test_invalid_arguments_rejected_without_device(lib):
     lib.sgrid_compute_near_surface_integrals.argtypes = [P, P, P, P, P, P]
     assert lib.sgrid_compute_near_surface_integrals(None, None, None, None, None, None) == E_INVALID
     lib.sgrid_set_sweep_config.argtypes = [ctypes.c_int32, ctypes.c_int32]
-    assert lib.sgrid_set_sweep_config(7, 1) == E_INVALID
+    assert lib.sgrid_set_sweep_config(8, 1) == E_INVALID
     assert lib.sgrid_set_sweep_config(0, 9) == E_INVALID
     lib.sgrid_sequential_update.argtypes = [P, ctypes.c_int, P, ctypes.c_double, P]
     assert lib.sgrid_sequential_update(None, 0, P(16), 1e-3, None) == E_INVALID

@@ -170,6 +170,18 @@ def test_torus2048_full_size(sg):
     pos = synth.particles_for(cfg)
     wl = workload.setup(cfg["shape"], N, cfg["noise_amp"], cfg["noise_seed"], particles=pos)
     g = wl.grid
+    # the worklist-ordered storage variant (which the autotuner may pick here)
+    # against the default sweep, bit for bit, over a few iterations
+    outs = []
+    for variant in (0, 7):
+        sg.set_sweep_config(variant, 1)
+        wl.reset()
+        sg.reinitialize(g, wl.phi, wl.scratch, 4)
+        outs.append(wl.phi.clone())
+    sg.set_sweep_config(0, 1)
+    assert torch.equal(outs[0], outs[1])
+    del outs
+    wl.reset()
     sg.reinitialize(g, wl.phi, wl.scratch, n_iter)
     packed = torch.empty((g.n_total, 64, 4), device="cuda")
     sg.compute_gradient_packed(g, wl.phi, packed)

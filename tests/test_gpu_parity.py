@@ -306,7 +306,7 @@ def test_sweep_variants_identical(sg):
     wl = workload.setup(cfg["shape"], cfg["N"], cfg["noise_amp"], cfg["noise_seed"])
     results = []
     for variant, groups in [(0, 1), (0, 2), (0, 3), (0, 4), (0, 8), (1, 1), (1, 2), (1, 3), (2, 1), (2, 2), (2, 4), (2, 8),
-                           (3, 1), (3, 2), (3, 4), (4, 1), (5, 1), (5, 2), (5, 4), (6, 1), (6, 3), (6, 8)]:
+                           (3, 1), (3, 2), (3, 4), (4, 1), (5, 1), (5, 2), (5, 4), (6, 1), (6, 3), (6, 8), (7, 1)]:
         sg.set_sweep_config(variant, groups)
         wl.reset()
         sg.reinitialize(wl.grid, wl.phi, wl.scratch, 7)
@@ -314,6 +314,28 @@ def test_sweep_variants_identical(sg):
     sg.set_sweep_config(0, 1)
     for r in results[1:]:
         assert torch.equal(r, results[0])
+
+
+def test_worklist_storage_sweep_iteration_counts(sg):
+    """Variant 7 holds the field in worklist order between its first and last
+    sweep: one sweep (id order to id order), two (gather then scatter), and
+    odd and even longer counts (the last result copied back when it lands in
+    the scratch buffer) all give the bits of the default sweep, and leave the
+    far-field rows untouched."""
+    from paper_2512_11473_amd import workload
+    prism128 = {"shape": synth.prism(), "N": 128, "noise_amp": 0.05, "noise_seed": 3}
+    for cfg in (synth.config_c1(), prism128):
+        wl = workload.setup(cfg["shape"], cfg["N"], cfg["noise_amp"], cfg["noise_seed"])
+        for n_iter in (1, 2, 3, 4, 9):
+            out = []
+            for variant in (0, 7):
+                sg.set_sweep_config(variant, 1)
+                wl.reset()
+                sg.reinitialize(wl.grid, wl.phi, wl.scratch, n_iter)
+                out.append(wl.phi.clone())
+            sg.set_sweep_config(0, 1)
+            assert torch.equal(out[1], out[0]), n_iter
+            assert torch.all(out[1][0] == -16 * wl.h) and torch.all(out[1][1] == 16 * wl.h)
 
 
 def test_persistent_sweep_rounds(sg):
