@@ -201,6 +201,7 @@ __global__ __launch_bounds__(256) void probe_field_kernel(Corner<float, true> fi
 
 constexpr int kScanItems = 4096;    // entries per scan block: 1024 lanes x 4
 constexpr int kRadixBits = 8, kRadixBins = 1 << kRadixBits;
+constexpr int kDigitsPerLane = kRadixBins / 256;   // digits per lane of a 256-lane workgroup
 constexpr int kSortTile = 4096;     // elements per tile: 4 wavefronts x 16 rounds x 64
 constexpr int kSortRounds = 16;
 
@@ -232,7 +233,7 @@ __global__ __launch_bounds__(256) void radix_count_kernel(const float *__restric
                                                           float inv_h, int shift, uint32_t *__restrict__ counts,
                                                           int64_t n_tiles) {
     __shared__ uint32_t s_hist[kRadixBins];
-    s_hist[threadIdx.x] = 0u;
+    for (int d = threadIdx.x; d < kRadixBins; d += 256) s_hist[d] = 0u;
     __syncthreads();
     const int64_t t0 = (int64_t)blockIdx.x * kSortTile;
 #pragma unroll 4
@@ -241,7 +242,7 @@ __global__ __launch_bounds__(256) void radix_count_kernel(const float *__restric
         if (e < n) atomicAdd(&s_hist[(sort_key_at<FIRST>(pos, keys, e, M, inv_h) >> shift) & (kRadixBins - 1)], 1u);
     }
     __syncthreads();
-    counts[(int64_t)threadIdx.x * n_tiles + blockIdx.x] = s_hist[threadIdx.x];
+    for (int d = threadIdx.x; d < kRadixBins; d += 256) counts[(int64_t)d * n_tiles + blockIdx.x] = s_hist[d];
 }
 
 // Exclusive scan of one block of kScanItems entries in place; the block's
@@ -320,8 +321,9 @@ __global__ __launch_bounds__(256) void radix_scatter_kernel(const float *__restr
     __shared__ uint32_t s_key[kSortTile], s_idx[kSortTile];
     __shared__ uint32_t s_wsum[4];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    for (int d = threadIdx.x; d < kRadixBins; d += 256)
 #pragma unroll
-    for (int k = 0; k < 4; ++k) s_cnt[k][threadIdx.x] = 0u;
+        for (int k = 0; k < 4; ++k) s_cnt[k][d] = 0u;
     __syncthreads();
     const int64_t tile0 = (int64_t)blockIdx.x * kSortTile;
     const int64_t w0 = tile0 + 1024 * w;
@@ -348,12 +350,19 @@ __global__ __launch_bounds__(256) void radix_scatter_kernel(const float *__restr
         rank[j] = pre + lower;
     }
     __syncthreads();
-    // thread d: the digit's counts in the four wavefronts, its tile start
-    // (exclusive scan over the digits) and each wavefront's base
-    const int d = threadIdx.x;
-    const uint32_t c0 = s_cnt[0][d], c1 = s_cnt[1][d], c2 = s_cnt[2][d], c3 = s_cnt[3][d];
-    const uint32_t tot = c0 + c1 + c2 + c3;
-    uint32_t inc = tot;
+    // lane t: digits kDigitsPerLane t .. (consecutive), their counts in the
+    // four wavefronts, their tile starts (exclusive scan over the digits) and
+    // each wavefront's base
+    uint32_t c[kDigitsPerLane][4], tot[kDigitsPerLane], lane_sum = 0;
+#pragma unroll
+    for (int u = 0; u < kDigitsPerLane; ++u) {
+        const int d = kDigitsPerLane * threadIdx.x + u;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) c[u][k] = s_cnt[k][d];
+        tot[u] = c[u][0] + c[u][1] + c[u][2] + c[u][3];
+        lane_sum += tot[u];
+    }
+    uint32_t inc = lane_sum;
 #pragma unroll
     for (int k = 1; k < 64; k <<= 1) {
         const uint32_t o = __shfl_up(inc, k);
@@ -361,15 +370,20 @@ __global__ __launch_bounds__(256) void radix_scatter_kernel(const float *__restr
     }
     if (lane == 63) s_wsum[w] = inc;
     __syncthreads();
-    uint32_t start = inc - tot;
+    uint32_t start = inc - lane_sum;
     for (int k = 0; k < w; ++k) start += s_wsum[k];
-    s_start[d] = start;
-    s_cnt[0][d] = start;
-    s_cnt[1][d] = start + c0;
-    s_cnt[2][d] = start + c0 + c1;
-    s_cnt[3][d] = start + c0 + c1 + c2;
-    const int64_t oi = (int64_t)d * n_tiles + blockIdx.x;
-    s_goff[d] = offs[oi] + sums[oi / kScanItems];
+#pragma unroll
+    for (int u = 0; u < kDigitsPerLane; ++u) {
+        const int d = kDigitsPerLane * threadIdx.x + u;
+        s_start[d] = start;
+        s_cnt[0][d] = start;
+        s_cnt[1][d] = start + c[u][0];
+        s_cnt[2][d] = start + c[u][0] + c[u][1];
+        s_cnt[3][d] = start + c[u][0] + c[u][1] + c[u][2];
+        const int64_t oi = (int64_t)d * n_tiles + blockIdx.x;
+        s_goff[d] = offs[oi] + sums[oi / kScanItems];
+        start += tot[u];
+    }
     __syncthreads();
 #pragma unroll
     for (int j = 0; j < kSortRounds; ++j) {
