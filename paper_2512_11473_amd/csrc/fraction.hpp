@@ -4,8 +4,12 @@
 // V is the volume fraction of a cell on the phi > 0 side of the plane
 // phi_j + g_j . (y - x_j).  It is evaluated with the case analysis of
 // Scardovelli & Zaleski (J. Comput. Phys. 164, 2000) on the normal sorted and
-// scaled to unit 1-norm, with the cases rewritten so that every division is by
-// a bounded ratio (no cancellation when one or two normal components vanish).
+// scaled to unit 1-norm.  Every case is written with bounded ratios (alpha /
+// m_k with alpha < m_k, or (alpha - m_2) / m_1 with alpha - m_2 < m_1), so no
+// case cancels when one or two normal components vanish; the divisions are
+// products with the hardware reciprocals of the m_k (1 ulp each).  All five
+// cases are evaluated and the right one selected, which costs less than
+// divergent branches over a wavefront whose points fall in different cases.
 #pragma once
 
 #include "common.hpp"
@@ -13,46 +17,49 @@
 namespace sgrid {
 
 __device__ __forceinline__ float sz_volume_below(float alpha, float m1, float m2, float m3) {
-    // |{w in [0,1]^3 : m.w < alpha}| for 0 <= m1 <= m2 <= m3, m1 + m2 + m3 = 1, 0 <= alpha <= 1/2
-    if (alpha <= 0.0f) return 0.0f;
+    // |{w in [0,1]^3 : m.w < alpha}| for 0 <= m1 <= m2 <= m3, m1 + m2 + m3 = 1
+    // and 2^-26 <= alpha <= 1/2 (alpha = fl(x + 1/2) > 0 is a multiple of
+    // 2^-26).  A reciprocal is infinite only where m_k = 0 (or is subnormal),
+    // and then no case that uses it is the selected one: case A needs
+    // m1 > alpha, B m2 > alpha, C and D need alpha < m1 + m2 with alpha >= m2,
+    // so m1 > alpha - m2 >= 0 is not absorbed into m2.
+    const float i1 = __builtin_amdgcn_rcpf(m1), i2 = __builtin_amdgcn_rcpf(m2), i3 = __builtin_amdgcn_rcpf(m3);
+    const float c3 = i3 * (1.0f / 6.0f);
     const float m12 = m1 + m2;
-    if (alpha < m1) return (alpha / m1) * (alpha / m2) * (alpha / m3) * (1.0f / 6.0f);
-    if (alpha < m2) {
-        const float r = alpha / m2;
-        return (3.0f * r * alpha - 3.0f * r * m1 + (m1 / m2) * m1) / (6.0f * m3);
-    }
-    if (alpha < m12 && alpha < m3) {
-        const float e = alpha - m2;
-        const float base = (3.0f * (alpha / m2) * alpha - 3.0f * (alpha / m2) * m1 + (m1 / m2) * m1) / (6.0f * m3);
-        return base - (e / m1) * (e / m2) * e / (6.0f * m3);
-    }
-    if (m3 < m12) {
-        const float e2 = alpha - m2, e3 = alpha - m3;
-        const float base = (3.0f * (alpha / m2) * alpha - 3.0f * (alpha / m2) * m1 + (m1 / m2) * m1) / (6.0f * m3);
-        return base - ((e2 / m1) * (e2 / m2) * e2 + (e3 / m1) * (e3 / m2) * e3) / (6.0f * m3);
-    }
-    return (2.0f * alpha - m12) / (2.0f * m3);
+    const float r = alpha * i2;
+    // B, m1 <= alpha < m2: the wedge past the m1 vertex plane
+    const float vb = (3.0f * r * alpha - 3.0f * r * m1 + (m1 * i2) * m1) * c3;
+    // C and D subtract the corners cut off past the m2 (and m3) vertex planes
+    const float e2 = alpha - m2, e3 = alpha - m3;
+    const float t2 = (e2 * i1) * (e2 * i2) * e2;
+    const float t3 = (e3 * i1) * (e3 * i2) * e3;
+    const float va = (alpha * i1) * r * (alpha * i3) * (1.0f / 6.0f);   // A, alpha < m1: the corner tetrahedron
+    const float vc = vb - t2 * c3;
+    const float vd = vb - (t2 + t3) * c3;
+    const float ve = (2.0f * alpha - m12) * (0.5f * i3);                // E: a prism over the m3 axis
+    float v = m3 < m12 ? vd : ve;
+    v = (alpha < m12 && alpha < m3) ? vc : v;
+    v = alpha < m2 ? vb : v;
+    return alpha < m1 ? va : v;
 }
 
 // Fraction of the cube u in [-1/2, 1/2]^3 where a + g.u > 0.
 __device__ __forceinline__ float plane_cube_fraction(float a, float gx, float gy, float gz) {
-    float m1 = fabsf(gx), m2 = fabsf(gy), m3 = fabsf(gz);
-    // sort ascending
-    float t;
-    if (m1 > m2) { t = m1; m1 = m2; m2 = t; }
-    if (m2 > m3) { t = m2; m2 = m3; m3 = t; }
-    if (m1 > m2) { t = m1; m1 = m2; m2 = t; }
-    const float s = m1 + m2 + m3;
-    if (!(s > 0.0f)) return a > 0.0f ? 1.0f : (a < 0.0f ? 0.0f : 0.5f);
-    const float inv = 1.0f / s;
-    m1 *= inv;
-    m2 *= inv;
-    m3 *= inv;
+    const float ax = fabsf(gx), ay = fabsf(gy), az = fabsf(gz);
+    const float s = ax + ay + az;
+    if (!(s > 0.0f)) return a > 0.0f ? 1.0f : (a < 0.0f ? 0.0f : 0.5f);   // no gradient (or NaN)
+    const float inv = __builtin_amdgcn_rcpf(s);
     const float alpha = a * inv + 0.5f;   // (a + s/2) / s
     if (alpha >= 1.0f) return 1.0f;
     if (alpha <= 0.0f) return 0.0f;
-    if (alpha > 0.5f) return 1.0f - sz_volume_below(1.0f - alpha, m1, m2, m3);
-    return sz_volume_below(alpha, m1, m2, m3);
+    // sorted ascending (median by v_med3)
+    const float m1 = fminf(fminf(ax, ay), az) * inv;
+    const float m2 = __builtin_amdgcn_fmed3f(ax, ay, az) * inv;
+    const float m3 = fmaxf(fmaxf(ax, ay), az) * inv;
+    // the part above 1/2 by the symmetry w -> 1 - w (1 - alpha is exact there)
+    const bool flip = alpha > 0.5f;
+    const float vb = sz_volume_below(flip ? 1.0f - alpha : alpha, m1, m2, m3);
+    return flip ? 1.0f - vb : vb;
 }
 
 }  // namespace sgrid

@@ -21,46 +21,77 @@ constexpr int kVolN = kVol * kVol * kVol;
 using sgrid::wendland_u;
 using sgrid::wendland_dr_over_r_u;
 
-// The 32 taps of the dual-cell query of point (i, j, k) over the 7^3 cut
-// fractions V (window coordinates -1..5): K_W and the three K_grad sums.
+// LDS layout of the 7^3 cut fractions V (window coordinates -1..5): rows of 8
+// along x (x = 0..5 at 0..5, x = -1 at 7, 6 unused), 8 floats per y step and
+// 60 per z step.  A row is two aligned 16-byte words, and the 32 lanes of a
+// half-wavefront (i, j in 0..3, k in 0..1) read 32 distinct banks at any tap.
+constexpr int kVRow = 8, kVPlane = 60, kVWinN = kVol * kVPlane;
+__device__ __forceinline__ int vidx(int x, int y, int z) { return (x & 7) + kVRow * (y + 1) + kVPlane * (z + 1); }
+
+// One 2 x 2 x 2 block of taps, v[a][b][c] at offsets (a, b, c) along x, y, z
+// from the block's first corner, slot 0 on the + side of the query point:
+// the block's sum and its three signed half-differences.
+struct Block {
+    float t, dx, dy, dz;
+};
+__device__ __forceinline__ Block block_sums(const float *V, int x, int y, int z, int sx, int sy, int sz) {
+    const float v000 = V[vidx(x, y, z)], v001 = V[vidx(x, y, z + sz)];
+    const float v010 = V[vidx(x, y + sy, z)], v011 = V[vidx(x, y + sy, z + sz)];
+    const float v100 = V[vidx(x + sx, y, z)], v101 = V[vidx(x + sx, y, z + sz)];
+    const float v110 = V[vidx(x + sx, y + sy, z)], v111 = V[vidx(x + sx, y + sy, z + sz)];
+    const float c00 = v000 + v001, c01 = v010 + v011, c10 = v100 + v101, c11 = v110 + v111;
+    const float x0 = c00 + c01, x1 = c10 + c11;
+    Block b;
+    b.t = x0 + x1;
+    b.dx = x0 - x1;
+    b.dy = (c00 + c10) - (c01 + c11);
+    b.dz = ((v000 + v010) + (v100 + v110)) - ((v001 + v011) + (v101 + v111));
+    return b;
+}
+
+// The 32 taps of the dual-cell query of point (i, j, k) over the cut
+// fractions V: K_W and the three K_grad sums.  A tap at offset o in
+// {-1, 0, 1, 2}^3 has d = (1/2, 1/2, 1/2) - o, |d|^2 < 4, weight W(|d|) and
+// gradient weight W'(|d|) / |d| * d.  The taps form four 2 x 2 x 2 blocks:
+// the eight nearest (|d| = sqrt(3)/2, o in {0, 1}^3) and, per axis, the eight
+// with that offset in {-1, 2} and the others in {0, 1} (|d| = sqrt(11)/2);
+// inside a block each weight is constant and each gradient weight takes two
+// values of opposite sign per axis, so a block contributes its sum and its
+// three half-differences.
 __device__ __forceinline__ void tap_sums(const float *V, int i, int j, int k, float &kw, float &kx, float &ky,
                                          float &kz) {
     const float Wn = (float)wendland_u(sqrt(0.75)), Wf = (float)wendland_u(sqrt(2.75));
-    const float Dn = (float)wendland_dr_over_r_u(sqrt(0.75)), Df = (float)wendland_dr_over_r_u(sqrt(2.75));
-    kw = kx = ky = kz = 0.f;
-    for (int oz = -1; oz <= 2; ++oz)
-        for (int oy = -1; oy <= 2; ++oy)
-            for (int ox = -1; ox <= 2; ++ox) {
-                const float dx = 0.5f - ox, dy = 0.5f - oy, dz = 0.5f - oz;
-                const float r2 = dx * dx + dy * dy + dz * dz;
-                if (r2 >= 4.0f) continue;
-                const bool nearp = r2 < 1.0f;
-                const float vv = V[(i + ox + 1) + kVol * ((j + oy + 1) + kVol * (k + oz + 1))];
-                const float Wt = nearp ? Wn : Wf, Dt = nearp ? Dn : Df;
-                kw += Wt * vv;
-                kx += Dt * dx * vv;
-                ky += Dt * dy * vv;
-                kz += Dt * dz * vv;
-            }
+    const float Dn = (float)(0.5 * wendland_dr_over_r_u(sqrt(0.75)));
+    const float Dh = (float)(0.5 * wendland_dr_over_r_u(sqrt(2.75)));   // far taps, the +-1/2 components
+    const float Dw = (float)(1.5 * wendland_dr_over_r_u(sqrt(2.75)));   // far taps, the +-3/2 component
+    const Block n = block_sums(V, i, j, k, 1, 1, 1);
+    const Block fx = block_sums(V, i - 1, j, k, 3, 1, 1);
+    const Block fy = block_sums(V, i, j - 1, k, 1, 3, 1);
+    const Block fz = block_sums(V, i, j, k - 1, 1, 1, 3);
+    kw = Wn * n.t + Wf * ((fx.t + fy.t) + fz.t);
+    kx = Dn * n.dx + (Dw * fx.dx + Dh * (fy.dx + fz.dx));
+    ky = Dn * n.dy + (Dw * fy.dy + Dh * (fx.dy + fz.dy));
+    kz = Dn * n.dz + (Dw * fz.dz + Dh * (fx.dz + fy.dz));
 }
 
 // The cut fractions of the 7^3 points -1..5 of a package from its staged
 // 9^3 phi window f, by the wavefront's 64 lanes.
 __device__ __forceinline__ void window_fractions(const float *f, int lane, float inv_h, float inv_2h, float *V) {
     for (int v = lane; v < kVolN; v += 64) {
-        const int x = v % kVol + 1, y = (v / kVol) % kVol + 1, z = v / (kVol * kVol) + 1;   // in window coords
-        const int c = x + kWin * (y + kWin * z);
+        const int x = v % kVol, y = (v / kVol) % kVol, z = v / (kVol * kVol);   // window coords + 1
+        const int c = (x + 1) + kWin * ((y + 1) + kWin * (z + 1));
         const float gx = (f[c + 1] - f[c - 1]) * inv_2h;
         const float gy = (f[c + kWin] - f[c - kWin]) * inv_2h;
         const float gz = (f[c + kWin * kWin] - f[c - kWin * kWin]) * inv_2h;
-        V[v] = sgrid::plane_cube_fraction(f[c] * inv_h, gx, gy, gz);
+        V[vidx(x - 1, y - 1, z - 1)] = sgrid::plane_cube_fraction(f[c] * inv_h, gx, gy, gz);
     }
 }
 
 // FIELD = false: the core packages of `list`, output [4][n * 64] in list
 // order.  FIELD = true: every activated package (ids 2 .. n + 1, `list`
 // unused), output one float4 (K_W, h K_grad) per data point in the packed
-// blocked layout of the probe fields.
+// blocked layout of the probe fields.  Each wavefront works on its own
+// package and LDS slices alone, so it waits for no other.
 template <bool FIELD>
 __global__ __launch_bounds__(256) void integrals_plain_kernel(const float *__restrict__ phi,
                                                               const uint32_t *__restrict__ nbr,
@@ -68,19 +99,18 @@ __global__ __launch_bounds__(256) void integrals_plain_kernel(const float *__res
                                                               int64_t n, float inv_h, float inv_2h,
                                                               float *__restrict__ out) {
     __shared__ float s_phi[4][kWinN];
-    __shared__ float s_v[4][kVolN];
+    __shared__ __align__(16) float s_v[4][kVWinN];
     __shared__ uint32_t s_ids[4][27];
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int64_t ci = (int64_t)blockIdx.x * 4 + w;
-    const bool live = ci < n;
-    const int64_t p = live ? (FIELD ? ci + 2 : (int64_t)list[ci]) : 0;
-    if (live && lane < 27) s_ids[w][lane] = nbr[p * 27 + lane];
-    __syncthreads();
-    if (live) sgrid::stage_window_part<64>(phi, s_ids[w], lane, s_phi[w]);
-    __syncthreads();
-    if (live) window_fractions(s_phi[w], lane, inv_h, inv_2h, s_v[w]);
-    __syncthreads();
-    if (!live) return;
+    if (ci >= n) return;
+    const int64_t p = FIELD ? ci + 2 : (int64_t)list[ci];
+    if (lane < 27) s_ids[w][lane] = nbr[p * 27 + lane];
+    __builtin_amdgcn_wave_barrier();
+    sgrid::stage_window_part<64>(phi, s_ids[w], lane, s_phi[w]);
+    __builtin_amdgcn_wave_barrier();
+    window_fractions(s_phi[w], lane, inv_h, inv_2h, s_v[w]);
+    __builtin_amdgcn_wave_barrier();
     const int i = lane & 3, j = (lane >> 2) & 3, k = lane >> 4;
     float kw, kx, ky, kz;
     tap_sums(s_v[w], i, j, k, kw, kx, ky, kz);
@@ -96,62 +126,73 @@ __global__ __launch_bounds__(256) void integrals_plain_kernel(const float *__res
 }
 
 // Second pass of the factorised integrals: one wavefront per core package
-// stages the 7^3 cut fractions around it from the first pass's array (through
-// the neighbour row, index shift of Sec. 5.2 with the window origin at -1)
-// and sums the taps.  A core package's 26 neighbours are all activated inside
-// the domain, so the window reads only band points there; a package at a
-// domain face has far-field neighbours, whose window points take their
-// fractions from the mixed neighbourhood of the face rather than from a
-// shared far-field row: such a wavefront stages its phi window and evaluates
-// the fractions itself, as the plain kernel does.  The taps and the fractions
-// are the plain kernel's expressions, so the output carries its bits.
+// gathers the 7^3 cut fractions around it from the first pass's array
+// (through the neighbour row, index shift of Sec. 5.2 with the window origin
+// at -1), one window row of 7 per lane: the 4 of the package's own row as one
+// 16-byte load, x = -1 from the -x neighbour and x = 4, 5 from the +x
+// neighbour.  Then it sums the taps.  A core package's 26 neighbours are all
+// activated inside the domain, so the window reads only band points there; a
+// package at a domain face has far-field neighbours, whose window points take
+// their fractions from the mixed neighbourhood of the face rather than from a
+// shared far-field row: such a wavefront evaluates the fractions itself from
+// phi, with the plain kernel's expressions, in a rolled loop straight from
+// memory (this rare path then needs no LDS window and does not raise the
+// register count of the common one).  The taps and the fractions are the
+// plain kernel's, so the output carries its bits.
 __global__ __launch_bounds__(256) void integrals_factorised_kernel(const float *__restrict__ phi,
                                                                    const float *__restrict__ vfrac,
                                                                    const uint32_t *__restrict__ nbr,
                                                                    const uint32_t *__restrict__ list, int64_t n,
                                                                    int64_t n_blocks, float inv_h, float inv_2h,
                                                                    float *__restrict__ out) {
-    __shared__ float s_phi[4][kWinN];
-    __shared__ float s_v[4][kVolN];
-    __shared__ uint32_t s_ids[4][28];
+    __shared__ __align__(16) float s_v[4][kVWinN];
+    __shared__ uint32_t s_ids[4][27];
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int64_t ci = xcd_block(blockIdx.x, n_blocks) * 4 + w;
-    const bool live = ci < n;
-    const int64_t p = live ? (int64_t)list[ci] : 0;
-    if (live && lane < 27) s_ids[w][lane] = nbr[p * 27 + lane];
-    __syncthreads();
-    const uint32_t *ids = s_ids[w];
-    bool edge = false;
-    if (live)
-        for (int q = 0; q < 27; ++q) edge |= ids[q] < 2u;
-    if (live && edge) sgrid::stage_window_part<64>(phi, ids, lane, s_phi[w]);
-    __syncthreads();
-    if (live) {
-        if (edge) {
-            window_fractions(s_phi[w], lane, inv_h, inv_2h, s_v[w]);
-        } else {
-            constexpr int kIters = (kVolN + 63) / 64;
-            float v[kIters];
-#pragma unroll
-            for (int u = 0; u < kIters; ++u) {
-                const int q = min(lane + 64 * u, kVolN - 1);
-                const int x = q % kVol - 1, y = (q / kVol) % kVol - 1, z = q / (kVol * kVol) - 1;
-                const int kx = (x + 4) >> 2, ky = (y + 4) >> 2, kz = (z + 4) >> 2;
-                const int d = (x + 4 - 4 * kx) + 4 * (y + 4 - 4 * ky) + 16 * (z + 4 - 4 * kz);
-                v[u] = vfrac[(int64_t)ids[kx + 3 * ky + 9 * kz] * 64 + d];
-            }
-#pragma unroll
-            for (int u = 0; u < kIters; ++u) {
-                const int q = lane + 64 * u;
-                if (q < kVolN) s_v[w][q] = v[u];
-            }
+    if (ci >= n) return;
+    const int64_t p = (int64_t)list[ci];
+    const uint32_t id = lane < 27 ? nbr[p * 27 + lane] : 2u;
+    const bool edge = __ballot(id < 2u) != 0;   // a far-field neighbour
+    float *V = s_v[w];
+    if (edge) {
+        // the fractions of the window points straight from phi (the values
+        // and expressions of window_fractions)
+        if (lane < 27) s_ids[w][lane] = id;
+        __builtin_amdgcn_wave_barrier();
+        const uint32_t *ids = s_ids[w];
+#pragma unroll 1
+        for (int v = lane; v < kVolN; v += 64) {
+            const int x = v % kVol, y = (v / kVol) % kVol, z = v / (kVol * kVol);   // window coords + 1
+            const int c = (x + 1) + kWin * ((y + 1) + kWin * (z + 1));
+            const float fc = phi[sgrid::window_source(ids, c)];
+            const float gx = (phi[sgrid::window_source(ids, c + 1)] - phi[sgrid::window_source(ids, c - 1)]) * inv_2h;
+            const float gy =
+                (phi[sgrid::window_source(ids, c + kWin)] - phi[sgrid::window_source(ids, c - kWin)]) * inv_2h;
+            const float gz = (phi[sgrid::window_source(ids, c + kWin * kWin)] -
+                              phi[sgrid::window_source(ids, c - kWin * kWin)]) * inv_2h;
+            V[vidx(x - 1, y - 1, z - 1)] = sgrid::plane_cube_fraction(fc * inv_h, gx, gy, gz);
+        }
+    } else {
+        // window row of this lane (lanes 49..63 repeat row 48 and store nothing)
+        const int rl = min(lane, kVol * kVol - 1);
+        const int y = rl % kVol - 1, z = rl / kVol - 1;
+        const int ky = (y + 4) >> 2, kz = (z + 4) >> 2;
+        const int row = 4 * ((y + 4 - 4 * ky) + 4 * (z + 4 - 4 * kz));
+        const int s = 3 * ky + 9 * kz;
+        const uint32_t im = __shfl(id, s), ic = __shfl(id, s + 1), ip = __shfl(id, s + 2);
+        const float xm = vfrac[(int64_t)im * 64 + row + 3];
+        const float4 c = *reinterpret_cast<const float4 *>(vfrac + (int64_t)ic * 64 + row);
+        const float2 xp = *reinterpret_cast<const float2 *>(vfrac + (int64_t)ip * 64 + row);
+        if (lane < kVol * kVol) {
+            float4 *dst = reinterpret_cast<float4 *>(V + kVRow * (y + 1) + kVPlane * (z + 1));
+            dst[0] = c;
+            dst[1] = make_float4(xp.x, xp.y, 0.f, xm);
         }
     }
-    __syncthreads();
-    if (!live) return;
+    __builtin_amdgcn_wave_barrier();
     const int i = lane & 3, j = (lane >> 2) & 3, k = lane >> 4;
     float kw, kx, ky, kz;
-    tap_sums(s_v[w], i, j, k, kw, kx, ky, kz);
+    tap_sums(V, i, j, k, kw, kx, ky, kz);
     const int64_t o = ci * 64 + lane, stride = n * 64;
     out[o] = kw;
     out[stride + o] = kx;

@@ -574,38 +574,82 @@ __global__ __launch_bounds__(256) void gradient_kernel(const T *__restrict__ phi
 // sums it over each core point's 32 taps without evaluating any fraction
 // again.  The expressions are those of the plain integral kernel, so the
 // fractions carry the same bits.  Far-field rows: phi = -B gives 0, +B gives 1.
+//
+// Most points of the band lie more than half a cell (in the 1-norm of the
+// gradient) from the surface, where V is 0 or 1 by the sign of phi alone.
+// Only the cut points go through the case analysis: a wavefront lists its cut
+// points (at most 256, four per lane) in LDS by ballot and evaluates them one
+// per lane, so the case code runs once per 64 cut points instead of once per
+// row position of every lane.
 template <bool WORK>
 __global__ __launch_bounds__(256) void cut_fraction_kernel(const float *__restrict__ phi, float *__restrict__ vfrac,
                                                            const uint32_t *__restrict__ face,
                                                            const uint32_t *__restrict__ wface, int64_t n_total,
                                                            int64_t n_blocks, float inv_h, float inv_2h, bool nt) {
+    __shared__ float4 s_q[4][256];
+    __shared__ float s_res[4][256];
+    __shared__ uint8_t s_dst[4][256];
     const int64_t b = xcd_block(blockIdx.x, n_blocks);
-    const int lane = threadIdx.x & 63;
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int r = lane & 15;
-    const int64_t e = (b * 4 + (threadIdx.x >> 6)) * 4 + (lane >> 4);
-    if (e >= n_total) return;
-    uint4 f0;
-    uint2 f1;
-    const int64_t p = stencil_package<WORK>(e, face, wface, f0, f1);
-    Row<float> v;
-    if (p < 2) {
-        const Row<float> c = load_row(phi + p * 64 + r * 4);
+    const int64_t e = (b * 4 + w) * 4 + (lane >> 4);
+    const bool live = e < n_total;
+    float a[4], gx[4] = {0.f, 0.f, 0.f, 0.f}, gy[4] = {0.f, 0.f, 0.f, 0.f}, gz[4] = {0.f, 0.f, 0.f, 0.f};
+    int64_t p = 0;
+    if (live) {
+        uint4 f0;
+        uint2 f1;
+        p = stencil_package<WORK>(e, face, wface, f0, f1);
+        if (p < 2) {
+            const Row<float> c = load_row(phi + p * 64 + r * 4);
 #pragma unroll
-        for (int i = 0; i < 4; ++i) v.v[i] = sgrid::plane_cube_fraction(c.v[i] * inv_h, 0.f, 0.f, 0.f);
-    } else {
-        Loads<float> l;
-        issue_data(phi, p, r, f0, f1, l);
-        const Stencil<float> s = assemble(r, l);
+            for (int i = 0; i < 4; ++i) a[i] = c.v[i] * inv_h;
+        } else {
+            Loads<float> l;
+            issue_data(phi, p, r, f0, f1, l);
+            const Stencil<float> s = assemble(r, l);
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const float xm = i > 0 ? s.c.v[i - 1] : s.xm;
-            const float xp = i < 3 ? s.c.v[i + 1] : s.xp;
-            const float gx = (xp - xm) * inv_2h;
-            const float gy = (s.yp.v[i] - s.ym.v[i]) * inv_2h;
-            const float gz = (s.zp.v[i] - s.zm.v[i]) * inv_2h;
-            v.v[i] = sgrid::plane_cube_fraction(s.c.v[i] * inv_h, gx, gy, gz);
+            for (int i = 0; i < 4; ++i) {
+                const float xm = i > 0 ? s.c.v[i - 1] : s.xm;
+                const float xp = i < 3 ? s.c.v[i + 1] : s.xp;
+                a[i] = s.c.v[i] * inv_h;
+                gx[i] = (xp - xm) * inv_2h;
+                gy[i] = (s.yp.v[i] - s.ym.v[i]) * inv_2h;
+                gz[i] = (s.zp.v[i] - s.zm.v[i]) * inv_2h;
+            }
         }
     }
+    // |a| > 0.51 |g|_1 puts the plane beyond the cell by a margin that covers
+    // the rounding of the fraction's own normalisation, so there V is exactly
+    // what the fraction returns (1 or 0 by the sign of a); NaN / huge inputs
+    // take the full evaluation
+    bool cut[4];
+    int n_cut = 0, slot[4];
+    const uint64_t below = (1ull << lane) - 1ull;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const float s1 = fabsf(gx[i]) + fabsf(gy[i]) + fabsf(gz[i]);
+        cut[i] = live && !(fabsf(a[i]) > 0.51f * s1 && s1 < 1e30f);
+        const uint64_t m = __ballot(cut[i]);
+        slot[i] = n_cut + (int)__popcll(m & below);
+        n_cut += (int)__popcll(m);
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+        if (cut[i]) {
+            s_q[w][slot[i]] = make_float4(a[i], gx[i], gy[i], gz[i]);
+            s_dst[w][slot[i]] = (uint8_t)(lane * 4 + i);
+        }
+    __builtin_amdgcn_wave_barrier();
+    for (int t = lane; t < n_cut; t += 64) {
+        const float4 q = s_q[w][t];
+        s_res[w][s_dst[w][t]] = sgrid::plane_cube_fraction(q.x, q.y, q.z, q.w);
+    }
+    __builtin_amdgcn_wave_barrier();
+    if (!live) return;
+    Row<float> v;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) v.v[i] = cut[i] ? s_res[w][lane * 4 + i] : (a[i] > 0.0f ? 1.0f : 0.0f);
     store_row(vfrac + p * 64 + r * 4, v, nt);
 }
 
