@@ -125,79 +125,127 @@ __global__ __launch_bounds__(256) void integrals_plain_kernel(const float *__res
     }
 }
 
-// Second pass of the factorised integrals: one wavefront per core package
-// gathers the 7^3 cut fractions around it from the first pass's array
-// (through the neighbour row, index shift of Sec. 5.2 with the window origin
-// at -1), one window row of 7 per lane: the 4 of the package's own row as one
-// 16-byte load, x = -1 from the -x neighbour and x = 4, 5 from the +x
-// neighbour.  Then it sums the taps.  A core package's 26 neighbours are all
+// The cut fractions of the window of a package at a domain face straight
+// from phi (the values and expressions of window_fractions), in a rolled
+// loop: this rare path needs no LDS window and does not raise the register
+// count of the common one.
+__device__ __forceinline__ void edge_window_fractions(const float *__restrict__ phi, const uint32_t *ids, int lane,
+                                                      float inv_h, float inv_2h, float *V) {
+#pragma unroll 1
+    for (int v = lane; v < kVolN; v += 64) {
+        const int x = v % kVol, y = (v / kVol) % kVol, z = v / (kVol * kVol);   // window coords + 1
+        const int c = (x + 1) + kWin * ((y + 1) + kWin * (z + 1));
+        const float fc = phi[sgrid::window_source(ids, c)];
+        const float gx = (phi[sgrid::window_source(ids, c + 1)] - phi[sgrid::window_source(ids, c - 1)]) * inv_2h;
+        const float gy = (phi[sgrid::window_source(ids, c + kWin)] - phi[sgrid::window_source(ids, c - kWin)]) * inv_2h;
+        const float gz = (phi[sgrid::window_source(ids, c + kWin * kWin)] -
+                          phi[sgrid::window_source(ids, c - kWin * kWin)]) * inv_2h;
+        V[vidx(x - 1, y - 1, z - 1)] = sgrid::plane_cube_fraction(fc * inv_h, gx, gy, gz);
+    }
+}
+
+// Second pass of the factorised integrals: each wavefront takes G
+// consecutive core packages.  Per package it gathers the 7^3 cut fractions
+// around it from the first pass's array (through the neighbour row, index
+// shift of Sec. 5.2 with the window origin at -1), one window row of 7 per
+// lane: the 4 of the package's own row as one 16-byte load, x = -1 from the
+// -x neighbour and x = 4, 5 from the +x neighbour.  All G packages' neighbour
+// rows, then all their window rows, are requested before the first package's
+// taps are summed, so the later packages' loads are in flight while the
+// earlier ones are summed and stored.  The windows pass one by one through
+// the wavefront's LDS slice.  A core package's 26 neighbours are all
 // activated inside the domain, so the window reads only band points there; a
 // package at a domain face has far-field neighbours, whose window points take
 // their fractions from the mixed neighbourhood of the face rather than from a
-// shared far-field row: such a wavefront evaluates the fractions itself from
-// phi, with the plain kernel's expressions, in a rolled loop straight from
-// memory (this rare path then needs no LDS window and does not raise the
-// register count of the common one).  The taps and the fractions are the
-// plain kernel's, so the output carries its bits.
+// shared far-field row: such a package's fractions are evaluated from phi, as
+// the plain kernel does.  The taps and the fractions are the plain kernel's
+// expressions, so the output carries its bits.
+template <int G>
 __global__ __launch_bounds__(256) void integrals_factorised_kernel(const float *__restrict__ phi,
                                                                    const float *__restrict__ vfrac,
                                                                    const uint32_t *__restrict__ nbr,
                                                                    const uint32_t *__restrict__ list, int64_t n,
                                                                    int64_t n_blocks, float inv_h, float inv_2h,
                                                                    float *__restrict__ out) {
-    __shared__ __align__(16) float s_v[4][kVWinN];
+    __shared__ __align__(16) float s_v[4][kVWinN + kVRow * (64 - kVol * kVol)];
     __shared__ uint32_t s_ids[4][27];
-    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int64_t ci = xcd_block(blockIdx.x, n_blocks) * 4 + w;
-    if (ci >= n) return;
-    const int64_t p = (int64_t)list[ci];
-    const uint32_t id = lane < 27 ? nbr[p * 27 + lane] : 2u;
-    const bool edge = __ballot(id < 2u) != 0;   // a far-field neighbour
-    float *V = s_v[w];
-    if (edge) {
-        // the fractions of the window points straight from phi (the values
-        // and expressions of window_fractions)
-        if (lane < 27) s_ids[w][lane] = id;
-        __builtin_amdgcn_wave_barrier();
-        const uint32_t *ids = s_ids[w];
-#pragma unroll 1
-        for (int v = lane; v < kVolN; v += 64) {
-            const int x = v % kVol, y = (v / kVol) % kVol, z = v / (kVol * kVol);   // window coords + 1
-            const int c = (x + 1) + kWin * ((y + 1) + kWin * (z + 1));
-            const float fc = phi[sgrid::window_source(ids, c)];
-            const float gx = (phi[sgrid::window_source(ids, c + 1)] - phi[sgrid::window_source(ids, c - 1)]) * inv_2h;
-            const float gy =
-                (phi[sgrid::window_source(ids, c + kWin)] - phi[sgrid::window_source(ids, c - kWin)]) * inv_2h;
-            const float gz = (phi[sgrid::window_source(ids, c + kWin * kWin)] -
-                              phi[sgrid::window_source(ids, c - kWin * kWin)]) * inv_2h;
-            V[vidx(x - 1, y - 1, z - 1)] = sgrid::plane_cube_fraction(fc * inv_h, gx, gy, gz);
-        }
-    } else {
-        // window row of this lane (lanes 49..63 repeat row 48 and store nothing)
-        const int rl = min(lane, kVol * kVol - 1);
-        const int y = rl % kVol - 1, z = rl / kVol - 1;
-        const int ky = (y + 4) >> 2, kz = (z + 4) >> 2;
-        const int row = 4 * ((y + 4 - 4 * ky) + 4 * (z + 4 - 4 * kz));
-        const int s = 3 * ky + 9 * kz;
-        const uint32_t im = __shfl(id, s), ic = __shfl(id, s + 1), ip = __shfl(id, s + 2);
-        const float xm = vfrac[(int64_t)im * 64 + row + 3];
-        const float4 c = *reinterpret_cast<const float4 *>(vfrac + (int64_t)ic * 64 + row);
-        const float2 xp = *reinterpret_cast<const float2 *>(vfrac + (int64_t)ip * 64 + row);
-        if (lane < kVol * kVol) {
-            float4 *dst = reinterpret_cast<float4 *>(V + kVRow * (y + 1) + kVPlane * (z + 1));
-            dst[0] = c;
-            dst[1] = make_float4(xp.x, xp.y, 0.f, xm);
-        }
+    // (the wavefront index through readfirstlane: the compiler then knows it
+    // is uniform and reads the list with scalar loads)
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+    const int64_t c0 = (xcd_block(blockIdx.x, n_blocks) * 4 + w) * G;
+    if (c0 >= n) return;
+    const int64_t stride = n * 64;
+    uint32_t p[G], id[G];
+#pragma unroll
+    for (int g = 0; g < G; ++g) p[g] = list[min(c0 + g, n - 1)];
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+        const uint32_t v = nbr[(int64_t)p[g] * 27 + min(lane, 26)];
+        id[g] = lane < 27 ? v : 2u;
     }
-    __builtin_amdgcn_wave_barrier();
+    // window row of this lane (lanes 49..63 repeat row 48 and write it to a
+    // spare row of their own past the window)
+    const int rl = min(lane, kVol * kVol - 1);
+    const int y = rl % kVol - 1, z = rl / kVol - 1;
+    const int ky = (y + 4) >> 2, kz = (z + 4) >> 2;
+    const int row = 4 * ((y + 4 - 4 * ky) + 4 * (z + 4 - 4 * kz));
+    const int s = 3 * ky + 9 * kz;
+    // (an edge package's loads read the far-field rows 0 / 1, in bounds, and
+    // are not used)
+    float xm[G];
+    float4 c[G];
+    float2 xp[G];
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+        const uint32_t im = __shfl(id[g], s), ic = __shfl(id[g], s + 1), ip = __shfl(id[g], s + 2);
+        xm[g] = vfrac[(int64_t)im * 64 + row + 3];
+        c[g] = *reinterpret_cast<const float4 *>(vfrac + (int64_t)ic * 64 + row);
+        xp[g] = *reinterpret_cast<const float2 *>(vfrac + (int64_t)ip * 64 + row);
+    }
+    float *V = s_v[w];
     const int i = lane & 3, j = (lane >> 2) & 3, k = lane >> 4;
-    float kw, kx, ky, kz;
-    tap_sums(V, i, j, k, kw, kx, ky, kz);
-    const int64_t o = ci * 64 + lane, stride = n * 64;
-    out[o] = kw;
-    out[stride + o] = kx;
-    out[2 * stride + o] = ky;
-    out[3 * stride + o] = kz;
+    // The common path has no branch, so the compiler keeps every load where
+    // it is issued: a tail package repeats the last one and stores the same
+    // values to the same place.  Packages with a far-field neighbour get their
+    // stores overwritten below.
+    float4 *dst = reinterpret_cast<float4 *>(
+        V + (lane < kVol * kVol ? kVRow * (y + 1) + kVPlane * (z + 1) : kVWinN + kVRow * (lane - kVol * kVol)));
+    uint32_t edge = 0;
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+        edge |= (__ballot(id[g] < 2u) != 0 ? 1u : 0u) << g;
+        dst[0] = c[g];
+        dst[1] = make_float4(xp[g].x, xp[g].y, 0.f, xm[g]);
+        __builtin_amdgcn_wave_barrier();
+        float kw, kx, ky_, kz_;
+        tap_sums(V, i, j, k, kw, kx, ky_, kz_);
+        __builtin_amdgcn_wave_barrier();
+        const int64_t o = min(c0 + g, n - 1) * 64 + lane;
+        out[o] = kw;
+        out[stride + o] = kx;
+        out[2 * stride + o] = ky_;
+        out[3 * stride + o] = kz_;
+    }
+    if (edge == 0u) return;
+#pragma unroll 1
+    for (int g = 0; g < G; ++g) {
+        if (!((edge >> g) & 1u) || c0 + g >= n) continue;
+        uint32_t idg = id[0];
+#pragma unroll
+        for (int q = 1; q < G; ++q) idg = g == q ? id[q] : idg;
+        if (lane < 27) s_ids[w][lane] = idg;
+        __builtin_amdgcn_wave_barrier();
+        edge_window_fractions(phi, s_ids[w], lane, inv_h, inv_2h, V);
+        __builtin_amdgcn_wave_barrier();
+        float kw, kx, ky_, kz_;
+        tap_sums(V, i, j, k, kw, kx, ky_, kz_);
+        __builtin_amdgcn_wave_barrier();
+        const int64_t o = (c0 + g) * 64 + lane;
+        out[o] = kw;
+        out[stride + o] = kx;
+        out[2 * stride + o] = ky_;
+        out[3 * stride + o] = kz_;
+    }
 }
 
 // Rows 0 and 1 of the integral field: the far-field packages, whose points
@@ -260,9 +308,11 @@ extern "C" sgrid_status sgrid_compute_near_surface_integrals_factorised(const sg
     hipStream_t st = sg_stream(stream);
     sgrid_status s = sgrid::launch_cut_fractions(g, phi, vfrac, st);
     if (s != SGRID_OK) return s;
-    const int64_t nb = (g->n_core + 3) / 4;
-    hipLaunchKernelGGL(integrals_factorised_kernel, dim3((unsigned)nb), dim3(256), 0, st, phi, (const float *)vfrac,
-                       g->nbr, g->core_list, g->n_core, nb, (float)(1.0 / g->h), (float)(0.5 / g->h), out);
+    constexpr int kG = 4;   // core packages per wavefront
+    const int64_t nb = (g->n_core + 4 * kG - 1) / (4 * kG);
+    hipLaunchKernelGGL(integrals_factorised_kernel<kG>, dim3((unsigned)nb), dim3(256), 0, st, phi,
+                       (const float *)vfrac, g->nbr, g->core_list, g->n_core, nb, (float)(1.0 / g->h),
+                       (float)(0.5 / g->h), out);
     SG_CHECK_LAUNCH("factorised integrals");
     return SGRID_OK;
 }
