@@ -75,15 +75,86 @@ __device__ __forceinline__ void tap_sums(const float *V, int i, int j, int k, fl
 }
 
 // The cut fractions of the 7^3 points -1..5 of a package from its staged
-// 9^3 phi window f, by the wavefront's 64 lanes.
-__device__ __forceinline__ void window_fractions(const float *f, int lane, float inv_h, float inv_2h, float *V) {
-    for (int v = lane; v < kVolN; v += 64) {
-        const int x = v % kVol, y = (v / kVol) % kVol, z = v / (kVol * kVol);   // window coords + 1
+// 9^3 phi window f, by the wavefront's 64 lanes.  A point more than half a
+// cell (in the 1-norm of its gradient) from the surface has V = 0 or 1 by the
+// sign of phi; the cut points are listed (ballot, in LDS) and evaluated one
+// per lane afterwards, so the case code runs once per 64 cut points rather
+// than once per 64 window points.  The test |a| > 0.51 |g|_1 leaves a margin
+// over the rounding of the fraction's own normalisation, so the value of a
+// listed-out point is the one the fraction returns; NaN or huge inputs are
+// listed.
+__device__ __forceinline__ void window_fractions(const float *f, int lane, float inv_h, float inv_2h, float *V,
+                                                 uint16_t *cut_list) {
+    const uint64_t below = (1ull << lane) - 1ull;
+    int n_cut = 0;
+#pragma unroll
+    for (int u = 0; u < (kVolN + 63) / 64; ++u) {
+        const int v = lane + 64 * u;
+        const int vc = min(v, kVolN - 1);
+        const int x = vc % kVol, y = (vc / kVol) % kVol, z = vc / (kVol * kVol);   // window coords + 1
+        const int c = (x + 1) + kWin * ((y + 1) + kWin * (z + 1));
+        const float a = f[c] * inv_h;
+        const float gx = (f[c + 1] - f[c - 1]) * inv_2h;
+        const float gy = (f[c + kWin] - f[c - kWin]) * inv_2h;
+        const float gz = (f[c + kWin * kWin] - f[c - kWin * kWin]) * inv_2h;
+        const float s1 = fabsf(gx) + fabsf(gy) + fabsf(gz);
+        const bool sat = fabsf(a) > 0.51f * s1 && s1 < 1e30f;
+        if (v < kVolN && sat) V[vidx(x - 1, y - 1, z - 1)] = a > 0.0f ? 1.0f : 0.0f;
+        const bool cut = v < kVolN && !sat;
+        const uint64_t m = __ballot(cut);
+        if (cut) cut_list[n_cut + (int)__popcll(m & below)] = (uint16_t)v;
+        n_cut += (int)__popcll(m);
+    }
+    __builtin_amdgcn_wave_barrier();
+    for (int t = lane; t < n_cut; t += 64) {
+        const int v = cut_list[t];
+        const int x = v % kVol, y = (v / kVol) % kVol, z = v / (kVol * kVol);
         const int c = (x + 1) + kWin * ((y + 1) + kWin * (z + 1));
         const float gx = (f[c + 1] - f[c - 1]) * inv_2h;
         const float gy = (f[c + kWin] - f[c - kWin]) * inv_2h;
         const float gz = (f[c + kWin * kWin] - f[c - kWin * kWin]) * inv_2h;
         V[vidx(x - 1, y - 1, z - 1)] = sgrid::plane_cube_fraction(f[c] * inv_h, gx, gy, gz);
+    }
+}
+
+// The 9^3 phi window of a package into LDS (x fastest, window coordinates
+// -2..6), one window row of 9 per lane and step (81 rows): x = -2, -1 from
+// the -x neighbour's row (8-byte load), x = 0..3 the package's own row
+// (16-byte load), x = 4..6 from the +x neighbour's row (16-byte load, the
+// fourth value unused).  The neighbours through the 27-entry row ids with the
+// index shift of Sec. 5.2.
+__device__ __forceinline__ void stage_window_rows(const float *__restrict__ phi, const uint32_t *ids, int lane,
+                                                  float *f) {
+    constexpr int kRows = kWin * kWin;
+    constexpr int kSteps = (kRows + 63) / 64;
+    float2 m[kSteps];
+    float4 c[kSteps], q[kSteps];
+#pragma unroll
+    for (int u = 0; u < kSteps; ++u) {
+        const int r = min(lane + 64 * u, kRows - 1);
+        const int y = r % kWin - 2, z = r / kWin - 2;
+        const int ky = (y + 4) >> 2, kz = (z + 4) >> 2;
+        const int row = 4 * ((y + 4 - 4 * ky) + 4 * (z + 4 - 4 * kz));
+        const int s = 3 * ky + 9 * kz;
+        m[u] = *reinterpret_cast<const float2 *>(phi + (int64_t)ids[s] * 64 + row + 2);
+        c[u] = *reinterpret_cast<const float4 *>(phi + (int64_t)ids[s + 1] * 64 + row);
+        q[u] = *reinterpret_cast<const float4 *>(phi + (int64_t)ids[s + 2] * 64 + row);
+    }
+#pragma unroll
+    for (int u = 0; u < kSteps; ++u) {
+        const int r = lane + 64 * u;
+        if (r < kRows) {
+            float *d = f + kWin * r;
+            d[0] = m[u].x;
+            d[1] = m[u].y;
+            d[2] = c[u].x;
+            d[3] = c[u].y;
+            d[4] = c[u].z;
+            d[5] = c[u].w;
+            d[6] = q[u].x;
+            d[7] = q[u].y;
+            d[8] = q[u].z;
+        }
     }
 }
 
@@ -100,16 +171,17 @@ __global__ __launch_bounds__(256) void integrals_plain_kernel(const float *__res
                                                               float *__restrict__ out) {
     __shared__ float s_phi[4][kWinN];
     __shared__ __align__(16) float s_v[4][kVWinN];
+    __shared__ uint16_t s_cut[4][kVolN + 1];
     __shared__ uint32_t s_ids[4][27];
-    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
     const int64_t ci = (int64_t)blockIdx.x * 4 + w;
     if (ci >= n) return;
     const int64_t p = FIELD ? ci + 2 : (int64_t)list[ci];
     if (lane < 27) s_ids[w][lane] = nbr[p * 27 + lane];
     __builtin_amdgcn_wave_barrier();
-    sgrid::stage_window_part<64>(phi, s_ids[w], lane, s_phi[w]);
+    stage_window_rows(phi, s_ids[w], lane, s_phi[w]);
     __builtin_amdgcn_wave_barrier();
-    window_fractions(s_phi[w], lane, inv_h, inv_2h, s_v[w]);
+    window_fractions(s_phi[w], lane, inv_h, inv_2h, s_v[w], s_cut[w]);
     __builtin_amdgcn_wave_barrier();
     const int i = lane & 3, j = (lane >> 2) & 3, k = lane >> 4;
     float kw, kx, ky, kz;
