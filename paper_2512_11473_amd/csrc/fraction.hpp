@@ -62,6 +62,16 @@ __device__ __forceinline__ float plane_cube_fraction(float a, float gx, float gy
     return flip ? 1.0f - vb : vb;
 }
 
+// Saturation: the plane lies beyond the cell, |a| > 0.51 |g|_1 (|g|_1 / 2 is
+// its reach over the cell; the extra 2 % covers the rounding of the fraction's
+// normalisation, 1 ulp in the reciprocal and in the product), so
+// plane_cube_fraction returns exactly 1 or 0 there, by the sign of a.  NaN and
+// huge gradients are not saturated.
+__device__ __forceinline__ bool fraction_saturated(float a, float gx, float gy, float gz) {
+    const float s1 = fabsf(gx) + fabsf(gy) + fabsf(gz);
+    return fabsf(a) > 0.51f * s1 && s1 < 1e30f;
+}
+
 }  // namespace sgrid
 
 namespace sgrid {
@@ -76,6 +86,54 @@ __host__ __device__ __forceinline__ double wendland_u(double r) {
 __host__ __device__ __forceinline__ double wendland_dr_over_r_u(double r) {
     const double e = 1.0 - 0.5 * r;
     return -105.0 / (16.0 * M_PI) * e * e * e;
+}
+
+// The 32 taps of the dual-cell query of data point (i, j, k), over cut
+// fractions V(x, y, z) (x, y, z the window points i - 1 .. i + 2 etc.): K_W
+// and the three K_grad sums.  A tap at offset o in {-1, 0, 1, 2}^3 has d =
+// (1/2, 1/2, 1/2) - o, |d|^2 < 4, weight W(|d|) and gradient weight W'(|d|) /
+// |d| * d.  The taps form four 2 x 2 x 2 blocks: the eight nearest (|d| =
+// sqrt(3)/2, o in {0, 1}^3) and, per axis, the eight with that offset in
+// {-1, 2} and the others in {0, 1} (|d| = sqrt(11)/2); inside a block each
+// weight is constant and each gradient weight takes two values of opposite
+// sign per axis, so a block contributes its sum and its three
+// half-differences.  V is called once per tap.  Every path that sums taps
+// (plain, factorised, fallback, saturated points of the learned path) uses
+// this, so they agree bit for bit wherever their fractions do.
+struct TapBlock {
+    float t, dx, dy, dz;
+};
+template <class VF>
+__device__ __forceinline__ TapBlock tap_block(const VF &V, int x, int y, int z, int sx, int sy, int sz) {
+    // v[a][b][c] at (x + a sx, y + b sy, z + c sz), slot 0 on the + side of d
+    const float v000 = V(x, y, z), v001 = V(x, y, z + sz);
+    const float v010 = V(x, y + sy, z), v011 = V(x, y + sy, z + sz);
+    const float v100 = V(x + sx, y, z), v101 = V(x + sx, y, z + sz);
+    const float v110 = V(x + sx, y + sy, z), v111 = V(x + sx, y + sy, z + sz);
+    const float c00 = v000 + v001, c01 = v010 + v011, c10 = v100 + v101, c11 = v110 + v111;
+    const float x0 = c00 + c01, x1 = c10 + c11;
+    TapBlock b;
+    b.t = x0 + x1;
+    b.dx = x0 - x1;
+    b.dy = (c00 + c10) - (c01 + c11);
+    b.dz = ((v000 + v010) + (v100 + v110)) - ((v001 + v011) + (v101 + v111));
+    return b;
+}
+template <class VF>
+__device__ __forceinline__ void tap_sums(const VF &V, int i, int j, int k, float &kw, float &kx, float &ky,
+                                         float &kz) {
+    const float Wn = (float)wendland_u(sqrt(0.75)), Wf = (float)wendland_u(sqrt(2.75));
+    const float Dn = (float)(0.5 * wendland_dr_over_r_u(sqrt(0.75)));
+    const float Dh = (float)(0.5 * wendland_dr_over_r_u(sqrt(2.75)));   // far taps, the +-1/2 components
+    const float Dw = (float)(1.5 * wendland_dr_over_r_u(sqrt(2.75)));   // far taps, the +-3/2 component
+    const TapBlock n = tap_block(V, i, j, k, 1, 1, 1);
+    const TapBlock fx = tap_block(V, i - 1, j, k, 3, 1, 1);
+    const TapBlock fy = tap_block(V, i, j - 1, k, 1, 3, 1);
+    const TapBlock fz = tap_block(V, i, j, k - 1, 1, 1, 3);
+    kw = Wn * n.t + Wf * ((fx.t + fy.t) + fz.t);
+    kx = Dn * n.dx + (Dw * fx.dx + Dh * (fy.dx + fz.dx));
+    ky = Dn * n.dy + (Dw * fy.dy + Dh * (fx.dy + fz.dy));
+    kz = Dn * n.dz + (Dw * fz.dz + Dh * (fx.dz + fy.dz));
 }
 
 }  // namespace sgrid

@@ -28,50 +28,10 @@ using sgrid::wendland_dr_over_r_u;
 constexpr int kVRow = 8, kVPlane = 60, kVWinN = kVol * kVPlane;
 __device__ __forceinline__ int vidx(int x, int y, int z) { return (x & 7) + kVRow * (y + 1) + kVPlane * (z + 1); }
 
-// One 2 x 2 x 2 block of taps, v[a][b][c] at offsets (a, b, c) along x, y, z
-// from the block's first corner, slot 0 on the + side of the query point:
-// the block's sum and its three signed half-differences.
-struct Block {
-    float t, dx, dy, dz;
-};
-__device__ __forceinline__ Block block_sums(const float *V, int x, int y, int z, int sx, int sy, int sz) {
-    const float v000 = V[vidx(x, y, z)], v001 = V[vidx(x, y, z + sz)];
-    const float v010 = V[vidx(x, y + sy, z)], v011 = V[vidx(x, y + sy, z + sz)];
-    const float v100 = V[vidx(x + sx, y, z)], v101 = V[vidx(x + sx, y, z + sz)];
-    const float v110 = V[vidx(x + sx, y + sy, z)], v111 = V[vidx(x + sx, y + sy, z + sz)];
-    const float c00 = v000 + v001, c01 = v010 + v011, c10 = v100 + v101, c11 = v110 + v111;
-    const float x0 = c00 + c01, x1 = c10 + c11;
-    Block b;
-    b.t = x0 + x1;
-    b.dx = x0 - x1;
-    b.dy = (c00 + c10) - (c01 + c11);
-    b.dz = ((v000 + v010) + (v100 + v110)) - ((v001 + v011) + (v101 + v111));
-    return b;
-}
-
-// The 32 taps of the dual-cell query of point (i, j, k) over the cut
-// fractions V: K_W and the three K_grad sums.  A tap at offset o in
-// {-1, 0, 1, 2}^3 has d = (1/2, 1/2, 1/2) - o, |d|^2 < 4, weight W(|d|) and
-// gradient weight W'(|d|) / |d| * d.  The taps form four 2 x 2 x 2 blocks:
-// the eight nearest (|d| = sqrt(3)/2, o in {0, 1}^3) and, per axis, the eight
-// with that offset in {-1, 2} and the others in {0, 1} (|d| = sqrt(11)/2);
-// inside a block each weight is constant and each gradient weight takes two
-// values of opposite sign per axis, so a block contributes its sum and its
-// three half-differences.
+// The 32 taps of data point (i, j, k) over the LDS window of cut fractions.
 __device__ __forceinline__ void tap_sums(const float *V, int i, int j, int k, float &kw, float &kx, float &ky,
                                          float &kz) {
-    const float Wn = (float)wendland_u(sqrt(0.75)), Wf = (float)wendland_u(sqrt(2.75));
-    const float Dn = (float)(0.5 * wendland_dr_over_r_u(sqrt(0.75)));
-    const float Dh = (float)(0.5 * wendland_dr_over_r_u(sqrt(2.75)));   // far taps, the +-1/2 components
-    const float Dw = (float)(1.5 * wendland_dr_over_r_u(sqrt(2.75)));   // far taps, the +-3/2 component
-    const Block n = block_sums(V, i, j, k, 1, 1, 1);
-    const Block fx = block_sums(V, i - 1, j, k, 3, 1, 1);
-    const Block fy = block_sums(V, i, j - 1, k, 1, 3, 1);
-    const Block fz = block_sums(V, i, j, k - 1, 1, 1, 3);
-    kw = Wn * n.t + Wf * ((fx.t + fy.t) + fz.t);
-    kx = Dn * n.dx + (Dw * fx.dx + Dh * (fy.dx + fz.dx));
-    ky = Dn * n.dy + (Dw * fy.dy + Dh * (fx.dy + fz.dy));
-    kz = Dn * n.dz + (Dw * fz.dz + Dh * (fx.dz + fy.dz));
+    sgrid::tap_sums([V](int x, int y, int z) { return V[vidx(x, y, z)]; }, i, j, k, kw, kx, ky, kz);
 }
 
 // The cut fractions of the 7^3 points -1..5 of a package from its staged
@@ -79,10 +39,8 @@ __device__ __forceinline__ void tap_sums(const float *V, int i, int j, int k, fl
 // cell (in the 1-norm of its gradient) from the surface has V = 0 or 1 by the
 // sign of phi; the cut points are listed (ballot, in LDS) and evaluated one
 // per lane afterwards, so the case code runs once per 64 cut points rather
-// than once per 64 window points.  The test |a| > 0.51 |g|_1 leaves a margin
-// over the rounding of the fraction's own normalisation, so the value of a
-// listed-out point is the one the fraction returns; NaN or huge inputs are
-// listed.
+// than once per 64 window points.  A saturated point's value is the one the
+// fraction returns (see fraction_saturated).
 __device__ __forceinline__ void window_fractions(const float *f, int lane, float inv_h, float inv_2h, float *V,
                                                  uint16_t *cut_list) {
     const uint64_t below = (1ull << lane) - 1ull;
@@ -97,8 +55,7 @@ __device__ __forceinline__ void window_fractions(const float *f, int lane, float
         const float gx = (f[c + 1] - f[c - 1]) * inv_2h;
         const float gy = (f[c + kWin] - f[c - kWin]) * inv_2h;
         const float gz = (f[c + kWin * kWin] - f[c - kWin * kWin]) * inv_2h;
-        const float s1 = fabsf(gx) + fabsf(gy) + fabsf(gz);
-        const bool sat = fabsf(a) > 0.51f * s1 && s1 < 1e30f;
+        const bool sat = sgrid::fraction_saturated(a, gx, gy, gz);
         if (v < kVolN && sat) V[vidx(x - 1, y - 1, z - 1)] = a > 0.0f ? 1.0f : 0.0f;
         const bool cut = v < kVolN && !sat;
         const uint64_t m = __ballot(cut);

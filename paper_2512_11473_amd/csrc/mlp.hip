@@ -680,7 +680,7 @@ struct WindowX {
 };
 
 // Saturation of the cut fraction at the 7^3 tap points: bit 0 = V in {0, 1}
-// (|phi/h| >= |g|_1 / 2 with phi != 0), bit 1 = phi > 0.
+// (fraction_saturated), bit 1 = phi > 0.
 __device__ __forceinline__ void saturation_flags(const float *f, float inv_h, float inv_2h, uint8_t *s_sat) {
     for (int v = threadIdx.x; v < kVolN; v += blockDim.x) {
         const int x = v % kVol + 1, y = (v / kVol) % kVol + 1, z = v / (kVol * kVol) + 1;
@@ -689,40 +689,9 @@ __device__ __forceinline__ void saturation_flags(const float *f, float inv_h, fl
         const float gy = (f[c + kWin] - f[c - kWin]) * inv_2h;
         const float gz = (f[c + kWin * kWin] - f[c - kWin * kWin]) * inv_2h;
         const float a = f[c] * inv_h;
-        const bool sat = a != 0.f && fabsf(a) >= 0.5f * (fabsf(gx) + fabsf(gy) + fabsf(gz));
+        const bool sat = sgrid::fraction_saturated(a, gx, gy, gz);
         s_sat[v] = (uint8_t)((sat ? 1 : 0) | (a > 0.f ? 2 : 0));
     }
-}
-
-struct Taps {
-    float Wn, Wf, Dn, Df;
-};
-
-// The 32 taps of a point's query: offsets o in {-1, 0, 1, 2}^3 with
-// |(1/2, 1/2, 1/2) - o| < 2, in the order oz, oy, ox.
-struct TapOffset {
-    int x, y, z;
-};
-constexpr int tap_r2x4(int ox, int oy, int oz) {   // 4 |(1/2, 1/2, 1/2) - o|^2
-    return (1 - 2 * ox) * (1 - 2 * ox) + (1 - 2 * oy) * (1 - 2 * oy) + (1 - 2 * oz) * (1 - 2 * oz);
-}
-struct TapTable {
-    TapOffset t[32];
-    constexpr TapTable() : t() {
-        int n = 0;
-        for (int oz = -1; oz <= 2; ++oz)
-            for (int oy = -1; oy <= 2; ++oy)
-                for (int ox = -1; ox <= 2; ++ox)
-                    if (tap_r2x4(ox, oy, oz) < 16) t[n++] = TapOffset{ox, oy, oz};
-    }
-};
-constexpr TapTable kTapTable{};
-constexpr const TapOffset *kTapOffsets = kTapTable.t;
-static_assert(tap_r2x4(-1, 0, 0) == 11 && kTapTable.t[31].z == 2, "tap table");
-
-__device__ __forceinline__ Taps make_taps() {
-    return Taps{(float)sgrid::wendland_u(sqrt(0.75)), (float)sgrid::wendland_u(sqrt(2.75)),
-                (float)sgrid::wendland_dr_over_r_u(sqrt(0.75)), (float)sgrid::wendland_dr_over_r_u(sqrt(2.75))};
 }
 
 __global__ __launch_bounds__(256) void zero_u32_kernel(uint32_t *p) { *p = 0u; }
@@ -732,7 +701,7 @@ __global__ __launch_bounds__(64) void add_u32_kernel(uint32_t *total, const uint
 // four wavefronts.
 //  1. Each package's 128 lanes stage its 9^3 window, the saturation flags of
 //     the 7^3 tap points and the BF16 hi + lo parts of the network inputs.
-//  2. Two lanes per point sum the 32 taps' saturated fractions.  A point
+//  2. One lane per point sums the 32 taps' saturated fractions.  A point
 //     whose taps are all saturated takes that exact sum (the plain value);
 //     the others are listed, in LDS, for the network.
 //  3. The listed points go through the network in 16-point MFMA tiles, tile
@@ -904,7 +873,7 @@ __global__ __launch_bounds__(256, 3) void learned_kernel(MlpDev W, const float *
         const float gy = (L.phi[c + kWin] - L.phi[c - kWin]) * inv_2h;
         const float gz = (L.phi[c + kWin * kWin] - L.phi[c - kWin * kWin]) * inv_2h;
         const float a = L.phi[c] * inv_h;
-        const bool sat = a != 0.f && fabsf(a) >= 0.5f * (fabsf(gx) + fabsf(gy) + fabsf(gz));
+        const bool sat = sgrid::fraction_saturated(a, gx, gy, gz);
         L.sat[v] = (uint8_t)((sat ? 1 : 0) | (a > 0.f ? 2 : 0));
     }
     for (int v = t128; v < kWinN; v += 128) {   // the network inputs, once per window value
@@ -915,37 +884,22 @@ __global__ __launch_bounds__(256, 3) void learned_kernel(MlpDev W, const float *
     }
     __syncthreads();
     const int64_t stride = n_core * 64;
-    // 2. exact sums of saturated points; two lanes per point, lane `part`
-    // takes the taps 2i + part of the 32 (in the order oz, oy, ox), chosen by
-    // a select of constants rather than a branch
-    {
-        const Taps tp = make_taps();
-        const int c = t128 >> 1, part = t128 & 1;
-        const int ci_ = c & 3, cj = (c >> 2) & 3, ck = c >> 4;
+    // 2. saturated points: one lane per point (the first 64 of each
+    // package's 128) sums its 32 taps' fractions, 1 or 0 by the sign of phi,
+    // with the plain kernels' tap sums, so the value is the plain one bit for
+    // bit; a point with a cut tap is listed
+    if (t128 < 64) {
+        const int c = t128;
         bool sat = true;
-        float kw = 0.f, kx = 0.f, ky = 0.f, kz = 0.f;
-#pragma unroll
-        for (int i = 0; i < 16; ++i) {
-            const TapOffset a = kTapOffsets[2 * i], b = kTapOffsets[2 * i + 1];
-            const int ox = part ? b.x : a.x, oy = part ? b.y : a.y, oz = part ? b.z : a.z;
-            const float dx = 0.5f - ox, dy = 0.5f - oy, dz = 0.5f - oz;
-            const uint8_t f = L.sat[(ci_ + ox + 1) + kVol * ((cj + oy + 1) + kVol * (ck + oz + 1))];
-            sat = sat && (f & 1);
-            const float vv = (f & 2) ? 1.f : 0.f;
-            const bool nearp = dx * dx + dy * dy + dz * dz < 1.0f;
-            const float Wt = nearp ? tp.Wn : tp.Wf, Dt = nearp ? tp.Dn : tp.Df;
-            kw += Wt * vv;
-            kx += Dt * dx * vv;
-            ky += Dt * dy * vv;
-            kz += Dt * dz * vv;
-        }
-        kw += __shfl_xor(kw, 1);
-        kx += __shfl_xor(kx, 1);
-        ky += __shfl_xor(ky, 1);
-        kz += __shfl_xor(kz, 1);
-        const int other = __shfl_xor(sat ? 1 : 0, 1);
-        sat = sat && other != 0;
-        if (live && part == 0) {
+        float kw, kx, ky, kz;
+        sgrid::tap_sums(
+            [&](int x, int y, int z) {
+                const uint8_t f = L.sat[(x + 1) + kVol * ((y + 1) + kVol * (z + 1))];
+                sat = sat && (f & 1);
+                return (f & 2) ? 1.f : 0.f;
+            },
+            c & 3, (c >> 2) & 3, c >> 4, kw, kx, ky, kz);
+        if (live) {
             if (sat) {
                 const int64_t o = ci * 64 + c;
                 out[o] = kw;
@@ -1037,39 +991,28 @@ __global__ __launch_bounds__(256, 3) void learned_kernel(MlpDev W, const float *
 
 // Plain integral of single cells (the fallback): the 32 taps of the cell's
 // dual-cell query, each with its own cut fraction from central differences,
-// in the same arithmetic and summation order as the plain package kernel.
+// with the plain kernels' fractions and tap sums, so the value is the plain
+// one bit for bit.
 __device__ __forceinline__ void fallback_point(const float *__restrict__ phi, const uint32_t *__restrict__ nbr,
                                                const uint32_t *__restrict__ core_list, int64_t n_core, float inv_h,
                                                float inv_2h, int64_t o, float *__restrict__ out) {
     const int64_t ci = o / 64;
     const int c = (int)(o % 64);
-    const int i = c & 3, j = (c >> 2) & 3, k = c >> 4;
     const uint32_t *row = nbr + (int64_t)core_list[ci] * 27;
     auto at = [&](int x, int y, int z) -> float {   // local shift in [-2, 6] per axis
         const int kx = (x + 4) >> 2, ky = (y + 4) >> 2, kz = (z + 4) >> 2;
         const int d = (x + 4 - 4 * kx) + 4 * (y + 4 - 4 * ky) + 16 * (z + 4 - 4 * kz);
         return phi[(int64_t)row[kx + 3 * ky + 9 * kz] * 64 + d];
     };
-    const Taps tp = make_taps();
-    float kw = 0.f, kx = 0.f, ky = 0.f, kz = 0.f;
-    for (int oz = -1; oz <= 2; ++oz)
-        for (int oy = -1; oy <= 2; ++oy)
-            for (int ox = -1; ox <= 2; ++ox) {
-                const float dx = 0.5f - ox, dy = 0.5f - oy, dz = 0.5f - oz;
-                const float r2 = dx * dx + dy * dy + dz * dz;
-                if (r2 >= 4.0f) continue;
-                const int x = i + ox, y = j + oy, z = k + oz;
-                const float gx = (at(x + 1, y, z) - at(x - 1, y, z)) * inv_2h;
-                const float gy = (at(x, y + 1, z) - at(x, y - 1, z)) * inv_2h;
-                const float gz = (at(x, y, z + 1) - at(x, y, z - 1)) * inv_2h;
-                const float vv = sgrid::plane_cube_fraction(at(x, y, z) * inv_h, gx, gy, gz);
-                const bool nearp = r2 < 1.0f;
-                const float Wt = nearp ? tp.Wn : tp.Wf, Dt = nearp ? tp.Dn : tp.Df;
-                kw += Wt * vv;
-                kx += Dt * dx * vv;
-                ky += Dt * dy * vv;
-                kz += Dt * dz * vv;
-            }
+    float kw, kx, ky, kz;
+    sgrid::tap_sums(
+        [&](int x, int y, int z) {
+            const float gx = (at(x + 1, y, z) - at(x - 1, y, z)) * inv_2h;
+            const float gy = (at(x, y + 1, z) - at(x, y - 1, z)) * inv_2h;
+            const float gz = (at(x, y, z + 1) - at(x, y, z - 1)) * inv_2h;
+            return sgrid::plane_cube_fraction(at(x, y, z) * inv_h, gx, gy, gz);
+        },
+        c & 3, (c >> 2) & 3, c >> 4, kw, kx, ky, kz);
     const int64_t stride = n_core * 64;
     out[o] = kw;
     out[stride + o] = kx;

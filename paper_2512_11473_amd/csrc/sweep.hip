@@ -619,17 +619,14 @@ __global__ __launch_bounds__(256) void cut_fraction_kernel(const float *__restri
             }
         }
     }
-    // |a| > 0.51 |g|_1 puts the plane beyond the cell by a margin that covers
-    // the rounding of the fraction's own normalisation, so there V is exactly
-    // what the fraction returns (1 or 0 by the sign of a); NaN / huge inputs
-    // take the full evaluation
+    // a saturated point's V is what the fraction returns, 1 or 0 by the sign
+    // of a (see fraction_saturated)
     bool cut[4];
     int n_cut = 0, slot[4];
     const uint64_t below = (1ull << lane) - 1ull;
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-        const float s1 = fabsf(gx[i]) + fabsf(gy[i]) + fabsf(gz[i]);
-        cut[i] = live && !(fabsf(a[i]) > 0.51f * s1 && s1 < 1e30f);
+        cut[i] = live && !sgrid::fraction_saturated(a[i], gx[i], gy[i], gz[i]);
         const uint64_t m = __ballot(cut[i]);
         slot[i] = n_cut + (int)__popcll(m & below);
         n_cut += (int)__popcll(m);
