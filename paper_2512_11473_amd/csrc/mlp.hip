@@ -725,16 +725,40 @@ struct LearnLds {
     uint8_t sat[kVolN + 13];
 };
 
+// Layer 1's weights pass through LDS, one 32-input slice of W1 (128 rows x 32
+// BF16, 8 KB) per step, double-buffered in the activation area (free until
+// layer 1 ends), so the workgroup's four wavefronts read each slice from L2
+// once instead of four times.  Rows are padded to kW1Row BF16.
+constexpr int kW1Row = 40;
+constexpr int kW1Slice = kH * kW1Row;   // BF16 per buffered slice
+constexpr int kW1Steps = kInPad / 32;
+
+// Thread tid's share of W1 slice s: row tid / 2, inputs 32 s + 16 (tid % 2) .. + 15.
+struct W1Part {
+    bf16x8 a, b;
+};
+__device__ __forceinline__ W1Part w1_load(const MlpDev &W, int s, int tid) {
+    const bf16 *src = W.w1b + (tid >> 1) * kInPad + 32 * s + 16 * (tid & 1);
+    return W1Part{ld8(src), ld8(src + 8)};
+}
+__device__ __forceinline__ void w1_store(bf16 *buf, const W1Part &v, int tid) {
+    bf16 *dst = buf + (tid >> 1) * kW1Row + 16 * (tid & 1);
+    *reinterpret_cast<bf16x8 *>(dst) = v.a;
+    *reinterpret_cast<bf16x8 *>(dst + 8) = v.b;
+}
+
 // The network over the listed points of TILES tiles (rows 16 tile + r of the
 // list): layer outputs through the wavefront's own activation rows, the
-// outputs y to s_y[row][4].
+// outputs y to s_y[row][4].  Every wavefront of the workgroup calls it (TILES
+// = 0 for one without tiles: it helps stage W1 and meets the barriers).
 template <int TILES>
 __device__ __forceinline__ void learned_network(const MlpDev &W, const LearnLds *lds, const int16_t *s_off,
                                                 const uint8_t *s_list, int n_list, const int tile[2], bf16 *s_act,
                                                 float *s_y, int lane) {
-    const int r = lane & 15, q = lane >> 4;
-    int base[TILES];
-    const LearnLds *win[TILES];
+    const int r = lane & 15, q = lane >> 4, tid = threadIdx.x;
+    constexpr int NT = TILES > 0 ? TILES : 1;
+    int base[NT];
+    const LearnLds *win[NT];
 #pragma unroll
     for (int m = 0; m < TILES; ++m) {
         const int row = 16 * tile[m] + r;
@@ -745,40 +769,48 @@ __device__ __forceinline__ void learned_network(const MlpDev &W, const LearnLds 
     }
     // layer 1: [16 x 224] (hi + lo BF16 parts of phi / h) x W1^T per tile;
     // accumulators start from the biases, as in forward_tile
-    floatx4 acc[TILES][8];
+    floatx4 acc[NT][8];
 #pragma unroll
     for (int t = 0; t < 8; ++t) {
         const float bb = W.w[oB1 + 16 * t + r];
 #pragma unroll
         for (int m = 0; m < TILES; ++m) acc[m][t] = floatx4{bb, bb, bb, bb};
     }
-    // the weight fragments of step s + 1 load while step s multiplies
-    bf16x8 bw[8], bn[8];
-#pragma unroll
-    for (int t = 0; t < 8; ++t) bn[t] = ld8(W.w1b + (16 * t + r) * kInPad + 8 * q);
-    for (int s = 0; s < kInPad / 32; ++s) {
-#pragma unroll
-        for (int t = 0; t < 8; ++t) bw[t] = bn[t];
-        if (s + 1 < kInPad / 32) {
-#pragma unroll
-            for (int t = 0; t < 8; ++t) bn[t] = ld8(W.w1b + (16 * t + r) * kInPad + 32 * (s + 1) + 8 * q);
+    // slice s + 1 is stored at the start of step s (its buffer was last read in
+    // step s - 1, which ended with a barrier) and slice s + 2 loads meanwhile
+    W1Part part = w1_load(W, 0, tid);
+    w1_store(s_act, part, tid);
+    part = w1_load(W, 1, tid);
+    __syncthreads();
+    for (int s = 0; s < kW1Steps; ++s) {
+        if (s + 1 < kW1Steps) {
+            w1_store(s_act + ((s + 1) & 1) * kW1Slice, part, tid);
+            if (s + 2 < kW1Steps) part = w1_load(W, s + 2, tid);
         }
+        if (TILES > 0) {
+            const bf16 *wb = s_act + (s & 1) * kW1Slice;
+            bf16x8 bw[8];
 #pragma unroll
-        for (int m = 0; m < TILES; ++m) {
-            bf16x8 ah, al;
+            for (int t = 0; t < 8; ++t) bw[t] = ld8(wb + (16 * t + r) * kW1Row + 8 * q);
 #pragma unroll
-            for (int e = 0; e < 8; ++e) {
-                const int off = base[m] + s_off[32 * s + 8 * q + e];
-                ah[e] = win[m]->xh[off];
-                al[e] = win[m]->xl[off];
-            }
+            for (int m = 0; m < TILES; ++m) {
+                bf16x8 ah, al;
 #pragma unroll
-            for (int t = 0; t < 8; ++t) {
-                acc[m][t] = mfma(ah, bw[t], acc[m][t]);
-                acc[m][t] = mfma(al, bw[t], acc[m][t]);
+                for (int e = 0; e < 8; ++e) {
+                    const int off = base[m] + s_off[32 * s + 8 * q + e];
+                    ah[e] = win[m]->xh[off];
+                    al[e] = win[m]->xl[off];
+                }
+#pragma unroll
+                for (int t = 0; t < 8; ++t) {
+                    acc[m][t] = mfma(ah, bw[t], acc[m][t]);
+                    acc[m][t] = mfma(al, bw[t], acc[m][t]);
+                }
             }
         }
+        __syncthreads();
     }
+    if (TILES == 0) return;
 #pragma unroll
     for (int t = 0; t < 8; ++t)
 #pragma unroll
@@ -813,7 +845,7 @@ __device__ __forceinline__ void learned_network(const MlpDev &W, const LearnLds 
             for (int i = 0; i < 4; ++i)
                 s_act[(16 * tile[m] + 4 * q + i) * kActStride + 16 * t + r] = (bf16)gelu(acc[m][t][i]);
     // layer 3
-    floatx4 y[TILES];
+    floatx4 y[NT];
     const float b3 = r < kOut ? W.w[oB3 + r] : 0.f;
 #pragma unroll
     for (int m = 0; m < TILES; ++m) y[m] = floatx4{b3, b3, b3, b3};
@@ -916,12 +948,15 @@ __global__ __launch_bounds__(256, 3) void learned_kernel(MlpDev W, const float *
     const int n_tiles = (n_list + 15) / 16;
     const int tile[2] = {w, w + 4};
     const int mine = (w < n_tiles ? 1 : 0) + (w + 4 < n_tiles ? 1 : 0);
-    if (mine == 0) return;
+    if (n_tiles == 0) return;   // the same for the whole workgroup
     // 3. the network over this wavefront's tiles
     if (mine == 2)
         learned_network<2>(W, lds, s_off, s_list, n_list, tile, s_act, s_y, lane);
-    else
+    else if (mine == 1)
         learned_network<1>(W, lds, s_off, s_list, n_list, tile, s_act, s_y, lane);
+    else
+        learned_network<0>(W, lds, s_off, s_list, n_list, tile, s_act, s_y, lane);
+    if (mine == 0) return;
     // 4. the gate of this wavefront's points, two lanes per point: lanes
     // 0..31 the rows of tile w, lanes 32..63 those of tile w + 4.
     // Non-planarity: mean squared residual of the window after its
@@ -942,19 +977,22 @@ __global__ __launch_bounds__(256, 3) void learned_kernel(MlpDev W, const float *
     const LearnLds &Lp = lds[pt >> 6];
     const int c = pt & 63;
     const int ci_ = c & 3, cj = (c >> 2) & 3, ck = c >> 4;
+    // (per window row: its sum and its x moment, then the row's share of the
+    // y and z moments from its sum)
     float s0 = 0.f, sx = 0.f, sy = 0.f, sz = 0.f;
 #pragma unroll 1
     for (int i = 0; i < 18; ++i) {
         const int ez = (2 * i) / 6, ey = (2 * i) % 6 + part;
         const float *wrow = Lp.phi + ci_ + kWin * ((cj + ey) + kWin * (ck + ez));
+        float v[6];
 #pragma unroll
-        for (int ex = 0; ex < 6; ++ex) {
-            const float v = wrow[ex];
-            s0 += v;
-            sx += (ex - 2.5f) * v;
-            sy += (ey - 2.5f) * v;
-            sz += (ez - 2.5f) * v;
-        }
+        for (int ex = 0; ex < 6; ++ex) v[ex] = wrow[ex];
+        const float r0 = ((v[0] + v[1]) + (v[2] + v[3])) + (v[4] + v[5]);
+        const float rx = 2.5f * (v[5] - v[0]) + (1.5f * (v[4] - v[1]) + 0.5f * (v[3] - v[2]));
+        s0 += r0;
+        sx += rx;
+        sy += (ey - 2.5f) * r0;
+        sz += (ez - 2.5f) * r0;
     }
     s0 += __shfl_xor(s0, 1);
     sx += __shfl_xor(sx, 1);

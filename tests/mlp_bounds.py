@@ -162,8 +162,11 @@ def nonplanarity_f64(x):
 def nonplanarity_f32_bound(x):
     """Bound of the FP32 evaluation error of the kernel's non-planarity: the
     fit's coefficients c0 = s0 / 216 and c_a = s_a / 630 from moments summed
-    over 108 terms per lane and two lanes combined, then the explicit sum of
-    squared residuals r_i = v_i - (c0 + c . o_i) in a second pass.
+    per window row (six values: the row sum and its x moment, at most five
+    roundings each) and then over 18 rows per lane, two lanes combined (at
+    most 25 roundings in a chain, so within the 110 used below), then the
+    explicit sum of squared residuals r_i = v_i - (c0 + c . o_i) in a second
+    pass.
 
     With p~_i the plane through the computed coefficients, the computed sum
     is sum (r_i + e_i)^2 up to the rounding of the sum, where e_i is the
