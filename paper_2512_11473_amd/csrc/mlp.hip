@@ -725,24 +725,27 @@ struct LearnLds {
     uint8_t sat[kVolN + 13];
 };
 
-// Layer 1's weights pass through LDS, one 32-input slice of W1 (128 rows x 32
-// BF16, 8 KB) per step, double-buffered in the activation area (free until
-// layer 1 ends), so the workgroup's four wavefronts read each slice from L2
-// once instead of four times.  Rows are padded to kW1Row BF16.
-constexpr int kW1Row = 40;
-constexpr int kW1Slice = kH * kW1Row;   // BF16 per buffered slice
-constexpr int kW1Steps = kInPad / 32;
+// The weights of layers 1 and 2 pass through LDS, one 32-input slice (128
+// rows x 32 BF16, 8 KB) per step, so the workgroup's four wavefronts read each
+// slice from L2 once instead of four times.  W1's slices are double-buffered
+// in the activation area (free until layer 1 ends); W2's go, one at a time,
+// where the windows were (free once every wavefront has evaluated its gate
+// and passed layer 1).  Rows are padded to kWRow BF16.
+constexpr int kWRow = 40;
+constexpr int kWSlice = kH * kWRow;   // BF16 per buffered slice
+constexpr int kW1Steps = kInPad / 32, kW2Steps = kH / 32;
 
-// Thread tid's share of W1 slice s: row tid / 2, inputs 32 s + 16 (tid % 2) .. + 15.
-struct W1Part {
+// Thread tid's share of slice s of a [128][row_len] weight matrix: row
+// tid / 2, inputs 32 s + 16 (tid % 2) .. + 15.
+struct WPart {
     bf16x8 a, b;
 };
-__device__ __forceinline__ W1Part w1_load(const MlpDev &W, int s, int tid) {
-    const bf16 *src = W.w1b + (tid >> 1) * kInPad + 32 * s + 16 * (tid & 1);
-    return W1Part{ld8(src), ld8(src + 8)};
+__device__ __forceinline__ WPart w_load(const bf16 *w, int row_len, int s, int tid) {
+    const bf16 *src = w + (tid >> 1) * row_len + 32 * s + 16 * (tid & 1);
+    return WPart{ld8(src), ld8(src + 8)};
 }
-__device__ __forceinline__ void w1_store(bf16 *buf, const W1Part &v, int tid) {
-    bf16 *dst = buf + (tid >> 1) * kW1Row + 16 * (tid & 1);
+__device__ __forceinline__ void w_store(bf16 *buf, const WPart &v, int tid) {
+    bf16 *dst = buf + (tid >> 1) * kWRow + 16 * (tid & 1);
     *reinterpret_cast<bf16x8 *>(dst) = v.a;
     *reinterpret_cast<bf16x8 *>(dst + 8) = v.b;
 }
@@ -750,9 +753,10 @@ __device__ __forceinline__ void w1_store(bf16 *buf, const W1Part &v, int tid) {
 // The network over the listed points of TILES tiles (rows 16 tile + r of the
 // list): layer outputs through the wavefront's own activation rows, the
 // outputs y to s_y[row][4].  Every wavefront of the workgroup calls it (TILES
-// = 0 for one without tiles: it helps stage W1 and meets the barriers).
+// = 0 for one without tiles: it helps stage the weights and meets the
+// barriers), after its gate.
 template <int TILES>
-__device__ __forceinline__ void learned_network(const MlpDev &W, const LearnLds *lds, const int16_t *s_off,
+__device__ __forceinline__ void learned_network(const MlpDev &W, LearnLds *lds, const int16_t *s_off,
                                                 const uint8_t *s_list, int n_list, const int tile[2], bf16 *s_act,
                                                 float *s_y, int lane) {
     const int r = lane & 15, q = lane >> 4, tid = threadIdx.x;
@@ -778,20 +782,20 @@ __device__ __forceinline__ void learned_network(const MlpDev &W, const LearnLds 
     }
     // slice s + 1 is stored at the start of step s (its buffer was last read in
     // step s - 1, which ended with a barrier) and slice s + 2 loads meanwhile
-    W1Part part = w1_load(W, 0, tid);
-    w1_store(s_act, part, tid);
-    part = w1_load(W, 1, tid);
+    WPart part = w_load(W.w1b, kInPad, 0, tid);
+    w_store(s_act, part, tid);
+    part = w_load(W.w1b, kInPad, 1, tid);
     __syncthreads();
     for (int s = 0; s < kW1Steps; ++s) {
         if (s + 1 < kW1Steps) {
-            w1_store(s_act + ((s + 1) & 1) * kW1Slice, part, tid);
-            if (s + 2 < kW1Steps) part = w1_load(W, s + 2, tid);
+            w_store(s_act + ((s + 1) & 1) * kWSlice, part, tid);
+            if (s + 2 < kW1Steps) part = w_load(W.w1b, kInPad, s + 2, tid);
         }
         if (TILES > 0) {
-            const bf16 *wb = s_act + (s & 1) * kW1Slice;
+            const bf16 *wb = s_act + (s & 1) * kWSlice;
             bf16x8 bw[8];
 #pragma unroll
-            for (int t = 0; t < 8; ++t) bw[t] = ld8(wb + (16 * t + r) * kW1Row + 8 * q);
+            for (int t = 0; t < 8; ++t) bw[t] = ld8(wb + (16 * t + r) * kWRow + 8 * q);
 #pragma unroll
             for (int m = 0; m < TILES; ++m) {
                 bf16x8 ah, al;
@@ -810,7 +814,6 @@ __device__ __forceinline__ void learned_network(const MlpDev &W, const LearnLds 
         }
         __syncthreads();
     }
-    if (TILES == 0) return;
 #pragma unroll
     for (int t = 0; t < 8; ++t)
 #pragma unroll
@@ -818,25 +821,35 @@ __device__ __forceinline__ void learned_network(const MlpDev &W, const LearnLds 
 #pragma unroll
             for (int i = 0; i < 4; ++i)
                 s_act[(16 * tile[m] + 4 * q + i) * kActStride + 16 * t + r] = (bf16)gelu(acc[m][t][i]);
-    // layer 2
+    // layer 2, W2's slices one at a time in the windows' LDS (a wavefront
+    // reads back only activation rows it wrote itself)
+    static_assert(sizeof(LearnLds) * kLearnPkgs >= kWSlice * sizeof(bf16), "W2 slice buffer");
+    bf16 *w2buf = reinterpret_cast<bf16 *>(lds);
 #pragma unroll
     for (int t = 0; t < 8; ++t) {
         const float bb = W.w[oB2 + 16 * t + r];
 #pragma unroll
         for (int m = 0; m < TILES; ++m) acc[m][t] = floatx4{bb, bb, bb, bb};
     }
+    part = w_load(W.w2b, kH, 0, tid);
+    for (int s = 0; s < kW2Steps; ++s) {
+        w_store(w2buf, part, tid);
+        if (s + 1 < kW2Steps) part = w_load(W.w2b, kH, s + 1, tid);
+        __syncthreads();
+        if (TILES > 0) {
+            bf16x8 bv[8];
 #pragma unroll
-    for (int s = 0; s < kH / 32; ++s) {
-        bf16x8 bv[8];
+            for (int t = 0; t < 8; ++t) bv[t] = ld8(w2buf + (16 * t + r) * kWRow + 8 * q);
 #pragma unroll
-        for (int t = 0; t < 8; ++t) bv[t] = ld8(W.w2b + (16 * t + r) * kH + 32 * s + 8 * q);
+            for (int m = 0; m < TILES; ++m) {
+                const bf16x8 a = ld8(s_act + (16 * tile[m] + r) * kActStride + 32 * s + 8 * q);
 #pragma unroll
-        for (int m = 0; m < TILES; ++m) {
-            const bf16x8 a = ld8(s_act + (16 * tile[m] + r) * kActStride + 32 * s + 8 * q);
-#pragma unroll
-            for (int t = 0; t < 8; ++t) acc[m][t] = mfma(a, bv[t], acc[m][t]);
+                for (int t = 0; t < 8; ++t) acc[m][t] = mfma(a, bv[t], acc[m][t]);
+            }
         }
+        __syncthreads();
     }
+    if (TILES == 0) return;
 #pragma unroll
     for (int t = 0; t < 8; ++t)
 #pragma unroll
@@ -871,7 +884,7 @@ __global__ __launch_bounds__(256, 3) void learned_kernel(MlpDev W, const float *
                                                          float tau, float kw_lo, float kw_hi,
                                                          float *__restrict__ out, uint32_t *__restrict__ fb_list,
                                                          uint32_t *__restrict__ fb_count) {
-    __shared__ LearnLds lds[kLearnPkgs];
+    __shared__ __attribute__((aligned(16))) LearnLds lds[kLearnPkgs];   // 16-byte rows of W2 go here later
     // window offset of network input kk (ox + 9 oy + 81 oz); the padding
     // inputs 216..223 meet zero columns of W1, so they read any finite window
     // value (offset 0) and add exactly zero, without a branch per input
@@ -949,16 +962,9 @@ __global__ __launch_bounds__(256, 3) void learned_kernel(MlpDev W, const float *
     const int tile[2] = {w, w + 4};
     const int mine = (w < n_tiles ? 1 : 0) + (w + 4 < n_tiles ? 1 : 0);
     if (n_tiles == 0) return;   // the same for the whole workgroup
-    // 3. the network over this wavefront's tiles
-    if (mine == 2)
-        learned_network<2>(W, lds, s_off, s_list, n_list, tile, s_act, s_y, lane);
-    else if (mine == 1)
-        learned_network<1>(W, lds, s_off, s_list, n_list, tile, s_act, s_y, lane);
-    else
-        learned_network<0>(W, lds, s_off, s_list, n_list, tile, s_act, s_y, lane);
-    if (mine == 0) return;
-    // 4. the gate of this wavefront's points, two lanes per point: lanes
-    // 0..31 the rows of tile w, lanes 32..63 those of tile w + 4.
+    // 3. the gate of this wavefront's points, two lanes per point: lanes
+    // 0..31 the rows of tile w, lanes 32..63 those of tile w + 4 (before the
+    // network, whose second layer reuses the windows' LDS).
     // Non-planarity: mean squared residual of the window after its
     // least-squares affine fit.  The basis 1, ox, oy, oz (offsets centred at
     // 2.5) is orthogonal on the window, so the fit's coefficients are the
@@ -978,10 +984,12 @@ __global__ __launch_bounds__(256, 3) void learned_kernel(MlpDev W, const float *
     const int c = pt & 63;
     const int ci_ = c & 3, cj = (c >> 2) & 3, ck = c >> 4;
     // (per window row: its sum and its x moment, then the row's share of the
-    // y and z moments from its sum)
+    // y and z moments from its sum; a wavefront without points skips both
+    // passes)
+    const int n_rows = mine > 0 ? 18 : 0;
     float s0 = 0.f, sx = 0.f, sy = 0.f, sz = 0.f;
 #pragma unroll 1
-    for (int i = 0; i < 18; ++i) {
+    for (int i = 0; i < n_rows; ++i) {
         const int ez = (2 * i) / 6, ey = (2 * i) % 6 + part;
         const float *wrow = Lp.phi + ci_ + kWin * ((cj + ey) + kWin * (ck + ez));
         float v[6];
@@ -1001,7 +1009,7 @@ __global__ __launch_bounds__(256, 3) void learned_kernel(MlpDev W, const float *
     const float c0 = s0 / 216.f, cx = sx / 630.f, cy = sy / 630.f, cz = sz / 630.f;   // units of phi
     float rr = 0.f;
 #pragma unroll 1
-    for (int i = 0; i < 18; ++i) {
+    for (int i = 0; i < n_rows; ++i) {
         const int ez = (2 * i) / 6, ey = (2 * i) % 6 + part;
         const float *wrow = Lp.phi + ci_ + kWin * ((cj + ey) + kWin * (ck + ez));
         const float pyz = c0 + cy * (ey - 2.5f) + cz * (ez - 2.5f);
@@ -1013,9 +1021,21 @@ __global__ __launch_bounds__(256, 3) void learned_kernel(MlpDev W, const float *
     }
     rr += __shfl_xor(rr, 1);
     const float res = rr * inv_h * inv_h * (1.0f / 216.f);
-    if (valid && part == 0) {
-        const int64_t o = (ci0 + (int64_t)blockIdx.x * kLearnPkgs + (pt >> 6)) * 64 + c;
-        const float *yv = s_y + row * kOut;
+    // 4. the network over this wavefront's tiles (every wavefront takes part)
+    if (mine == 2)
+        learned_network<2>(W, lds, s_off, s_list, n_list, tile, s_act, s_y, lane);
+    else if (mine == 1)
+        learned_network<1>(W, lds, s_off, s_list, n_list, tile, s_act, s_y, lane);
+    else
+        learned_network<0>(W, lds, s_off, s_list, n_list, tile, s_act, s_y, lane);
+    if (mine == 0) return;
+    // 5. the network's value or the fallback list (the point's row and list
+    // entry read again rather than kept across the network)
+    const int row_o = 16 * tile[lane >> 5] + ((lane >> 1) & 15);
+    if (row_o < n_list && (lane & 1) == 0) {
+        const int pt_o = s_list[row_o];
+        const int64_t o = (ci0 + (int64_t)blockIdx.x * kLearnPkgs + (pt_o >> 6)) * 64 + (pt_o & 63);
+        const float *yv = s_y + row_o * kOut;
         if (res <= tau && yv[0] >= kw_lo && yv[0] <= kw_hi) {
             out[o] = yv[0];
             out[stride + o] = yv[1];
