@@ -255,8 +255,13 @@ def test_integrals_factorised_domain_faces(sg):
     t = {k: v.cpu().numpy() for k, v in wl.grid.tables().items()}
     nbr = t["pkg_nbr"].view(np.uint32)
     core = t["core_list"].astype(np.int64)
-    assert np.any(np.any(nbr[core] < 2, axis=1))            # some core windows leave the domain
-    assert np.any(np.all(nbr[core] >= 2, axis=1))           # and some do not
+    edge = np.any(nbr[core] < 2, axis=1)
+    assert edge.any() and not edge.all()                    # some core windows leave the domain, some do not
+    # a second-pass wavefront takes four consecutive core packages: some take
+    # both kinds, and the last (a partial one) takes domain-face packages
+    groups = [edge[i:i + 4] for i in range(0, edge.size, 4)]
+    assert any(gr.any() and not gr.all() for gr in groups)
+    assert edge.size % 4 != 0 and groups[-1].any()
     n = wl.grid.n_core * 64
     direct = torch.empty((4, n), device="cuda")
     fact = torch.empty((4, n), device="cuda")
@@ -276,21 +281,23 @@ def test_integrals_factorised_domain_faces(sg):
 
 
 def test_integrals_factorised_ragged_and_empty(sg):
-    """Core counts that leave the last workgroup partly empty, and a grid with
-    no core package at all (a call that launches nothing)."""
+    """Core counts that leave the last workgroup partly empty (the second pass
+    takes four core packages per wavefront and sixteen per workgroup, so
+    counts of 6 and 14 mod 16 leave a wavefront with two), and a grid with no
+    core package at all (a call that launches nothing)."""
     from paper_2512_11473_amd import workload
     seen = set()
     for r, seed in ((0.11, 3), (0.17, 4), (0.23, 5), (0.29, 6)):
         wl = workload.setup(synth.sphere((0.5, 0.47, 0.52), r), 64, 0.1, seed)
         n = wl.grid.n_core * 64
-        seen.add(wl.grid.n_core % 4)
+        seen.add(wl.grid.n_core % 16)
         direct = torch.empty((4, n), device="cuda")
         fact = torch.empty((4, n), device="cuda")
         sg.compute_near_surface_integrals(wl.grid, wl.phi, direct)
         sg.compute_near_surface_integrals_factorised(wl.grid, wl.phi, torch.empty_like(wl.phi), fact)
         torch.cuda.synchronize()
         assert torch.equal(fact, direct)
-    assert seen - {0}
+    assert any(x % 4 for x in seen)
     d = torch.full((8 ** 3,), 1.0, device="cuda")           # every coarse cell far outside: P = 0
     g = sg.build_packages(d, 1.0 / 32)
     assert g.n_core == 0
@@ -298,6 +305,28 @@ def test_integrals_factorised_ragged_and_empty(sg):
     sg.compute_near_surface_integrals_factorised(g, phi, torch.zeros_like(phi), torch.empty((4, 0), device="cuda"))
     torch.cuda.synchronize()
     g.destroy()
+
+
+def test_integrals_every_point_cut(sg):
+    """phi = 0 at every band point: every cut fraction is 1/2 (zero gradient,
+    a = 0), so every point of every window goes through the listed-point path
+    of both forms (full lists: 256 points per first-pass wavefront, 343 per
+    direct window).  By symmetry K_grad is exactly 0 and K_W is half the full
+    kernel sum."""
+    from paper_2512_11473_amd import workload
+    wl = workload.setup(synth.sphere((0.5, 0.47, 0.52), 0.23), 64, 0.1, 5)
+    phi = wl.phi.clone()
+    phi[2:] = 0.0                                           # far-field rows keep -B / +B
+    n = wl.grid.n_core * 64
+    direct = torch.empty((4, n), device="cuda")
+    fact = torch.empty((4, n), device="cuda")
+    sg.compute_near_surface_integrals(wl.grid, phi, direct)
+    sg.compute_near_surface_integrals_factorised(wl.grid, phi, torch.empty_like(phi), fact)
+    torch.cuda.synchronize()
+    assert torch.equal(fact, direct)
+    got = direct.double().cpu().numpy()
+    assert np.all(got[1:] == 0.0)
+    assert np.max(np.abs(got[0] - 0.5 * oracle.c_full())) <= 1e-6
 
 
 def test_sweep_variants_identical(sg):
