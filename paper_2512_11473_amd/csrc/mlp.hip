@@ -704,13 +704,16 @@ __global__ __launch_bounds__(64) void add_u32_kernel(uint32_t *total, const uint
 //  2. One lane per point sums the 32 taps' saturated fractions.  A point
 //     whose taps are all saturated takes that exact sum (the plain value);
 //     the others are listed, in LDS, for the network.
-//  3. The listed points go through the network in 16-point MFMA tiles, tile
-//     T on wavefront T mod 4 (each BF16 weight fragment read from L2 feeds
-//     both of a wavefront's tiles, hi and lo parts).  A wavefront reads back
-//     only activation rows it wrote, so the layers need no barrier.
-//  4. The same wavefront evaluates the gate of its tiles' points, two lanes
-//     per point, and writes the network's value or lists the point for the
-//     plain fallback.
+//  3. The listed points are spread in 16-point tiles over the wavefronts,
+//     tile T on wavefront T mod 4, and each wavefront evaluates the gate of
+//     its tiles' points, two lanes per point.
+//  4. The network over the tiles: W1's and W2's 32-input slices are staged
+//     in LDS once per workgroup (every wavefront takes part in the staging
+//     and its barriers) and each weight fragment feeds both of a wavefront's
+//     tiles, hi and lo parts.  A wavefront reads back only activation rows it
+//     wrote.
+//  5. The same wavefront writes the network's value or lists the point for
+//     the plain fallback.
 // Every listed point's network row is computed in the MFMA accumulation
 // order of forward_tile, so the outputs are the bits of sgrid_mlp_forward on
 // the gathered windows.
