@@ -254,6 +254,9 @@ sgrid_status sgrid_sort_particles(const sgrid_grid *grid, const float *pos_dev, 
  * With `model` non-NULL the surrogate network is evaluated instead and every
  * point whose gate fails falls back to the plain integral; the number of
  * fallback points is written to *n_fallback_dev when that pointer is non-NULL.
+ * A point whose 32 taps all lie more than half a cell from the surface
+ * (saturated: every V_j is 0 or 1) skips the network; it and every fallback
+ * point get the plain kernel's bits.
  */
 sgrid_status sgrid_compute_near_surface_integrals(const sgrid_grid *grid, const float *phi_dev,
                                                   const sgrid_mlp *model, float *out_dev,
