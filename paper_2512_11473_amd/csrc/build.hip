@@ -4,7 +4,7 @@
 //
 // Pipeline on the caller's stream (coarse cells held as bitmaps, 64 cells of a
 // row per word):
-//   bits_kernel     one wavefront per four words: core flag |d| < l_c and sign of d,
+//   bits_kernel     one wavefront per 16 words: core flag |d| < l_c and sign of d,
 //                   one ballot each;
 //   dilate_kernel   one lane per word: activated = core dilated by one cell in
 //                   x, y, z (word shifts and ORs); per-group counts;
@@ -141,6 +141,13 @@ __device__ __forceinline__ uint64_t lanemask_lt() {
     return lane == 0 ? 0ull : (~0ull >> (64 - lane));
 }
 
+// Quotient of a word or row index by a row length, in 32-bit arithmetic when
+// the index fits (M^2 W words stay below 2^32 up to M = 4096): a few
+// instructions instead of the fifty of a 64-bit division.
+__device__ __forceinline__ int64_t quot(int64_t a, int b) {
+    return a < 0x100000000ll ? (int64_t)((uint32_t)a / (uint32_t)b) : a / b;
+}
+
 // Bitmaps of the background grid.  Row r = y + M z holds its M cells in
 // W = ceil(M / 64) words; bit b of word r W + i is the cell x = 64 i + b.
 // Bits of x >= M are zero.  Word order is linear cell order.
@@ -148,28 +155,40 @@ __device__ __forceinline__ uint64_t lanemask_lt() {
 // Pass 1: one wavefront per word: the core flag |d| < l_c (compared in double,
 // so that a non-representable l_c rounds as the definition does) and the sign
 // of d, each one ballot.
+constexpr int kBitsWords = 16;   // words per wavefront of bits_kernel
+
 __global__ __launch_bounds__(256) void bits_kernel(const float *__restrict__ d, int M, int W, int64_t n_words,
                                                    double lc, uint64_t *__restrict__ core,
                                                    uint64_t *__restrict__ neg) {
-    // four consecutive words per wavefront, their loads issued together
-    const int64_t w0 = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * 4;
+    // kBitsWords consecutive words per wavefront, their loads issued together
+    // (4 KiB in flight per wavefront); the words' rows and offsets advance
+    // from the first word's (one division per wavefront)
+    const int64_t w0 = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * kBitsWords;
     if (w0 >= n_words) return;   // whole wavefronts
     const int lane = threadIdx.x & 63;
-    float v[4];
+    const int64_t r0 = quot(w0, W);
+    const int i0 = (int)(w0 - r0 * W);
+    float v[kBitsWords];
+    bool in[kBitsWords];
+    {
+        int64_t r = r0;
+        int i = i0;
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        const int64_t w = w0 + k < n_words ? w0 + k : n_words - 1;
-        const int64_t r = w / W;
-        const int x = (int)(w - r * W) * 64 + lane;
-        v[k] = d[r * M + (x < M ? x : M - 1)];
+        for (int k = 0; k < kBitsWords; ++k) {
+            const int x = i * 64 + lane;
+            in[k] = w0 + k < n_words && x < M;
+            v[k] = d[in[k] ? r * M + x : 0];   // every lane loads, in bounds
+            if (++i == W) {
+                i = 0;
+                ++r;
+            }
+        }
     }
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
+    for (int k = 0; k < kBitsWords; ++k) {
         const int64_t w = w0 + k;
-        const int64_t r = w / W;
-        const bool in = w < n_words && (int)(w - r * W) * 64 + lane < M;
-        const uint64_t bc = __ballot(in && fabs((double)v[k]) < lc);
-        const uint64_t bn = __ballot(in && v[k] < 0.0f);
+        const uint64_t bc = __ballot(in[k] && fabs((double)v[k]) < lc);
+        const uint64_t bn = __ballot(in[k] && v[k] < 0.0f);
         if (lane == 0 && w < n_words) {
             core[w] = bc;
             neg[w] = bn;
@@ -188,9 +207,10 @@ __global__ __launch_bounds__(256) void dilate_kernel(const uint64_t *__restrict_
     const int64_t w = (int64_t)blockIdx.x * 256 + threadIdx.x;
     uint64_t a = 0, own = 0;
     if (w < n_words) {
-        const int64_t r = w / W;
+        const int64_t r = quot(w, W);
         const int i = (int)(w - r * W);
-        const int y = (int)(r % M), z = (int)(r / M);
+        const int64_t rz = quot(r, M);
+        const int y = (int)(r - rz * M), z = (int)rz;
         for (int dz = -1; dz <= 1; ++dz) {
             const int zz = z + dz;
             if (zz < 0 || zz >= M) continue;
@@ -410,7 +430,7 @@ __global__ __launch_bounds__(256) void scatter_kernel(const uint64_t *__restrict
         const int k = lane >> 1, hf = lane & 1;
         const int64_t w = w0 + k;
         if (w < n_words) {
-            const int64_t r = w / W;
+            const int64_t r = quot(w, W);
             const int half = (int)(w - r * W) * 2 + hf;
             if (half < W32) {
                 uint32_t before = pa;
@@ -435,7 +455,7 @@ __global__ __launch_bounds__(256) void scatter_kernel(const uint64_t *__restrict
     const uint64_t below = (1ull << b0) - 1ull;
     ra += (uint32_t)__popcll(ak & below);
     rc += (uint32_t)__popcll(ck & below);
-    const int64_t r = w / W;
+    const int64_t r = quot(w, W);
     const int x0 = (int)(w - r * W) * 64 + b0;
     if (x0 >= M) return;
     uint32_t v[4];
@@ -691,9 +711,10 @@ __global__ __launch_bounds__(256) void refine_bits_kernel(const uint4 *__restric
     if (w >= n_words) return;   // whole wavefronts
     const int lane = threadIdx.x & 63;
     const int Mf = 2 * Mc;
-    const int64_t r = w / W;
+    const int64_t r = quot(w, W);
     const int x = (int)(w - r * W) * 64 + lane;
-    const int y = (int)(r % Mf), z = (int)(r / Mf);
+    const int64_t rz = quot(r, Mf);
+    const int y = (int)(r - rz * Mf), z = (int)rz;
     bool is_core = false, is_neg = false;
     if (x < Mf) {
         const int px = x >> 1, py = y >> 1, pz = z >> 1;
@@ -902,7 +923,8 @@ extern "C" sgrid_status sgrid_build_packages(const sgrid_desc *desc, const float
     sgrid_status s = new_grid(M, desc->h, &g, ws);
     if (s != SGRID_OK) return s;
     const double lc = 4.0 * desc->h;
-    hipLaunchKernelGGL(bits_kernel, dim3((unsigned)((ws.n_words + 15) / 16)), dim3(256), 0, st, coarse_sdf, (int)M,
+    hipLaunchKernelGGL(bits_kernel, dim3((unsigned)((ws.n_words + 4 * kBitsWords - 1) / (4 * kBitsWords))), dim3(256), 0,
+                       st, coarse_sdf, (int)M,
                        (int)ws.W, ws.n_words, lc, ws.core_bits, ws.neg_bits);
     SG_HIP_OR_FREE(hipGetLastError());
     s = finish_grid(g, ws, st);
