@@ -405,84 +405,94 @@ __global__ __launch_bounds__(256) void scatter_kernel(const uint64_t *__restrict
                                                       uint8_t *__restrict__ pkg_type,
                                                       uint32_t *__restrict__ core_list,
                                                       uint4 *__restrict__ rank_map, int W32) {
-    // a wavefront owns four consecutive words; lane l the four cells of bits
+    // a wavefront owns one group of 16 words, in four steps of four
+    // consecutive words; in a step lane l takes the four cells of bits
     // 4 (l mod 16) .. 4 (l mod 16) + 3 of word l / 16, stored with one 16-byte
-    // write where the row allows it
-    const int64_t grp = blockIdx.x;
+    // write where the row allows it.  Lane l < 16 loads word l of the group
+    // (the loads issued together) and the counts before each word come from
+    // one scan over the 16 lanes; the other lanes read words and counts from
+    // them.
     const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int64_t w0 = grp * 16 + wv * 4;
-    if (w0 >= n_words) return;   // the same for the whole wavefront
-    uint32_t pa = off_act[grp], pc = off_core[grp];
-    for (int64_t w = grp * 16; w < w0; ++w) {
-        pa += (uint32_t)__popcll(act[w]);
-        pc += (uint32_t)__popcll(core[w]);
-    }
-    uint64_t a[4], cb[4], nb[4];
+    const int64_t grp = (int64_t)blockIdx.x * 4 + wv;
+    const int64_t g0 = grp * 16;
+    if (g0 >= n_words) return;   // the same for the whole wavefront
+    const int64_t wl = g0 + (lane & 15);
+    const bool inl = wl < n_words;
+    const uint64_t la = inl ? act[wl] : 0ull, lcw = inl ? core[wl] : 0ull, ln = inl ? neg[wl] : 0ull;
+    uint32_t ea = (uint32_t)__popcll(la), ec = (uint32_t)__popcll(lcw);   // inclusive, then exclusive, counts
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        const bool in = w0 + k < n_words;
-        a[k] = in ? act[w0 + k] : 0ull;
-        cb[k] = in ? core[w0 + k] : 0ull;
-        nb[k] = in ? neg[w0 + k] : 0ull;
+    for (int o = 1; o < 16; o <<= 1) {
+        const uint32_t ta = __shfl_up(ea, o, 16), tc = __shfl_up(ec, o, 16);
+        if ((lane & 15) >= o) {
+            ea += ta;
+            ec += tc;
+        }
     }
-    // the rank map entries of the four words' 32-cell halves (lanes 0..7)
-    if (lane < 8) {
-        const int k = lane >> 1, hf = lane & 1;
+    ea -= (uint32_t)__popcll(la);
+    ec -= (uint32_t)__popcll(lcw);
+    const uint32_t pa = off_act[grp], pc = off_core[grp];
+    auto word = [](uint64_t v, int src) {
+        return ((uint64_t)(uint32_t)__shfl((int)(v >> 32), src) << 32) | (uint32_t)__shfl((int)(uint32_t)v, src);
+    };
+#pragma unroll
+    for (int step = 0; step < 4; ++step) {
+        const int64_t w0 = g0 + 4 * step;
+        if (w0 >= n_words) break;
+        // the rank map entries of the four words' 32-cell halves (lanes 0..7)
+        {
+            const int k = (lane >> 1) & 3, hf = lane & 1;
+            const int j = 4 * step + k;
+            const uint64_t aj = word(la, j), nj = word(ln, j);
+            const uint32_t before_j = (uint32_t)__shfl((int)ea, j);
+            const int64_t w = w0 + k;
+            if (lane < 8 && w < n_words) {
+                const int64_t r = quot(w, W);
+                const int half = (int)(w - r * W) * 2 + hf;
+                if (half < W32) {
+                    const uint32_t before = pa + before_j + (hf ? (uint32_t)__popc((uint32_t)aj) : 0u);
+                    rank_map[r * W32 + half] = make_uint4((uint32_t)(hf ? aj >> 32 : aj),
+                                                          (uint32_t)(hf ? nj >> 32 : nj), before, 0u);
+                }
+            }
+        }
+        const int k = lane >> 4, b0 = 4 * (lane & 15);
+        const int j = 4 * step + k;
+        const uint64_t ak = word(la, j), ck = word(lcw, j), nk = word(ln, j);
+        uint32_t ra = pa + (uint32_t)__shfl((int)ea, j), rc = pc + (uint32_t)__shfl((int)ec, j);
         const int64_t w = w0 + k;
-        if (w < n_words) {
-            const int64_t r = quot(w, W);
-            const int half = (int)(w - r * W) * 2 + hf;
-            if (half < W32) {
-                uint32_t before = pa;
-                for (int j = 0; j < k; ++j) before += (uint32_t)__popcll(a[j]);
-                if (hf) before += (uint32_t)__popc((uint32_t)a[k]);
-                rank_map[r * W32 + half] = make_uint4((uint32_t)(hf ? a[k] >> 32 : a[k]),
-                                                      (uint32_t)(hf ? nb[k] >> 32 : nb[k]), before, 0u);
+        if (w >= n_words) continue;
+        const uint64_t below = (1ull << b0) - 1ull;
+        ra += (uint32_t)__popcll(ak & below);
+        rc += (uint32_t)__popcll(ck & below);
+        const int64_t r = quot(w, W);
+        const int x0 = (int)(w - r * W) * 64 + b0;
+        if (x0 >= M) continue;
+        uint32_t v[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int bit = b0 + i;
+            const int64_t c = r * M + x0 + i;
+            if ((ak >> bit) & 1ull) {
+                const uint32_t id = 2u + ra++;
+                v[i] = id;
+                if (x0 + i < M) {
+                    pkg_cell[id] = (uint32_t)c;
+                    const bool is_core = (ck >> bit) & 1ull;
+                    pkg_type[id] = is_core ? 1 : 2;
+                    if (is_core) core_list[rc++] = id;
+                }
+            } else {
+                v[i] = ((nk >> bit) & 1ull) ? sgrid::kFarNeg : sgrid::kFarPos;
             }
         }
-    }
-    const int k = lane >> 4, b0 = 4 * (lane & 15);
-    const int64_t w = w0 + k;
-    if (w >= n_words) return;
-    uint32_t ra = pa, rc = pc;
-#pragma unroll
-    for (int j = 0; j < 4; ++j)
-        if (j < k) {
-            ra += (uint32_t)__popcll(a[j]);
-            rc += (uint32_t)__popcll(cb[j]);
-        }
-    const uint64_t ak = a[k], ck = cb[k], nk = nb[k];
-    const uint64_t below = (1ull << b0) - 1ull;
-    ra += (uint32_t)__popcll(ak & below);
-    rc += (uint32_t)__popcll(ck & below);
-    const int64_t r = quot(w, W);
-    const int x0 = (int)(w - r * W) * 64 + b0;
-    if (x0 >= M) return;
-    uint32_t v[4];
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        const int bit = b0 + i;
-        const int64_t c = r * M + x0 + i;
-        if ((ak >> bit) & 1ull) {
-            const uint32_t id = 2u + ra++;
-            v[i] = id;
-            if (x0 + i < M) {
-                pkg_cell[id] = (uint32_t)c;
-                const bool is_core = (ck >> bit) & 1ull;
-                pkg_type[id] = is_core ? 1 : 2;
-                if (is_core) core_list[rc++] = id;
-            }
+        uint32_t *dst = cell_pkg + r * M + x0;
+        if ((M & 3) == 0) {   // x0 and M multiples of 4: the four cells are in the row and 16-byte aligned
+            *reinterpret_cast<uint4 *>(dst) = make_uint4(v[0], v[1], v[2], v[3]);
         } else {
-            v[i] = ((nk >> bit) & 1ull) ? sgrid::kFarNeg : sgrid::kFarPos;
-        }
-    }
-    uint32_t *dst = cell_pkg + r * M + x0;
-    if ((M & 3) == 0) {   // x0 and M multiples of 4: the four cells are in the row and 16-byte aligned
-        *reinterpret_cast<uint4 *>(dst) = make_uint4(v[0], v[1], v[2], v[3]);
-    } else {
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
-            if (x0 + i < M) dst[i] = v[i];
+            for (int i = 0; i < 4; ++i)
+                if (x0 + i < M) dst[i] = v[i];
+        }
     }
 }
 
@@ -847,7 +857,8 @@ sgrid_status finish_grid(sgrid_grid *g, const BuildWs &ws, hipStream_t st) {
     SG_HIP_OR_FREE(hipGetLastError());
     g->W32 = (int32_t)((M + 31) / 32);
     SG_ALLOC(g->rank_map, M * M * g->W32 * 16, "rank map");
-    hipLaunchKernelGGL(scatter_kernel, dim3((unsigned)n_groups), dim3(256), 0, st, act_bits, core_bits, neg_bits,
+    hipLaunchKernelGGL(scatter_kernel, dim3((unsigned)((n_groups + 3) / 4)), dim3(256), 0, st, act_bits, core_bits,
+                       neg_bits,
                        (int)M, (int)W, n_words, ca, cc, g->cell_pkg, g->pkg_cell, g->pkg_type, g->core_list,
                        g->rank_map, g->W32);
     SG_HIP_OR_FREE(hipGetLastError());
