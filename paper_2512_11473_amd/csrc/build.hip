@@ -11,12 +11,12 @@
 //   scan_pair       exclusive scan of the counts (block sums, one workgroup
 //                   over them, block scans);
 //   (host)          read back P and n_core once, allocate the package tables;
-//   scatter_kernel  four words per wavefront, four cells per lane: rank by
+//   scatter_kernel  16 words per wavefront in steps of four, four cells per lane: rank by
 //                   popcount below the cell plus word offsets from the scan,
 //                   id = 2 + rank in ascending linear order (no sort needed);
 //                   the cell map in 16-byte stores, the rank map;
-//   nbr_kernel      27 lanes per package: the neighbour table and the six face
-//                   slots copied into a 32-byte row per package;
+//   nbr_kernel      27 lanes per four packages: the neighbour table and the six
+//                   face slots copied into a 32-byte row per package;
 //   morton_*        the sweep worklist in Morton order of the cells, one lane
 //                   per 4 x 4 x 4 box of codes.
 // The next layer of the multi-resolution construction replaces bits_kernel by
@@ -650,33 +650,42 @@ __global__ void far_rows_kernel(uint32_t *__restrict__ pkg_cell, uint8_t *__rest
     }
 }
 
-// One lane per (package, slot).
+// One lane per slot for each of kNbrPkgs packages.
+constexpr int kNbrPkgs = 4;   // consecutive packages per 27-lane group of nbr_kernel
+
 __global__ __launch_bounds__(256) void nbr_kernel(const uint32_t *__restrict__ cell_pkg,
                                                   const uint32_t *__restrict__ pkg_cell, int M,
                                                   int64_t n_total, uint32_t *__restrict__ nbr,
                                                   uint32_t *__restrict__ face) {
-    // nine packages per workgroup, 27 lanes each (lanes 243.. idle): 32-bit
+    // nine groups of 27 lanes per workgroup (lanes 243.. idle), each group
+    // kNbrPkgs consecutive packages, lane s their slot s: the packages' cells,
+    // then their neighbours' map entries, are requested together.  32-bit
     // index arithmetic, divisions by constants
     const int tl = (int)threadIdx.x;
     if (tl >= 9 * 27) return;
-    const int64_t p = (int64_t)blockIdx.x * 9 + tl / 27;
-    if (p >= n_total) return;
+    const int64_t p0 = ((int64_t)blockIdx.x * 9 + tl / 27) * kNbrPkgs;
+    if (p0 >= n_total) return;
     const int s = tl % 27;
-    const int64_t t = p * 27 + s;
-    uint32_t v;
-    if (p < 2) {
-        v = (uint32_t)p;
-    } else {
-        const uint32_t c = pkg_cell[p], um = (uint32_t)M;
-        const uint32_t cyz = c / um;
-        const int x = (int)(c - cyz * um) + s % 3 - 1;
-        const int y = (int)(cyz % um) + (s / 3) % 3 - 1;
-        const int z = (int)(cyz / um) + s / 9 - 1;
-        v = (x < 0 || y < 0 || z < 0 || x >= M || y >= M || z >= M)
-                ? sgrid::kFarPos
-                : cell_pkg[x + (int64_t)M * y + (int64_t)M * M * z];
+    const int dx = s % 3 - 1, dy = (s / 3) % 3 - 1, dz = s / 9 - 1;
+    uint32_t c[kNbrPkgs];
+#pragma unroll
+    for (int g = 0; g < kNbrPkgs; ++g) {
+        const int64_t p = p0 + g;
+        c[g] = (p >= 2 && p < n_total) ? pkg_cell[p] : 0u;
     }
-    nbr[t] = v;
+    uint32_t v[kNbrPkgs];
+#pragma unroll
+    for (int g = 0; g < kNbrPkgs; ++g) {
+        const int64_t p = p0 + g;
+        const uint32_t um = (uint32_t)M;
+        const uint32_t cyz = c[g] / um;
+        const int x = (int)(c[g] - cyz * um) + dx;
+        const int y = (int)(cyz % um) + dy;
+        const int z = (int)(cyz / um) + dz;
+        const bool out = x < 0 || y < 0 || z < 0 || x >= M || y >= M || z >= M;
+        const uint32_t m = cell_pkg[out ? 0 : x + (int64_t)M * y + (int64_t)M * M * z];   // in bounds
+        v[g] = p < 2 ? (uint32_t)p : (out ? sgrid::kFarPos : m);
+    }
     // face row: -x, +x, -y, +y, -z, +z, then the package itself twice
     int f = -1;
     switch (s) {
@@ -688,10 +697,16 @@ __global__ __launch_bounds__(256) void nbr_kernel(const uint32_t *__restrict__ c
         case 22: f = 5; break;
         default: break;
     }
-    if (f >= 0) face[p * 8 + f] = v;
-    if (s == 13) {
-        face[p * 8 + 6] = v;
-        face[p * 8 + 7] = v;
+#pragma unroll
+    for (int g = 0; g < kNbrPkgs; ++g) {
+        const int64_t p = p0 + g;
+        if (p >= n_total) break;
+        nbr[p * 27 + s] = v[g];
+        if (f >= 0) face[p * 8 + f] = v[g];
+        if (s == 13) {
+            face[p * 8 + 6] = v[g];
+            face[p * 8 + 7] = v[g];
+        }
     }
 }
 
@@ -862,8 +877,8 @@ sgrid_status finish_grid(sgrid_grid *g, const BuildWs &ws, hipStream_t st) {
                        (int)M, (int)W, n_words, ca, cc, g->cell_pkg, g->pkg_cell, g->pkg_type, g->core_list,
                        g->rank_map, g->W32);
     SG_HIP_OR_FREE(hipGetLastError());
-    hipLaunchKernelGGL(nbr_kernel, dim3((unsigned)((nt + 8) / 9)), dim3(256), 0, st, g->cell_pkg, g->pkg_cell,
-                       (int)M, nt, g->nbr, g->face);
+    hipLaunchKernelGGL(nbr_kernel, dim3((unsigned)((nt + 9 * kNbrPkgs - 1) / (9 * kNbrPkgs))), dim3(256), 0, st,
+                       g->cell_pkg, g->pkg_cell, (int)M, nt, g->nbr, g->face);
     SG_HIP_OR_FREE(hipGetLastError());
     // Morton-order sweep worklist: count activated codes per block of
     // kCodesPerBlock codes, scan, scatter (the counts and the scan's block sums
