@@ -723,7 +723,7 @@ constexpr int kActStride = kH + 8;   // bf16 per activation row in LDS
 
 struct LearnLds {
     float phi[kWinN + 3];
-    bf16 xh[kWinN + 7], xl[kWinN + 7];   // BF16 hi and lo parts of the window's phi / h
+    uint32_t xhl[kWinN + 3];   // BF16 hi (low half) and lo (high half) parts of the window's phi / h
     uint32_t ids[28];
     uint8_t sat[kVolN + 13];
 };
@@ -805,8 +805,9 @@ __device__ __forceinline__ void learned_network(const MlpDev &W, LearnLds *lds, 
 #pragma unroll
                 for (int e = 0; e < 8; ++e) {
                     const int off = base[m] + s_off[32 * s + 8 * q + e];
-                    ah[e] = win[m]->xh[off];
-                    al[e] = win[m]->xl[off];
+                    const uint32_t hl = win[m]->xhl[off];   // both parts in one read
+                    ah[e] = __builtin_bit_cast(bf16, (uint16_t)(hl & 0xFFFFu));
+                    al[e] = __builtin_bit_cast(bf16, (uint16_t)(hl >> 16));
                 }
 #pragma unroll
                 for (int t = 0; t < 8; ++t) {
@@ -927,8 +928,8 @@ __global__ __launch_bounds__(256, 3) void learned_kernel(MlpDev W, const float *
     for (int v = t128; v < kWinN; v += 128) {   // the network inputs, once per window value
         const float x = L.phi[v] * inv_h;
         const bf16 hi = (bf16)x;
-        L.xh[v] = hi;
-        L.xl[v] = (bf16)(x - (float)hi);
+        const bf16 lo = (bf16)(x - (float)hi);
+        L.xhl[v] = (uint32_t)__builtin_bit_cast(uint16_t, hi) | ((uint32_t)__builtin_bit_cast(uint16_t, lo) << 16);
     }
     __syncthreads();
     const int64_t stride = n_core * 64;
