@@ -520,7 +520,11 @@ __device__ __forceinline__ int64_t stencil_package(int64_t e, const uint32_t *__
 // PACKED = false writes the three components as separate [P^][64] arrays;
 // PACKED = true writes one [P^][64] array of (phi, gx, gy, gz) quadruples in
 // the blocked point order (blocked_index), the layout the packed probe gathers
-// with one 16-byte (FP32) load per corner.
+// with one 16-byte (FP32) load per corner.  In FP32 the quadruples pass
+// through LDS in that order, so that each of a lane's four stores writes, with
+// the wavefront's other lanes, one package's 1 KiB contiguously (written in
+// place, a store instruction would fill half of every 64-byte segment of four
+// packages).
 template <typename T, bool PACKED, bool WORK>
 __global__ __launch_bounds__(256) void gradient_kernel(const T *__restrict__ phi, T *__restrict__ out,
                                                        const uint32_t *__restrict__ face,
@@ -529,8 +533,13 @@ __global__ __launch_bounds__(256) void gradient_kernel(const T *__restrict__ phi
     const int64_t b = xcd_block(blockIdx.x, n_blocks);
     const int lane = threadIdx.x & 63;
     const int r = lane & 15;
-    const int64_t e = (b * 4 + (threadIdx.x >> 6)) * 4 + (lane >> 4);
-    if (e >= n_total) return;
+    const int64_t e_lane = (b * 4 + (threadIdx.x >> 6)) * 4 + (lane >> 4);
+    // the FP32 packed layout is stored by the whole wavefront, so a package
+    // row past the end repeats the last package instead of leaving
+    constexpr bool kStaged = PACKED && sizeof(T) == 4;
+    if (!kStaged && e_lane >= n_total) return;
+    if (kStaged && e_lane - (lane >> 4) >= n_total) return;   // the whole wavefront is past the end
+    const int64_t e = e_lane < n_total ? e_lane : n_total - 1;
     uint4 f0;
     uint2 f1;
     const int64_t p = stencil_package<WORK>(e, face, wface, f0, f1);
@@ -553,7 +562,27 @@ __global__ __launch_bounds__(256) void gradient_kernel(const T *__restrict__ phi
             oz.v[i] = (s.zp.v[i] - s.zm.v[i]) * inv_2h;
         }
     }
-    if (PACKED) {
+    if constexpr (kStaged) {
+        // (every lane of the wavefront takes part in every store; the stores
+        // of a repeated package are skipped)
+        __shared__ float4 s_pk[4][256];
+        const int j = r & 3, k = r >> 2, w = threadIdx.x >> 6, q = lane >> 4;
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+            s_pk[w][64 * q + blocked_index(i, j, k)] = make_float4(c.v[i], ox.v[i], oy.v[i], oz.v[i]);
+        __builtin_amdgcn_wave_barrier();
+        const int64_t e0 = e_lane - q;   // the wavefront's first package
+#pragma unroll
+        for (int g = 0; g < 4; ++g) {
+            const int64_t pg = __shfl(p, 16 * g);
+            if (e0 + g < n_total) {
+                float *o = reinterpret_cast<float *>(out) + pg * 256 + 4 * lane;
+                store_row(o, Row<float>{{s_pk[w][64 * g + lane].x, s_pk[w][64 * g + lane].y, s_pk[w][64 * g + lane].z,
+                                         s_pk[w][64 * g + lane].w}},
+                          nt);
+            }
+        }
+    } else if constexpr (PACKED) {
         const int j = r & 3, k = r >> 2;
         T *o = out + p * 64 * 4;
 #pragma unroll
@@ -992,10 +1021,11 @@ static sgrid_status gradient_entry(const sgrid_grid *g, sgrid_dtype dtype, const
     const int64_t nb = (nt + 15) / 16;
     const bool work = sgrid::stencil_in_worklist_order();
     // streaming stores when phi and the output together exceed the last-level
-    // cache; not for the packed layout, whose four stores per lane each fill
-    // only parts of lines (the cache merges them, streaming writes would not)
-    const bool stream_out =
-        !PACKED && (double)nt * 64.0 * (dtype == SGRID_F32 ? 4.0 : 8.0) * 4.0 > sgrid::kLastLevelCacheBytes;
+    // cache; not for the FP64 packed layout, whose four stores per lane each
+    // fill only parts of lines (the cache merges them, streaming writes would
+    // not; the FP32 packed layout is written by whole lines)
+    const bool stream_out = !(PACKED && dtype == SGRID_F64) &&
+                            (double)nt * 64.0 * (dtype == SGRID_F32 ? 4.0 : 8.0) * 4.0 > sgrid::kLastLevelCacheBytes;
     if (dtype == SGRID_F32) {
         if (work)
             hipLaunchKernelGGL((gradient_kernel<float, PACKED, true>), dim3((unsigned)nb), dim3(256), 0, st,
