@@ -598,44 +598,48 @@ __global__ __launch_bounds__(256) void worklist_pos_kernel(const uint32_t *__res
     if (e < P) wpos[work[e]] = (uint32_t)e;
 }
 
-// Face rows in worklist order, twice: wface holds the six face neighbours'
-// package ids and the package's own id; sface marks a neighbour in the same
-// group of kGroup entries by its slot in the group (flagged with kLocal).
+// Face rows in worklist order, three times: wface holds the six face
+// neighbours' package ids and the package's own id; sface marks a neighbour
+// in the same group of kGroup entries by its slot in the group (flagged with
+// kLocal); mface gives the neighbours' rows in the worklist-ordered copy of a
+// field (row 2 + e holds the package at worklist position e, rows 0 and 1 the
+// far fields), then the own id.  Eight lanes per entry (one per row slot),
+// each taking kFacePkgs consecutive entries whose loads are issued together.
+constexpr int kFacePkgs = 4;
+
 __global__ __launch_bounds__(256) void sweep_face_kernel(const uint32_t *__restrict__ work,
                                                          const uint32_t *__restrict__ face,
                                                          const uint32_t *__restrict__ wpos, int64_t P,
-                                                         uint32_t *__restrict__ wface, uint32_t *__restrict__ sface) {
+                                                         uint32_t *__restrict__ wface, uint32_t *__restrict__ sface,
+                                                         uint32_t *__restrict__ mface) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= P * 8) return;
-    const int64_t e = t >> 3;
     const int f = (int)(t & 7);
-    const uint32_t p = work[e];
-    uint32_t v, w;
-    if (f < 6) {
-        const uint32_t n = face[(int64_t)p * 8 + f];
-        v = w = n;
-        if (n >= 2u) {
-            const uint32_t en = wpos[n];
-            if ((int64_t)en / sgrid::kGroup == e / sgrid::kGroup) v = sgrid::kLocal | (en % sgrid::kGroup);
+    const int64_t e0 = (t >> 3) * kFacePkgs;
+    if (e0 >= P) return;
+    uint32_t p[kFacePkgs], n[kFacePkgs], en[kFacePkgs];
+#pragma unroll
+    for (int g = 0; g < kFacePkgs; ++g) p[g] = work[e0 + g < P ? e0 + g : P - 1];
+#pragma unroll
+    for (int g = 0; g < kFacePkgs; ++g) n[g] = f < 6 ? face[(int64_t)p[g] * 8 + f] : 0u;
+#pragma unroll
+    for (int g = 0; g < kFacePkgs; ++g) en[g] = wpos[n[g]];   // n < 2: a far-field row's entry, not used
+#pragma unroll
+    for (int g = 0; g < kFacePkgs; ++g) {
+        const int64_t e = e0 + g;
+        if (e >= P) break;
+        uint32_t v, w, m;
+        if (f < 6) {
+            v = w = n[g];
+            m = n[g] < 2u ? n[g] : 2u + en[g];
+            if (n[g] >= 2u && (int64_t)en[g] / sgrid::kGroup == e / sgrid::kGroup)
+                v = sgrid::kLocal | (en[g] % sgrid::kGroup);
+        } else {
+            v = w = m = f == 6 ? p[g] : 0u;
         }
-    } else {
-        v = w = f == 6 ? p : 0u;
+        wface[e * 8 + f] = w;
+        sface[e * 8 + f] = v;
+        mface[e * 8 + f] = m;
     }
-    wface[t] = w;
-    sface[t] = v;
-}
-
-// Face rows of the worklist-ordered copy of a field (row 2 + e holds the
-// package at worklist position e, rows 0 and 1 the far fields): the six face
-// neighbours' rows in that copy, then the package's own id.
-__global__ __launch_bounds__(256) void morton_face_kernel(const uint32_t *__restrict__ wface,
-                                                          const uint32_t *__restrict__ wpos, int64_t P,
-                                                          uint32_t *__restrict__ mface) {
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= P * 8) return;
-    const int f = (int)(t & 7);
-    const uint32_t n = wface[t];
-    mface[t] = f < 6 ? (n < 2u ? n : 2u + wpos[n]) : (f == 6 ? n : 0u);
 }
 
 __global__ __launch_bounds__(256) void fill_zero_kernel(uint32_t *__restrict__ p, int64_t n) {
@@ -915,15 +919,13 @@ sgrid_status finish_grid(sgrid_grid *g, const BuildWs &ws, hipStream_t st) {
             hipLaunchKernelGGL(worklist_pos_kernel, dim3((unsigned)((g->P + 255) / 256)), dim3(256), 0, st, g->work,
                                g->P, wpos);
             SG_HIP_OR_FREE(hipGetLastError());
-            hipLaunchKernelGGL(sweep_face_kernel, dim3((unsigned)((g->P * 8 + 255) / 256)), dim3(256), 0, st, g->work,
-                               g->face, wpos, g->P, g->wface, g->sface);
-            SG_HIP_OR_FREE(hipGetLastError());
         }
         g->wpos = wpos;
         SG_ALLOC(g->mface, (g->P > 0 ? g->P : 1) * 32, "worklist-ordered face table");
         if (g->P > 0) {
-            hipLaunchKernelGGL(morton_face_kernel, dim3((unsigned)((g->P * 8 + 255) / 256)), dim3(256), 0, st,
-                               g->wface, wpos, g->P, g->mface);
+            const int64_t groups = (g->P + kFacePkgs - 1) / kFacePkgs;
+            hipLaunchKernelGGL(sweep_face_kernel, dim3((unsigned)((groups * 8 + 255) / 256)), dim3(256), 0, st,
+                               g->work, g->face, wpos, g->P, g->wface, g->sface, g->mface);
             SG_HIP_OR_FREE(hipGetLastError());
         }
     }
