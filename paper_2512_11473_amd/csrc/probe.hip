@@ -191,19 +191,22 @@ __global__ __launch_bounds__(256) void probe_field_kernel(Corner<float, true> fi
 //
 // LSD radix sort, 8 bits per pass, stable, so the result is unique: keys
 // non-decreasing, equal keys in their input order.  Per pass, one kernel
-// counts each 4096-element tile's digits in LDS, a scan turns the
+// counts each 8192-element tile's digits in LDS, a scan turns the
 // digit-major [256][tiles] counts into output offsets, and a second kernel
 // ranks the tile's elements stably (wavefront ballots over the digit bits,
 // then per-wavefront running counts in LDS), reorders the tile by digit in
 // LDS and writes each digit's run contiguously.  The first pass computes the
 // keys from the positions; the last writes the permutation and gathers the
-// sorted positions.
+// sorted positions.  Both kernels take their tiles in XCD-aware order: the
+// runs of one digit from consecutive tiles are adjacent in the output, and
+// the partial cache lines where they meet are then written from one L2.
 
 constexpr int kScanItems = 4096;    // entries per scan block: 1024 lanes x 4
 constexpr int kRadixBits = 8, kRadixBins = 1 << kRadixBits;
-constexpr int kDigitsPerLane = kRadixBins / 256;   // digits per lane of a 256-lane workgroup
-constexpr int kSortTile = 4096;     // elements per tile: 4 wavefronts x 16 rounds x 64
+constexpr int kSortWaves = 8, kSortThreads = 64 * kSortWaves;
 constexpr int kSortRounds = 16;
+constexpr int kSortTile = kSortThreads * kSortRounds;   // 8192 elements per tile
+static_assert(kRadixBins <= kSortThreads && kRadixBins % 64 == 0, "one digit per thread of whole wavefronts");
 
 __device__ __forceinline__ uint32_t spread3(uint32_t v) {   // bit b of v (b < 10) to bit 3b
     v &= 0x3FFu;
@@ -235,14 +238,39 @@ __global__ __launch_bounds__(256) void radix_count_kernel(const float *__restric
     __shared__ uint32_t s_hist[kRadixBins];
     for (int d = threadIdx.x; d < kRadixBins; d += 256) s_hist[d] = 0u;
     __syncthreads();
-    const int64_t t0 = (int64_t)blockIdx.x * kSortTile;
+    const int64_t tile = xcd_block(blockIdx.x, n_tiles);
+    const int64_t t0 = tile * kSortTile;
+    if constexpr (FIRST) {
 #pragma unroll 4
-    for (int k = 0; k < kSortTile / 256; ++k) {
-        const int64_t e = t0 + k * 256 + threadIdx.x;
-        if (e < n) atomicAdd(&s_hist[(sort_key_at<FIRST>(pos, keys, e, M, inv_h) >> shift) & (kRadixBins - 1)], 1u);
+        for (int k = 0; k < kSortTile / 256; ++k) {
+            const int64_t e = t0 + k * 256 + threadIdx.x;
+            if (e < n) atomicAdd(&s_hist[(home_key(pos + 3 * e, M, inv_h) >> shift) & (kRadixBins - 1)], 1u);
+        }
+    } else {
+        // four consecutive keys per lane and step, one 16-byte load each (the
+        // key arrays are 256-byte aligned and tiles start at multiples of 4),
+        // all of a lane's loads issued before its LDS atomics
+        constexpr int kSteps = kSortTile / 1024;
+        uint4 q[kSteps];
+#pragma unroll
+        for (int k = 0; k < kSteps; ++k) {
+            const int64_t e = t0 + 4 * (k * 256 + threadIdx.x);
+            if (e + 3 < n)
+                q[k] = *reinterpret_cast<const uint4 *>(keys + e);
+            else
+                q[k] = make_uint4(e < n ? keys[e] : 0u, e + 1 < n ? keys[e + 1] : 0u, e + 2 < n ? keys[e + 2] : 0u, 0u);
+        }
+#pragma unroll
+        for (int k = 0; k < kSteps; ++k) {
+            const int64_t e = t0 + 4 * (k * 256 + threadIdx.x);
+            const uint32_t v[4] = {q[k].x, q[k].y, q[k].z, q[k].w};
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+                if (e + u < n) atomicAdd(&s_hist[(v[u] >> shift) & (kRadixBins - 1)], 1u);
+        }
     }
     __syncthreads();
-    for (int d = threadIdx.x; d < kRadixBins; d += 256) counts[(int64_t)d * n_tiles + blockIdx.x] = s_hist[d];
+    for (int d = threadIdx.x; d < kRadixBins; d += 256) counts[(int64_t)d * n_tiles + tile] = s_hist[d];
 }
 
 // Exclusive scan of one block of kScanItems entries in place; the block's
@@ -306,7 +334,7 @@ __global__ __launch_bounds__(1024) void scan_sums_kernel(uint32_t *__restrict__ 
 // order inside the tile: wavefront w holds elements [1024 w, 1024 (w + 1)),
 // taken in rounds of 64 consecutive ones.
 template <bool FIRST, bool LAST>
-__global__ __launch_bounds__(256) void radix_scatter_kernel(const float *__restrict__ pos,
+__global__ __launch_bounds__(kSortThreads) void radix_scatter_kernel(const float *__restrict__ pos,
                                                             const uint32_t *__restrict__ keys_in,
                                                             const uint32_t *__restrict__ idx_in, int64_t n, int M,
                                                             float inv_h, int shift,
@@ -315,18 +343,17 @@ __global__ __launch_bounds__(256) void radix_scatter_kernel(const float *__restr
                                                             uint32_t *__restrict__ keys_out,
                                                             uint32_t *__restrict__ idx_out,
                                                             float *__restrict__ pos_out) {
-    __shared__ uint32_t s_cnt[4][kRadixBins];   // running count per wavefront, then its base
-    __shared__ uint32_t s_start[kRadixBins];    // first tile position of each digit
-    __shared__ uint32_t s_goff[kRadixBins];     // output position of each digit's run
+    __shared__ uint32_t s_cnt[kSortWaves][kRadixBins];   // running count per wavefront, then its base
+    __shared__ uint32_t s_start[kRadixBins];             // first tile position of each digit
+    __shared__ uint32_t s_goff[kRadixBins];              // output position of each digit's run
     __shared__ uint32_t s_key[kSortTile], s_idx[kSortTile];
-    __shared__ uint32_t s_wsum[4];
+    __shared__ uint32_t s_wsum[kRadixBins / 64];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    for (int d = threadIdx.x; d < kRadixBins; d += 256)
-#pragma unroll
-        for (int k = 0; k < 4; ++k) s_cnt[k][d] = 0u;
+    for (int i = threadIdx.x; i < kSortWaves * kRadixBins; i += kSortThreads) s_cnt[i / kRadixBins][i % kRadixBins] = 0u;
     __syncthreads();
-    const int64_t tile0 = (int64_t)blockIdx.x * kSortTile;
-    const int64_t w0 = tile0 + 1024 * w;
+    const int64_t tile = xcd_block(blockIdx.x, n_tiles);
+    const int64_t tile0 = tile * kSortTile;
+    const int64_t w0 = tile0 + (int64_t)(64 * kSortRounds) * w;
     const uint64_t below = (1ull << lane) - 1ull;
     uint32_t key[kSortRounds], idx[kSortRounds], rank[kSortRounds];
 #pragma unroll
@@ -350,39 +377,35 @@ __global__ __launch_bounds__(256) void radix_scatter_kernel(const float *__restr
         rank[j] = pre + lower;
     }
     __syncthreads();
-    // lane t: digits kDigitsPerLane t .. (consecutive), their counts in the
-    // four wavefronts, their tile starts (exclusive scan over the digits) and
-    // each wavefront's base
-    uint32_t c[kDigitsPerLane][4], tot[kDigitsPerLane], lane_sum = 0;
+    // thread d < kRadixBins owns digit d: its counts in the wavefronts, its
+    // tile start (exclusive scan over the digits) and each wavefront's base
+    const bool owner = threadIdx.x < kRadixBins;
+    const int d = threadIdx.x;
+    uint32_t c[kSortWaves], tot = 0;
 #pragma unroll
-    for (int u = 0; u < kDigitsPerLane; ++u) {
-        const int d = kDigitsPerLane * threadIdx.x + u;
-#pragma unroll
-        for (int k = 0; k < 4; ++k) c[u][k] = s_cnt[k][d];
-        tot[u] = c[u][0] + c[u][1] + c[u][2] + c[u][3];
-        lane_sum += tot[u];
+    for (int k = 0; k < kSortWaves; ++k) {
+        c[k] = owner ? s_cnt[k][d] : 0u;
+        tot += c[k];
     }
-    uint32_t inc = lane_sum;
+    uint32_t inc = tot;
 #pragma unroll
     for (int k = 1; k < 64; k <<= 1) {
         const uint32_t o = __shfl_up(inc, k);
         if (lane >= k) inc += o;
     }
-    if (lane == 63) s_wsum[w] = inc;
+    if (owner && lane == 63) s_wsum[w] = inc;
     __syncthreads();
-    uint32_t start = inc - lane_sum;
-    for (int k = 0; k < w; ++k) start += s_wsum[k];
-#pragma unroll
-    for (int u = 0; u < kDigitsPerLane; ++u) {
-        const int d = kDigitsPerLane * threadIdx.x + u;
+    if (owner) {
+        uint32_t start = inc - tot;
+        for (int k = 0; k < w; ++k) start += s_wsum[k];
         s_start[d] = start;
-        s_cnt[0][d] = start;
-        s_cnt[1][d] = start + c[u][0];
-        s_cnt[2][d] = start + c[u][0] + c[u][1];
-        s_cnt[3][d] = start + c[u][0] + c[u][1] + c[u][2];
-        const int64_t oi = (int64_t)d * n_tiles + blockIdx.x;
+#pragma unroll
+        for (int k = 0; k < kSortWaves; ++k) {
+            s_cnt[k][d] = start;
+            start += c[k];
+        }
+        const int64_t oi = (int64_t)d * n_tiles + tile;
         s_goff[d] = offs[oi] + sums[oi / kScanItems];
-        start += tot[u];
     }
     __syncthreads();
 #pragma unroll
@@ -397,8 +420,8 @@ __global__ __launch_bounds__(256) void radix_scatter_kernel(const float *__restr
     __syncthreads();
     const int64_t n_tile = n - tile0 < kSortTile ? n - tile0 : kSortTile;
 #pragma unroll 4
-    for (int k = 0; k < kSortTile / 256; ++k) {
-        const int p = k * 256 + threadIdx.x;
+    for (int k = 0; k < kSortTile / kSortThreads; ++k) {
+        const int p = k * kSortThreads + threadIdx.x;
         if (p < n_tile) {
             const uint32_t kp = s_key[p], ip = s_idx[p];
             const uint32_t dd = (kp >> shift) & (kRadixBins - 1);
@@ -531,7 +554,7 @@ sgrid_status radix_pass(const sgrid_grid *g, const float *pos, const uint32_t *k
     SG_CHECK_LAUNCH("sort scan");
     hipLaunchKernelGGL(scan_sums_kernel, dim3(1), dim3(1024), 0, st, sums, sp.n_sums);
     SG_CHECK_LAUNCH("sort scan of block totals");
-    hipLaunchKernelGGL((radix_scatter_kernel<FIRST, LAST>), dim3((unsigned)sp.n_tiles), dim3(256), 0, st, pos,
+    hipLaunchKernelGGL((radix_scatter_kernel<FIRST, LAST>), dim3((unsigned)sp.n_tiles), dim3(kSortThreads), 0, st, pos,
                        keys_in, idx_in, n, g->M, inv_h, shift, (const uint32_t *)counts, (const uint32_t *)sums,
                        sp.n_tiles, keys_out, idx_out, pos_out);
     SG_CHECK_LAUNCH("sort scatter");
