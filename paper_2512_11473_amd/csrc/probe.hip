@@ -86,46 +86,66 @@ struct RankMap {
 };
 
 // Trilinear blend of the four components (phi and g, or an integral field)
-// over the eight corners.  The
-// corners' packages are the home cell's package and, for corners past a face
-// of the home cell, those of the neighbouring cells (the index shift of
-// Sec. 5.2 per axis: slot = (s + 4) / 4, data = s + 4 - 4 slot).  A particle
-// whose home cell is far field reads the far-field constant at every corner,
-// as the far-field packages neighbour themselves.  All rank-map reads issue
-// before any is used, then all corner reads.
+// over the eight corners.  The corners' packages are the home cell's package
+// and, for corners past a face of the home cell, those of the neighbouring
+// cells (the index shift of Sec. 5.2 per axis: slot = (s + 4) / 4, data =
+// s + 4 - 4 slot).  A particle whose home cell is far field reads the
+// far-field constant at every corner, as the far-field packages neighbour
+// themselves.
+//
+// Per axis the corners lie in at most two cells, c0 <= c1 (equal unless the
+// base shift is -1 or 3), and the home cell is one of them.  A rank-map entry
+// spans 32 cells along x, so the four (y, z) pairs' entries at c0's x word
+// serve all eight corners, except for a particle whose two x cells straddle a
+// 32-cell boundary, which also reads the entries at c1's word.  All rank-map
+// reads issue before any is used, then all corner reads.
 template <typename T, bool PACKED>
 __device__ __forceinline__ void blend(const Corner<T, PACKED> &field, const RankMap &rm, const int cc[3],
                                       const int sh[3], const T t[3], T &v, T &gx, T &gy, T &gz) {
     const int M = rm.M;
-    uint4 e[8];
-    int cx[8];
-    bool out[8];
+    int c0[3], c1[3];
 #pragma unroll
-    for (int b = 0; b < 8; ++b) {
-        const int bx = b & 1, by = (b >> 1) & 1, bz = (b >> 2) & 1;
-        const int x = cc[0] + ((sh[0] + bx + 4) >> 2) - 1;
-        const int y = cc[1] + ((sh[1] + by + 4) >> 2) - 1;
-        const int z = cc[2] + ((sh[2] + bz + 4) >> 2) - 1;
-        out[b] = x < 0 || y < 0 || z < 0 || x >= M || y >= M || z >= M;
-        cx[b] = x;
-        e[b] = rm.map[out[b] ? 0 : rm.entry(x, y, z)];
+    for (int a = 0; a < 3; ++a) {
+        c0[a] = cc[a] + ((sh[a] + 4) >> 2) - 1;   // cc - 1 or cc
+        c1[a] = cc[a] + ((sh[a] + 5) >> 2) - 1;   // cc or cc + 1
     }
-    // the home cell's own entry (one of the eight above, read again rather than
-    // picked by a per-lane index into the register array)
-    const uint4 eh = rm.map[rm.entry(cc[0], cc[1], cc[2])];
-    const uint32_t home = RankMap::id(eh, cc[0]);
-    uint32_t pk[8];
+    const int wx0 = max(c0[0], 0) >> 5, wx1 = min(c1[0], M - 1) >> 5;   // x words (cells clamped into the domain)
+    uint4 ea[4], eb[4];
+    bool yz_out[4];
+#pragma unroll
+    for (int p = 0; p < 4; ++p) {
+        const int y = (p & 1) ? c1[1] : c0[1], z = (p & 2) ? c1[2] : c0[2];
+        yz_out[p] = y < 0 || z < 0 || y >= M || z >= M;
+        ea[p] = rm.map[yz_out[p] ? 0 : ((int64_t)y + (int64_t)M * z) * rm.W32 + wx0];
+        eb[p] = ea[p];
+    }
+    if (wx1 != wx0) {
+#pragma unroll
+        for (int p = 0; p < 4; ++p) {
+            const int y = (p & 1) ? c1[1] : c0[1], z = (p & 2) ? c1[2] : c0[2];
+            eb[p] = rm.map[yz_out[p] ? 0 : ((int64_t)y + (int64_t)M * z) * rm.W32 + wx1];
+        }
+    }
+    uint32_t own[8];
     int d[8];
 #pragma unroll
     for (int b = 0; b < 8; ++b) {
         const int bx = b & 1, by = (b >> 1) & 1, bz = (b >> 2) & 1;
+        const int x = bx ? c1[0] : c0[0];
+        const bool out = x < 0 || x >= M || yz_out[b >> 1];
+        own[b] = out ? sgrid::kFarPos : RankMap::id(bx ? eb[b >> 1] : ea[b >> 1], x);
         const int s0 = sh[0] + bx + 4, s1 = sh[1] + by + 4, s2 = sh[2] + bz + 4;   // shift + 4 in [3, 8]
-        const int k0 = s0 >> 2, k1 = s1 >> 2, k2 = s2 >> 2;                        // neighbour slot per axis
-        const int di = s0 - 4 * k0, dj = s1 - 4 * k1, dk = s2 - 4 * k2;            // data index
+        const int di = s0 - 4 * (s0 >> 2), dj = s1 - 4 * (s1 >> 2), dk = s2 - 4 * (s2 >> 2);   // data index
         d[b] = PACKED ? blocked_index(di, dj, dk) : di + 4 * dj + 16 * dk;
-        const uint32_t own = out[b] ? sgrid::kFarPos : RankMap::id(e[b], cx[b]);
-        pk[b] = home < 2u ? home : own;
     }
+    // the home cell is the corner cell (cc == c0 ? c0 : c1) on every axis
+    const int bh = (cc[0] == c0[0] ? 0 : 1) + (cc[1] == c0[1] ? 0 : 2) + (cc[2] == c0[2] ? 0 : 4);
+    uint32_t home = own[0];
+#pragma unroll
+    for (int b = 1; b < 8; ++b) home = b == bh ? own[b] : home;
+    uint32_t pk[8];
+#pragma unroll
+    for (int b = 0; b < 8; ++b) pk[b] = home < 2u ? home : own[b];
     v = T(0);
     gx = T(0);
     gy = T(0);
