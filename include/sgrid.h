@@ -210,7 +210,9 @@ sgrid_status sgrid_compute_gradient_packed(const sgrid_grid *grid, sgrid_dtype d
  * contains it; the eight corners are reached from it through the neighbour
  * table (index shifts in [-1, 4]), so a particle in a far-field cell reads that
  * far-field package everywhere.  `pos_dev` [n][3], `phi_out_dev` [n],
- * `normal_out_dev` [n][3], all in `dtype`.  n may be 0.
+ * `normal_out_dev` [n][3], all in `dtype`.  n may be 0.  The grid must have
+ * M <= 4096 (SGRID_E_INVALID otherwise; cell_pkg alone takes 256 GiB at
+ * 4096), as for sgrid_probe_integral_field.
  */
 sgrid_status sgrid_probe_particles(const sgrid_grid *grid, sgrid_dtype dtype, const void *phi_dev,
                                    const void *grad_dev, const void *pos_dev, int64_t n,

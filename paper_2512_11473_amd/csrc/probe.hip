@@ -72,6 +72,7 @@ __device__ __forceinline__ void locate(const T *x, int M, T inv_h, int cc[3], in
 // sign; cells outside the domain belong to the positive far field (the
 // neighbour table's rule).  These are the values of cell_pkg, read from a
 // table 64 times smaller that stays in the caches.
+constexpr int kProbeMaxM = 4096;   // rank-map indices in 32 bits (cell_pkg alone takes 256 GiB there)
 struct RankMap {
     const uint4 *map;
     int M, W32;
@@ -110,21 +111,26 @@ __device__ __forceinline__ void blend(const Corner<T, PACKED> &field, const Rank
         c1[a] = cc[a] + ((sh[a] + 5) >> 2) - 1;   // cc or cc + 1
     }
     const int wx0 = max(c0[0], 0) >> 5, wx1 = min(c1[0], M - 1) >> 5;   // x words (cells clamped into the domain)
+    // entry index (y + M z) W32 + word, in 32 bits: below M^3 / 32 <= 2^31 for
+    // M <= 4096, from products of 24-bit operands (|c| <= M, M W32 <= 2^19);
+    // pairs with a cell outside the domain read entry 0 instead
+    const int zrow = M * rm.W32;
+    const int e00 = __mul24(c0[1], rm.W32) + __mul24(c0[2], zrow) + wx0;
+    const int ey = c1[1] != c0[1] ? rm.W32 : 0, ez = c1[2] != c0[2] ? zrow : 0;
     uint4 ea[4], eb[4];
     bool yz_out[4];
+    int ei[4];
 #pragma unroll
     for (int p = 0; p < 4; ++p) {
         const int y = (p & 1) ? c1[1] : c0[1], z = (p & 2) ? c1[2] : c0[2];
         yz_out[p] = y < 0 || z < 0 || y >= M || z >= M;
-        ea[p] = rm.map[yz_out[p] ? 0 : ((int64_t)y + (int64_t)M * z) * rm.W32 + wx0];
+        ei[p] = yz_out[p] ? 0 : e00 + ((p & 1) ? ey : 0) + ((p & 2) ? ez : 0);
+        ea[p] = rm.map[(uint32_t)ei[p]];
         eb[p] = ea[p];
     }
     if (wx1 != wx0) {
 #pragma unroll
-        for (int p = 0; p < 4; ++p) {
-            const int y = (p & 1) ? c1[1] : c0[1], z = (p & 2) ? c1[2] : c0[2];
-            eb[p] = rm.map[yz_out[p] ? 0 : ((int64_t)y + (int64_t)M * z) * rm.W32 + wx1];
-        }
+        for (int p = 0; p < 4; ++p) eb[p] = rm.map[(uint32_t)(yz_out[p] ? 0 : ei[p] + 1)];
     }
     uint32_t own[8];
     int d[8];
@@ -474,6 +480,8 @@ static sgrid_status probe_entry(const sgrid_grid *g, sgrid_dtype dtype, const vo
     SG_REQUIRE(sg_aligned(phi, 16) && (PACKED || sg_aligned(grad, 16)), "fields must be 16-byte aligned");
     SG_REQUIRE(sg_aligned(pos, es) && sg_aligned(phi_out, es) && sg_aligned(normal_out, es),
                "particle arrays must be aligned to their element size");
+    SG_REQUIRE(g->M <= kProbeMaxM, "the probe takes grids of at most %d coarse cells per axis (got %d)", kProbeMaxM,
+               (int)g->M);
     hipStream_t st = sg_stream(stream);
     const int64_t nb = (n + 255) / 256;
     SG_REQUIRE(nb <= kMaxGrid, "too many particles for one launch");
@@ -513,6 +521,8 @@ extern "C" sgrid_status sgrid_probe_integral_field(const sgrid_grid *g, const fl
     SG_REQUIRE(field && pos && out, "NULL field or particle array");
     SG_REQUIRE(sg_aligned(field, 16) && sg_aligned(out, 16), "field / out must be 16-byte aligned");
     SG_REQUIRE(sg_aligned(pos, 4), "pos must be 4-byte aligned");
+    SG_REQUIRE(g->M <= kProbeMaxM, "the probe takes grids of at most %d coarse cells per axis (got %d)", kProbeMaxM,
+               (int)g->M);
     hipStream_t st = sg_stream(stream);
     const int64_t nb = (n + 255) / 256;
     SG_REQUIRE(nb <= kMaxGrid, "too many particles for one launch");
