@@ -215,10 +215,11 @@ __global__ __launch_bounds__(256) void probe_field_kernel(Corner<float, true> fi
 // wavefront's corners fall on a few shared lines and the packages a stretch of
 // particles gathers from stay in the L2 of the XCD that probes them.
 //
-// LSD radix sort, 8 bits per pass, stable, so the result is unique: keys
-// non-decreasing, equal keys in their input order.  Per pass, one kernel
-// counts each 8192-element tile's digits in LDS, a scan turns the
-// digit-major [256][tiles] counts into output offsets, and a second kernel
+// LSD radix sort, 9 bits per pass (three passes for 512^3 coarse cells),
+// stable, so the result is unique: keys non-decreasing, equal keys in their
+// input order.  Per pass, one kernel counts each 4096-element tile's digits in
+// LDS, a scan turns the digit-major [512][tiles] counts into output offsets,
+// and a second kernel (eight wavefronts, three workgroups per CU)
 // ranks the tile's elements stably (wavefront ballots over the digit bits,
 // then per-wavefront running counts in LDS), reorders the tile by digit in
 // LDS and writes each digit's run contiguously.  The first pass computes the
@@ -228,10 +229,10 @@ __global__ __launch_bounds__(256) void probe_field_kernel(Corner<float, true> fi
 // the partial cache lines where they meet are then written from one L2.
 
 constexpr int kScanItems = 4096;    // entries per scan block: 1024 lanes x 4
-constexpr int kRadixBits = 8, kRadixBins = 1 << kRadixBits;
+constexpr int kRadixBits = 9, kRadixBins = 1 << kRadixBits;
 constexpr int kSortWaves = 8, kSortThreads = 64 * kSortWaves;
-constexpr int kSortRounds = 16;
-constexpr int kSortTile = kSortThreads * kSortRounds;   // 8192 elements per tile
+constexpr int kSortRounds = 8;
+constexpr int kSortTile = kSortThreads * kSortRounds;   // 4096 elements per tile
 static_assert(kRadixBins <= kSortThreads && kRadixBins % 64 == 0, "one digit per thread of whole wavefronts");
 
 __device__ __forceinline__ uint32_t spread3(uint32_t v) {   // bit b of v (b < 10) to bit 3b
@@ -357,8 +358,8 @@ __global__ __launch_bounds__(1024) void scan_sums_kernel(uint32_t *__restrict__ 
 }
 
 // One stable pass over a tile: rank, reorder in LDS, write runs.  Element
-// order inside the tile: wavefront w holds elements [1024 w, 1024 (w + 1)),
-// taken in rounds of 64 consecutive ones.
+// order inside the tile: wavefront w holds elements [64 R w, 64 R (w + 1)),
+// R = kSortRounds, taken in rounds of 64 consecutive ones.
 template <bool FIRST, bool LAST>
 __global__ __launch_bounds__(kSortThreads) void radix_scatter_kernel(const float *__restrict__ pos,
                                                             const uint32_t *__restrict__ keys_in,

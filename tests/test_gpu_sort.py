@@ -138,3 +138,20 @@ def test_sort_keys_follow_worklist(sg):
     assert np.all(np.diff(keys) > 0)                       # one particle per cell
     order = t["sweep_order"].view(np.uint32).astype(np.int64)
     assert np.array_equal(cells.size - 1 - perm.cpu().numpy().astype(np.int64), order - 2)
+
+
+def test_sort_single_pass(sg):
+    """At 8 coarse cells per axis the Morton key has 9 bits: one pass, which
+    both computes the keys and gathers the sorted positions.  (Two passes run
+    at 16 cells per axis above, three at 128 and 512 in the full-size tests.)"""
+    from paper_2512_11473_amd import workload
+    wl = workload.setup(synth.sphere(), 32, 0.1, 1)
+    M = wl.grid.n_coarse
+    assert M == 8
+    rng = np.random.default_rng(11)
+    for n in (1, 4096, 4097, 30001):
+        pos = rng.random((n, 3)).astype(np.float32)
+        pt, ps, perm = _sort(sg, wl.grid, pos)
+        keys = assert_sorted(M, wl.h, pos, ps.cpu().numpy(), perm.cpu().numpy())
+        if n == 30001:
+            assert len(np.unique(keys)) == M ** 3             # every cell of the box holds particles
