@@ -235,7 +235,7 @@ sgrid_status sgrid_probe_particles_packed(const sgrid_grid *grid, sgrid_dtype dt
  * the result is unique.  Probing pos_sorted gives each particle's values in
  * sorted order; perm maps them back.  `workspace_dev` (caller-owned,
  * 256-byte aligned, contents on return unspecified) of at least the bytes
- * sgrid_sort_particles_workspace_size returns (about 16 n + 0.25 n bytes).
+ * sgrid_sort_particles_workspace_size returns (about 16.5 n bytes).
  * n in [0, 2^32 - 1]; pos and pos_sorted distinct.  Asynchronous on `stream`.
  */
 sgrid_status sgrid_sort_particles_workspace_size(const sgrid_grid *grid, int64_t n, int64_t *bytes);
