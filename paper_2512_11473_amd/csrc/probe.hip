@@ -222,9 +222,9 @@ __global__ __launch_bounds__(256) void probe_field_kernel(Corner<float, true> fi
 // and a second kernel (eight wavefronts, three workgroups per CU)
 // ranks the tile's elements stably (wavefront ballots over the digit bits,
 // then per-wavefront running counts in LDS), reorders the tile by digit in
-// LDS and writes each digit's run contiguously.  The first pass computes the
-// keys from the positions; the last writes the permutation and gathers the
-// sorted positions.  Both kernels take their tiles in XCD-aware order: the
+// LDS and writes each digit's run contiguously.  The first pass's counts
+// compute the keys from the positions and store them for its scatter; the
+// last pass writes the permutation and gathers the sorted positions.  Both kernels take their tiles in XCD-aware order: the
 // runs of one digit from consecutive tiles are adjacent in the output, and
 // the partial cache lines where they meet are then written from one L2.
 
@@ -250,18 +250,15 @@ __device__ __forceinline__ uint32_t home_key(const float *x, int M, float inv_h)
     return spread3((uint32_t)cx) | (spread3((uint32_t)cy) << 1) | (spread3((uint32_t)cz) << 2);
 }
 
-template <bool FIRST>
-__device__ __forceinline__ uint32_t sort_key_at(const float *__restrict__ pos, const uint32_t *__restrict__ keys,
-                                                int64_t e, int M, float inv_h) {
-    return FIRST ? home_key(pos + 3 * e, M, inv_h) : keys[e];
-}
 
 // counts[d * n_tiles + tile] = elements of the tile whose digit is d.
+// The first pass's counts compute the keys from the positions and, when the
+// sort has more passes, store them for the first scatter (keys_out).
 template <bool FIRST>
 __global__ __launch_bounds__(256) void radix_count_kernel(const float *__restrict__ pos,
                                                           const uint32_t *__restrict__ keys, int64_t n, int M,
                                                           float inv_h, int shift, uint32_t *__restrict__ counts,
-                                                          int64_t n_tiles) {
+                                                          int64_t n_tiles, uint32_t *__restrict__ keys_out) {
     __shared__ uint32_t s_hist[kRadixBins];
     for (int d = threadIdx.x; d < kRadixBins; d += 256) s_hist[d] = 0u;
     __syncthreads();
@@ -271,7 +268,11 @@ __global__ __launch_bounds__(256) void radix_count_kernel(const float *__restric
 #pragma unroll 4
         for (int k = 0; k < kSortTile / 256; ++k) {
             const int64_t e = t0 + k * 256 + threadIdx.x;
-            if (e < n) atomicAdd(&s_hist[(home_key(pos + 3 * e, M, inv_h) >> shift) & (kRadixBins - 1)], 1u);
+            if (e < n) {
+                const uint32_t k = home_key(pos + 3 * e, M, inv_h);
+                if (keys_out) keys_out[e] = k;
+                atomicAdd(&s_hist[(k >> shift) & (kRadixBins - 1)], 1u);
+            }
         }
     } else {
         // four consecutive keys per lane and step, one 16-byte load each (the
@@ -388,7 +389,9 @@ __global__ __launch_bounds__(kSortThreads) void radix_scatter_kernel(const float
         const int64_t e = w0 + 64 * j + lane;
         const bool valid = e < n;
         const int64_t ec = valid ? e : n - 1;
-        key[j] = sort_key_at<FIRST>(pos, keys_in, ec, M, inv_h);
+        // (a single-pass sort computes the keys here; otherwise the first
+        // pass's counts have stored them)
+        key[j] = (FIRST && LAST) ? home_key(pos + 3 * ec, M, inv_h) : keys_in[ec];
         idx[j] = FIRST ? (uint32_t)ec : idx_in[ec];
         const uint32_t d = (key[j] >> shift) & (kRadixBins - 1);
         // lanes of this round with the same digit (the valid ones)
@@ -578,8 +581,10 @@ sgrid_status radix_pass(const sgrid_grid *g, const float *pos, const uint32_t *k
                         int64_t n, int shift, const SortPlan &sp, uint32_t *counts, uint32_t *sums,
                         uint32_t *keys_out, uint32_t *idx_out, float *pos_out, hipStream_t st) {
     const float inv_h = (float)(1.0 / g->h);
+    // the first of several passes: the counts store the keys where the scatter reads them
+    uint32_t *first_keys = FIRST && !LAST ? const_cast<uint32_t *>(keys_in) : nullptr;
     hipLaunchKernelGGL(radix_count_kernel<FIRST>, dim3((unsigned)sp.n_tiles), dim3(256), 0, st, pos, keys_in, n, g->M,
-                       inv_h, shift, counts, sp.n_tiles);
+                       inv_h, shift, counts, sp.n_tiles, first_keys);
     SG_CHECK_LAUNCH("sort digit counts");
     hipLaunchKernelGGL(scan_block_kernel, dim3((unsigned)sp.n_sums), dim3(1024), 0, st, counts, sp.n_counts, sums);
     SG_CHECK_LAUNCH("sort scan");
@@ -624,7 +629,8 @@ extern "C" sgrid_status sgrid_sort_particles(const sgrid_grid *g, const float *p
     sgrid_status s;
     if (sp.passes == 1)
         return radix_pass<true, true>(g, pos, nullptr, nullptr, n, 0, sp, counts, sums, nullptr, perm, pos_sorted, st);
-    s = radix_pass<true, false>(g, pos, nullptr, nullptr, n, 0, sp, counts, sums, keys[0], idx[0], nullptr, st);
+    // (keys[1] holds the first pass's keys until the second pass writes it)
+    s = radix_pass<true, false>(g, pos, keys[1], nullptr, n, 0, sp, counts, sums, keys[0], idx[0], nullptr, st);
     if (s != SGRID_OK) return s;
     int cur = 0;
     for (int p = 1; p + 1 < sp.passes; ++p, cur ^= 1) {
