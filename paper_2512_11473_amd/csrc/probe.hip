@@ -250,7 +250,6 @@ __device__ __forceinline__ uint32_t home_key(const float *x, int M, float inv_h)
     return spread3((uint32_t)cx) | (spread3((uint32_t)cy) << 1) | (spread3((uint32_t)cz) << 2);
 }
 
-
 // counts[d * n_tiles + tile] = elements of the tile whose digit is d.
 // The first pass's counts compute the keys from the positions and, when the
 // sort has more passes, store them for the first scatter (keys_out).
@@ -269,9 +268,9 @@ __global__ __launch_bounds__(256) void radix_count_kernel(const float *__restric
         for (int k = 0; k < kSortTile / 256; ++k) {
             const int64_t e = t0 + k * 256 + threadIdx.x;
             if (e < n) {
-                const uint32_t k = home_key(pos + 3 * e, M, inv_h);
-                if (keys_out) keys_out[e] = k;
-                atomicAdd(&s_hist[(k >> shift) & (kRadixBins - 1)], 1u);
+                const uint32_t key = home_key(pos + 3 * e, M, inv_h);
+                if (keys_out) keys_out[e] = key;
+                atomicAdd(&s_hist[(key >> shift) & (kRadixBins - 1)], 1u);
             }
         }
     } else {
